@@ -1,0 +1,114 @@
+"""Random-block tight-binding lattices shaped like the paper's test systems.
+
+The paper times its inverse on s-valent nearest-neighbour tight-binding
+chains, square and cubic lattices (Sec. III, Fig. 4).  These inputs keep that
+geometry with 4 orbitals per site and random blocks:
+
+* site index s = x + Lx (y + Ly z) (x fastest); basis index 4 s + orbital;
+  the coordinates of every orbital are its site's lattice coordinates;
+* open boundaries;
+* H onsite block: 4x4 symmetric, upper triangle (with diagonal) iid N(0, 1) eV;
+* H bond block: an independent 4x4 block per bond, iid N(0, 0.5) eV (0.5 is
+  the standard deviation), H_ts = H_st^T;
+* S onsite block: identity; S bond block: 0.05 * iid N(0, 1), S_ts = S_st^T;
+* neighbours: "nn" = the 2 d axis neighbours, "nn2" = nn plus the face
+  diagonals (4 in 2D, 12 in 3D).
+
+Random numbers are drawn in a fixed order from numpy's default_rng(seed):
+onsite blocks (all sites), then H bond blocks, then S bond blocks, bonds
+enumerated offset by offset and, within an offset, by increasing site index.
+"""
+import numpy as np
+
+_NN = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+_NN2 = [(1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)]
+
+
+def _bonds(dims, offsets):
+    lx, ly, lz = dims
+    xs, ys, zs = np.meshgrid(np.arange(lx), np.arange(ly), np.arange(lz), indexing="ij")
+    # lexicographic site order with x fastest
+    x = xs.transpose(2, 1, 0).ravel()
+    y = ys.transpose(2, 1, 0).ravel()
+    z = zs.transpose(2, 1, 0).ravel()
+    src, dst = [], []
+    for dx, dy, dz in offsets:
+        tx, ty, tz = x + dx, y + dy, z + dz
+        ok = (tx >= 0) & (tx < lx) & (ty >= 0) & (ty < ly) & (tz >= 0) & (tz < lz)
+        s = np.nonzero(ok)[0]
+        t = tx[ok] + lx * (ty[ok] + ly * tz[ok])
+        src.append(s)
+        dst.append(t)
+    if src:
+        return np.concatenate(src), np.concatenate(dst), np.stack([x, y, z], axis=1)
+    return np.zeros(0, np.int64), np.zeros(0, np.int64), np.stack([x, y, z], axis=1)
+
+
+def lattice(dims, neighbours="nn", seed=0, norb=4, onsite_std=1.0, hop_std=0.5, s_scale=0.05):
+    """Build one system.  Returns a dict with n, row_ptr (int64), col (int32),
+    h, s (float64, CSR order, both triangles), coords (n x 3 float64), dims."""
+    dims = tuple(int(d) for d in dims) + (1,) * (3 - len(dims))
+    offsets = list(_NN)
+    if neighbours == "nn2":
+        offsets += _NN2
+    elif neighbours != "nn":
+        raise ValueError("neighbours must be 'nn' or 'nn2'")
+    offsets = [o for o in offsets if all(dims[a] > 1 or o[a] == 0 for a in range(3))]
+    src, dst, site_xyz = _bonds(dims, offsets)
+    nsites = site_xyz.shape[0]
+    nb = src.shape[0]
+    rng = np.random.default_rng(seed)
+    raw = rng.normal(0.0, onsite_std, (nsites, norb, norb))
+    onsite = np.triu(raw) + np.transpose(np.triu(raw, 1), (0, 2, 1))
+    hop = rng.normal(0.0, hop_std, (nb, norb, norb))
+    sov = s_scale * rng.normal(0.0, 1.0, (nb, norb, norb))
+
+    # COO of all 4x4 blocks: onsite, (s,t) and the transposed (t,s) block
+    bi = np.arange(norb)
+    rr = np.repeat(bi, norb)      # row orbital within block
+    cc = np.tile(bi, norb)        # col orbital within block
+    rows = [(norb * np.arange(nsites))[:, None] + rr[None, :],
+            (norb * src)[:, None] + rr[None, :],
+            (norb * dst)[:, None] + rr[None, :]]
+    cols = [(norb * np.arange(nsites))[:, None] + cc[None, :],
+            (norb * dst)[:, None] + cc[None, :],
+            (norb * src)[:, None] + cc[None, :]]
+    hv = [onsite.reshape(nsites, -1), hop.reshape(nb, -1),
+          np.transpose(hop, (0, 2, 1)).reshape(nb, -1)]
+    eye = np.broadcast_to(np.eye(norb).ravel(), (nsites, norb * norb))
+    sv = [eye, sov.reshape(nb, -1), np.transpose(sov, (0, 2, 1)).reshape(nb, -1)]
+    r = np.concatenate([a.ravel() for a in rows]).astype(np.int64)
+    c = np.concatenate([a.ravel() for a in cols]).astype(np.int64)
+    h = np.concatenate([a.ravel() for a in hv])
+    s = np.concatenate([a.ravel() for a in sv])
+    n = nsites * norb
+    order = np.lexsort((c, r))
+    r, c, h, s = r[order], c[order], h[order], s[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, r + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    coords = np.repeat(site_xyz.astype(np.float64), norb, axis=0)
+    return {"n": n, "row_ptr": row_ptr, "col": c.astype(np.int32), "h": h, "s": s,
+            "coords": coords, "dims": dims, "neighbours": neighbours, "seed": seed}
+
+
+# The five workloads: 1D chain, 2D lattice, 3D lattice, eight uneven 2D
+# lattices, large 3D lattice.  kT = 0.1 eV everywhere (beta = 10 / eV).
+CONFIGS = {
+    "chain1d_256x4": {"dims": (256,), "neighbours": "nn", "seed": 0, "n_poles": 60},
+    "square2d_64x4": {"dims": (64, 64), "neighbours": "nn2", "seed": 1, "n_poles": 80},
+    "cubic3d_24x4": {"dims": (24, 24, 24), "neighbours": "nn", "seed": 2, "n_poles": 80},
+    "multi2d_8x4": {"dims": [(k, k) for k in (32, 40, 48, 56, 64, 72, 80, 96)],
+                    "neighbours": "nn", "seed": 30, "n_poles": 100},
+    "cubic3d_40x4": {"dims": (40, 40, 40), "neighbours": "nn2", "seed": 4, "n_poles": 100},
+}
+KT_EV = 0.1
+BETA = 1.0 / KT_EV
+
+
+def config_system(name, index=0):
+    """The system of a named workload (``index`` picks a lattice of multi2d)."""
+    cfg = CONFIGS[name]
+    if name == "multi2d_8x4":
+        return lattice(cfg["dims"][index], cfg["neighbours"], cfg["seed"] + index)
+    return lattice(cfg["dims"], cfg["neighbours"], cfg["seed"])

@@ -1,0 +1,229 @@
+"""Pins of the oracle against facts fixed by the paper and by mathematics.
+
+Nothing here re-types an oracle formula: each check uses a value the paper
+prints, a closed form derived independently (open chains), an invariant, or a
+different algorithm (backward-recurrence continued fraction, dense inverse
+versus eigen decomposition).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import chain, dense, poles
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- poles (Eq. (7))
+
+@pytest.mark.parametrize("n_poles", [1, 2, 7, 60, 80, 100])
+def test_residue_sum_closed_form(n_poles):
+    # tanh_M(y) -> M(M+1)/(2y) as y -> infinity for even depth M = 2 N_p, so
+    # x f_M(x) -> ... gives sum_p R_p = -N_p(2N_p+1)/2 exactly.
+    z, r = poles.cf_poles(n_poles)
+    assert len(z) == n_poles and np.all(np.diff(z) > 0)
+    assert r.sum() == pytest.approx(-n_poles * (2 * n_poles + 1) / 2.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("n_poles", [60, 80, 100])
+def test_lowest_poles_are_matsubara(n_poles):
+    # Near the real axis the CF poles coincide with the Matsubara poles
+    # (2k+1) pi with residue -1 (Sec. II A: poles on the imaginary axis,
+    # denser near the real axis).
+    z, r = poles.cf_poles(n_poles)
+    k = np.arange(8)
+    assert np.allclose(z[:8], (2 * k + 1) * np.pi, rtol=1e-12, atol=0)
+    assert np.allclose(r[:8], -1.0, rtol=0, atol=1e-12)
+    assert np.all(np.diff(np.diff(z)) > -1e-9)       # spacing grows away from the axis
+
+
+@pytest.mark.parametrize("n_poles", [3, 20, 60, 100])
+def test_pole_form_equals_backward_recurrence(n_poles):
+    z, r = poles.cf_poles(n_poles)
+    x = np.linspace(-5.0 * n_poles ** 2, 5.0 * n_poles ** 2, 4001)
+    a = poles.fermi_pole_form(x, z, r)
+    b = poles.fermi_cf_backward(x, 2 * n_poles)
+    assert np.max(np.abs(a - b)) < 2e-14
+
+
+@pytest.mark.parametrize("n_poles", [60, 80, 100])
+def test_cf_reproduces_fermi_in_double_precision(n_poles):
+    # "100 poles at 600 K are exact within double precision" (Sec. II A).
+    # With N_p poles the truncated fraction matches 1/(1+e^x) to a few ulp for
+    # |x| up to about N_p^2/4.
+    z, r = poles.cf_poles(n_poles)
+    x = np.linspace(-n_poles ** 2 / 4.0, n_poles ** 2 / 4.0, 20001)
+    err = np.abs(poles.fermi_pole_form(x, z, r) - poles.fermi(x))
+    assert err.max() < 3e-14
+    # far outside that window the truncation must show (the check is not vacuous)
+    xf = np.array([50.0 * n_poles ** 2])
+    assert abs(poles.fermi_pole_form(xf, z, r) - poles.fermi(xf))[0] > 1e-10
+
+
+def test_pole_weights_sign_convention():
+    # rho = M0 + sum_p w_p Re G(alpha_p) must give 2 f for one level at eps:
+    # 1 + sum_p w_p Re 1/(alpha_p - eps) = 2 f(beta(eps - mu)).
+    mu, beta = 0.3, 10.0
+    alpha, w = poles.pole_shifts_and_weights(mu, beta, 60)
+    for eps in (-3.0, -0.2, 0.3, 0.31, 0.5, 4.0):
+        val = 1.0 + np.sum(w * (1.0 / (alpha - eps)).real)
+        assert val == pytest.approx(2.0 * poles.fermi(beta * (eps - mu)), abs=1e-13)
+
+
+# ------------------------------------------------------- closed-form chains (Eqs. (5), (6))
+
+@pytest.mark.parametrize("n,a,b,s,mu", [(9, 0.2, -1.0, 0.1, 0.05), (40, -0.3, 0.7, -0.2, 0.4),
+                                        (64, 1.0, 1.0, 0.0, 0.9)])
+def test_dense_eigen_rho_matches_closed_form_chain(n, a, b, s, mu):
+    beta = 10.0
+    h, sm = chain.chain_matrices(n, a, b, s)
+    eps, c = dense.eigen(h, sm)
+    assert np.allclose(np.sort(chain.chain_eigenvalues(n, a, b, s)), eps, atol=1e-13)
+    rows, cols = np.nonzero(np.ones((n, n)))
+    got = dense.rho_exact_pattern(eps, c, mu, beta, rows, cols)
+    ref = chain.chain_rho(n, a, b, s, mu, beta)[rows, cols]
+    assert np.max(np.abs(got - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("n,a,b,s,mu,n_poles", [(12, 0.2, -1.0, 0.1, 0.05, 60), (30, -0.3, 0.7, -0.2, 0.4, 40)])
+def test_pole_sum_by_dense_inverse_matches_closed_form_chain(n, a, b, s, mu, n_poles):
+    # Eq. (8) with a dense inverse per pole reproduces the exact rho (the
+    # spectrum is far inside the window where the CF is exact).
+    beta = 10.0
+    h, sm = chain.chain_matrices(n, a, b, s)
+    rows, cols = np.nonzero(np.abs(h) + np.abs(sm) > 0)
+    got = dense.rho_poles_dense(h, sm, mu, beta, n_poles, rows, cols)
+    ref = chain.chain_rho(n, a, b, s, mu, beta)[rows, cols]
+    assert np.max(np.abs(got - ref)) < 2e-13
+
+
+def test_green_dense_matches_closed_form_chain():
+    n, a, b, s = 17, 0.1, -0.8, 0.15
+    h, sm = chain.chain_matrices(n, a, b, s)
+    for zc in (0.3 + 0.314j, -1.0 + 2.0j, 0.0 + 500.0j):
+        g = dense.green_dense(h, sm, zc)
+        assert np.max(np.abs(g - chain.chain_green(n, a, b, s, zc))) < 1e-13 * max(1.0, np.abs(g).max())
+        assert np.allclose(g, g.T, atol=1e-14)          # complex symmetric, not Hermitian
+
+
+def test_block_chain_four_orbitals():
+    rng = np.random.default_rng(5)
+    q, _ = np.linalg.qr(rng.normal(size=(4, 4)))
+    e = rng.normal(size=4)
+    v = 0.5 * rng.normal(size=4)
+    w = 0.1 * rng.uniform(-1, 1, size=4)
+    n, mu, beta = 15, 0.1, 10.0
+    h, sm = chain.block_chain_matrices(n, q, e, v, w)
+    eps, c = dense.eigen(h, sm)
+    rows, cols = np.nonzero(np.abs(h) + np.abs(sm) > 1e-15)
+    got = dense.rho_exact_pattern(eps, c, mu, beta, rows, cols)
+    ref = chain.block_chain_rho(n, q, e, v, w, mu, beta)[rows, cols]
+    assert np.max(np.abs(got - ref)) < 1e-12
+    got2 = dense.rho_poles_dense(h, sm, mu, beta, 60, rows, cols)
+    assert np.max(np.abs(got2 - ref)) < 1e-12
+
+
+# ------------------------------------------------------------- invariants
+
+def _small_lattice(dims, nb, seed):
+    import scipy.sparse as sp
+    from synth import lattice
+    sysd = lattice(dims, nb, seed)
+    n = sysd["n"]
+    h = sp.csr_matrix((sysd["h"], sysd["col"], sysd["row_ptr"]), shape=(n, n))
+    s = sp.csr_matrix((sysd["s"], sysd["col"], sysd["row_ptr"]), shape=(n, n))
+    rows = np.repeat(np.arange(n), np.diff(sysd["row_ptr"]))
+    return sysd, h, s, rows, sysd["col"].astype(np.int64)
+
+
+def test_trace_rho_s_equals_electron_count():
+    # Eq. (40): Tr(rho S) = N_ideal at the half-filling mu; Tr needs rho only
+    # on the pattern of S.
+    sysd, h, s, rows, cols = _small_lattice((6, 5), "nn2", 11)
+    beta = 10.0
+    eps, c = dense.eigen(h, s)
+    n = sysd["n"]
+    mu = dense.mu_for_count(eps, beta, float(n))
+    assert dense.electron_count(eps, mu, beta) == pytest.approx(n, abs=1e-9)
+    rho = dense.rho_exact_pattern(eps, c, mu, beta, rows, cols)
+    assert dense.trace_rho_s(rho, sysd["s"]) == pytest.approx(n, abs=1e-9)
+    rho_p = dense.rho_poles_dense(h, s, mu, beta, 60, rows, cols)
+    assert dense.trace_rho_s(rho_p, sysd["s"]) == pytest.approx(n, abs=1e-9)
+    assert np.max(np.abs(rho_p - rho)) < 1e-12
+    rho_cf = dense.rho_cf_pattern(eps, c, mu, beta, 60, rows, cols)
+    assert np.max(np.abs(rho_cf - rho)) < 1e-12
+
+
+def test_s_inverse_from_eigenvectors():
+    sysd, h, s, rows, cols = _small_lattice((3, 3, 2), "nn", 2)
+    eps, c = dense.eigen(h, s)
+    got = dense.s_inverse_pattern(c, rows, cols)
+    ref = np.linalg.inv(s.toarray())[rows, cols]
+    assert np.max(np.abs(got - ref)) < 1e-13
+
+
+def test_mu_bisection_brackets_gap_for_insulator():
+    # Two flat levels at -1 and +1 (two-site molecule): half filling puts mu at 0.
+    eps = np.array([-1.0, -1.0, 1.0, 1.0])
+    mu = dense.mu_for_count(eps, 10.0, 4.0)
+    assert mu == pytest.approx(0.0, abs=1e-10)
+
+
+# ------------------------------------------------------------- Appendix A
+
+def _appendix_a():
+    with open(os.path.join(GOLDEN, "appendix_a.json")) as f:
+        fx = json.load(f)
+    x = np.zeros((7, 7))
+    for i, j in fx["matrix_nonzeros"]:
+        x[i - 1, j - 1] = fx["matrix_value"]
+    return fx, x
+
+
+def test_appendix_a_selected_inverse_dense():
+    fx, x = _appendix_a()
+    assert np.allclose(x, x.T)
+    # G(0) = (0 S - H)^{-1} with H = -X gives X^{-1} through the oracle's routine
+    g = dense.green_dense(-x, np.eye(7), 0.0)
+    for i, j, v in fx["selected_inverse"]:
+        assert g[i - 1, j - 1].real == pytest.approx(v, abs=1e-14)
+    # every printed entry sits on the pattern, and every pattern entry is printed
+    printed = {(i, j) for i, j, _ in fx["selected_inverse"]}
+    assert printed == {tuple(p) for p in fx["matrix_nonzeros"]}
+
+
+def test_appendix_a_is_the_chain_closed_form():
+    fx, x = _appendix_a()
+    order = [k - 1 for k in fx["chain_order"]]
+    # chain with a = b = 1, s = 0 at z = 0: G(0) = -H^{-1} = -X^{-1}
+    gc = chain.chain_green(7, 1.0, 1.0, 0.0, 0.0)
+    inv_structured = np.empty((7, 7))
+    for p, i in enumerate(order):
+        for q, j in enumerate(order):
+            inv_structured[i, j] = -gc[p, q]
+    for i, j, v in fx["selected_inverse"]:
+        assert inv_structured[i - 1, j - 1] == pytest.approx(v, abs=1e-13)
+
+
+def test_appendix_a_intermediates():
+    fx, x = _appendix_a()
+    it = fx["intermediates"]
+    # leaf domains {1},{2} with separator {3}; {4},{5} with {6}; top separator {7}
+    a00, a01, c00 = x[0, 0], x[1, 1], x[2, 2]
+    b00, b01 = x[2, 0], x[2, 1]
+    s00 = c00 - b00 * (b00 / a00) - b01 * (b01 / a01)       # Eq. (20) with L = B A^{-1}
+    assert [s00] == [it["S0"][0]]
+    blk = x[np.ix_([0, 1, 2], [0, 1, 2])]
+    pre = np.linalg.inv(blk)
+    for i, j, v in it["precursor_X10_inv_selected"]:
+        assert pre[i - 1, j - 1] == pytest.approx(v, abs=1e-14)
+    # L_{1,0}^T = X_{left}^{-1} B_{1,0}^T and L_{1,1}^T likewise (Eq. (24))
+    b10 = x[6, [0, 1, 2]]
+    b11 = x[6, [3, 4, 5]]
+    l10 = np.linalg.inv(x[np.ix_([0, 1, 2], [0, 1, 2])]) @ b10
+    l11 = np.linalg.inv(x[np.ix_([3, 4, 5], [3, 4, 5])]) @ b11
+    assert np.allclose(l10, it["L10T"]) and np.allclose(l11, it["L11T"])
+    s10 = x[6, 6] - b10 @ l10 - b11 @ l11
+    assert s10 == pytest.approx(it["S10"])
