@@ -1,0 +1,196 @@
+/*
+ * ndrho -- selected elements of the density matrix by nested dissection and
+ * selected inversion, on one MI355X (gfx950) GPU.
+ *
+ * Method (T. Ozaki, "Numerically exact O(N^{7/3}) method for large-scale
+ * electronic structure calculations"):
+ *   rho = M0 + Im(-(4i/beta) sum_p G(alpha_p) R_p),   alpha_p = mu + i z_p/beta
+ *   (Sec. II A, Eq. (8)), with G(Z) = (Z S - H)^{-1} (Eq. (6)) evaluated only
+ *   on the sparsity pattern of H and S (Sec. II B): the matrix is reordered by
+ *   nested dissection (Sec. II B 1), factored by block LDL^T (Eqs. (18)-(20))
+ *   front by front, and selectively inverted back down the dissection tree
+ *   (Eq. (21), Eqs. (38)-(39)).  M0 = S^{-1} on the pattern (the zeroth moment
+ *   of G; the constant 1/2 of Eq. (7) times the spin factor 2).
+ *
+ * Conventions for every entry point:
+ *   - every call returns an int status (NDRHO_OK or a negative code); no C++
+ *     exception crosses this interface;
+ *   - after a non-OK status, ndrho_last_error() returns a message;
+ *   - a context is not thread safe: the caller serialises calls on it;
+ *   - all device work is ordered on the context's HIP stream;
+ *   - input arrays are copied; the caller keeps ownership of all its buffers.
+ *
+ * CSR input format (set_structure): 0-based, n rows, row_ptr[n+1] (int64,
+ * row_ptr[0] = 0, non-decreasing), col_idx[nnz] (int32, strictly increasing
+ * within each row), the diagonal present in every row, the pattern
+ * structurally symmetric, values H and S real symmetric on it (|a_ij - a_ji|
+ * <= 1e-12 max|a|), all finite; S positive definite.
+ */
+#ifndef NDRHO_H
+#define NDRHO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ndrho_ctx ndrho_ctx;
+typedef struct ndrho_plan ndrho_plan;
+
+enum {
+  NDRHO_OK = 0,
+  NDRHO_EINVAL = -1,      /* malformed argument or input matrix */
+  NDRHO_ENOMEM = -2,      /* device or host allocation failed / plan exceeds memory */
+  NDRHO_ENOTSPD = -3,     /* S is not positive definite (a pivot of S <= 0) */
+  NDRHO_ESINGULAR = -4,   /* a zero, tiny or non-finite pivot in alpha S - H */
+  NDRHO_EDEVICE = -5,     /* HIP runtime error, or no usable gfx950 device */
+  NDRHO_ESTATE = -6,      /* call out of order (e.g. density_matrix before set_poles) */
+  NDRHO_EUNSUPPORTED = -7 /* option not supported by this build */
+};
+
+enum { NDRHO_FP64 = 0 };  /* arithmetic of the factorization (complex128) */
+
+typedef struct {
+  int32_t leaf_rows;   /* nested dissection stops at domains of <= leaf_rows rows (default 32) */
+  int32_t precision;   /* NDRHO_FP64 */
+  int32_t pole_batch;  /* poles per device pass; 0 = largest that fits the memory budget */
+  double mem_fraction; /* fraction of free device memory the workspace may use (default 0.8) */
+  int32_t verbose;     /* 0 = quiet */
+} ndrho_options;
+
+/* Fill *opt with the defaults listed above. */
+int ndrho_default_options(ndrho_options* opt);
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t owned
+ * by the caller (the context never destroys it), or NULL for a stream owned
+ * by the context.  opt: NULL for defaults.  *out receives the context.
+ * Errors: EINVAL (out NULL, bad option), EDEVICE (no such device, not gfx950). */
+int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_options* opt);
+
+/* Release every device and host resource of the context.  NULL is a no-op. */
+int ndrho_destroy(ndrho_ctx* ctx);
+
+/* Message for the last non-OK status on ctx (owned by ctx, valid until the
+ * next call on ctx).  With ctx == NULL, the last error of a failed create. */
+const char* ndrho_last_error(const ndrho_ctx* ctx);
+
+/* Register one H, S pair (Sec. II, Eq. (2)): validates the CSR (format above),
+ * computes the nested-dissection ordering (Sec. II B 1; geometric, from coords
+ * when given as n*3 doubles of basis-function centres, row-major), the
+ * front tree and index maps (the "table function" of Sec. II B 2), uploads
+ * everything to the device, and computes M0 = S^{-1} on the pattern by one
+ * real selected inversion of S, which also checks that S is positive
+ * definite.  *struct_id receives the handle for later calls.
+ * Host pointers only.  Errors: EINVAL (format, asymmetry, non-finite),
+ * ENOTSPD (S not positive definite), ENOMEM, EDEVICE. */
+int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                        const double* H, const double* S, const double* coords, int32_t* struct_id);
+
+/* Replace the values of H and S of a registered structure (same pattern).
+ * Recomputes M0.  Errors as set_structure. */
+int ndrho_update_values(ndrho_ctx* ctx, int32_t struct_id, const double* H, const double* S);
+
+/* Choose the poles of Eq. (8) for a structure: z_p, R_p of the continued
+ * fraction of depth 2*n_poles (Eq. (7)), alpha_p = mu + i z_p/beta and
+ * weights w_p = -(4/beta) R_p.  mu in the energy unit of H, beta = 1/kT in
+ * its inverse.  Errors: EINVAL (n_poles < 1, beta <= 0 or non-finite). */
+int ndrho_set_poles(ndrho_ctx* ctx, int32_t struct_id, double mu, double beta, int32_t n_poles);
+
+/* General weighted sum instead of Eq. (8)'s poles: the next density_matrix
+ * returns (add_m0 ? M0 : 0) + sum_k weight[k] Re G(alpha_k)_ij on the pattern,
+ * with alpha_k = alpha_re[k] + i alpha_im[k] (host arrays of length n).
+ * Real or near-real shifts are the caller's risk: the factorization does not
+ * pivot, and a vanishing pivot returns ESINGULAR. */
+int ndrho_set_shifts(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double* alpha_re,
+                     const double* alpha_im, const double* weight, int32_t add_m0);
+
+/* rho_ij on the pattern (Eq. (8), spin factor 2 included), nnz doubles in the
+ * caller's CSR order.  rho_out is a host pointer (on_device = 0; the call
+ * synchronises) or a device pointer on the context's device (on_device = 1;
+ * the result is ready when the context stream reaches that point).
+ * Errors: ESTATE (no poles set), ESINGULAR, EDEVICE, ENOMEM. */
+int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int32_t on_device);
+
+/* Same for k structures, in the order given. */
+int ndrho_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, double* const* rho_outs,
+                               int32_t on_device);
+
+typedef struct {
+  int64_t n, nnz;
+  int32_t n_fronts, n_levels;      /* fronts of the dissection tree; depth + 1 */
+  int32_t max_front_j, max_front_u;/* largest pivot block and update set */
+  int32_t root_j;                  /* pivot rows of the (largest) root front */
+  int32_t n_poles, pole_batch;     /* poles set; poles per device pass */
+  double flops_per_pole;           /* algorithmic flop model (8 real flops per complex FMA) */
+  double flops_exec_per_pole;      /* flops the kernels actually execute per pole */
+  double bytes_per_pole;           /* algorithmic HBM bytes of the front data per pole */
+  double factor_bytes_per_pole;    /* device bytes of the factor panels per pole */
+  double workspace_bytes;          /* device workspace currently allocated */
+  double last_ms;                  /* wall time of the last density_matrix (host clock) */
+  int64_t launches_per_pass;       /* kernel launches of one pass over a pole batch */
+} ndrho_stats_t;
+
+int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out);
+
+/* Kernel kinds reported by the profile below. */
+enum { NDRHO_K_EXTADD = 0, NDRHO_K_ASSEMBLE = 1, NDRHO_K_PIVOT_INV = 2, NDRHO_K_GEMM = 3, NDRHO_K_COPY = 4,
+       NDRHO_K_GATHER = 5, NDRHO_K_ACCUM = 6, NDRHO_K_COUNT = 7 };
+
+/* enable != 0: from now on every launch is bracketed by HIP events on the
+ * context stream and its duration is added to a per-kind total (clears the
+ * totals); enable == 0 stops recording.  Instrumented calls are slower. */
+int ndrho_profile(ndrho_ctx* ctx, int32_t enable);
+/* Per-kind totals since profiling was enabled: kernel milliseconds, useful
+ * flops (complex GEMMs: 8 real flops per complex multiply-add, symmetric
+ * outputs counted once), and launch counts; arrays of NDRHO_K_COUNT. */
+int ndrho_profile_read(const ndrho_ctx* ctx, double* ms, double* flops, int64_t* launches);
+
+/* Device memory on the context's device for callers without their own
+ * allocator (e.g. a device-resident rho_out).  ndrho_device_alloc returns
+ * `bytes` of device memory in *ptr (EINVAL for bytes <= 0, ENOMEM);
+ * ndrho_device_free releases it (NULL is a no-op); ndrho_device_to_host
+ * copies `bytes` from device `src` to host `dst` after the context stream's
+ * pending work, and synchronises. */
+int ndrho_device_alloc(ndrho_ctx* ctx, int64_t bytes, void** ptr);
+int ndrho_device_free(ndrho_ctx* ctx, void* ptr);
+int ndrho_device_to_host(ndrho_ctx* ctx, void* dst, const void* src, int64_t bytes);
+
+/* ---------------- host-only utilities (no device needed) ---------------- */
+
+/* Poles z[n_poles] (increasing) and residues R[n_poles] of the continued
+ * fraction of depth 2*n_poles (Eq. (7)): f(x) = 1/2 + sum_p R_p [1/(x - i z_p)
+ * + 1/(x + i z_p)].  Errors: EINVAL. */
+int ndrho_cf_poles(int32_t n_poles, double* z, double* R);
+
+/* Nested dissection and symbolic analysis only (Sec. II B), for inspection.
+ * Same input rules as set_structure (values are not needed). */
+int ndrho_plan_create(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* coords,
+                      int32_t leaf_rows, ndrho_plan** out);
+int ndrho_plan_destroy(ndrho_plan* plan);
+const char* ndrho_plan_last_error(void);
+/* Sizes: counts[0] = n_fronts, [1] = n_levels, [2] = sum |U_f|, [3] = nnz,
+ * [4] = panel elements per pole (sum (J+U) J), [5] = max J, [6] = max U. */
+int ndrho_plan_counts(const ndrho_plan* plan, int64_t* counts);
+/* perm[k] = original index of the k-th eliminated row (n int32). Per front f
+ * (postorder, children before parents): parent[f] (-1 = root), depth[f],
+ * j0[f] (first permuted position of its pivot rows), nj[f], nu[f],
+ * u_off[f] (offset into the concatenated update lists).  u_rows[sum U]:
+ * permuted positions of every front's update rows, increasing within a front;
+ * rel[sum U]: index of each update row in the parent's local (J then U) order.
+ * Any pointer may be NULL to skip it. */
+int ndrho_plan_export(const ndrho_plan* plan, int32_t* perm, int32_t* parent, int32_t* depth, int64_t* j0,
+                      int32_t* nj, int32_t* nu, int64_t* u_off, int32_t* u_rows, int32_t* rel);
+/* Per CSR entry e: out_slot[e] = offset (complex elements) of G_ij in the
+ * per-pole panel storage, asm_slot[e] = offset where X_ij is assembled, or -1
+ * when the transposed entry carries it; panel_off[f] = start of front f's
+ * column-major (J+U) x J panel. */
+int ndrho_plan_slots(const ndrho_plan* plan, int64_t* out_slot, int64_t* asm_slot, int64_t* panel_off);
+/* Flop and byte model per pole (8 real flops per complex multiply-add). */
+int ndrho_plan_model(const ndrho_plan* plan, double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NDRHO_H */

@@ -1,0 +1,65 @@
+"""Sampled-column reference for systems too large for dense algebra.
+
+For a few columns j, G(alpha_p) e_j = (alpha_p S - H)^{-1} e_j (Eq. (6)) is
+obtained by a sparse solve, M0 e_j = S^{-1} e_j likewise, and column j of rho
+follows from Eq. (8): rho e_j = S^{-1} e_j + sum_p w_p Re G(alpha_p) e_j with
+w_p = -(4/beta) R_p.  Restricted to the pattern rows of column j this is the
+exact density matrix up to the solver's rounding (sparse LU), or up to its
+tolerance (GMRES).
+"""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+
+from .poles import cf_poles
+
+
+def csr_matrices(n, row_ptr, col, hv, sv):
+    h = sp.csr_matrix((hv, col, row_ptr), shape=(n, n))
+    s = sp.csr_matrix((sv, col, row_ptr), shape=(n, n))
+    return h, s
+
+
+def unit_columns(n, cols, dtype):
+    e = np.zeros((n, len(cols)), dtype=dtype)
+    e[np.asarray(cols), np.arange(len(cols))] = 1.0
+    return e
+
+
+def green_columns_lu(h, s, alpha, cols):
+    """(alpha S - H)^{-1}[:, cols] by a sparse LU factorization (SuperLU)."""
+    x = (alpha * s.astype(np.complex128) - h).tocsc()
+    lu = spl.splu(x)
+    return lu.solve(unit_columns(h.shape[0], cols, np.complex128))
+
+
+def s_inverse_columns(s, cols):
+    """S^{-1}[:, cols] by a sparse LU factorization (the exact M0 of Eq. (8))."""
+    lu = spl.splu(s.tocsc())
+    return lu.solve(unit_columns(s.shape[0], cols, np.float64))
+
+
+def green_column_gmres(h, s, alpha, j, rtol=1e-13):
+    """(alpha S - H)^{-1} e_j by unpreconditioned GMRES(200)."""
+    x = (alpha * s.astype(np.complex128) - h).tocsr()
+    b = np.zeros(h.shape[0], dtype=np.complex128)
+    b[j] = 1.0
+    sol, info = spl.gmres(x, b, rtol=rtol, atol=0.0, restart=200, maxiter=50)
+    if info != 0:
+        raise RuntimeError("GMRES did not converge (info=%d)" % info)
+    return sol
+
+
+def rho_columns(h, s, mu, beta, n_poles, cols, pool=None):
+    """Columns `cols` of rho (Eq. (8)) from one sparse LU per pole.
+
+    pool: optional multiprocessing pool mapping over poles."""
+    z, r = cf_poles(n_poles)
+    alphas = mu + 1j * z / beta
+    w = -(4.0 / beta) * r
+    out = s_inverse_columns(s, cols).copy()
+    args = [(h, s, a, cols) for a in alphas]
+    cols_g = pool.starmap(green_columns_lu, args) if pool is not None else [green_columns_lu(*a) for a in args]
+    for wp, g in zip(w, cols_g):
+        out += wp * g.real
+    return out

@@ -1,0 +1,718 @@
+// C interface of the ndrho library: contexts, structures, poles, and the
+// executor that replays a structure's launch program for each pole batch.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+
+using namespace ndrho;
+
+namespace {
+
+#define HIP_OK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) fail(NDRHO_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+T* upload(const std::vector<T>& v, hipStream_t st) {
+  if (v.empty()) return nullptr;
+  T* p = nullptr;
+  if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) fail(NDRHO_ENOMEM, "device allocation failed");
+  HIP_OK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return p;
+}
+
+struct DevStruct {
+  Plan plan;
+  std::vector<void*> allocs;
+  double *h = nullptr, *s = nullptr, *m0 = nullptr;
+  GemmProb* gemm = nullptr;
+  TileRef* gemm_tiles = nullptr;
+  InvDesc* inv = nullptr;
+  CopyDesc* copy = nullptr;
+  CopyTile* copy_tiles = nullptr;
+  ExtAddDesc* ext = nullptr;
+  ExtAddChild* ext_child = nullptr;
+  int32_t* ext_inv = nullptr;
+  ElemTile *ext_tiles = nullptr, *gat_tiles = nullptr;
+  GatherDesc* gat = nullptr;
+  int32_t* rel = nullptr;
+  int64_t* asm_slot = nullptr;
+  int32_t* asm_entry = nullptr;
+  int64_t* acc_slot = nullptr;
+  int32_t* acc_entry = nullptr;
+  // shifts and weights
+  int n_shifts = 0;
+  bool add_m0 = true;
+  double2* d_alpha = nullptr;
+  double* d_w = nullptr;
+
+  template <class T>
+  T* put(const std::vector<T>& v, hipStream_t st) {
+    T* p = upload(v, st);
+    if (p) allocs.push_back(p);
+    return p;
+  }
+  void release() {
+    for (void* p : allocs) (void)hipFree(p);
+    allocs.clear();
+    if (d_alpha) (void)hipFree(d_alpha);
+    if (d_w) (void)hipFree(d_w);
+    d_alpha = nullptr;
+    d_w = nullptr;
+  }
+};
+
+thread_local std::string g_err;  // errors without a context (create, plan utilities)
+
+}  // namespace
+
+struct ndrho_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  ndrho_options opt{};
+  std::string err;
+  std::vector<std::unique_ptr<DevStruct>> structs;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  double* acc = nullptr;
+  double* outbuf = nullptr;
+  int64_t acc_len = 0;
+  int* status = nullptr;
+  double last_ms = 0;
+  int last_batch = 0;
+  // profiling: events around launches, folded into per-kind totals
+  bool prof = false;
+  std::vector<hipEvent_t> events;
+  struct Rec {
+    int kind;
+    size_t ev;
+    double flops;
+  };
+  std::vector<Rec> recs;
+  double prof_ms[NDRHO_K_COUNT] = {0};
+  double prof_flops[NDRHO_K_COUNT] = {0};
+  int64_t prof_n[NDRHO_K_COUNT] = {0};
+
+  hipEvent_t event(size_t i) {
+    while (events.size() <= i) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      events.push_back(e);
+    }
+    return events[i];
+  }
+  // bracket a launch when profiling
+  template <class L>
+  void timed(int kind, double flops, L&& launch) {
+    if (!prof) {
+      launch();
+      return;
+    }
+    const size_t i = 2 * recs.size();
+    HIP_OK(hipEventRecord(event(i), stream));
+    launch();
+    HIP_OK(hipEventRecord(event(i + 1), stream));
+    recs.push_back(Rec{kind, i, flops});
+  }
+  // fold recorded events into the totals (stream must be complete)
+  void fold_profile() {
+    for (const Rec& r : recs) {
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, events[r.ev], events[r.ev + 1]));
+      prof_ms[r.kind] += ms;
+      prof_flops[r.kind] += r.flops;
+      prof_n[r.kind] += 1;
+    }
+    recs.clear();
+  }
+
+  ~ndrho_ctx() {
+    for (auto& s : structs)
+      if (s) s->release();
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (ws) (void)hipFree(ws);
+    if (acc) (void)hipFree(acc);
+    if (outbuf) (void)hipFree(outbuf);
+    if (status) (void)hipFree(status);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+
+  DevStruct& get(int32_t id) {
+    if (id < 0 || id >= static_cast<int32_t>(structs.size()) || !structs[id])
+      fail(NDRHO_EINVAL, "invalid struct_id");
+    return *structs[id];
+  }
+
+  static int64_t per_pole_elems(const Plan& P) { return P.panel_total + 2 * P.upd_total + P.temp_total; }
+
+  // Workspace for `nb` poles of plan P (grown, never shrunk).
+  void ensure_ws(const Plan& P, int nb) {
+    const size_t need = static_cast<size_t>(per_pole_elems(P)) * nb * sizeof(double2);
+    if (need > ws_bytes) {
+      if (ws) HIP_OK(hipFree(ws));
+      ws = nullptr;
+      ws_bytes = 0;
+      if (hipMalloc(&ws, need) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(NDRHO_ENOMEM, "workspace allocation of " + std::to_string(need) + " bytes failed");
+      }
+      ws_bytes = need;
+    }
+    if (P.nnz > acc_len) {
+      if (acc) HIP_OK(hipFree(acc));
+      if (outbuf) HIP_OK(hipFree(outbuf));
+      acc = outbuf = nullptr;
+      if (hipMalloc(&acc, P.nnz * sizeof(double)) != hipSuccess ||
+          hipMalloc(&outbuf, P.nnz * sizeof(double)) != hipSuccess)
+        fail(NDRHO_ENOMEM, "accumulator allocation failed");
+      acc_len = P.nnz;
+    }
+  }
+
+  // Poles per device pass for plan P.
+  int batch_for(const Plan& P, int n_shifts) {
+    if (opt.pole_batch > 0) return std::min(opt.pole_batch, n_shifts);
+    size_t free_b = 0, total_b = 0;
+    HIP_OK(hipMemGetInfo(&free_b, &total_b));
+    const double budget = opt.mem_fraction * (static_cast<double>(free_b) + static_cast<double>(ws_bytes));
+    const double pp = static_cast<double>(per_pole_elems(P)) * sizeof(double2);
+    int nb = static_cast<int>(budget / pp);
+    if (nb < 1) fail(NDRHO_ENOMEM, "one pole needs " + std::to_string(pp) + " bytes; budget " + std::to_string(budget));
+    return std::min(nb, n_shifts);
+  }
+
+  // One pass of the whole program over `nb` poles.
+  void run_pass(DevStruct& S, int nb, const double2* alpha, const double* w, double hcoef, int spd_check) {
+    const Plan& P = S.plan;
+    double2* base = static_cast<double2*>(ws);
+    double2* bufs[BUF_COUNT];
+    int64_t strides[BUF_COUNT];
+    bufs[BUF_PANEL] = base;
+    strides[BUF_PANEL] = P.panel_total;
+    bufs[BUF_UPD0] = base + P.panel_total * nb;
+    strides[BUF_UPD0] = P.upd_total;
+    bufs[BUF_UPD1] = bufs[BUF_UPD0] + P.upd_total * nb;
+    strides[BUF_UPD1] = P.upd_total;
+    bufs[BUF_TEMP] = bufs[BUF_UPD1] + P.upd_total * nb;
+    strides[BUF_TEMP] = P.temp_total;
+    auto resolve = [&](const Op& op) {
+      DevOp d;
+      d.flags = op.flags;
+      d.npoles = nb;
+      d.count = op.count;
+      d.tile_count = op.tile_count;
+      d.a = bufs[op.buf_a], d.sa = strides[op.buf_a];
+      d.b = bufs[op.buf_b], d.sb = strides[op.buf_b];
+      d.c0 = bufs[op.buf_c0], d.sc0 = strides[op.buf_c0];
+      d.c = bufs[op.buf_c], d.sc = strides[op.buf_c];
+      return d;
+    };
+    auto run = [&](const Op& op) {
+      DevOp d = resolve(op);
+      hipError_t e = hipSuccess;
+      switch (op.kind) {
+        case OP_EXTADD:
+          d.ext = S.ext + op.begin;
+          d.ext_child = S.ext_child;
+          d.ext_inv = S.ext_inv;
+          d.elem_tiles = S.ext_tiles + op.tile_begin;
+          timed(NDRHO_K_EXTADD, 0.0, [&] { e = launch_extadd(d, stream); });
+          break;
+        case OP_ASSEMBLE:
+          d.slot = S.asm_slot + op.begin;
+          d.entry = S.asm_entry + op.begin;
+          timed(NDRHO_K_ASSEMBLE, 0.0, [&] { e = launch_assemble(d, S.h, S.s, alpha, hcoef, stream); });
+          break;
+        case OP_SMALLINV:
+          d.inv = S.inv + op.begin;
+          timed(NDRHO_K_PIVOT_INV, 0.0, [&] { e = launch_smallinv(d, status, spd_check, stream); });
+          break;
+        case OP_GEMM:
+          d.gemm = S.gemm + op.begin;
+          d.gemm_tiles = S.gemm_tiles + op.tile_begin;
+          timed(NDRHO_K_GEMM, op.flops * nb, [&] { e = launch_gemm(d, stream); });
+          break;
+        case OP_COPY:
+          d.copy = S.copy + op.begin;
+          d.copy_tiles = S.copy_tiles + op.tile_begin;
+          timed(NDRHO_K_COPY, 0.0, [&] { e = launch_copy(d, stream); });
+          break;
+        case OP_GATHER:
+          d.gat = S.gat + op.begin;
+          d.rel = S.rel;
+          d.elem_tiles = S.gat_tiles + op.tile_begin;
+          timed(NDRHO_K_GATHER, 0.0, [&] { e = launch_gather(d, stream); });
+          break;
+      }
+      if (e != hipSuccess) fail(NDRHO_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    };
+    for (const Op& op : P.upward) run(op);
+    for (const Op& op : P.downward) run(op);
+    hipError_t ea = hipSuccess;
+    timed(NDRHO_K_ACCUM, 0.0,
+          [&] { ea = launch_accum(S.acc_slot, P.nnz, bufs[BUF_PANEL], P.panel_total, w, nb, acc, stream); });
+    HIP_OK(ea);
+  }
+
+  // Full weighted sum over the structure's shifts into `acc` (sorted order).
+  void evaluate(DevStruct& S, const double2* alpha, const double* w, int n, bool add_m0, double hcoef,
+                int spd_check) {
+    const Plan& P = S.plan;
+    const int nb = batch_for(P, n);
+    ensure_ws(P, nb);
+    last_batch = nb;
+    HIP_OK(launch_init_acc(S.m0, P.nnz, add_m0 ? 1 : 0, acc, status, stream));
+    for (int p0 = 0; p0 < n; p0 += nb) {
+      const int cnt = std::min(nb, n - p0);
+      run_pass(S, cnt, alpha + p0, w + p0, hcoef, spd_check);
+    }
+  }
+
+  void read_status(int* st) {
+    HIP_OK(hipMemcpyAsync(st, status, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    if (!recs.empty()) fold_profile();
+  }
+
+  // M0 = S^{-1} on the pattern: the real selected inversion of S (alpha = 1,
+  // no H), which also tests S for positive definiteness through its pivots.
+  void compute_m0(DevStruct& S) {
+    const Plan& P = S.plan;
+    std::vector<double2> one(1, make_double2(1.0, 0.0));
+    std::vector<double> w1(1, 1.0);
+    double2* da = upload(one, stream);
+    double* dw = upload(w1, stream);
+    if (!S.m0) {
+      if (hipMalloc(&S.m0, P.nnz * sizeof(double)) != hipSuccess) fail(NDRHO_ENOMEM, "M0 allocation failed");
+      S.allocs.push_back(S.m0);
+    }
+    try {
+      evaluate(S, da, dw, 1, false, 0.0, 1);
+      int st[2];
+      read_status(st);
+      if (st[0] || st[1]) fail(NDRHO_ENOTSPD, "S is not positive definite (a non-positive pivot of S)");
+      HIP_OK(hipMemcpyAsync(S.m0, acc, P.nnz * sizeof(double), hipMemcpyDeviceToDevice, stream));
+      HIP_OK(hipStreamSynchronize(stream));
+    } catch (...) {
+      (void)hipFree(da);
+      (void)hipFree(dw);
+      throw;
+    }
+    (void)hipFree(da);
+    (void)hipFree(dw);
+  }
+
+  void set_shifts(DevStruct& S, const std::vector<double2>& alpha, const std::vector<double>& w, bool add_m0) {
+    if (S.d_alpha) HIP_OK(hipFree(S.d_alpha));
+    if (S.d_w) HIP_OK(hipFree(S.d_w));
+    S.d_alpha = nullptr;
+    S.d_w = nullptr;
+    S.d_alpha = upload(alpha, stream);
+    S.d_w = upload(w, stream);
+    HIP_OK(hipStreamSynchronize(stream));
+    S.n_shifts = static_cast<int>(alpha.size());
+    S.add_m0 = add_m0;
+  }
+};
+
+namespace {
+
+template <class F>
+int guarded(ndrho_ctx* ctx, F&& f) {
+  try {
+    f();
+    return NDRHO_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->err = e.what();
+    else g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "host allocation failed";
+    else g_err = "host allocation failed";
+    return NDRHO_ENOMEM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    else g_err = e.what();
+    return NDRHO_EINVAL;
+  }
+}
+
+}  // namespace
+
+struct ndrho_plan {
+  Plan plan;
+};
+
+extern "C" {
+
+int ndrho_default_options(ndrho_options* opt) {
+  if (!opt) return NDRHO_EINVAL;
+  opt->leaf_rows = 32;
+  opt->precision = NDRHO_FP64;
+  opt->pole_batch = 0;
+  opt->mem_fraction = 0.8;
+  opt->verbose = 0;
+  return NDRHO_OK;
+}
+
+int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_options* opt) {
+  if (!out) {
+    g_err = "out is NULL";
+    return NDRHO_EINVAL;
+  }
+  *out = nullptr;
+  std::unique_ptr<ndrho_ctx> c(new (std::nothrow) ndrho_ctx());
+  if (!c) return NDRHO_ENOMEM;
+  int rc = guarded(nullptr, [&] {
+    ndrho_default_options(&c->opt);
+    if (opt) c->opt = *opt;
+    if (c->opt.leaf_rows < 1) fail(NDRHO_EINVAL, "leaf_rows must be >= 1");
+    if (c->opt.precision != NDRHO_FP64) fail(NDRHO_EUNSUPPORTED, "only NDRHO_FP64 is available");
+    if (c->opt.pole_batch < 0) fail(NDRHO_EINVAL, "pole_batch must be >= 0");
+    if (!(c->opt.mem_fraction > 0.0 && c->opt.mem_fraction <= 1.0)) fail(NDRHO_EINVAL, "mem_fraction must be in (0, 1]");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) fail(NDRHO_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= count) fail(NDRHO_EDEVICE, "device index out of range");
+    HIP_OK(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      fail(NDRHO_EDEVICE, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+    c->device = device;
+    if (hip_stream) {
+      c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      HIP_OK(hipStreamCreate(&c->stream));
+      c->own_stream = true;
+    }
+    if (hipMalloc(&c->status, 2 * sizeof(int)) != hipSuccess) fail(NDRHO_ENOMEM, "status allocation failed");
+  });
+  if (rc == NDRHO_OK) *out = c.release();
+  return rc;
+}
+
+int ndrho_destroy(ndrho_ctx* ctx) {
+  if (!ctx) return NDRHO_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return NDRHO_OK;
+}
+
+const char* ndrho_last_error(const ndrho_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* H,
+                        const double* S, const double* coords, int32_t* struct_id) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    if (!H || !S || !struct_id) fail(NDRHO_EINVAL, "H, S and struct_id are required");
+    HIP_OK(hipSetDevice(ctx->device));
+    validate_csr(n, row_ptr, col_idx, H, S);
+    if (coords)
+      for (int64_t i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(coords[i])) fail(NDRHO_EINVAL, "non-finite coordinate");
+    std::unique_ptr<DevStruct> ds(new DevStruct());
+    try {
+      build_plan(ds->plan, n, row_ptr, col_idx, coords, ctx->opt.leaf_rows);
+      Plan& P = ds->plan;
+      hipStream_t st = ctx->stream;
+      std::vector<double> hv(H, H + P.nnz), sv(S, S + P.nnz);
+      ds->h = ds->put(hv, st);
+      ds->s = ds->put(sv, st);
+      ds->gemm = ds->put(P.gemm, st);
+      ds->gemm_tiles = ds->put(P.gemm_tiles, st);
+      ds->inv = ds->put(P.inv, st);
+      ds->copy = ds->put(P.copy, st);
+      ds->copy_tiles = ds->put(P.copy_tiles, st);
+      ds->ext = ds->put(P.ext, st);
+      ds->ext_child = ds->put(P.ext_child, st);
+      ds->ext_inv = ds->put(P.ext_inv, st);
+      ds->ext_tiles = ds->put(P.ext_tiles, st);
+      ds->gat = ds->put(P.gat, st);
+      ds->gat_tiles = ds->put(P.gat_tiles, st);
+      ds->rel = ds->put(P.rel_all, st);
+      ds->asm_slot = ds->put(P.asm_slot_sorted, st);
+      ds->asm_entry = ds->put(P.asm_entry_sorted, st);
+      ds->acc_slot = ds->put(P.acc_slot, st);
+      ds->acc_entry = ds->put(P.acc_entry, st);
+      HIP_OK(hipStreamSynchronize(st));
+      ctx->compute_m0(*ds);
+    } catch (...) {
+      ds->release();
+      throw;
+    }
+    ctx->structs.push_back(std::move(ds));
+    *struct_id = static_cast<int32_t>(ctx->structs.size()) - 1;
+  });
+}
+
+int ndrho_update_values(ndrho_ctx* ctx, int32_t struct_id, const double* H, const double* S) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    DevStruct& ds = ctx->get(struct_id);
+    if (!H || !S) fail(NDRHO_EINVAL, "H and S are required");
+    const Plan& P = ds.plan;
+    validate_csr(P.n, P.row_ptr.data(), P.col.data(), H, S);
+    HIP_OK(hipSetDevice(ctx->device));
+    HIP_OK(hipMemcpyAsync(ds.h, H, P.nnz * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_OK(hipMemcpyAsync(ds.s, S, P.nnz * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    ctx->compute_m0(ds);
+  });
+}
+
+int ndrho_set_poles(ndrho_ctx* ctx, int32_t struct_id, double mu, double beta, int32_t n_poles) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    DevStruct& ds = ctx->get(struct_id);
+    if (n_poles < 1 || n_poles > 100000) fail(NDRHO_EINVAL, "n_poles must be in [1, 100000]");
+    if (!(beta > 0.0) || !std::isfinite(beta)) fail(NDRHO_EINVAL, "beta must be positive and finite");
+    if (!std::isfinite(mu)) fail(NDRHO_EINVAL, "mu must be finite");
+    std::vector<double> z(n_poles), r(n_poles), w(n_poles);
+    cf_poles(n_poles, z.data(), r.data());
+    std::vector<double2> a(n_poles);
+    for (int p = 0; p < n_poles; ++p) {
+      a[p] = make_double2(mu, z[p] / beta);  // alpha_p = mu + i z_p / beta
+      w[p] = -(4.0 / beta) * r[p];          // Im(-(4i/beta) G R) = -(4/beta) R Re G
+    }
+    HIP_OK(hipSetDevice(ctx->device));
+    ctx->set_shifts(ds, a, w, true);
+  });
+}
+
+int ndrho_set_shifts(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double* alpha_re, const double* alpha_im,
+                     const double* weight, int32_t add_m0) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    DevStruct& ds = ctx->get(struct_id);
+    if (n < 1 || !alpha_re || !alpha_im || !weight) fail(NDRHO_EINVAL, "n >= 1 and all arrays are required");
+    std::vector<double2> a(n);
+    std::vector<double> w(n);
+    for (int k = 0; k < n; ++k) {
+      if (!std::isfinite(alpha_re[k]) || !std::isfinite(alpha_im[k]) || !std::isfinite(weight[k]))
+        fail(NDRHO_EINVAL, "non-finite shift or weight");
+      a[k] = make_double2(alpha_re[k], alpha_im[k]);
+      w[k] = weight[k];
+    }
+    HIP_OK(hipSetDevice(ctx->device));
+    ctx->set_shifts(ds, a, w, add_m0 != 0);
+  });
+}
+
+int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int32_t on_device) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    DevStruct& ds = ctx->get(struct_id);
+    if (!rho_out) fail(NDRHO_EINVAL, "rho_out is NULL");
+    if (ds.n_shifts < 1) fail(NDRHO_ESTATE, "set_poles (or set_shifts) has not been called for this structure");
+    HIP_OK(hipSetDevice(ctx->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    const Plan& P = ds.plan;
+    ctx->evaluate(ds, ds.d_alpha, ds.d_w, ds.n_shifts, ds.add_m0, 1.0, 0);
+    double* dst = on_device ? rho_out : ctx->outbuf;
+    HIP_OK(launch_scatter(ds.acc_entry, P.nnz, ctx->acc, dst, ctx->stream));
+    int st[2];
+    ctx->read_status(st);
+    if (st[0]) fail(NDRHO_ESINGULAR, "a zero, tiny or non-finite pivot occurred in alpha S - H");
+    if (!on_device) {
+      HIP_OK(hipMemcpyAsync(rho_out, ctx->outbuf, P.nnz * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_OK(hipStreamSynchronize(ctx->stream));
+    }
+    ctx->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  });
+}
+
+int ndrho_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, double* const* rho_outs,
+                               int32_t on_device) {
+  if (!ctx) return NDRHO_EINVAL;
+  if (k < 0 || (k > 0 && (!struct_ids || !rho_outs))) {
+    ctx->err = "invalid batch arguments";
+    return NDRHO_EINVAL;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int32_t i = 0; i < k; ++i) {
+    int rc = ndrho_density_matrix(ctx, struct_ids[i], rho_outs[i], on_device);
+    if (rc != NDRHO_OK) return rc;
+  }
+  ctx->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return NDRHO_OK;
+}
+
+int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out) {
+  if (!ctx || !out) return NDRHO_EINVAL;
+  ndrho_ctx* c = const_cast<ndrho_ctx*>(ctx);
+  return guarded(c, [&] {
+    DevStruct& ds = c->get(struct_id);
+    const Plan& P = ds.plan;
+    std::memset(out, 0, sizeof(*out));
+    out->n = P.n;
+    out->nnz = P.nnz;
+    out->n_fronts = static_cast<int32_t>(P.fronts.size());
+    out->n_levels = P.n_levels;
+    for (const Front& F : P.fronts) {
+      out->max_front_j = std::max(out->max_front_j, F.nj);
+      out->max_front_u = std::max(out->max_front_u, F.nu);
+      if (F.parent < 0) out->root_j = std::max(out->root_j, F.nj);
+    }
+    out->n_poles = ds.n_shifts;
+    out->pole_batch = c->last_batch;
+    out->flops_per_pole = P.flops_model;
+    out->flops_exec_per_pole = P.flops_exec;
+    out->bytes_per_pole = P.bytes_model;
+    out->factor_bytes_per_pole = static_cast<double>(P.panel_total) * sizeof(double2);
+    out->workspace_bytes = static_cast<double>(c->ws_bytes);
+    out->last_ms = c->last_ms;
+    out->launches_per_pass = static_cast<int64_t>(P.upward.size() + P.downward.size() + 1);
+  });
+}
+
+int ndrho_profile(ndrho_ctx* ctx, int32_t enable) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    if (!ctx->recs.empty()) ctx->fold_profile();
+    ctx->prof = enable != 0;
+    if (ctx->prof)
+      for (int k = 0; k < NDRHO_K_COUNT; ++k) ctx->prof_ms[k] = ctx->prof_flops[k] = 0, ctx->prof_n[k] = 0;
+  });
+}
+
+int ndrho_profile_read(const ndrho_ctx* ctx, double* ms, double* flops, int64_t* launches) {
+  if (!ctx) return NDRHO_EINVAL;
+  for (int k = 0; k < NDRHO_K_COUNT; ++k) {
+    if (ms) ms[k] = ctx->prof_ms[k];
+    if (flops) flops[k] = ctx->prof_flops[k];
+    if (launches) launches[k] = ctx->prof_n[k];
+  }
+  return NDRHO_OK;
+}
+
+int ndrho_device_alloc(ndrho_ctx* ctx, int64_t bytes, void** ptr) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    if (!ptr || bytes <= 0) fail(NDRHO_EINVAL, "bytes must be positive and ptr non-NULL");
+    HIP_OK(hipSetDevice(ctx->device));
+    *ptr = nullptr;
+    if (hipMalloc(ptr, static_cast<size_t>(bytes)) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(NDRHO_ENOMEM, "device allocation failed");
+    }
+  });
+}
+
+int ndrho_device_free(ndrho_ctx* ctx, void* ptr) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    if (!ptr) return;
+    HIP_OK(hipSetDevice(ctx->device));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    HIP_OK(hipFree(ptr));
+  });
+}
+
+int ndrho_device_to_host(ndrho_ctx* ctx, void* dst, const void* src, int64_t bytes) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    if (!dst || !src || bytes < 0) fail(NDRHO_EINVAL, "invalid copy arguments");
+    HIP_OK(hipSetDevice(ctx->device));
+    HIP_OK(hipMemcpyAsync(dst, src, static_cast<size_t>(bytes), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int ndrho_cf_poles(int32_t n_poles, double* z, double* R) {
+  return guarded(nullptr, [&] {
+    if (!z || !R) fail(NDRHO_EINVAL, "z and R are required");
+    cf_poles(n_poles, z, R);
+  });
+}
+
+int ndrho_plan_create(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* coords,
+                      int32_t leaf_rows, ndrho_plan** out) {
+  return guarded(nullptr, [&] {
+    if (!out) fail(NDRHO_EINVAL, "out is NULL");
+    *out = nullptr;
+    validate_csr(n, row_ptr, col_idx, nullptr, nullptr);
+    std::unique_ptr<ndrho_plan> p(new ndrho_plan());
+    build_plan(p->plan, n, row_ptr, col_idx, coords, leaf_rows);
+    *out = p.release();
+  });
+}
+
+int ndrho_plan_destroy(ndrho_plan* plan) {
+  delete plan;
+  return NDRHO_OK;
+}
+
+const char* ndrho_plan_last_error(void) { return g_err.c_str(); }
+
+int ndrho_plan_counts(const ndrho_plan* plan, int64_t* counts) {
+  if (!plan || !counts) return NDRHO_EINVAL;
+  const Plan& P = plan->plan;
+  int64_t su = 0, mj = 0, mu = 0;
+  for (const Front& F : P.fronts) {
+    su += F.nu;
+    mj = std::max<int64_t>(mj, F.nj);
+    mu = std::max<int64_t>(mu, F.nu);
+  }
+  counts[0] = static_cast<int64_t>(P.fronts.size());
+  counts[1] = P.n_levels;
+  counts[2] = su;
+  counts[3] = P.nnz;
+  counts[4] = P.panel_total;
+  counts[5] = mj;
+  counts[6] = mu;
+  return NDRHO_OK;
+}
+
+int ndrho_plan_export(const ndrho_plan* plan, int32_t* perm, int32_t* parent, int32_t* depth, int64_t* j0,
+                      int32_t* nj, int32_t* nu, int64_t* u_off, int32_t* u_rows, int32_t* rel) {
+  if (!plan) return NDRHO_EINVAL;
+  const Plan& P = plan->plan;
+  if (perm) std::memcpy(perm, P.perm.data(), P.n * sizeof(int32_t));
+  int64_t off = 0;
+  for (size_t f = 0; f < P.fronts.size(); ++f) {
+    const Front& F = P.fronts[f];
+    if (parent) parent[f] = F.parent;
+    if (depth) depth[f] = F.depth;
+    if (j0) j0[f] = F.j0;
+    if (nj) nj[f] = F.nj;
+    if (nu) nu[f] = F.nu;
+    if (u_off) u_off[f] = off;
+    for (int k = 0; k < F.nu; ++k) {
+      if (u_rows) u_rows[off + k] = F.u[k];
+      if (rel) rel[off + k] = F.parent >= 0 ? F.rel[k] : -1;
+    }
+    off += F.nu;
+  }
+  return NDRHO_OK;
+}
+
+int ndrho_plan_slots(const ndrho_plan* plan, int64_t* out_slot, int64_t* asm_slot, int64_t* panel_off) {
+  if (!plan) return NDRHO_EINVAL;
+  const Plan& P = plan->plan;
+  if (out_slot) std::memcpy(out_slot, P.out_slot.data(), P.nnz * sizeof(int64_t));
+  if (asm_slot) std::memcpy(asm_slot, P.asm_slot.data(), P.nnz * sizeof(int64_t));
+  if (panel_off)
+    for (size_t f = 0; f < P.fronts.size(); ++f) panel_off[f] = P.fronts[f].panel_off;
+  return NDRHO_OK;
+}
+
+int ndrho_plan_model(const ndrho_plan* plan, double* flops, double* bytes) {
+  if (!plan) return NDRHO_EINVAL;
+  if (flops) *flops = plan->plan.flops_model;
+  if (bytes) *bytes = plan->plan.bytes_model;
+  return NDRHO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,46 @@
+// Device-side views of the plan descriptors and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.h"
+
+namespace ndrho {
+
+// One resolved launch: descriptor pointers already offset to the op's range,
+// buffers already resolved to (base pointer, pole stride).
+struct DevOp {
+  int flags = 0;
+  int npoles = 1;
+  int64_t count = 0, tile_count = 0;
+  const GemmProb* gemm = nullptr;
+  const TileRef* gemm_tiles = nullptr;
+  const InvDesc* inv = nullptr;
+  const CopyDesc* copy = nullptr;
+  const CopyTile* copy_tiles = nullptr;
+  const ExtAddDesc* ext = nullptr;
+  const ExtAddChild* ext_child = nullptr;
+  const int32_t* ext_inv = nullptr;
+  const ElemTile* elem_tiles = nullptr;
+  const GatherDesc* gat = nullptr;
+  const int32_t* rel = nullptr;
+  const int64_t* slot = nullptr;
+  const int32_t* entry = nullptr;
+  double2 *a = nullptr, *b = nullptr, *c0 = nullptr, *c = nullptr;
+  int64_t sa = 0, sb = 0, sc0 = 0, sc = 0;
+};
+
+hipError_t launch_extadd(const DevOp& o, hipStream_t st);
+hipError_t launch_assemble(const DevOp& o, const double* hv, const double* sv, const double2* alpha, double hcoef,
+                           hipStream_t st);
+hipError_t launch_smallinv(const DevOp& o, int* status, int spd_check, hipStream_t st);
+hipError_t launch_gemm(const DevOp& o, hipStream_t st);
+hipError_t launch_copy(const DevOp& o, hipStream_t st);
+hipError_t launch_gather(const DevOp& o, hipStream_t st);
+hipError_t launch_accum(const int64_t* slot, int64_t count, const double2* panel, int64_t ps, const double* w,
+                        int npoles, double* acc, hipStream_t st);
+hipError_t launch_init_acc(const double* m0, int64_t count, int add_m0, double* acc, int* status, hipStream_t st);
+hipError_t launch_scatter(const int32_t* entry, int64_t count, const double* acc, double* out, hipStream_t st);
+
+}  // namespace ndrho

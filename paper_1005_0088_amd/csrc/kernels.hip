@@ -1,0 +1,518 @@
+// Device kernels of the front-by-front block LDL^T factorization and selected
+// inversion (Sec. II B 2, Eqs. (18)-(21), (38)-(39)) and of the pole sum of
+// Eq. (8), for gfx950.  Complex numbers are interleaved (re, im) doubles;
+// every per-pole buffer is laid out as [pole][elements] with a pole stride.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace ndrho {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ----------------------------------------------------------------- helpers
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// 1/p with scaling against overflow of |p|^2.
+__device__ __forceinline__ double2 cinv(double2 p) {
+  const double s = fmax(fabs(p.x), fabs(p.y));
+  const double xr = p.x / s, xi = p.y / s;
+  const double d = (xr * xr + xi * xi) * s;
+  return make_double2(xr / d, -xi / d);
+}
+
+// Blocks of a launch are dealt to the 8 XCDs round-robin by linear id; this
+// remap gives every XCD one contiguous range of logical work items, so the
+// tiles of one pole (which share operand panels) meet in one L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t total) {
+  const int64_t x = b % 8, local = b / 8, q = total / 8, r = total % 8;
+  return x * q + (x < r ? x : r) + local;
+}
+
+// ----------------------------------------------------------------- extend-add
+//
+// Pull form of the child-to-parent accumulation of Schur complements
+// (Eq. (32); the (B[C])^T bookkeeping of Eq. (28)): every element of the
+// parent's panel (columns in J) and of its own U x U block is written once
+// as the sum, in child order, of the children's update entries that map onto
+// it.  Writing (not adding) also clears the panel before assembly, so no
+// separate fill is needed and no two threads touch one target.
+__global__ __launch_bounds__(256) void k_extadd(const ExtAddDesc* __restrict__ descs,
+                                                const ExtAddChild* __restrict__ kids,
+                                                const int32_t* __restrict__ inv, const ElemTile* __restrict__ tiles,
+                                                int64_t ntiles, double2* __restrict__ panel, int64_t ps,
+                                                const double2* __restrict__ cupd, int64_t cs,
+                                                double2* __restrict__ upd, int64_t us) {
+  const int64_t pole = blockIdx.y;
+  const ElemTile t = tiles[blockIdx.x];
+  const ExtAddDesc d = descs[t.desc];
+  const int64_t ld = d.nj + d.nu;
+  const int64_t tp = ld * d.nj;
+  const int64_t total = tp + int64_t(d.nu) * d.nu;
+  double2* pan = panel + pole * ps + d.panel_off;
+  double2* own = upd + pole * us + d.upd_off;
+  const double2* cu = cupd + pole * cs;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t e = t.e0 + threadIdx.x + 256 * i;
+    if (e >= total) break;
+    int64_t r, s;
+    if (e < tp) {
+      r = e % ld;
+      s = e / ld;
+    } else {
+      const int64_t e2 = e - tp;
+      r = d.nj + e2 % d.nu;
+      s = d.nj + e2 / d.nu;
+    }
+    double2 sum = make_double2(0.0, 0.0);
+    for (int c = 0; c < d.child_count; ++c) {
+      const ExtAddChild k = kids[d.child_begin + c];
+      const int32_t* im = inv + k.inv_off;
+      const int32_t a = im[r], b = im[s];
+      if (a >= 0 && b >= 0) {
+        const double2 v = cu[k.upd_off + a + int64_t(b) * k.nu];
+        sum.x += v.x;
+        sum.y += v.y;
+      }
+    }
+    if (e < tp) pan[r + s * ld] = sum;
+    else own[(r - d.nj) + (s - d.nj) * d.nu] = sum;
+  }
+}
+
+// ----------------------------------------------------------------- assembly
+//
+// X = alpha_p S - h H for every pole of the batch, added into the panels at
+// the table positions (each position receives at most one entry).
+__global__ __launch_bounds__(256) void k_assemble(const int64_t* __restrict__ slot, const int32_t* __restrict__ entry,
+                                                  int64_t count, const double* __restrict__ hv,
+                                                  const double* __restrict__ sv, const double2* __restrict__ alpha,
+                                                  int npoles, double hcoef, double2* __restrict__ panel, int64_t ps) {
+  const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (k >= count) return;
+  const int64_t sl = slot[k];
+  const int32_t e = entry[k];
+  const double h = hcoef * hv[e], s = sv[e];
+  for (int p = 0; p < npoles; ++p) {
+    const double2 a = alpha[p];
+    double2* x = panel + int64_t(p) * ps + sl;
+    double2 v = *x;
+    v.x += a.x * s - h;
+    v.y += a.y * s;
+    *x = v;
+  }
+}
+
+// ----------------------------------------------------------------- pivot inverse
+//
+// In-place inverse of an n x n (n <= 64) pivot block by Gauss-Jordan
+// elimination without pivoting, one workgroup per (block, pole), the block
+// held in registers (each thread owns up to 16 entries) with row k and column
+// k broadcast through LDS.  The pivots met are the D of the block's LDL^T
+// (Eq. (18)), so they are checked here: |d| <= 1e-14 max|a_ii| or non-finite
+// counts as singular; with spd_check a pivot with d <= 0 or Im d != 0 counts
+// as "not positive definite" (used for the real factorization of S).  The
+// result is written symmetrized from its lower triangle.
+__global__ __launch_bounds__(256) void k_smallinv(const InvDesc* __restrict__ descs, double2* __restrict__ panel,
+                                                  int64_t ps, int* __restrict__ status, int spd_check) {
+  __shared__ double2 colk[2][64];
+  __shared__ double2 rowk[2][64];
+  __shared__ double sdiag;
+  const InvDesc d = descs[blockIdx.x];
+  const int n = d.n;
+  const int64_t ld = d.ld;
+  double2* a = panel + int64_t(blockIdx.y) * ps + d.off;
+  const int tid = threadIdx.x;
+  const int nn = n * n;
+  double2 v[16];
+  int rr[16], cc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = tid + 256 * i;
+    rr[i] = e < nn ? e % n : -1;
+    cc[i] = e < nn ? e / n : -1;
+    v[i] = e < nn ? a[rr[i] + cc[i] * ld] : make_double2(0.0, 0.0);
+  }
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double2 x = a[i + i * ld];
+      m = fmax(m, fabs(x.x) + fabs(x.y));
+    }
+    sdiag = m;
+  }
+  int bad_sing = 0, bad_spd = 0;
+  for (int k = 0; k < n; ++k) {
+    const int b = k & 1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (cc[i] == k) colk[b][rr[i]] = v[i];
+      if (rr[i] == k) rowk[b][cc[i]] = v[i];
+    }
+    __syncthreads();
+    const double2 p = colk[b][k];
+    if (tid == 0) {
+      const double mag = fabs(p.x) + fabs(p.y);
+      if (!(mag > 1e-14 * sdiag) || !isfinite(p.x) || !isfinite(p.y)) bad_sing = 1;
+      if (spd_check && !(p.x > 0.0 && p.y == 0.0)) bad_spd = 1;
+    }
+    const double2 pinv = cinv(p);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = rr[i], c = cc[i];
+      if (r < 0) continue;
+      if (r == k && c == k) {
+        v[i] = pinv;
+      } else if (r == k) {
+        v[i] = cmul(rowk[b][c], pinv);
+      } else if (c == k) {
+        const double2 t = cmul(colk[b][r], pinv);
+        v[i] = make_double2(-t.x, -t.y);
+      } else {
+        const double2 t = cmul(cmul(colk[b][r], pinv), rowk[b][c]);
+        v[i].x -= t.x;
+        v[i].y -= t.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int r = rr[i], c = cc[i];
+    if (r < 0 || r < c) continue;
+    a[r + c * ld] = v[i];
+    if (r != c) a[c + r * ld] = v[i];
+  }
+  if (tid == 0) {
+    if (bad_sing) atomicAdd(&status[0], 1);
+    if (bad_spd) atomicAdd(&status[1], 1);
+  }
+}
+
+// ----------------------------------------------------------------- complex GEMM
+//
+// C = [C0 +] (+/-) op(A) op(B), grouped over problems and batched over poles,
+// complex FP64 on the matrix cores (v_mfma_f64_16x16x4f64, four real products
+// per complex step).  Transposes are plain transposes (the matrices are
+// complex symmetric, never Hermitian).  One 64x64 output tile per workgroup
+// of four waves (2 x 2 waves of 32 x 32), K staged through LDS in steps of 16
+// with double buffering.  The MFMA operands are swapped (B-tile as the A
+// operand) so that each lane owns one row of C (the accumulator of the f64
+// 16x16x4 instruction holds D[4r + lane/16][lane%16] in register r), and a
+// wave's stores run down the columns of the column-major C.  With G_SYM only tiles
+// on or below the diagonal are computed and each lower element is also
+// written to its mirror, so symmetric results stay exactly symmetric.
+constexpr int BM = 64, BN = 64, BK = 16;
+
+template <int FLAGS>
+__global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ probs,
+                                                  const TileRef* __restrict__ tiles, int64_t ntiles, int64_t npoles,
+                                                  const double2* __restrict__ A, int64_t sA,
+                                                  const double2* __restrict__ B, int64_t sB, const double2* C0,
+                                                  int64_t sC0, double2* C, int64_t sC) {
+  constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  __shared__ double2 As[2][BK][BM + 1];
+  __shared__ double2 Bs[2][BK][BN + 1];
+
+  const int64_t total = ntiles * npoles;
+  const int64_t logical = xcd_remap(blockIdx.x, total);
+  const int64_t pole = logical / ntiles;
+  const TileRef tr = tiles[logical % ntiles];
+  const GemmProb pr = probs[tr.prob];
+  const double2* Ap = A + pole * sA + pr.a_off;
+  const double2* Bp = B + pole * sB + pr.b_off;
+  const int M = pr.m, N = pr.n, K = pr.k;
+  const int m0 = tr.tm * BM, n0 = tr.tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  d4 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc_re[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      acc_im[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  double2 ra[4], rb[4];
+  const double2 zero = make_double2(0.0, 0.0);
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!TA) {
+        const int m = tid & 63, k = (tid >> 6) + 4 * i;
+        const int gm = m0 + m, gk = k0 + k;
+        ra[i] = (gm < M && gk < K) ? Ap[gm + int64_t(gk) * pr.lda] : zero;
+      } else {
+        const int k = tid & 15, m = (tid >> 4) + 16 * i;
+        const int gm = m0 + m, gk = k0 + k;
+        ra[i] = (gm < M && gk < K) ? Ap[gk + int64_t(gm) * pr.lda] : zero;
+      }
+      if (!TB) {
+        const int k = tid & 15, n = (tid >> 4) + 16 * i;
+        const int gn = n0 + n, gk = k0 + k;
+        rb[i] = (gn < N && gk < K) ? Bp[gk + int64_t(gn) * pr.ldb] : zero;
+      } else {
+        const int n = tid & 63, k = (tid >> 6) + 4 * i;
+        const int gn = n0 + n, gk = k0 + k;
+        rb[i] = (gn < N && gk < K) ? Bp[gn + int64_t(gk) * pr.ldb] : zero;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!TA) As[buf][(tid >> 6) + 4 * i][tid & 63] = ra[i];
+      else As[buf][tid & 15][(tid >> 4) + 16 * i] = ra[i];
+      if (!TB) Bs[buf][tid & 15][(tid >> 4) + 16 * i] = rb[i];
+      else Bs[buf][(tid >> 6) + 4 * i][tid & 63] = rb[i];
+    }
+  };
+
+  const int nk = (K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      double2 av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[i] = As[cur][kr][wm * 32 + i * 16 + (lane & 15)];
+        bv[i] = Bs[cur][kr][wn * 32 + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j].x, av[i].x, acc_re[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bv[j].y, av[i].y, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j].x, av[i].y, acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j].y, av[i].x, acc_im[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
+  double2* Cp = C + pole * sC + pr.c_off;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 32 + i * 16 + (lane & 15);
+        const int n = n0 + wn * 32 + j * 16 + 4 * r + (lane >> 4);
+        if (m >= M || n >= N) continue;
+        if (SYM && m < n) continue;
+        double2 v = make_double2(acc_re[i][j][r], acc_im[i][j][r]);
+        if (NEG) v = make_double2(-v.x, -v.y);
+        if (BETA) {
+          const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
+          v.x += c0.x;
+          v.y += c0.y;
+        }
+        Cp[m + int64_t(n) * pr.ldc] = v;
+        if (SYM && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+      }
+}
+
+// ----------------------------------------------------------------- copy
+//
+// dst (rows x cols) <- src, or <- src^T through an LDS tile so that both the
+// reads and the writes run down columns.
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_copy(const CopyDesc* __restrict__ descs, const CopyTile* __restrict__ tiles,
+                                              const double2* __restrict__ src, int64_t ss, double2* __restrict__ dst,
+                                              int64_t ds) {
+  __shared__ double2 t[64][65];
+  const CopyTile ct = tiles[blockIdx.x];
+  const CopyDesc d = descs[ct.desc];
+  const double2* s = src + int64_t(blockIdx.y) * ss + d.src_off;
+  double2* o = dst + int64_t(blockIdx.y) * ds + d.dst_off;
+  const int tid = threadIdx.x;
+  if (!TRANS) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = ct.r0 + (tid & 63), c = ct.c0 + (tid >> 6) + 4 * i;
+      if (r < d.rows && c < d.cols) o[r + int64_t(c) * d.ldd] = s[r + int64_t(c) * d.lds];
+    }
+  } else {
+    // dst(r, c) = src(c, r): read src rows c0.. (as its row index) coalesced
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int sr = tid & 63, sc = (tid >> 6) + 4 * i;  // src row = dst col, src col = dst row
+      const int gr = ct.c0 + sr, gc = ct.r0 + sc;
+      if (gr < d.cols && gc < d.rows) t[sc][sr] = s[gr + int64_t(gc) * d.lds];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = tid & 63, c = (tid >> 6) + 4 * i;
+      const int gr = ct.r0 + r, gc = ct.c0 + c;
+      if (gr < d.rows && gc < d.cols) o[gr + int64_t(gc) * d.ldd] = t[r][c];
+    }
+  }
+}
+
+// ----------------------------------------------------------------- gather G_UU
+//
+// Downward pass: the entries of G on U_f x U_f are read from the parent's
+// selected block, i.e. from its G_JJ and G_UJ panel (either orientation, G is
+// symmetric) or from the parent's own gathered G_UU (Eq. (38): the blocks
+// X^{-1}_{p,2n}, X^{-1}_{p,2n+1} needed by the next level).
+__global__ __launch_bounds__(256) void k_gather(const GatherDesc* __restrict__ descs,
+                                                const int32_t* __restrict__ rel, const ElemTile* __restrict__ tiles,
+                                                const double2* __restrict__ pguu, int64_t gs,
+                                                const double2* __restrict__ panel, int64_t ps,
+                                                double2* __restrict__ guu, int64_t us) {
+  const int64_t pole = blockIdx.y;
+  const ElemTile t = tiles[blockIdx.x];
+  const GatherDesc d = descs[t.desc];
+  const int64_t total = int64_t(d.nu) * d.nu;
+  const int32_t* rl = rel + d.rel_off;
+  const double2* pan = panel + pole * ps + d.ppanel_off;
+  const double2* pg = pguu + pole * gs + d.pguu_off;
+  double2* out = guu + pole * us + d.dst_off;
+  const int64_t pld = d.pnj + d.pnu;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t e = t.e0 + threadIdx.x + 256 * i;
+    if (e >= total) break;
+    const int a = static_cast<int>(e % d.nu), b = static_cast<int>(e / d.nu);
+    const int r = rl[a], s = rl[b];
+    double2 v;
+    if (s < d.pnj) v = pan[r + int64_t(s) * pld];
+    else if (r < d.pnj) v = pan[s + int64_t(r) * pld];
+    else v = pg[(r - d.pnj) + int64_t(s - d.pnj) * d.pnu];
+    out[e] = v;
+  }
+}
+
+// ----------------------------------------------------------------- pole sum
+//
+// acc[k] += sum_p w_p Re G_p[slot_k], poles in increasing order (Eq. (8)):
+// one thread per pattern position, positions sorted by panel offset so that
+// a wave reads neighbouring panel entries.
+__global__ __launch_bounds__(256) void k_accum(const int64_t* __restrict__ slot, int64_t count,
+                                               const double2* __restrict__ panel, int64_t ps,
+                                               const double* __restrict__ w, int npoles, double* __restrict__ acc) {
+  const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (k >= count) return;
+  const double* pr = reinterpret_cast<const double*>(panel) + 2 * slot[k];
+  double v = acc[k];
+  for (int p = 0; p < npoles; ++p) v += w[p] * pr[2 * int64_t(p) * ps];
+  acc[k] = v;
+}
+
+// Starts the sum at M0 (or 0) and clears the pivot status words (a kernel
+// rather than a memset, so the sequence can be captured in a graph).
+__global__ __launch_bounds__(256) void k_init_acc(const double* __restrict__ m0, int64_t count, int add_m0,
+                                                  double* __restrict__ acc, int* __restrict__ status) {
+  const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (k < 2) status[k] = 0;
+  if (k < count) acc[k] = add_m0 ? m0[k] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ entry, int64_t count,
+                                                 const double* __restrict__ acc, double* __restrict__ out) {
+  const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (k < count) out[entry[k]] = acc[k];
+}
+
+// ----------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(int64_t n, int per) { return static_cast<unsigned>((n + per - 1) / per); }
+
+hipError_t launch_extadd(const DevOp& o, hipStream_t st) {
+  if (o.tile_count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_extadd, dim3(static_cast<unsigned>(o.tile_count), o.npoles), dim3(256), 0, st, o.ext, o.ext_child,
+                     o.ext_inv, o.elem_tiles, o.tile_count, o.c, o.sc, o.a, o.sa, o.b, o.sb);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(const DevOp& o, const double* hv, const double* sv, const double2* alpha, double hcoef,
+                           hipStream_t st) {
+  if (o.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assemble, dim3(blocks_for(o.count, 256)), dim3(256), 0, st, o.slot, o.entry, o.count, hv, sv,
+                     alpha, o.npoles, hcoef, o.c, o.sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_smallinv(const DevOp& o, int* status, int spd_check, hipStream_t st) {
+  if (o.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_smallinv, dim3(static_cast<unsigned>(o.count), o.npoles), dim3(256), 0, st, o.inv, o.c, o.sc,
+                     status, spd_check);
+  return hipGetLastError();
+}
+
+template <int F>
+static void gemm_inst(const DevOp& o, hipStream_t st) {
+  const int64_t total = o.tile_count * o.npoles;
+  hipLaunchKernelGGL(k_zgemm<F>, dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
+                     o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
+}
+
+hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
+  if (o.tile_count == 0) return hipSuccess;
+  switch (o.flags) {
+    case 0: gemm_inst<0>(o, st); break;
+    case G_NEG: gemm_inst<G_NEG>(o, st); break;
+    case G_TB | G_SYM | G_BETA | G_NEG: gemm_inst<G_TB | G_SYM | G_BETA | G_NEG>(o, st); break;
+    case G_TA | G_SYM | G_BETA | G_NEG: gemm_inst<G_TA | G_SYM | G_BETA | G_NEG>(o, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const DevOp& o, hipStream_t st) {
+  if (o.tile_count == 0) return hipSuccess;
+  if (o.flags & 1)
+    hipLaunchKernelGGL(k_copy<true>, dim3(static_cast<unsigned>(o.tile_count), o.npoles), dim3(256), 0, st, o.copy,
+                       o.copy_tiles, o.a, o.sa, o.c, o.sc);
+  else
+    hipLaunchKernelGGL(k_copy<false>, dim3(static_cast<unsigned>(o.tile_count), o.npoles), dim3(256), 0, st, o.copy,
+                       o.copy_tiles, o.a, o.sa, o.c, o.sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const DevOp& o, hipStream_t st) {
+  if (o.tile_count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3(static_cast<unsigned>(o.tile_count), o.npoles), dim3(256), 0, st, o.gat, o.rel,
+                     o.elem_tiles, o.a, o.sa, o.b, o.sb, o.c, o.sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_accum(const int64_t* slot, int64_t count, const double2* panel, int64_t ps, const double* w,
+                        int npoles, double* acc, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_accum, dim3(blocks_for(count, 256)), dim3(256), 0, st, slot, count, panel, ps, w, npoles, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_acc(const double* m0, int64_t count, int add_m0, double* acc, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_acc, dim3(blocks_for(count > 2 ? count : 2, 256)), dim3(256), 0, st, m0, count, add_m0, acc,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const int32_t* entry, int64_t count, const double* acc, double* out, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(count, 256)), dim3(256), 0, st, entry, count, acc, out);
+  return hipGetLastError();
+}
+
+}  // namespace ndrho

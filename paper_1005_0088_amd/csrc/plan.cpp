@@ -1,0 +1,698 @@
+// Nested dissection (Sec. II B 1), symbolic front tree, the "table function"
+// of pattern positions (Sec. II B 2) and the launch program of the block
+// LDL^T factorization and selected inversion (Eqs. (18)-(21), (38)-(39)).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <numeric>
+
+#include "plan.h"
+
+namespace ndrho {
+
+// ----------------------------------------------------------------- validation
+
+void validate_csr(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* h, const double* s) {
+  if (n < 1 || n > (int64_t(1) << 31) - 2) fail(NDRHO_EINVAL, "n must be in [1, 2^31-2]");
+  if (!row_ptr || !col) fail(NDRHO_EINVAL, "row_ptr and col_idx are required");
+  if (row_ptr[0] != 0) fail(NDRHO_EINVAL, "row_ptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) fail(NDRHO_EINVAL, "row_ptr must be non-decreasing");
+  for (int64_t i = 0; i < n; ++i) {
+    bool diag = false;
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      const int32_t j = col[e];
+      if (j < 0 || j >= n) fail(NDRHO_EINVAL, "column index out of range in row " + std::to_string(i));
+      if (e > row_ptr[i] && col[e - 1] >= j)
+        fail(NDRHO_EINVAL, "column indices must be strictly increasing in row " + std::to_string(i));
+      if (j == i) diag = true;
+    }
+    if (!diag) fail(NDRHO_EINVAL, "missing diagonal entry in row " + std::to_string(i));
+  }
+  double hmax = 0, smax = 0;
+  const int64_t nnz = row_ptr[n];
+  for (int64_t e = 0; e < nnz; ++e) {
+    if (h) {
+      if (!std::isfinite(h[e])) fail(NDRHO_EINVAL, "non-finite H value");
+      hmax = std::max(hmax, std::fabs(h[e]));
+    }
+    if (s) {
+      if (!std::isfinite(s[e])) fail(NDRHO_EINVAL, "non-finite S value");
+      smax = std::max(smax, std::fabs(s[e]));
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      const int32_t j = col[e];
+      const int32_t* b = col + row_ptr[j];
+      const int32_t* en = col + row_ptr[j + 1];
+      const int32_t* it = std::lower_bound(b, en, static_cast<int32_t>(i));
+      if (it == en || *it != i) fail(NDRHO_EINVAL, "pattern is not structurally symmetric");
+      const int64_t et = row_ptr[j] + (it - b);
+      if (h && std::fabs(h[e] - h[et]) > 1e-12 * hmax) fail(NDRHO_EINVAL, "H is not symmetric");
+      if (s && std::fabs(s[e] - s[et]) > 1e-12 * smax) fail(NDRHO_EINVAL, "S is not symmetric");
+    }
+  }
+}
+
+// ----------------------------------------------------------- nested dissection
+//
+// Procedures (i), (iii)-(v) of Sec. II B 1.  Each domain is ordered along each
+// axis by the centre coordinate (ties broken by the other two coordinates,
+// then by index).  The nucleus is the function with the fewest overlaps inside
+// the domain; the subdomain grows from the end of the ordering nearest to the
+// nucleus one function at a time, and at each step N0 (subdomain), Ns (rows
+// between the subdomain and the farthest overlapping function) and
+// N1 = Nd - N0 - Ns give the measure |N0 - N1| + Ns.  The axis and size with
+// the smallest measure are taken, and both subdomains are dissected again
+// until they hold at most leaf_rows functions.  The screening of long-tail
+// functions, procedure (ii), is not applied (all functions of the lattices
+// have the same range).
+
+namespace {
+
+struct NdNode {
+  std::vector<int> members;   // original indices
+  std::vector<int> children;  // node ids
+};
+
+class Dissector {
+ public:
+  Dissector(int64_t n, const int64_t* rp, const int32_t* col, const double* coords, int leaf)
+      : n_(n), rp_(rp), col_(col), leaf_(leaf), xyz_(3 * n, 0.0), stamp_(n, -1), lab_(n, 0), pos_(n, 0),
+        naxes_(coords ? 3 : 1) {
+    if (coords) std::copy(coords, coords + 3 * n, xyz_.begin());
+  }
+
+  std::vector<int> run() {
+    std::vector<int> all(n_);
+    std::iota(all.begin(), all.end(), 0);
+    std::vector<int> lists[3];
+    for (int a = 0; a < naxes_; ++a) {
+      lists[a] = all;
+      sort_axis(lists[a], a);
+    }
+    return dissect(lists);
+  }
+
+  std::vector<NdNode> nodes;
+
+ private:
+  int64_t n_;
+  const int64_t* rp_;
+  const int32_t* col_;
+  int leaf_;
+  std::vector<double> xyz_;
+  std::vector<int> stamp_, lab_, pos_;
+  int naxes_;
+  int next_stamp_ = 0;
+
+  // Without coordinates: the breadth-first distance inside the domain from a
+  // pseudo-peripheral row serves as the single ordering axis (recomputed for
+  // every domain); disconnected pieces are laid out one after another.
+  void bfs_coordinate(const std::vector<int>& dom, int st) {
+    for (int v : dom) xyz_[3 * v] = -1.0;
+    auto bfs = [&](int src, double base) {
+      std::deque<int> q{src};
+      xyz_[3 * src] = base;
+      int last = src;
+      while (!q.empty()) {
+        int v = q.front();
+        q.pop_front();
+        last = v;
+        for (int64_t e = rp_[v]; e < rp_[v + 1]; ++e) {
+          int u = col_[e];
+          if (stamp_[u] == st && xyz_[3 * u] < 0) {
+            xyz_[3 * u] = xyz_[3 * v] + 1.0;
+            q.push_back(u);
+          }
+        }
+      }
+      return last;
+    };
+    double base = 0.0;
+    for (int v : dom) {
+      if (xyz_[3 * v] >= 0) continue;
+      // two sweeps to find a far end of this piece, then the final distances
+      std::vector<int> piece;
+      int far = bfs(v, base);
+      for (int u : dom)
+        if (xyz_[3 * u] >= base) piece.push_back(u);
+      for (int u : piece) xyz_[3 * u] = -1.0;
+      far = bfs(far, base);
+      double top = base;
+      for (int u : piece) top = std::max(top, xyz_[3 * u]);
+      base = top + 2.0;
+    }
+  }
+
+  void sort_axis(std::vector<int>& v, int a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    const double* x = xyz_.data();
+    std::sort(v.begin(), v.end(), [x, a, b, c](int p, int q) {
+      if (x[3 * p + a] != x[3 * q + a]) return x[3 * p + a] < x[3 * q + a];
+      if (x[3 * p + b] != x[3 * q + b]) return x[3 * p + b] < x[3 * q + b];
+      if (x[3 * p + c] != x[3 * q + c]) return x[3 * p + c] < x[3 * q + c];
+      return p < q;
+    });
+  }
+
+  int make_node(std::vector<int> members, std::vector<int> children) {
+    std::sort(members.begin(), members.end());
+    nodes.push_back(NdNode{std::move(members), std::move(children)});
+    return static_cast<int>(nodes.size()) - 1;
+  }
+
+  std::vector<int> dissect(std::vector<int> (&lists)[3]) {
+    const int nd = static_cast<int>(lists[0].size());
+    if (nd == 0) return {};
+    if (nd <= leaf_) return {make_node(lists[0], {})};
+    const int st = next_stamp_++;
+    for (int v : lists[0]) stamp_[v] = st;
+    if (naxes_ == 1) {
+      bfs_coordinate(lists[0], st);
+      sort_axis(lists[0], 0);
+    }
+    // (iii) nucleus: fewest overlaps with the other functions of the domain
+    int nucleus = -1, best_deg = 1 << 30;
+    for (int v : lists[0]) {
+      int deg = 0;
+      for (int64_t e = rp_[v]; e < rp_[v + 1]; ++e)
+        if (col_[e] != v && stamp_[col_[e]] == st) ++deg;
+      if (deg < best_deg || (deg == best_deg && v < nucleus)) {
+        best_deg = deg;
+        nucleus = v;
+      }
+    }
+    // (iv)-(v) growth along each axis
+    int64_t best_cost = -1, best_ns = 0;
+    int best_axis = -1, best_cut = 0, best_end = 0, best_far = 0;
+    std::vector<int> far(nd);
+    for (int a = 0; a < naxes_; ++a) {
+      const std::vector<int>& ord = lists[a];
+      for (int q = 0; q < nd; ++q) pos_[ord[q]] = q;
+      const bool low = pos_[nucleus] < nd - pos_[nucleus];
+      for (int q = 0; q < nd; ++q) {
+        int v = ord[q];
+        int ext = q;
+        for (int64_t e = rp_[v]; e < rp_[v + 1]; ++e) {
+          int u = col_[e];
+          if (stamp_[u] != st) continue;
+          ext = low ? std::max(ext, pos_[u]) : std::min(ext, pos_[u]);
+        }
+        far[q] = ext;
+      }
+      if (low) {
+        int nmax = -1;
+        for (int m = 1; m < nd; ++m) {  // subdomain = positions [0, m)
+          nmax = std::max(nmax, far[m - 1]);
+          const int64_t n0 = m, ns = nmax + 1 - m, n1 = nd - nmax - 1;
+          if (n1 < 1) break;
+          const int64_t cost = std::llabs(n0 - n1) + ns;
+          if (best_cost < 0 || cost < best_cost || (cost == best_cost && ns <= best_ns && a == best_axis)) {
+            best_cost = cost, best_ns = ns, best_axis = a, best_cut = m, best_end = 0, best_far = nmax;
+          }
+        }
+      } else {
+        int nmin = nd;
+        for (int m = nd - 1; m >= 1; --m) {  // subdomain = positions [m, nd)
+          nmin = std::min(nmin, far[m]);
+          const int64_t n0 = nd - m, ns = m - nmin, n1 = nmin;
+          if (n1 < 1) break;
+          const int64_t cost = std::llabs(n0 - n1) + ns;
+          if (best_cost < 0 || cost < best_cost || (cost == best_cost && ns <= best_ns && a == best_axis)) {
+            best_cost = cost, best_ns = ns, best_axis = a, best_cut = m, best_end = 1, best_far = nmin;
+          }
+        }
+      }
+    }
+    if (best_axis < 0) return {make_node(lists[0], {})};  // no separating cut exists
+    {
+      const std::vector<int>& ord = lists[best_axis];
+      for (int q = 0; q < nd; ++q) {
+        int l;
+        if (best_end == 0) l = q < best_cut ? 0 : (q <= best_far ? 1 : 2);
+        else l = q >= best_cut ? 0 : (q >= best_far ? 1 : 2);
+        lab_[ord[q]] = l;
+      }
+    }
+    std::vector<int> sub[3][3];  // [label][axis]
+    for (int a = 0; a < naxes_; ++a)
+      for (int v : lists[a]) sub[lab_[v]][a].push_back(v);
+    std::vector<int> sep = sub[1][0];
+    for (int a = 0; a < 3; ++a) std::vector<int>().swap(lists[a]);
+    std::vector<int> r0 = dissect(sub[0]);
+    std::vector<int> r1 = dissect(sub[2]);
+    r0.insert(r0.end(), r1.begin(), r1.end());
+    if (sep.empty()) return r0;  // disconnected pieces: no separator front
+    return {make_node(std::move(sep), std::move(r0))};
+  }
+};
+
+int64_t rec_temp(int n) {
+  if (n <= 64) return 0;
+  const int nb = (n + 63) / 64;
+  const int n1 = 64 * ((nb + 1) / 2), n2 = n - n1;
+  return std::max(rec_temp(n1), static_cast<int64_t>(n2) * n1 + rec_temp(n2));
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- program
+
+namespace {
+
+struct Builder {
+  Plan& P;
+  explicit Builder(Plan& p) : P(p) {}
+
+  // one GEMM op over a list of problems
+  void gemm(std::vector<Op>& prog, int flags, int ba, int bb, int bc0, int bc, const std::vector<GemmProb>& probs,
+            int depth) {
+    if (probs.empty()) return;
+    Op op;
+    op.kind = OP_GEMM;
+    op.flags = flags;
+    op.buf_a = ba, op.buf_b = bb, op.buf_c0 = bc0, op.buf_c = bc;
+    op.begin = static_cast<int64_t>(P.gemm.size());
+    op.count = static_cast<int64_t>(probs.size());
+    op.tile_begin = static_cast<int64_t>(P.gemm_tiles.size());
+    op.depth = depth;
+    double fl = 0;
+    for (size_t i = 0; i < probs.size(); ++i) {
+      const GemmProb& g = probs[i];
+      P.gemm.push_back(g);
+      const int tm = (g.m + 63) / 64, tn = (g.n + 63) / 64;
+      for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tn; ++b) {
+          if ((flags & G_SYM) && b > a) continue;
+          P.gemm_tiles.push_back(TileRef{static_cast<int32_t>(i), a, b, 0});
+        }
+      if (flags & G_SYM) fl += 8.0 * g.k * (double(g.n) * (g.n + 1) / 2);
+      else fl += 8.0 * double(g.m) * g.n * g.k;
+    }
+    op.tile_count = static_cast<int64_t>(P.gemm_tiles.size()) - op.tile_begin;
+    op.flops = fl;
+    P.flops_exec += fl;
+    prog.push_back(op);
+  }
+
+  void copy(std::vector<Op>& prog, bool transpose, int bs, int bd, const std::vector<CopyDesc>& descs, int depth) {
+    if (descs.empty()) return;
+    Op op;
+    op.kind = OP_COPY;
+    op.flags = transpose ? 1 : 0;
+    op.buf_a = bs, op.buf_c = bd;
+    op.begin = static_cast<int64_t>(P.copy.size());
+    op.count = static_cast<int64_t>(descs.size());
+    op.tile_begin = static_cast<int64_t>(P.copy_tiles.size());
+    op.depth = depth;
+    for (size_t i = 0; i < descs.size(); ++i) {
+      P.copy.push_back(descs[i]);
+      for (int r = 0; r < descs[i].rows; r += 64)
+        for (int c = 0; c < descs[i].cols; c += 64)
+          P.copy_tiles.push_back(CopyTile{static_cast<int32_t>(i), r, c, 0});
+    }
+    op.tile_count = static_cast<int64_t>(P.copy_tiles.size()) - op.tile_begin;
+    prog.push_back(op);
+  }
+
+  void smallinv(std::vector<Op>& prog, const std::vector<InvDesc>& descs, int depth) {
+    if (descs.empty()) return;
+    Op op;
+    op.kind = OP_SMALLINV;
+    op.buf_c = BUF_PANEL;
+    op.begin = static_cast<int64_t>(P.inv.size());
+    op.count = static_cast<int64_t>(descs.size());
+    op.depth = depth;
+    for (const InvDesc& d : descs) {
+      P.inv.push_back(d);
+      P.flops_exec += 8.0 * double(d.n) * d.n * d.n;
+    }
+    prog.push_back(op);
+  }
+
+  // In-place inverse of the leading nj x nj block of each front in `grp`
+  // (all with the same nj), by the block form of Eq. (21) applied
+  // recursively: A11^{-1}; L = A21 A11^{-1}; S = A22 - L A21^T; S^{-1};
+  // G21 = -S^{-1} L; G11 = A11^{-1} - L^T G21; G12 = G21^T.
+  void inverse(std::vector<Op>& prog, const std::vector<int>& grp, int n, int r0, int64_t tstack, int depth) {
+    if (n <= 64) {
+      std::vector<InvDesc> d;
+      for (int f : grp) {
+        const Front& F = P.fronts[f];
+        const int ld = F.nj + F.nu;
+        d.push_back(InvDesc{F.panel_off + r0 + int64_t(r0) * ld, ld, n});
+      }
+      smallinv(prog, d, depth);
+      return;
+    }
+    const int nb = (n + 63) / 64;
+    const int n1 = 64 * ((nb + 1) / 2), n2 = n - n1;
+    inverse(prog, grp, n1, r0, tstack, depth);
+    auto at = [&](const Front& F, int r, int c) { return F.panel_off + r + int64_t(c) * (F.nj + F.nu); };
+    std::vector<GemmProb> ga, gb, gc, gd;
+    std::vector<CopyDesc> ct;
+    for (int f : grp) {
+      const Front& F = P.fronts[f];
+      const int ld = F.nj + F.nu;
+      const int64_t t = F.temp_off + tstack;
+      // L = A21 A11^{-1}   (n2 x n1)
+      ga.push_back(GemmProb{n2, n1, n1, ld, ld, 0, n2, 0, at(F, r0 + n1, r0), at(F, r0, r0), 0, t});
+      // A22 <- A22 - L A21^T
+      gb.push_back(GemmProb{n2, n2, n1, n2, ld, ld, ld, 0, t, at(F, r0 + n1, r0), at(F, r0 + n1, r0 + n1),
+                            at(F, r0 + n1, r0 + n1)});
+      // A21 <- -S^{-1} L
+      gc.push_back(GemmProb{n2, n1, n2, ld, n2, 0, ld, 0, at(F, r0 + n1, r0 + n1), t, 0, at(F, r0 + n1, r0)});
+      // A11 <- A11^{-1} - L^T G21
+      gd.push_back(GemmProb{n1, n1, n2, n2, ld, ld, ld, 0, t, at(F, r0 + n1, r0), at(F, r0, r0), at(F, r0, r0)});
+      // A12 <- G21^T
+      ct.push_back(CopyDesc{at(F, r0 + n1, r0), at(F, r0, r0 + n1), ld, ld, n1, n2});
+    }
+    gemm(prog, 0, BUF_PANEL, BUF_PANEL, 0, BUF_TEMP, ga, depth);
+    gemm(prog, G_TB | G_SYM | G_BETA | G_NEG, BUF_TEMP, BUF_PANEL, BUF_PANEL, BUF_PANEL, gb, depth);
+    inverse(prog, grp, n2, r0 + n1, tstack + int64_t(n2) * n1, depth);
+    gemm(prog, G_NEG, BUF_PANEL, BUF_TEMP, 0, BUF_PANEL, gc, depth);
+    gemm(prog, G_TA | G_SYM | G_BETA | G_NEG, BUF_TEMP, BUF_PANEL, BUF_PANEL, BUF_PANEL, gd, depth);
+    copy(prog, true, BUF_PANEL, BUF_PANEL, ct, depth);
+  }
+};
+
+}  // namespace
+
+void build_plan(Plan& P, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* coords,
+                int leaf_rows) {
+  if (leaf_rows < 1) fail(NDRHO_EINVAL, "leaf_rows must be >= 1");
+  P = Plan();
+  P.n = n;
+  P.nnz = row_ptr[n];
+  P.row_ptr.assign(row_ptr, row_ptr + n + 1);
+  P.col.assign(col, col + P.nnz);
+
+  // ---- ordering
+  Dissector nd(n, row_ptr, col, coords, leaf_rows);
+  std::vector<int> roots = nd.run();
+  std::vector<NdNode>& nodes = nd.nodes;
+  // postorder: children (in order) before the node
+  std::vector<int> post;
+  post.reserve(nodes.size());
+  {
+    std::vector<std::pair<int, size_t>> stack;
+    for (int r : roots) {
+      stack.push_back({r, 0});
+      while (!stack.empty()) {
+        auto& top = stack.back();
+        if (top.second < nodes[top.first].children.size()) {
+          int c = nodes[top.first].children[top.second++];
+          stack.push_back({c, 0});
+        } else {
+          post.push_back(top.first);
+          stack.pop_back();
+        }
+      }
+    }
+  }
+  std::vector<int> node2front(nodes.size(), -1);
+  for (size_t i = 0; i < post.size(); ++i) node2front[post[i]] = static_cast<int>(i);
+  P.fronts.resize(post.size());
+  P.perm.resize(n);
+  P.iperm.resize(n);
+  int64_t next = 0;
+  for (size_t i = 0; i < post.size(); ++i) {
+    Front& F = P.fronts[i];
+    const NdNode& nd_node = nodes[post[i]];
+    F.j0 = next;
+    F.nj = static_cast<int>(nd_node.members.size());
+    for (int v : nd_node.members) {
+      P.perm[next] = v;
+      P.iperm[v] = static_cast<int32_t>(next);
+      ++next;
+    }
+    for (int c : nd_node.children) {
+      F.children.push_back(node2front[c]);
+      P.fronts[node2front[c]].parent = static_cast<int>(i);
+    }
+  }
+  if (next != n) fail(NDRHO_EINVAL, "dissection lost rows");
+  const int nf = static_cast<int>(P.fronts.size());
+  int maxdepth = 0;
+  for (int f = nf - 1; f >= 0; --f) {
+    Front& F = P.fronts[f];
+    F.depth = F.parent < 0 ? 0 : P.fronts[F.parent].depth + 1;
+    maxdepth = std::max(maxdepth, F.depth);
+  }
+  P.n_levels = maxdepth + 1;
+
+  // ---- symbolic: update sets U_f and relative maps
+  std::vector<int> owner(n, -1);
+  for (int f = 0; f < nf; ++f)
+    for (int64_t q = P.fronts[f].j0; q < P.fronts[f].j0 + P.fronts[f].nj; ++q) owner[q] = f;
+  std::vector<int> mark(n, -1);
+  for (int f = 0; f < nf; ++f) {
+    Front& F = P.fronts[f];
+    const int64_t end = F.j0 + F.nj;
+    std::vector<int>& U = F.u;
+    for (int64_t q = F.j0; q < end; ++q) {
+      const int v = P.perm[q];
+      for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+        const int p = P.iperm[col[e]];
+        if (p >= end && mark[p] != f) {
+          mark[p] = f;
+          U.push_back(p);
+        }
+      }
+    }
+    for (int c : F.children) {
+      for (int p : P.fronts[c].u) {
+        if (p < F.j0) fail(NDRHO_EINVAL, "dissection produced a separator that does not separate");
+        if (p >= end && mark[p] != f) {
+          mark[p] = f;
+          U.push_back(p);
+        }
+      }
+    }
+    std::sort(U.begin(), U.end());
+    F.nu = static_cast<int>(U.size());
+    if (F.parent < 0 && F.nu != 0) fail(NDRHO_EINVAL, "root front with a non-empty update set");
+    for (int c : F.children) {
+      Front& C = P.fronts[c];
+      C.rel.resize(C.nu);
+      for (int k = 0; k < C.nu; ++k) {
+        const int p = C.u[k];
+        if (p < end) {
+          C.rel[k] = static_cast<int>(p - F.j0);
+        } else {
+          auto it = std::lower_bound(U.begin(), U.end(), p);
+          if (it == U.end() || *it != p) fail(NDRHO_EINVAL, "update set of a child is not closed in its parent");
+          C.rel[k] = F.nj + static_cast<int>(it - U.begin());
+        }
+      }
+    }
+  }
+
+  // ---- storage offsets
+  std::vector<std::vector<int>> by_depth(P.n_levels);
+  for (int f = 0; f < nf; ++f) by_depth[P.fronts[f].depth].push_back(f);
+  int64_t po = 0;
+  for (int f = 0; f < nf; ++f) {
+    Front& F = P.fronts[f];
+    F.panel_off = po;
+    po += int64_t(F.nj + F.nu) * F.nj;
+    P.flops_model += 8.0 * (double(F.nj) * F.nj * F.nj + double(F.nu) * F.nj * F.nj +
+                            double(F.nu) * F.nu * F.nj / 2 + double(F.nu) * F.nu * F.nj +
+                            double(F.nu) * F.nj * F.nj / 2);
+    P.bytes_model += 16.0 * (2.0 * (double(F.nj) * F.nj + double(F.nu) * F.nj) + 3.0 * double(F.nu) * F.nu);
+  }
+  P.panel_total = po;
+  for (int d = 0; d < P.n_levels; ++d) {
+    int64_t uo = 0, to = 0;
+    for (int f : by_depth[d]) {
+      Front& F = P.fronts[f];
+      F.upd_off = uo;
+      uo += int64_t(F.nu) * F.nu;
+      F.temp_off = to;
+      to += std::max<int64_t>(int64_t(F.nu) * F.nj, rec_temp(F.nj));
+    }
+    P.upd_total = std::max(P.upd_total, uo);
+    P.temp_total = std::max(P.temp_total, to);
+  }
+  P.upd_total = std::max<int64_t>(P.upd_total, 1);
+  P.temp_total = std::max<int64_t>(P.temp_total, 1);
+
+  // ---- table of pattern positions (assembly and output slots)
+  P.out_slot.resize(P.nnz);
+  P.asm_slot.resize(P.nnz);
+  std::vector<std::vector<std::pair<int64_t, int32_t>>> asm_by_depth(P.n_levels);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      const int pi = P.iperm[i], pj = P.iperm[col[e]];
+      const int a = std::min(pi, pj), b = std::max(pi, pj);
+      const Front& F = P.fronts[owner[a]];
+      const int64_t ld = F.nj + F.nu;
+      const int la = static_cast<int>(a - F.j0);
+      if (b < F.j0 + F.nj) {
+        const int li = static_cast<int>(pi - F.j0), lj = static_cast<int>(pj - F.j0);
+        P.asm_slot[e] = F.panel_off + li + lj * ld;
+        P.out_slot[e] = F.panel_off + std::max(li, lj) + std::min(li, lj) * ld;
+      } else {
+        auto it = std::lower_bound(F.u.begin(), F.u.end(), b);
+        const int lb = F.nj + static_cast<int>(it - F.u.begin());
+        const int64_t slot = F.panel_off + lb + la * ld;
+        P.out_slot[e] = slot;
+        P.asm_slot[e] = (pi == b) ? slot : -1;
+      }
+      if (P.asm_slot[e] >= 0) asm_by_depth[F.depth].push_back({P.asm_slot[e], static_cast<int32_t>(e)});
+    }
+  }
+  P.asm_depth_begin.assign(P.n_levels + 1, 0);
+  for (int d = 0; d < P.n_levels; ++d) {
+    auto& v = asm_by_depth[d];
+    std::sort(v.begin(), v.end());
+    P.asm_depth_begin[d] = static_cast<int64_t>(P.asm_slot_sorted.size());
+    for (auto& pr : v) {
+      P.asm_slot_sorted.push_back(pr.first);
+      P.asm_entry_sorted.push_back(pr.second);
+    }
+  }
+  P.asm_depth_begin[P.n_levels] = static_cast<int64_t>(P.asm_slot_sorted.size());
+  {
+    std::vector<std::pair<int64_t, int32_t>> acc(P.nnz);
+    for (int64_t e = 0; e < P.nnz; ++e) acc[e] = {P.out_slot[e], static_cast<int32_t>(e)};
+    std::sort(acc.begin(), acc.end());
+    P.acc_slot.resize(P.nnz);
+    P.acc_entry.resize(P.nnz);
+    for (int64_t k = 0; k < P.nnz; ++k) {
+      P.acc_slot[k] = acc[k].first;
+      P.acc_entry[k] = acc[k].second;
+    }
+  }
+
+  // ---- relative maps, concatenated
+  std::vector<int64_t> rel_off(nf, 0);
+  for (int f = 0; f < nf; ++f) {
+    rel_off[f] = static_cast<int64_t>(P.rel_all.size());
+    P.rel_all.insert(P.rel_all.end(), P.fronts[f].rel.begin(), P.fronts[f].rel.end());
+  }
+
+  // ---- program
+  Builder B(P);
+  const int64_t kTile = 1024;
+  for (int d = P.n_levels - 1; d >= 0; --d) {
+    const std::vector<int>& fr = by_depth[d];
+    const int ubuf = (d % 2 == 0) ? BUF_UPD0 : BUF_UPD1;
+    const int cbuf = (d % 2 == 0) ? BUF_UPD1 : BUF_UPD0;
+    // extend-add (writes every panel element and the U x U block)
+    {
+      Op op;
+      op.kind = OP_EXTADD;
+      op.buf_a = cbuf, op.buf_b = ubuf, op.buf_c = BUF_PANEL;
+      op.begin = static_cast<int64_t>(P.ext.size());
+      op.tile_begin = static_cast<int64_t>(P.ext_tiles.size());
+      op.depth = d;
+      for (int f : fr) {
+        const Front& F = P.fronts[f];
+        ExtAddDesc ds{F.panel_off, F.upd_off, F.nj, F.nu, static_cast<int32_t>(P.ext_child.size()),
+                      static_cast<int32_t>(F.children.size())};
+        for (int c : F.children) {
+          const Front& C = P.fronts[c];
+          ExtAddChild ch{C.upd_off, static_cast<int64_t>(P.ext_inv.size()), C.nu, 0};
+          std::vector<int32_t> inv(F.nj + F.nu, -1);
+          for (int k = 0; k < C.nu; ++k) inv[C.rel[k]] = k;
+          P.ext_inv.insert(P.ext_inv.end(), inv.begin(), inv.end());
+          P.ext_child.push_back(ch);
+        }
+        const int32_t di = static_cast<int32_t>(P.ext.size() - op.begin);
+        P.ext.push_back(ds);
+        const int64_t total = int64_t(F.nj + F.nu) * F.nj + int64_t(F.nu) * F.nu;
+        for (int64_t e0 = 0; e0 < total; e0 += kTile) P.ext_tiles.push_back(ElemTile{di, 0, e0});
+      }
+      op.count = static_cast<int64_t>(P.ext.size()) - op.begin;
+      op.tile_count = static_cast<int64_t>(P.ext_tiles.size()) - op.tile_begin;
+      if (op.count) P.upward.push_back(op);
+    }
+    // assembly of alpha S - H into the panels of this depth
+    if (P.asm_depth_begin[d + 1] > P.asm_depth_begin[d]) {
+      Op op;
+      op.kind = OP_ASSEMBLE;
+      op.buf_c = BUF_PANEL;
+      op.begin = P.asm_depth_begin[d];
+      op.count = P.asm_depth_begin[d + 1] - P.asm_depth_begin[d];
+      op.depth = d;
+      P.upward.push_back(op);
+    }
+    // pivot-block inverses
+    {
+      std::vector<InvDesc> small;
+      std::map<int, std::vector<int>> groups;
+      for (int f : fr) {
+        const Front& F = P.fronts[f];
+        if (F.nj <= 64) small.push_back(InvDesc{F.panel_off, F.nj + F.nu, F.nj});
+        else groups[F.nj].push_back(f);
+      }
+      B.smallinv(P.upward, small, d);
+      for (auto& g : groups) B.inverse(P.upward, g.second, g.first, 0, 0, d);
+    }
+    // L = B A^{-1};  Upd = Upd - L B^T;  B <- L
+    {
+      std::vector<GemmProb> g1, g2;
+      std::vector<CopyDesc> c1;
+      for (int f : fr) {
+        const Front& F = P.fronts[f];
+        if (F.nu == 0) continue;
+        const int ld = F.nj + F.nu;
+        g1.push_back(GemmProb{F.nu, F.nj, F.nj, ld, ld, 0, F.nu, 0, F.panel_off + F.nj, F.panel_off, 0, F.temp_off});
+        g2.push_back(GemmProb{F.nu, F.nu, F.nj, F.nu, ld, F.nu, F.nu, 0, F.temp_off, F.panel_off + F.nj, F.upd_off,
+                              F.upd_off});
+        c1.push_back(CopyDesc{F.temp_off, F.panel_off + F.nj, F.nu, ld, F.nu, F.nj});
+      }
+      B.gemm(P.upward, 0, BUF_PANEL, BUF_PANEL, 0, BUF_TEMP, g1, d);
+      B.gemm(P.upward, G_TB | G_SYM | G_BETA | G_NEG, BUF_TEMP, BUF_PANEL, ubuf, ubuf, g2, d);
+      B.copy(P.upward, false, BUF_TEMP, BUF_PANEL, c1, d);
+    }
+  }
+  for (int d = 1; d < P.n_levels; ++d) {
+    const std::vector<int>& fr = by_depth[d];
+    const int ubuf = (d % 2 == 0) ? BUF_UPD0 : BUF_UPD1;
+    const int pbuf = (d % 2 == 0) ? BUF_UPD1 : BUF_UPD0;
+    {
+      Op op;
+      op.kind = OP_GATHER;
+      op.buf_a = pbuf, op.buf_b = BUF_PANEL, op.buf_c = ubuf;
+      op.begin = static_cast<int64_t>(P.gat.size());
+      op.tile_begin = static_cast<int64_t>(P.gat_tiles.size());
+      op.depth = d;
+      for (int f : fr) {
+        const Front& F = P.fronts[f];
+        if (F.nu == 0) continue;
+        const Front& Pa = P.fronts[F.parent];
+        const int32_t di = static_cast<int32_t>(P.gat.size() - op.begin);
+        P.gat.push_back(GatherDesc{F.upd_off, rel_off[f], Pa.panel_off, Pa.upd_off, F.nu, Pa.nj, Pa.nu, 0});
+        const int64_t total = int64_t(F.nu) * F.nu;
+        for (int64_t e0 = 0; e0 < total; e0 += kTile) P.gat_tiles.push_back(ElemTile{di, 0, e0});
+      }
+      op.count = static_cast<int64_t>(P.gat.size()) - op.begin;
+      op.tile_count = static_cast<int64_t>(P.gat_tiles.size()) - op.tile_begin;
+      if (op.count) P.downward.push_back(op);
+    }
+    std::vector<GemmProb> g3, g4;
+    std::vector<CopyDesc> c2;
+    for (int f : fr) {
+      const Front& F = P.fronts[f];
+      if (F.nu == 0) continue;
+      const int ld = F.nj + F.nu;
+      // T = -G_UU L
+      g3.push_back(GemmProb{F.nu, F.nj, F.nu, F.nu, ld, 0, F.nu, 0, F.upd_off, F.panel_off + F.nj, 0, F.temp_off});
+      // G_JJ = A^{-1} - L^T T
+      g4.push_back(GemmProb{F.nj, F.nj, F.nu, ld, F.nu, ld, ld, 0, F.panel_off + F.nj, F.temp_off, F.panel_off,
+                            F.panel_off});
+      c2.push_back(CopyDesc{F.temp_off, F.panel_off + F.nj, F.nu, ld, F.nu, F.nj});
+    }
+    B.gemm(P.downward, G_NEG, ubuf, BUF_PANEL, 0, BUF_TEMP, g3, d);
+    B.gemm(P.downward, G_TA | G_SYM | G_BETA | G_NEG, BUF_PANEL, BUF_TEMP, BUF_PANEL, BUF_PANEL, g4, d);
+    B.copy(P.downward, false, BUF_TEMP, BUF_PANEL, c2, d);
+  }
+}
+
+}  // namespace ndrho

@@ -1,0 +1,135 @@
+// Host-side plan: nested-dissection ordering, front tree, index maps and the
+// launch program replayed by the device executor for every pole batch.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace ndrho {
+
+void cf_poles(int n_poles, double* z, double* r);
+
+// One front of the dissection tree (a domain at the innermost level or a
+// separator, Sec. II B 1).  Its pivot rows J are the contiguous permuted
+// positions [j0, j0 + nj); its update rows U (permuted positions, increasing)
+// are the rows of ancestor separators coupled to its subtree.
+struct Front {
+  int parent = -1;
+  int depth = 0;
+  int64_t j0 = 0;
+  int nj = 0;
+  int nu = 0;
+  std::vector<int> u;         // update rows (permuted positions)
+  std::vector<int> rel;       // index of each u in the parent's (J, U) local order
+  std::vector<int> children;
+  int64_t panel_off = 0;      // column-major (nj+nu) x nj panel, per pole
+  int64_t upd_off = 0;        // nu x nu update / gathered-G block in the depth's buffer
+  int64_t temp_off = 0;       // scratch region in the temp buffer
+};
+
+// Work descriptors shared with the device code (plain structs, 8-byte aligned).
+struct GemmProb {
+  int32_t m, n, k, lda, ldb, ldc0, ldc, pad;
+  int64_t a_off, b_off, c0_off, c_off;
+};
+struct TileRef {  // one 64x64 output tile of problem `prob`
+  int32_t prob, tm, tn, pad;
+};
+struct InvDesc {  // in-place inverse of an n x n block (n <= 64)
+  int64_t off;
+  int32_t ld, n;
+};
+struct CopyDesc {  // dst (rows x cols) <- src or src^T
+  int64_t src_off, dst_off;
+  int32_t lds, ldd, rows, cols;
+};
+struct CopyTile {
+  int32_t desc, r0, c0, pad;
+};
+// Extend-add target: front p, whose children's update matrices are pulled
+// into its panel (columns in J) and its own update block (U x U).
+struct ExtAddDesc {
+  int64_t panel_off, upd_off;
+  int32_t nj, nu, child_begin, child_count;
+};
+struct ExtAddChild {
+  int64_t upd_off;     // child's update block in the deeper buffer
+  int64_t inv_off;     // into the inverse-map array: parent local index -> child U index or -1
+  int32_t nu, pad;
+};
+struct ElemTile {     // 1024 consecutive target elements of descriptor `desc`
+  int32_t desc;
+  int32_t pad;
+  int64_t e0;
+};
+// Gather of G_UU for front f from its parent p (downward pass).
+struct GatherDesc {
+  int64_t dst_off;          // f's block in the depth buffer
+  int64_t rel_off;          // into the rel array
+  int64_t ppanel_off;       // parent's panel
+  int64_t pguu_off;         // parent's gathered G_UU in the shallower buffer
+  int32_t nu, pnj, pnu, pad;
+};
+
+enum BufId { BUF_PANEL = 0, BUF_UPD0 = 1, BUF_UPD1 = 2, BUF_TEMP = 3, BUF_COUNT = 4 };
+
+enum OpKind { OP_EXTADD, OP_ASSEMBLE, OP_SMALLINV, OP_GEMM, OP_COPY, OP_GATHER };
+
+enum GemmFlags { G_TA = 1, G_TB = 2, G_SYM = 4, G_BETA = 8, G_NEG = 16 };
+
+struct Op {
+  OpKind kind;
+  int flags = 0;             // GEMM variant, COPY transpose flag
+  int buf_a = 0, buf_b = 0, buf_c0 = 0, buf_c = 0;  // for EXTADD: c = panel, a = child upd, b = own upd
+  int64_t begin = 0, count = 0;          // descriptor range
+  int64_t tile_begin = 0, tile_count = 0;
+  int depth = 0;
+  double flops = 0;          // useful flops per pole (GEMM)
+};
+
+struct Plan {
+  int64_t n = 0, nnz = 0;
+  std::vector<int64_t> row_ptr;
+  std::vector<int32_t> col;
+  std::vector<int32_t> perm, iperm;
+  std::vector<Front> fronts;   // postorder
+  int n_levels = 0;
+  int64_t panel_total = 0;     // complex elements per pole
+  int64_t upd_total = 0;       // per depth buffer, complex elements per pole (max over depths)
+  int64_t temp_total = 0;
+  std::vector<int64_t> out_slot, asm_slot;   // per CSR entry
+
+  // device program
+  std::vector<Op> upward, downward;
+  std::vector<GemmProb> gemm;
+  std::vector<TileRef> gemm_tiles;
+  std::vector<InvDesc> inv;
+  std::vector<CopyDesc> copy;
+  std::vector<CopyTile> copy_tiles;
+  std::vector<ExtAddDesc> ext;
+  std::vector<ExtAddChild> ext_child;
+  std::vector<int32_t> ext_inv;
+  std::vector<ElemTile> ext_tiles, gat_tiles;
+  std::vector<GatherDesc> gat;
+  std::vector<int32_t> rel_all;
+  // assembly entries grouped by depth (sorted by slot within a depth)
+  std::vector<int64_t> asm_slot_sorted;
+  std::vector<int32_t> asm_entry_sorted;
+  std::vector<int64_t> asm_depth_begin;       // n_levels + 1
+  // accumulation entries sorted by slot
+  std::vector<int64_t> acc_slot;
+  std::vector<int32_t> acc_entry;
+
+  double flops_model = 0, bytes_model = 0;    // per pole
+  double flops_exec = 0;                      // flops of the program per pole
+};
+
+// Validate the CSR pattern (and values if given); throws Error(EINVAL).
+void validate_csr(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* h, const double* s);
+// Ordering + symbolic analysis + program.
+void build_plan(Plan& plan, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* coords,
+                int leaf_rows);
+
+}  // namespace ndrho

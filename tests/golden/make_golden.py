@@ -1,0 +1,63 @@
+"""Write the stored expected values used by the full-size parity tests.
+
+Calls only the oracle (and the seeded input generator).  Usage:
+
+    python tests/golden/make_golden.py cubic3d_24x4 [--procs 6]
+    python tests/golden/make_golden.py square2d_64x4
+
+For each workload: a seeded sample of rows j, and rho_ij on every pattern
+entry of those rows (by symmetry also column j), from Eq. (8) with one sparse
+LU per pole (oracle.sampled).  mu is fixed (stated in the file), since the
+half-filling mu of these sizes is not available from dense algebra.
+"""
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import sampled  # noqa: E402
+from synth import CONFIGS, BETA, config_system  # noqa: E402
+
+MU = {"cubic3d_24x4": 0.0, "square2d_64x4": 0.0, "cubic3d_40x4": 0.0}
+N_ROWS = {"cubic3d_24x4": 8, "square2d_64x4": 8, "cubic3d_40x4": 4}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("workload")
+    ap.add_argument("--procs", type=int, default=6)
+    a = ap.parse_args()
+    name = a.workload
+    sysd = config_system(name)
+    n = sysd["n"]
+    n_poles = CONFIGS[name]["n_poles"]
+    rng = np.random.default_rng(12345)
+    rows = np.sort(rng.choice(n, size=N_ROWS[name], replace=False))
+    h, s = sampled.csr_matrices(n, sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"])
+    t0 = time.time()
+    with mp.get_context("fork").Pool(a.procs) as pool:
+        cols = sampled.rho_columns(h, s, MU[name], BETA, n_poles, rows, pool=pool)
+    entries, values = [], []
+    for k, j in enumerate(rows):
+        for e in range(sysd["row_ptr"][j], sysd["row_ptr"][j + 1]):
+            i = int(sysd["col"][e])
+            entries.append(int(e))
+            values.append(float(cols[i, k]))     # rho_ji = rho_ij
+    out = {"workload": name, "source": "oracle.sampled.rho_columns (sparse LU per pole, Eq. (8))",
+           "mu": MU[name], "beta": BETA, "n_poles": n_poles, "rows": [int(r) for r in rows],
+           "entries": entries, "values": values, "seconds": time.time() - t0}
+    path = os.path.join(HERE, "rho_sampled_%s.json" % name)
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path, len(entries), "entries in %.0f s" % out["seconds"])
+
+
+if __name__ == "__main__":
+    main()

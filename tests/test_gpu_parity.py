@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance: rho entries are O(1); the FP64 path must agree with the oracle to
+1e-10 absolute (max over pattern entries), single Green-function shifts to
+1e-11 relative to max|G|.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import chain, dense
+from synth import lattice
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+BETA = 10.0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1005_0088_amd as nd
+    c = nd.Context(0)
+    yield c
+    c.close()
+
+
+def _dense(sysd):
+    n = sysd["n"]
+    rows = np.repeat(np.arange(n), np.diff(sysd["row_ptr"]))
+    cols = sysd["col"].astype(np.int64)
+    h = np.zeros((n, n))
+    s = np.zeros((n, n))
+    h[rows, cols] = sysd["h"]
+    s[rows, cols] = sysd["s"]
+    return h, s, rows, cols
+
+
+def _register(ctx, sysd, coords=True):
+    print("case: dims=%s nb=%s n=%d" % (sysd.get("dims"), sysd.get("neighbours"), sysd["n"]), flush=True)
+    return ctx.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"],
+                             sysd["coords"] if coords else None)
+
+
+def test_appendix_a_worked_example(ctx):
+    with open(os.path.join(GOLDEN, "appendix_a.json")) as f:
+        fx = json.load(f)
+    n = 7
+    nz = sorted((i - 1, j - 1) for i, j in fx["matrix_nonzeros"])
+    rows = np.array([a for a, _ in nz])
+    cols = np.array([b for _, b in nz])
+    row_ptr = np.searchsorted(rows, np.arange(n + 1))
+    x = np.full(len(nz), fx["matrix_value"])
+    s = (rows == cols).astype(float)             # S = I stored on the pattern
+    sid = ctx.set_structure(n, row_ptr, cols, -x, s, None)   # X = 0*S - H with H = -X
+    ctx.set_shifts(sid, np.array([0.0 + 0.0j]), np.array([1.0]), add_m0=False)
+    g = ctx.density_matrix(sid)
+    want = {(i - 1, j - 1): v for i, j, v in fx["selected_inverse"]}
+    for e, (i, j) in enumerate(nz):
+        assert g[e] == pytest.approx(want[(i, j)], abs=1e-14)
+
+
+def test_m0_is_s_inverse(ctx):
+    sysd = lattice((5, 4, 3), "nn2", 21)
+    h, s, rows, cols = _dense(sysd)
+    sid = _register(ctx, sysd)
+    ctx.set_shifts(sid, np.array([1.0j]), np.array([0.0]), add_m0=True)
+    got = ctx.density_matrix(sid)
+    ref = np.linalg.inv(s)[rows, cols]
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("dims,nb,alpha", [((40,), "nn", 0.3 + 0.314j), ((11, 9), "nn2", -0.5 + 0.7j),
+                                           ((7, 7, 7), "nn", 0.1 + 0.314j), ((8, 8, 9), "nn", 2.0 + 40.0j),
+                                           ((16, 15), "nn2", 0.0 + 3000.0j)])
+def test_single_shift_green_function(ctx, dims, nb, alpha):
+    sysd = lattice(dims, nb, 5)
+    h, s, rows, cols = _dense(sysd)
+    sid = _register(ctx, sysd)
+    ctx.set_shifts(sid, np.array([alpha]), np.array([1.0]), add_m0=False)
+    got = ctx.density_matrix(sid)
+    g = dense.green_dense(h, s, alpha)
+    ref = g[rows, cols].real
+    assert np.max(np.abs(got - ref)) < 1e-11 * np.abs(g).max()
+
+
+def test_several_shifts_weighted(ctx):
+    sysd = lattice((9, 8, 4), "nn", 6)
+    h, s, rows, cols = _dense(sysd)
+    sid = _register(ctx, sysd)
+    alphas = np.array([0.2 + 0.4j, -1.0 + 1.5j, 0.5 + 10.0j])
+    w = np.array([0.7, -1.3, 2.0])
+    ctx.set_shifts(sid, alphas, w, add_m0=True)
+    got = ctx.density_matrix(sid)
+    ref = np.linalg.inv(s)[rows, cols]
+    for a, wk in zip(alphas, w):
+        ref = ref + wk * dense.green_dense(h, s, a)[rows, cols].real
+    assert np.max(np.abs(got - ref)) < 1e-11
+
+
+def test_chain_closed_form(ctx):
+    # scalar open chain, H = a I + b T, S = I + s T: rho from the closed form
+    n, a, b, sv, mu = 300, 0.1, -1.0, 0.12, 0.05
+    hm, sm = chain.chain_matrices(n, a, b, sv)
+    rows, cols = np.nonzero(np.abs(hm) + np.abs(sm) > 0)
+    row_ptr = np.searchsorted(rows, np.arange(n + 1))
+    coords = np.stack([np.arange(n, dtype=float), np.zeros(n), np.zeros(n)], 1)
+    sid = ctx.set_structure(n, row_ptr, cols, hm[rows, cols], sm[rows, cols], coords)
+    ctx.set_poles(sid, mu, BETA, 60)
+    got = ctx.density_matrix(sid)
+    ref = chain.chain_rho(n, a, b, sv, mu, BETA)[rows, cols]
+    assert np.max(np.abs(got - ref)) < 1e-10
+
+
+@pytest.mark.parametrize("dims,nb,n_poles,coords", [((256,), "nn", 60, True), ((12, 10), "nn2", 80, True),
+                                                    ((6, 6, 7), "nn", 80, True), ((10, 9), "nn", 40, False)])
+def test_rho_against_dense_eigen_oracle(ctx, dims, nb, n_poles, coords):
+    sysd = lattice(dims, nb, 0 if dims == (256,) else 8)
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    mu = dense.mu_for_count(eps, BETA, float(sysd["n"]))
+    sid = _register(ctx, sysd, coords)
+    ctx.set_poles(sid, mu, BETA, n_poles)
+    got = ctx.density_matrix(sid)
+    ref = dense.rho_cf_pattern(eps, c, mu, BETA, n_poles, rows, cols)
+    assert np.max(np.abs(got - ref)) < 1e-10
+    # electron count (Eq. (40)) from the pattern values alone
+    assert dense.trace_rho_s(got, sysd["s"]) == pytest.approx(sysd["n"], abs=1e-8)
+
+
+def test_batched_equals_unbatched_bitwise():
+    import paper_1005_0088_amd as nd
+    sysd = lattice((6, 5, 5), "nn2", 9)
+    outs = []
+    for pb in (0, 1, 7):
+        with nd.Context(0, pole_batch=pb) as c:
+            sid = _register(c, sysd)
+            c.set_poles(sid, 0.1, BETA, 30)
+            outs.append(c.density_matrix(sid))
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_repeatable_bitwise(ctx):
+    sysd = lattice((9, 9, 4), "nn", 12)
+    sid = _register(ctx, sysd)
+    ctx.set_poles(sid, -0.2, BETA, 40)
+    a = ctx.density_matrix(sid)
+    b = ctx.density_matrix(sid)
+    assert np.array_equal(a, b)
+
+
+def test_device_output_matches_host_output(ctx):
+    sysd = lattice((10, 8), "nn", 13)
+    sid = _register(ctx, sysd)
+    ctx.set_poles(sid, 0.0, BETA, 20)
+    host = ctx.density_matrix(sid)
+    dev = ctx.device_buffer(host.size)
+    ctx.density_matrix(sid, out=dev)
+    assert np.array_equal(dev.numpy(), host)
+    dev.free()
+
+
+def test_errors(ctx):
+    import paper_1005_0088_amd as nd
+    sysd = lattice((5, 5), "nn", 3)
+    sid = _register(ctx, sysd)
+    with pytest.raises(nd.NdrhoError) as e:
+        ctx.density_matrix(sid)
+    assert e.value.name == "ESTATE"
+    with pytest.raises(nd.NdrhoError) as e:
+        ctx.set_poles(sid, 0.0, -1.0, 10)
+    assert e.value.name == "EINVAL"
+    with pytest.raises(nd.NdrhoError) as e:
+        ctx.set_poles(sid, 0.0, BETA, 0)
+    assert e.value.name == "EINVAL"
+    bad = dict(sysd)
+    bad["s"] = sysd["s"].copy()
+    diag = np.nonzero(np.repeat(np.arange(sysd["n"]), np.diff(sysd["row_ptr"])) == sysd["col"])[0]
+    bad["s"][diag[7]] = -1.0
+    with pytest.raises(nd.NdrhoError) as e:
+        _register(ctx, bad)
+    assert e.value.name == "ENOTSPD"
+    asym = dict(sysd)
+    asym["h"] = sysd["h"].copy()
+    asym["h"][1] += 0.5
+    with pytest.raises(nd.NdrhoError) as e:
+        _register(ctx, asym)
+    assert e.value.name == "EINVAL"
+    # a shift on an eigenvalue of a 1-orbital chain gives a zero pivot
+    n = 2
+    rows = np.array([0, 0, 1, 1])
+    cols = np.array([0, 1, 0, 1])
+    sid2 = ctx.set_structure(n, np.array([0, 2, 4]), cols, np.array([0.0, 1.0, 1.0, 0.0]),
+                             (rows == cols).astype(float), None)
+    ctx.set_shifts(sid2, np.array([0.0 + 0.0j]), np.array([1.0]), add_m0=False)
+    with pytest.raises(nd.NdrhoError) as e:
+        ctx.set_shifts(sid2, np.array([1.0 + 0.0j]), np.array([1.0]), add_m0=False)
+        ctx.density_matrix(sid2)
+    assert e.value.name == "ESINGULAR"

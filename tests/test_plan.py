@@ -1,0 +1,229 @@
+"""Host-side checks of the library that need no GPU: the exported C symbols,
+the continued-fraction poles, the nested-dissection ordering and the symbolic
+front tree with its index tables.
+
+The last tests drive a small numpy model of the front-by-front factorization
+and selected inversion (test code, independent of the oracle and the
+kernels) through the library's exported plan, and compare the selected
+entries with a dense inverse: this validates the plan's maps on the CPU.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1005_0088_amd as nd
+from oracle import poles as opoles
+from synth import lattice
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = nd.load_library()
+    with open(os.path.join(ROOT, "include", "ndrho.h")) as f:
+        hdr = f.read()
+    names = set(re.findall(r"\b(ndrho_[a-z_0-9]+)\s*\(", hdr))
+    assert len(names) >= 15
+    for name in sorted(names):
+        assert hasattr(lib, name), name
+    declared = {s[0] for s in nd._binding.SIGNATURES}
+    assert names == declared
+
+
+@pytest.mark.parametrize("n_poles", [1, 2, 5, 60, 80, 100])
+def test_library_poles_match_oracle(n_poles):
+    z, r = nd.cf_poles(n_poles)
+    zo, ro = opoles.cf_poles(n_poles)
+    assert np.allclose(z, zo, rtol=1e-12, atol=0)
+    assert np.allclose(r, ro, rtol=1e-11, atol=1e-13)
+    assert r.sum() == pytest.approx(-n_poles * (2 * n_poles + 1) / 2.0, rel=1e-12)
+
+
+def test_library_poles_reject_bad_count():
+    with pytest.raises(nd.NdrhoError) as e:
+        nd.cf_poles(0)
+    assert e.value.name == "EINVAL"
+
+
+def _pattern(sysd):
+    n = sysd["n"]
+    rows = np.repeat(np.arange(n), np.diff(sysd["row_ptr"]))
+    return rows, sysd["col"].astype(np.int64)
+
+
+def _check_plan(sysd, leaf, coords=True):
+    n = sysd["n"]
+    P = nd.Plan(n, sysd["row_ptr"], sysd["col"], sysd["coords"] if coords else None, leaf)
+    ex = P.export()
+    perm = ex["perm"]
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    nf = P.n_fronts
+    j0, nj, nu, parent = ex["j0"], ex["nj"], ex["nu"], ex["parent"]
+    # postorder, contiguous J ranges covering all rows
+    assert j0[0] == 0 and np.all(j0[1:] == j0[:-1] + nj[:-1]) and j0[-1] + nj[-1] == n
+    for f in range(nf):
+        if parent[f] >= 0:
+            assert parent[f] > f
+            assert ex["depth"][f] == ex["depth"][parent[f]] + 1
+        else:
+            assert nu[f] == 0 and ex["depth"][f] == 0
+        u = ex["u_rows"][ex["u_off"][f]:ex["u_off"][f] + nu[f]]
+        assert np.all(np.diff(u) > 0) and (nu[f] == 0 or u[0] >= j0[f] + nj[f])
+        if parent[f] >= 0:
+            p = parent[f]
+            rel = ex["rel"][ex["u_off"][f]:ex["u_off"][f] + nu[f]]
+            pu = ex["u_rows"][ex["u_off"][p]:ex["u_off"][p] + nu[p]]
+            ploc = np.concatenate([np.arange(j0[p], j0[p] + nj[p]), pu])
+            assert np.all((rel >= 0) & (rel < nj[p] + nu[p]))
+            assert np.array_equal(ploc[rel], u)          # closure: U_f inside J_p + U_p
+    # leaves are small; every separator separates (checked through closure)
+    leaves = [f for f in range(nf) if not np.any(parent == f)]
+    assert all(nj[f] <= leaf for f in leaves)
+    # table function: assembly slots are unique, output slots inside the panel of the owner
+    out, asm, poff = P.slots()
+    a = asm[asm >= 0]
+    assert len(np.unique(a)) == len(a)
+    assert np.all((out >= 0) & (out < P.panel_total))
+    return P, ex
+
+
+@pytest.mark.parametrize("dims,nb,leaf", [((40,), "nn", 8), ((9, 7), "nn2", 12), ((5, 4, 6), "nn", 16),
+                                           ((6, 6, 5), "nn2", 32), ((256,), "nn", 32)])
+def test_plan_invariants(dims, nb, leaf):
+    sysd = lattice(dims, nb, 3)
+    _check_plan(sysd, leaf)
+
+
+def test_plan_without_coordinates():
+    sysd = lattice((7, 6), "nn", 1)
+    _check_plan(sysd, 10, coords=False)
+
+
+def test_plan_sizes_of_the_workloads():
+    # 1D 256 sites x 4: 63 fronts over 6 levels, root separator = one site
+    P, ex = _check_plan(lattice((256,), "nn", 0), 32)
+    assert P.n_fronts == 63 and P.n_levels == 6
+    assert ex["nj"][ex["parent"] < 0].tolist() == [4]
+    # 3D 24^3 x 4: the top separator is one 24 x 24 plane of sites (2304 rows)
+    sysd = lattice((24, 24, 24), "nn", 2)
+    P = nd.Plan(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["coords"], 32)
+    ex = P.export()
+    assert ex["nj"][ex["parent"] < 0].tolist() == [2304]
+    assert P.max_u <= 2304 + 4 * 24
+    flops, _ = P.model()
+    assert 7.5e11 < flops < 9.5e11
+
+
+def test_chain_dissection_has_one_atom_separators():
+    # Fig. 1: a ten-atom s-valent chain; every separator is a single atom and
+    # the top separator splits the chain into two domains of 5 and 4 atoms.
+    n = 10
+    rows, cols = [], []
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                rows.append(i)
+                cols.append(j)
+    row_ptr = np.searchsorted(rows, np.arange(n + 1))
+    coords = np.stack([np.arange(n, dtype=float), np.zeros(n), np.zeros(n)], 1)
+    P = nd.Plan(n, row_ptr, np.array(cols), coords, 2)
+    ex = P.export()
+    seps = [f for f in range(P.n_fronts) if np.any(ex["parent"] == f)]
+    assert all(ex["nj"][f] == 1 for f in seps)
+    root = int(np.nonzero(ex["parent"] < 0)[0][0])
+    top_atom = ex["perm"][ex["j0"][root]]
+    assert sorted([top_atom, n - 1 - top_atom]) == [4, 5]
+
+
+def test_plan_rejects_bad_csr():
+    sysd = lattice((4, 3), "nn", 0)
+    col = sysd["col"].copy()
+    col[5], col[6] = col[6], col[5]                 # unsorted row
+    with pytest.raises(nd.NdrhoError) as e:
+        nd.Plan(sysd["n"], sysd["row_ptr"], col, None, 8)
+    assert e.value.name == "EINVAL"
+    rp = sysd["row_ptr"].copy()
+    rp[0] = 1
+    with pytest.raises(nd.NdrhoError):
+        nd.Plan(sysd["n"], rp, sysd["col"], None, 8)
+
+
+# --------------------------------------------------------- numpy model of the fronts
+
+def _model_selected_inverse(P, ex, x_perm):
+    """Front-by-front block LDL^T and selected inversion in numpy, laid out in
+    the library's panel format; returns the flat panel array."""
+    nf = P.n_fronts
+    j0, nj, nu, parent = ex["j0"], ex["nj"], ex["nu"], ex["parent"]
+    children = [[] for _ in range(nf)]
+    for f in range(nf):
+        if parent[f] >= 0:
+            children[parent[f]].append(f)
+    U = [ex["u_rows"][ex["u_off"][f]:ex["u_off"][f] + nu[f]] for f in range(nf)]
+    rel = [ex["rel"][ex["u_off"][f]:ex["u_off"][f] + nu[f]] for f in range(nf)]
+    ainv, lmat, upd = {}, {}, {}
+    for f in range(nf):
+        J = np.arange(j0[f], j0[f] + nj[f])
+        idx = np.concatenate([J, U[f]])
+        F = np.zeros((len(idx), len(idx)), dtype=complex)
+        F[:, :nj[f]] = x_perm[np.ix_(idx, J)]
+        F[:nj[f], nj[f]:] = x_perm[np.ix_(J, U[f])]
+        for c in children[f]:
+            F[np.ix_(rel[c], rel[c])] += upd[c]
+        a = F[:nj[f], :nj[f]]
+        b = F[nj[f]:, :nj[f]]
+        ainv[f] = np.linalg.inv(a)
+        lmat[f] = b @ ainv[f]
+        upd[f] = F[nj[f]:, nj[f]:] - lmat[f] @ b.T
+    gjj, guj, guu = {}, {}, {}
+    for f in range(nf - 1, -1, -1):
+        if parent[f] < 0:
+            gjj[f] = ainv[f]
+            guj[f] = np.zeros((0, nj[f]), dtype=complex)
+            guu[f] = np.zeros((0, 0), dtype=complex)
+            continue
+        p = parent[f]
+        gfull = np.block([[gjj[p], guj[p].T], [guj[p], guu[p]]])
+        guu[f] = gfull[np.ix_(rel[f], rel[f])]
+        guj[f] = -guu[f] @ lmat[f]
+        gjj[f] = ainv[f] - lmat[f].T @ guj[f]
+    _, _, poff = P.slots()
+    flat = np.zeros(P.panel_total, dtype=complex)
+    for f in range(nf):
+        pan = np.vstack([gjj[f], guj[f]])
+        flat[poff[f]:poff[f] + pan.size] = pan.ravel(order="F")
+    return flat
+
+
+@pytest.mark.parametrize("dims,nb,leaf,alpha", [((30,), "nn", 8, 0.2 + 0.5j), ((7, 6), "nn2", 12, -0.3 + 0.314j),
+                                                 ((4, 4, 5), "nn", 16, 1.0 + 2.0j)])
+def test_front_model_through_plan_matches_dense_inverse(dims, nb, leaf, alpha):
+    sysd = lattice(dims, nb, 7)
+    n = sysd["n"]
+    rows, cols = _pattern(sysd)
+    h = np.zeros((n, n))
+    s = np.zeros((n, n))
+    h[rows, cols] = sysd["h"]
+    s[rows, cols] = sysd["s"]
+    x = alpha * s - h
+    P, ex = _check_plan(sysd, leaf)
+    perm = ex["perm"]
+    flat = _model_selected_inverse(P, ex, x[np.ix_(perm, perm)])
+    out, asm, _ = P.slots()
+    g = np.linalg.inv(x)
+    got = flat[out]
+    ref = g[rows, cols]
+    assert np.max(np.abs(got - ref)) < 1e-11 * np.abs(g).max()
+    # the assembly table places X_ij where the model's fronts read it
+    asm_flat = np.zeros(P.panel_total, dtype=complex)
+    asm_flat[asm[asm >= 0]] = x[rows[asm >= 0], cols[asm >= 0]]
+    _, _, poff = P.slots()
+    for f in range(P.n_fronts):
+        J = np.arange(ex["j0"][f], ex["j0"][f] + ex["nj"][f])
+        U = ex["u_rows"][ex["u_off"][f]:ex["u_off"][f] + ex["nu"][f]]
+        idx = np.concatenate([J, U])
+        want = x[np.ix_(perm[idx], perm[J])]
+        have = asm_flat[poff[f]:poff[f] + want.size].reshape(want.shape, order="F")
+        assert np.array_equal(have, want)
