@@ -186,6 +186,12 @@ int ndrho_plan_export(const ndrho_plan* plan, int32_t* perm, int32_t* parent, in
  * when the transposed entry carries it; panel_off[f] = start of front f's
  * column-major (J+U) x J panel. */
 int ndrho_plan_slots(const ndrho_plan* plan, int64_t* out_slot, int64_t* asm_slot, int64_t* panel_off);
+/* The launch program of one pass (upward then downward; the pole sum that
+ * ends a pass is not listed): per launch, its kernel kind (NDRHO_K_*), tree
+ * depth, useful flops per pole and work items (tiles or descriptors).
+ * *count receives the number of launches; arrays may be NULL to query it. */
+int ndrho_plan_program(const ndrho_plan* plan, int64_t* count, int32_t* kind, int32_t* depth, double* flops,
+                       int64_t* items);
 /* Flop and byte model per pole (8 real flops per complex multiply-add). */
 int ndrho_plan_model(const ndrho_plan* plan, double* flops, double* bytes);
 

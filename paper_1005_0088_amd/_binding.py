@@ -62,6 +62,7 @@ SIGNATURES = [
     ("ndrho_plan_counts", C.c_int, [_P, _I64P]),
     ("ndrho_plan_export", C.c_int, [_P, _I32P, _I32P, _I32P, _I64P, _I32P, _I32P, _I64P, _I32P, _I32P]),
     ("ndrho_plan_slots", C.c_int, [_P, _I64P, _I64P, _I64P]),
+    ("ndrho_plan_program", C.c_int, [_P, _I64P, _I32P, _I32P, _DP, _I64P]),
     ("ndrho_plan_model", C.c_int, [_P, _DP, _DP]),
 ]
 
@@ -149,6 +150,18 @@ class Plan:
         poff = np.empty(self.n_fronts, np.int64)
         self._lib.ndrho_plan_slots(self._h, _ptr(out, C.c_int64), _ptr(asm, C.c_int64), _ptr(poff, C.c_int64))
         return out, asm, poff
+
+    def program(self):
+        cnt = C.c_int64()
+        self._lib.ndrho_plan_program(self._h, C.byref(cnt), None, None, None, None)
+        m = cnt.value
+        kind = np.empty(m, np.int32)
+        depth = np.empty(m, np.int32)
+        flops = np.empty(m)
+        items = np.empty(m, np.int64)
+        self._lib.ndrho_plan_program(self._h, C.byref(cnt), _ptr(kind, C.c_int32), _ptr(depth, C.c_int32),
+                                     _ptr(flops, C.c_double), _ptr(items, C.c_int64))
+        return {"kind": kind, "depth": depth, "flops": flops, "items": items}
 
     def model(self):
         f = C.c_double()

@@ -708,6 +708,26 @@ int ndrho_plan_slots(const ndrho_plan* plan, int64_t* out_slot, int64_t* asm_slo
   return NDRHO_OK;
 }
 
+int ndrho_plan_program(const ndrho_plan* plan, int64_t* count, int32_t* kind, int32_t* depth, double* flops,
+                       int64_t* items) {
+  if (!plan || !count) return NDRHO_EINVAL;
+  const Plan& P = plan->plan;
+  int64_t i = 0;
+  auto put = [&](const Op& op) {
+    static const int kmap[] = {NDRHO_K_EXTADD, NDRHO_K_ASSEMBLE, NDRHO_K_PIVOT_INV,
+                               NDRHO_K_GEMM,   NDRHO_K_COPY,     NDRHO_K_GATHER};
+    if (kind) kind[i] = kmap[op.kind];
+    if (depth) depth[i] = op.depth;
+    if (flops) flops[i] = op.flops;
+    if (items) items[i] = op.tile_count ? op.tile_count : op.count;
+    ++i;
+  };
+  for (const Op& op : P.upward) put(op);
+  for (const Op& op : P.downward) put(op);
+  *count = i;
+  return NDRHO_OK;
+}
+
 int ndrho_plan_model(const ndrho_plan* plan, double* flops, double* bytes) {
   if (!plan) return NDRHO_EINVAL;
   if (flops) *flops = plan->plan.flops_model;

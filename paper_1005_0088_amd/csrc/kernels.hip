@@ -197,8 +197,10 @@ __global__ __launch_bounds__(256) void k_smallinv(const InvDesc* __restrict__ de
 // ----------------------------------------------------------------- complex GEMM
 //
 // C = [C0 +] (+/-) op(A) op(B), grouped over problems and batched over poles,
-// complex FP64 on the matrix cores (v_mfma_f64_16x16x4f64, four real products
-// per complex step).  Transposes are plain transposes (the matrices are
+// complex FP64 on the matrix cores (v_mfma_f64_16x16x4f64).  Each complex
+// product takes three real ones (P1 = Ar Br, P2 = Ai Bi, P3 = (Ar+Ai)(Br+Bi);
+// Re = P1 - P2, Im = P3 - P1 - P2), issued so that consecutive MFMAs never
+// share an accumulator.  Transposes are plain transposes (the matrices are
 // complex symmetric, never Hermitian).  One 64x64 output tile per workgroup
 // of four waves (2 x 2 waves of 32 x 32), K staged through LDS in steps of 16
 // with double buffering.  The MFMA operands are swapped (B-tile as the A
@@ -232,13 +234,14 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
-  d4 acc_re[2][2], acc_im[2][2];
+  d4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      acc_re[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      acc_im[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      p1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      p2[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      p3[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
   double2 ra[4], rb[4];
@@ -292,15 +295,24 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
         av[i] = As[cur][kr][wm * 32 + i * 16 + (lane & 15)];
         bv[i] = Bs[cur][kr][wn * 32 + i * 16 + (lane & 15)];
       }
+      double as[2], bs[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        as[i] = av[i].x + av[i].y;
+        bs[i] = bv[i].x + bv[i].y;
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j].x, av[i].x, acc_re[i][j], 0, 0, 0);
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bv[j].y, av[i].y, acc_re[i][j], 0, 0, 0);
-          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j].x, av[i].y, acc_im[i][j], 0, 0, 0);
-          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j].y, av[i].x, acc_im[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < 2; ++j) p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j].x, av[i].x, p1[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j].y, av[i].y, p2[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bs[j], as[i], p3[i][j], 0, 0, 0);
     }
     if (kt + 1 < nk) store(cur ^ 1);
     __syncthreads();
@@ -318,7 +330,7 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
         const int n = n0 + wn * 32 + j * 16 + 4 * r + (lane >> 4);
         if (m >= M || n >= N) continue;
         if (SYM && m < n) continue;
-        double2 v = make_double2(acc_re[i][j][r], acc_im[i][j][r]);
+        double2 v = make_double2(p1[i][j][r] - p2[i][j][r], p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
         if (NEG) v = make_double2(-v.x, -v.y);
         if (BETA) {
           const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
