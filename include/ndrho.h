@@ -49,14 +49,23 @@ enum {
   NDRHO_EUNSUPPORTED = -7 /* option not supported by this build */
 };
 
-enum { NDRHO_FP64 = 0 };  /* arithmetic of the factorization (complex128) */
+/* Arithmetic of the front updates.  Storage, pivot-block inverses, the
+ * assembly and the pole sum are FP64 (complex128) in every mode.
+ *   NDRHO_FP64:       every GEMM on the FP64 matrix cores.
+ *   NDRHO_MIXED_FP32: for poles away from the real axis (see fp64_poles,
+ *                     fp64_pole_im) the four front-update GEMMs (L = B A^{-1},
+ *                     Schur update, G_UJ, G_JJ) take FP32 products with FP32
+ *                     accumulation, results summed into FP64 storage. */
+enum { NDRHO_FP64 = 0, NDRHO_MIXED_FP32 = 1 };
 
 typedef struct {
-  int32_t leaf_rows;   /* nested dissection stops at domains of <= leaf_rows rows (default 32) */
-  int32_t precision;   /* NDRHO_FP64 */
-  int32_t pole_batch;  /* poles per device pass; 0 = largest that fits the memory budget */
-  double mem_fraction; /* fraction of free device memory the workspace may use (default 0.8) */
-  int32_t verbose;     /* 0 = quiet */
+  int32_t leaf_rows;    /* nested dissection stops at domains of <= leaf_rows rows (default 32) */
+  int32_t precision;    /* NDRHO_FP64 (default) or NDRHO_MIXED_FP32 */
+  int32_t pole_batch;   /* poles per device pass; 0 = largest that fits the memory budget */
+  double mem_fraction;  /* fraction of free device memory the workspace may use (default 0.8) */
+  int32_t verbose;      /* 0 = quiet */
+  int32_t fp64_poles;   /* mixed mode: the fp64_poles shifts nearest the real axis stay FP64 (default 8) */
+  double fp64_pole_im;  /* mixed mode: shifts with Im alpha < fp64_pole_im also stay FP64 (default 0.05) */
 } ndrho_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -129,6 +138,8 @@ typedef struct {
   double workspace_bytes;          /* device workspace currently allocated */
   double last_ms;                  /* wall time of the last density_matrix (host clock) */
   int64_t launches_per_pass;       /* kernel launches of one pass over a pole batch */
+  int32_t n_fp64_poles;            /* leading shifts run with FP64 front updates */
+  int32_t precision;               /* the context's precision mode */
 } ndrho_stats_t;
 
 int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out);

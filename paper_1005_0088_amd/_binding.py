@@ -7,6 +7,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libndrho.so")
 
+FP64, MIXED_FP32 = 0, 1
+PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32}
+
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD", -4: "ESINGULAR", -5: "EDEVICE",
                 -6: "ESTATE", -7: "EUNSUPPORTED"}
 
@@ -20,7 +23,8 @@ class NdrhoError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("leaf_rows", C.c_int32), ("precision", C.c_int32), ("pole_batch", C.c_int32),
-                ("mem_fraction", C.c_double), ("verbose", C.c_int32)]
+                ("mem_fraction", C.c_double), ("verbose", C.c_int32), ("fp64_poles", C.c_int32),
+                ("fp64_pole_im", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -29,7 +33,8 @@ class Stats(C.Structure):
                 ("n_poles", C.c_int32), ("pole_batch", C.c_int32), ("flops_per_pole", C.c_double),
                 ("flops_exec_per_pole", C.c_double), ("bytes_per_pole", C.c_double),
                 ("factor_bytes_per_pole", C.c_double), ("workspace_bytes", C.c_double),
-                ("last_ms", C.c_double), ("launches_per_pass", C.c_int64)]
+                ("last_ms", C.c_double), ("launches_per_pass", C.c_int64), ("n_fp64_poles", C.c_int32),
+                ("precision", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -205,13 +210,19 @@ class Context:
     as libndrho.so, or None (the context creates its own stream).
     """
 
-    def __init__(self, device=0, stream=None, leaf_rows=32, pole_batch=0, mem_fraction=0.8):
+    def __init__(self, device=0, stream=None, leaf_rows=32, pole_batch=0, mem_fraction=0.8, precision="fp64",
+                 fp64_poles=None, fp64_pole_im=None):
         self._lib = load_library()
         opt = Options()
         self._lib.ndrho_default_options(C.byref(opt))
         opt.leaf_rows = int(leaf_rows)
         opt.pole_batch = int(pole_batch)
         opt.mem_fraction = float(mem_fraction)
+        opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if fp64_poles is not None:
+            opt.fp64_poles = int(fp64_poles)
+        if fp64_pole_im is not None:
+            opt.fp64_pole_im = float(fp64_pole_im)
         handle = None
         if stream is not None:
             handle = getattr(stream, "cuda_stream", stream)

@@ -52,6 +52,7 @@ struct DevStruct {
   int32_t* acc_entry = nullptr;
   // shifts and weights
   int n_shifts = 0;
+  int n_hi = 0;  // leading shifts evaluated with FP64 front updates
   bool add_m0 = true;
   double2* d_alpha = nullptr;
   double* d_w = nullptr;
@@ -187,13 +188,14 @@ struct ndrho_ctx {
     HIP_OK(hipMemGetInfo(&free_b, &total_b));
     const double budget = opt.mem_fraction * (static_cast<double>(free_b) + static_cast<double>(ws_bytes));
     const double pp = static_cast<double>(per_pole_elems(P)) * sizeof(double2);
-    int nb = static_cast<int>(budget / pp);
-    if (nb < 1) fail(NDRHO_ENOMEM, "one pole needs " + std::to_string(pp) + " bytes; budget " + std::to_string(budget));
-    return std::min(nb, n_shifts);
+    const double fit = std::floor(budget / pp);  // may exceed the int range for tiny plans
+    if (fit < 1.0) fail(NDRHO_ENOMEM, "one pole needs " + std::to_string(pp) + " bytes; budget " + std::to_string(budget));
+    return fit >= static_cast<double>(n_shifts) ? n_shifts : static_cast<int>(fit);
   }
 
   // One pass of the whole program over `nb` poles.
-  void run_pass(DevStruct& S, int nb, const double2* alpha, const double* w, double hcoef, int spd_check) {
+  void run_pass(DevStruct& S, int nb, const double2* alpha, const double* w, double hcoef, int spd_check,
+                bool low) {
     const Plan& P = S.plan;
     double2* base = static_cast<double2*>(ws);
     double2* bufs[BUF_COUNT];
@@ -208,7 +210,8 @@ struct ndrho_ctx {
     strides[BUF_TEMP] = P.temp_total;
     auto resolve = [&](const Op& op) {
       DevOp d;
-      d.flags = op.flags;
+      d.flags = op.flags & 0xff;
+      d.fp32 = low && !(op.flags & OP_PIVOT);
       d.npoles = nb;
       d.count = op.count;
       d.tile_count = op.tile_count;
@@ -266,16 +269,20 @@ struct ndrho_ctx {
   }
 
   // Full weighted sum over the structure's shifts into `acc` (sorted order).
-  void evaluate(DevStruct& S, const double2* alpha, const double* w, int n, bool add_m0, double hcoef,
+  // The first n_hi shifts run with FP64 front updates, the rest in the
+  // context's low precision; the sum is taken in shift order either way.
+  void evaluate(DevStruct& S, const double2* alpha, const double* w, int n, int n_hi, bool add_m0, double hcoef,
                 int spd_check) {
     const Plan& P = S.plan;
     const int nb = batch_for(P, n);
     ensure_ws(P, nb);
     last_batch = nb;
     HIP_OK(launch_init_acc(S.m0, P.nnz, add_m0 ? 1 : 0, acc, status, stream));
-    for (int p0 = 0; p0 < n; p0 += nb) {
-      const int cnt = std::min(nb, n - p0);
-      run_pass(S, cnt, alpha + p0, w + p0, hcoef, spd_check);
+    for (int p0 = 0; p0 < n;) {
+      const bool low = p0 >= n_hi;
+      const int cnt = std::min(nb, (low ? n : n_hi) - p0);
+      run_pass(S, cnt, alpha + p0, w + p0, hcoef, spd_check, low);
+      p0 += cnt;
     }
   }
 
@@ -298,7 +305,7 @@ struct ndrho_ctx {
       S.allocs.push_back(S.m0);
     }
     try {
-      evaluate(S, da, dw, 1, false, 0.0, 1);
+      evaluate(S, da, dw, 1, 1, false, 0.0, 1);
       int st[2];
       read_status(st);
       if (st[0] || st[1]) fail(NDRHO_ENOTSPD, "S is not positive definite (a non-positive pivot of S)");
@@ -314,6 +321,16 @@ struct ndrho_ctx {
   }
 
   void set_shifts(DevStruct& S, const std::vector<double2>& alpha, const std::vector<double>& w, bool add_m0) {
+    // shifts kept in FP64 in mixed mode: the leading run of shifts that are
+    // among the fp64_poles nearest the real axis or below fp64_pole_im
+    int hi = static_cast<int>(alpha.size());
+    if (opt.precision == NDRHO_MIXED_FP32) {
+      hi = 0;
+      while (hi < static_cast<int>(alpha.size()) &&
+             (hi < opt.fp64_poles || std::fabs(alpha[hi].y) < opt.fp64_pole_im))
+        ++hi;
+    }
+    S.n_hi = hi;
     if (S.d_alpha) HIP_OK(hipFree(S.d_alpha));
     if (S.d_w) HIP_OK(hipFree(S.d_w));
     S.d_alpha = nullptr;
@@ -363,6 +380,8 @@ int ndrho_default_options(ndrho_options* opt) {
   opt->pole_batch = 0;
   opt->mem_fraction = 0.8;
   opt->verbose = 0;
+  opt->fp64_poles = 8;
+  opt->fp64_pole_im = 0.05;
   return NDRHO_OK;
 }
 
@@ -378,7 +397,9 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
     ndrho_default_options(&c->opt);
     if (opt) c->opt = *opt;
     if (c->opt.leaf_rows < 1) fail(NDRHO_EINVAL, "leaf_rows must be >= 1");
-    if (c->opt.precision != NDRHO_FP64) fail(NDRHO_EUNSUPPORTED, "only NDRHO_FP64 is available");
+    if (c->opt.precision != NDRHO_FP64 && c->opt.precision != NDRHO_MIXED_FP32)
+      fail(NDRHO_EUNSUPPORTED, "precision must be NDRHO_FP64 or NDRHO_MIXED_FP32");
+    if (c->opt.fp64_poles < 0 || !(c->opt.fp64_pole_im >= 0.0)) fail(NDRHO_EINVAL, "invalid FP64 pole rule");
     if (c->opt.pole_batch < 0) fail(NDRHO_EINVAL, "pole_batch must be >= 0");
     if (!(c->opt.mem_fraction > 0.0 && c->opt.mem_fraction <= 1.0)) fail(NDRHO_EINVAL, "mem_fraction must be in (0, 1]");
     int count = 0;
@@ -518,7 +539,7 @@ int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int
     HIP_OK(hipSetDevice(ctx->device));
     const auto t0 = std::chrono::steady_clock::now();
     const Plan& P = ds.plan;
-    ctx->evaluate(ds, ds.d_alpha, ds.d_w, ds.n_shifts, ds.add_m0, 1.0, 0);
+    ctx->evaluate(ds, ds.d_alpha, ds.d_w, ds.n_shifts, ds.n_hi, ds.add_m0, 1.0, 0);
     double* dst = on_device ? rho_out : ctx->outbuf;
     HIP_OK(launch_scatter(ds.acc_entry, P.nnz, ctx->acc, dst, ctx->stream));
     int st[2];
@@ -573,6 +594,8 @@ int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out) {
     out->workspace_bytes = static_cast<double>(c->ws_bytes);
     out->last_ms = c->last_ms;
     out->launches_per_pass = static_cast<int64_t>(P.upward.size() + P.downward.size() + 1);
+    out->n_fp64_poles = ds.n_hi;
+    out->precision = c->opt.precision;
   });
 }
 

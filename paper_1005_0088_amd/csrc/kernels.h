@@ -13,6 +13,7 @@ namespace ndrho {
 struct DevOp {
   int flags = 0;
   int npoles = 1;
+  bool fp32 = false;  // GEMM products on the FP32 matrix cores
   int64_t count = 0, tile_count = 0;
   const GemmProb* gemm = nullptr;
   const TileRef* gemm_tiles = nullptr;

@@ -12,6 +12,12 @@ namespace ndrho {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Row of the 16x16 accumulator held in register r by `lane` (columns are
+// lane % 16), as measured on gfx950: f64 16x16x4 interleaves the rows
+// (4r + lane/16), f32 16x16x4 keeps them in blocks of four (4 (lane/16) + r).
+#define F64_DROW(r, lane) (4 * (r) + ((lane) >> 4))
+#define F32_DROW(r, lane) (4 * ((lane) >> 4) + (r))
+
 // ----------------------------------------------------------------- helpers
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -327,10 +333,147 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm * 32 + i * 16 + (lane & 15);
-        const int n = n0 + wn * 32 + j * 16 + 4 * r + (lane >> 4);
+        const int n = n0 + wn * 32 + j * 16 + F64_DROW(r, lane);
         if (m >= M || n >= N) continue;
         if (SYM && m < n) continue;
         double2 v = make_double2(p1[i][j][r] - p2[i][j][r], p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
+        if (NEG) v = make_double2(-v.x, -v.y);
+        if (BETA) {
+          const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
+          v.x += c0.x;
+          v.y += c0.y;
+        }
+        Cp[m + int64_t(n) * pr.ldc] = v;
+        if (SYM && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+      }
+}
+
+// Same contraction with the products on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32) and FP32 accumulation: FP64 operands are rounded
+// to FP32 when staged into LDS, the four real products of each complex one
+// are accumulated in FP32, and the result is formed in FP64 (scaled, added
+// to C0 in FP64, stored as complex128).  Used for the front updates of poles
+// away from the real axis.
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int FLAGS>
+__global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__ probs,
+                                                    const TileRef* __restrict__ tiles, int64_t ntiles,
+                                                    int64_t npoles, const double2* __restrict__ A, int64_t sA,
+                                                    const double2* __restrict__ B, int64_t sB, const double2* C0,
+                                                    int64_t sC0, double2* C, int64_t sC) {
+  constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  __shared__ float2 As[2][BK][BM + 1];
+  __shared__ float2 Bs[2][BK][BN + 1];
+
+  const int64_t total = ntiles * npoles;
+  const int64_t logical = xcd_remap(blockIdx.x, total);
+  const int64_t pole = logical / ntiles;
+  const TileRef tr = tiles[logical % ntiles];
+  const GemmProb pr = probs[tr.prob];
+  const double2* Ap = A + pole * sA + pr.a_off;
+  const double2* Bp = B + pole * sB + pr.b_off;
+  const int M = pr.m, N = pr.n, K = pr.k;
+  const int m0 = tr.tm * BM, n0 = tr.tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  f4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      cim[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  double2 ra[4], rb[4];
+  const double2 zero = make_double2(0.0, 0.0);
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!TA) {
+        const int m = tid & 63, k = (tid >> 6) + 4 * i;
+        const int gm = m0 + m, gk = k0 + k;
+        ra[i] = (gm < M && gk < K) ? Ap[gm + int64_t(gk) * pr.lda] : zero;
+      } else {
+        const int k = tid & 15, m = (tid >> 4) + 16 * i;
+        const int gm = m0 + m, gk = k0 + k;
+        ra[i] = (gm < M && gk < K) ? Ap[gk + int64_t(gm) * pr.lda] : zero;
+      }
+      if (!TB) {
+        const int k = tid & 15, n = (tid >> 4) + 16 * i;
+        const int gn = n0 + n, gk = k0 + k;
+        rb[i] = (gn < N && gk < K) ? Bp[gk + int64_t(gn) * pr.ldb] : zero;
+      } else {
+        const int n = tid & 63, k = (tid >> 6) + 4 * i;
+        const int gn = n0 + n, gk = k0 + k;
+        rb[i] = (gn < N && gk < K) ? Bp[gn + int64_t(gk) * pr.ldb] : zero;
+      }
+    }
+  };
+  auto f2 = [](double2 v) { return make_float2(static_cast<float>(v.x), static_cast<float>(v.y)); };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!TA) As[buf][(tid >> 6) + 4 * i][tid & 63] = f2(ra[i]);
+      else As[buf][tid & 15][(tid >> 4) + 16 * i] = f2(ra[i]);
+      if (!TB) Bs[buf][tid & 15][(tid >> 4) + 16 * i] = f2(rb[i]);
+      else Bs[buf][(tid >> 6) + 4 * i][tid & 63] = f2(rb[i]);
+    }
+  };
+
+  const int nk = (K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      float2 av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[i] = As[cur][kr][wm * 32 + i * 16 + (lane & 15)];
+        bv[i] = Bs[cur][kr][wn * 32 + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j].x, av[i].x, cre[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j].x, av[i].y, cim[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-bv[j].y, av[i].y, cre[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j].y, av[i].x, cim[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
+  double2* Cp = C + pole * sC + pr.c_off;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 32 + i * 16 + (lane & 15);
+        const int n = n0 + wn * 32 + j * 16 + F32_DROW(r, lane);
+        if (m >= M || n >= N) continue;
+        if (SYM && m < n) continue;
+        double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
         if (NEG) v = make_double2(-v.x, -v.y);
         if (BETA) {
           const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
@@ -478,8 +621,25 @@ static void gemm_inst(const DevOp& o, hipStream_t st) {
                      o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
 }
 
+template <int F>
+static void gemm32_inst(const DevOp& o, hipStream_t st) {
+  const int64_t total = o.tile_count * o.npoles;
+  hipLaunchKernelGGL(k_cgemm32<F>, dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
+                     o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
+}
+
 hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
   if (o.tile_count == 0) return hipSuccess;
+  if (o.fp32) {
+    switch (o.flags) {
+      case 0: gemm32_inst<0>(o, st); break;
+      case G_NEG: gemm32_inst<G_NEG>(o, st); break;
+      case G_TB | G_SYM | G_BETA | G_NEG: gemm32_inst<G_TB | G_SYM | G_BETA | G_NEG>(o, st); break;
+      case G_TA | G_SYM | G_BETA | G_NEG: gemm32_inst<G_TA | G_SYM | G_BETA | G_NEG>(o, st); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (o.flags) {
     case 0: gemm_inst<0>(o, st); break;
     case G_NEG: gemm_inst<G_NEG>(o, st); break;

@@ -287,7 +287,7 @@ struct Builder {
       const int tm = (g.m + 63) / 64, tn = (g.n + 63) / 64;
       for (int a = 0; a < tm; ++a)
         for (int b = 0; b < tn; ++b) {
-          if ((flags & G_SYM) && b > a) continue;
+          if ((flags & G_SYM) && b > a) continue;  // lower tiles only
           P.gemm_tiles.push_back(TileRef{static_cast<int32_t>(i), a, b, 0});
         }
       if (flags & G_SYM) fl += 8.0 * g.k * (double(g.n) * (g.n + 1) / 2);
@@ -371,11 +371,11 @@ struct Builder {
       // A12 <- G21^T
       ct.push_back(CopyDesc{at(F, r0 + n1, r0), at(F, r0, r0 + n1), ld, ld, n1, n2});
     }
-    gemm(prog, 0, BUF_PANEL, BUF_PANEL, 0, BUF_TEMP, ga, depth);
-    gemm(prog, G_TB | G_SYM | G_BETA | G_NEG, BUF_TEMP, BUF_PANEL, BUF_PANEL, BUF_PANEL, gb, depth);
+    gemm(prog, OP_PIVOT, BUF_PANEL, BUF_PANEL, 0, BUF_TEMP, ga, depth);
+    gemm(prog, OP_PIVOT | G_TB | G_SYM | G_BETA | G_NEG, BUF_TEMP, BUF_PANEL, BUF_PANEL, BUF_PANEL, gb, depth);
     inverse(prog, grp, n2, r0 + n1, tstack + int64_t(n2) * n1, depth);
-    gemm(prog, G_NEG, BUF_PANEL, BUF_TEMP, 0, BUF_PANEL, gc, depth);
-    gemm(prog, G_TA | G_SYM | G_BETA | G_NEG, BUF_TEMP, BUF_PANEL, BUF_PANEL, BUF_PANEL, gd, depth);
+    gemm(prog, OP_PIVOT | G_NEG, BUF_PANEL, BUF_TEMP, 0, BUF_PANEL, gc, depth);
+    gemm(prog, OP_PIVOT | G_TA | G_SYM | G_BETA | G_NEG, BUF_TEMP, BUF_PANEL, BUF_PANEL, BUF_PANEL, gd, depth);
     copy(prog, true, BUF_PANEL, BUF_PANEL, ct, depth);
   }
 };

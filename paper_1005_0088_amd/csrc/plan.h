@@ -78,6 +78,9 @@ enum BufId { BUF_PANEL = 0, BUF_UPD0 = 1, BUF_UPD1 = 2, BUF_TEMP = 3, BUF_COUNT 
 enum OpKind { OP_EXTADD, OP_ASSEMBLE, OP_SMALLINV, OP_GEMM, OP_COPY, OP_GATHER };
 
 enum GemmFlags { G_TA = 1, G_TB = 2, G_SYM = 4, G_BETA = 8, G_NEG = 16 };
+// Op-level marker (not a kernel flag): the GEMM belongs to a pivot-block
+// inverse and always runs in FP64.
+constexpr int OP_PIVOT = 1 << 8;
 
 struct Op {
   OpKind kind;

@@ -199,3 +199,39 @@ def test_errors(ctx):
         ctx.set_shifts(sid2, np.array([1.0 + 0.0j]), np.array([1.0]), add_m0=False)
         ctx.density_matrix(sid2)
     assert e.value.name == "ESINGULAR"
+
+
+# ------------------------------------------------------------- precision form
+
+def test_mixed_fp32_single_shift_close_to_dense():
+    # FP32 products with FP32 accumulation: relative error of G well below 1e-5
+    import paper_1005_0088_amd as nd
+    sysd = lattice((7, 6, 5), "nn", 14)
+    h, s, rows, cols = _dense(sysd)
+    with nd.Context(0, precision="mixed_fp32", fp64_poles=0, fp64_pole_im=0.0) as c:
+        sid = _register(c, sysd)
+        c.set_shifts(sid, np.array([0.2 + 0.5j]), np.array([1.0]), add_m0=False)
+        got = c.density_matrix(sid)
+        assert c.stats(sid)["n_fp64_poles"] == 0
+    g = dense.green_dense(h, s, 0.2 + 0.5j)
+    err = np.max(np.abs(got - g[rows, cols].real)) / np.abs(g).max()
+    assert 1e-12 < err < 1e-5          # the FP32 path really ran, and is FP32-accurate
+
+
+@pytest.mark.parametrize("dims,nb,fp64_poles,tol", [((9, 9, 9), "nn", 8, 1e-7), ((9, 9, 9), "nn", 0, 1e-6),
+                                                    ((20, 18), "nn2", 8, 1e-7)])
+def test_mixed_rho_against_oracle(dims, nb, fp64_poles, tol):
+    import paper_1005_0088_amd as nd
+    sysd = lattice(dims, nb, 15)
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    mu = dense.mu_for_count(eps, BETA, float(sysd["n"]))
+    ref = dense.rho_cf_pattern(eps, c, mu, BETA, 80, rows, cols)
+    with nd.Context(0, precision="mixed_fp32", fp64_poles=fp64_poles, fp64_pole_im=0.05) as cx:
+        sid = _register(cx, sysd)
+        cx.set_poles(sid, mu, BETA, 80)
+        got = cx.density_matrix(sid)
+        assert cx.stats(sid)["n_fp64_poles"] == fp64_poles
+    err = np.max(np.abs(got - ref))
+    print("mixed fp64_poles=%d err=%.3e" % (fp64_poles, err))
+    assert err < tol
