@@ -194,8 +194,11 @@ struct ndrho_ctx {
   }
 
   // One pass of the whole program over `nb` poles.
+  // One pass of the whole program over `nb` poles; the first `nhi` of them
+  // take FP64 front updates, the rest the context's low precision (pivot
+  // inverses are FP64 for all).
   void run_pass(DevStruct& S, int nb, const double2* alpha, const double* w, double hcoef, int spd_check,
-                bool low) {
+                int nhi) {
     const Plan& P = S.plan;
     double2* base = static_cast<double2*>(ws);
     double2* bufs[BUF_COUNT];
@@ -211,7 +214,6 @@ struct ndrho_ctx {
     auto resolve = [&](const Op& op) {
       DevOp d;
       d.flags = op.flags & 0xff;
-      d.fp32 = low && !(op.flags & OP_PIVOT);
       d.npoles = nb;
       d.count = op.count;
       d.tile_count = op.tile_count;
@@ -241,11 +243,28 @@ struct ndrho_ctx {
           d.inv = S.inv + op.begin;
           timed(NDRHO_K_PIVOT_INV, 0.0, [&] { e = launch_smallinv(d, status, spd_check, stream); });
           break;
-        case OP_GEMM:
+        case OP_GEMM: {
           d.gemm = S.gemm + op.begin;
           d.gemm_tiles = S.gemm_tiles + op.tile_begin;
-          timed(NDRHO_K_GEMM, op.flops * nb, [&] { e = launch_gemm(d, stream); });
+          const bool split = !(op.flags & OP_PIVOT) && nhi < nb;
+          if (!split) {
+            timed(NDRHO_K_GEMM, op.flops * nb, [&] { e = launch_gemm(d, stream); });
+            break;
+          }
+          if (nhi > 0) {  // FP64 for the poles nearest the real axis
+            DevOp h = d;
+            h.npoles = nhi;
+            timed(NDRHO_K_GEMM, op.flops * nhi, [&] { e = launch_gemm(h, stream); });
+            if (e != hipSuccess) break;
+          }
+          DevOp l = d;  // FP32 products for the others
+          l.fp32 = true;
+          l.npoles = nb - nhi;
+          l.a += nhi * l.sa, l.b += nhi * l.sb, l.c += nhi * l.sc;
+          if (op.flags & G_BETA) l.c0 += nhi * l.sc0;
+          timed(NDRHO_K_GEMM, op.flops * (nb - nhi), [&] { e = launch_gemm(l, stream); });
           break;
+        }
         case OP_COPY:
           d.copy = S.copy + op.begin;
           d.copy_tiles = S.copy_tiles + op.tile_begin;
@@ -278,11 +297,10 @@ struct ndrho_ctx {
     ensure_ws(P, nb);
     last_batch = nb;
     HIP_OK(launch_init_acc(S.m0, P.nnz, add_m0 ? 1 : 0, acc, status, stream));
-    for (int p0 = 0; p0 < n;) {
-      const bool low = p0 >= n_hi;
-      const int cnt = std::min(nb, (low ? n : n_hi) - p0);
-      run_pass(S, cnt, alpha + p0, w + p0, hcoef, spd_check, low);
-      p0 += cnt;
+    for (int p0 = 0; p0 < n; p0 += nb) {
+      const int cnt = std::min(nb, n - p0);
+      const int nhi = std::max(0, std::min(cnt, n_hi - p0));
+      run_pass(S, cnt, alpha + p0, w + p0, hcoef, spd_check, nhi);
     }
   }
 

@@ -57,24 +57,26 @@ __global__ __launch_bounds__(256) void k_extadd(const ExtAddDesc* __restrict__ d
   const int64_t pole = blockIdx.y;
   const ElemTile t = tiles[blockIdx.x];
   const ExtAddDesc d = descs[t.desc];
-  const int64_t ld = d.nj + d.nu;
-  const int64_t tp = ld * d.nj;
-  const int64_t total = tp + int64_t(d.nu) * d.nu;
+  // per-front element counts stay far below 2^31: 32-bit index arithmetic
+  const uint32_t ld = d.nj + d.nu;
+  const uint32_t tp = ld * d.nj;
+  const uint32_t total = tp + uint32_t(d.nu) * d.nu;
   double2* pan = panel + pole * ps + d.panel_off;
   double2* own = upd + pole * us + d.upd_off;
   const double2* cu = cupd + pole * cs;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t e = t.e0 + threadIdx.x + 256 * i;
+    const uint32_t e = uint32_t(t.e0) + threadIdx.x + 256 * i;
     if (e >= total) break;
-    int64_t r, s;
+    uint32_t r, s;
     if (e < tp) {
-      r = e % ld;
       s = e / ld;
+      r = e - s * ld;
     } else {
-      const int64_t e2 = e - tp;
-      r = d.nj + e2 % d.nu;
-      s = d.nj + e2 / d.nu;
+      const uint32_t e2 = e - tp;
+      const uint32_t q = e2 / d.nu;
+      r = d.nj + (e2 - q * d.nu);
+      s = d.nj + q;
     }
     double2 sum = make_double2(0.0, 0.0);
     for (int c = 0; c < d.child_count; ++c) {
@@ -87,8 +89,8 @@ __global__ __launch_bounds__(256) void k_extadd(const ExtAddDesc* __restrict__ d
         sum.y += v.y;
       }
     }
-    if (e < tp) pan[r + s * ld] = sum;
-    else own[(r - d.nj) + (s - d.nj) * d.nu] = sum;
+    if (e < tp) pan[r + int64_t(s) * ld] = sum;
+    else own[(r - d.nj) + int64_t(s - d.nj) * d.nu] = sum;
   }
 }
 
@@ -537,7 +539,7 @@ __global__ __launch_bounds__(256) void k_gather(const GatherDesc* __restrict__ d
   const int64_t pole = blockIdx.y;
   const ElemTile t = tiles[blockIdx.x];
   const GatherDesc d = descs[t.desc];
-  const int64_t total = int64_t(d.nu) * d.nu;
+  const uint32_t total = uint32_t(d.nu) * d.nu;
   const int32_t* rl = rel + d.rel_off;
   const double2* pan = panel + pole * ps + d.ppanel_off;
   const double2* pg = pguu + pole * gs + d.pguu_off;
@@ -545,9 +547,9 @@ __global__ __launch_bounds__(256) void k_gather(const GatherDesc* __restrict__ d
   const int64_t pld = d.pnj + d.pnu;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t e = t.e0 + threadIdx.x + 256 * i;
+    const uint32_t e = uint32_t(t.e0) + threadIdx.x + 256 * i;
     if (e >= total) break;
-    const int a = static_cast<int>(e % d.nu), b = static_cast<int>(e / d.nu);
+    const uint32_t b = e / uint32_t(d.nu), a = e - b * uint32_t(d.nu);
     const int r = rl[a], s = rl[b];
     double2 v;
     if (s < d.pnj) v = pan[r + int64_t(s) * pld];

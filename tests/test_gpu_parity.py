@@ -235,3 +235,40 @@ def test_mixed_rho_against_oracle(dims, nb, fp64_poles, tol):
     err = np.max(np.abs(got - ref))
     print("mixed fp64_poles=%d err=%.3e" % (fp64_poles, err))
     assert err < tol
+
+
+# ------------------------------------------------------------- full-size sampled parity
+
+def _golden(name):
+    path = os.path.join(GOLDEN, "rho_sampled_%s.json" % name)
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle sample for %s" % name)
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name,precision,tol", [("cubic3d_24x4", "fp64", 1e-10), ("cubic3d_24x4", "mixed_fp32", 1e-7),
+                                                ("square2d_64x4", "fp64", 1e-10), ("square2d_64x4", "mixed_fp32", 1e-7)])
+def test_full_size_against_oracle_sample(name, precision, tol):
+    # the configuration the benchmark times, in the same launch configuration
+    import paper_1005_0088_amd as nd
+    from synth import config_system
+    g = _golden(name)
+    sysd = config_system(name)
+    with nd.Context(0, precision=precision) as c:
+        sid = _register(c, sysd)
+        c.set_poles(sid, g["mu"], g["beta"], g["n_poles"])
+        out = c.device_buffer(int(sysd["row_ptr"][-1]))
+        c.density_matrix(sid, out)
+        rho = out.numpy()
+        out.free()
+    err = np.max(np.abs(rho[np.asarray(g["entries"])] - np.asarray(g["values"])))
+    print("%s %s max err on %d sampled entries: %.3e" % (name, precision, len(g["entries"]), err))
+    assert err < tol
+    # properties at any size: symmetry of rho on the pattern
+    rows = np.repeat(np.arange(sysd["n"]), np.diff(sysd["row_ptr"]))
+    key = rows.astype(np.int64) * sysd["n"] + sysd["col"]
+    tkey = sysd["col"].astype(np.int64) * sysd["n"] + rows
+    order = np.argsort(key)
+    pos = order[np.searchsorted(key[order], tkey)]
+    assert np.max(np.abs(rho - rho[pos])) < tol
