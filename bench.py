@@ -55,6 +55,23 @@ def cpu_baseline(sysd, mu, beta, n_poles, budget_s=15.0):
                       "%.3f s per column; scaled by N=%d columns per pole" % (cols, dt, sysd["n"])}
 
 
+def measured_traffic(name, precision):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (calibrated FETCH_SIZE + WRITE_SIZE), or None when it is missing
+    or the kernels have changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (name, "mixed" if precision != "fp64" else "fp64"))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    with open(os.path.join(ROOT, "paper_1005_0088_amd", "csrc", "kernels.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if sha != t["kernels_hip_sha256_16"]:
+        return None
+    return t["read_bytes_per_launch"] + t["write_bytes_per_launch"]
+
+
 def golden_error(name, rho, mu, n_poles):
     path = os.path.join(ROOT, "tests", "golden", "rho_sampled_%s.json" % name)
     if not os.path.exists(path):
@@ -106,6 +123,10 @@ def main():
     ap.add_argument("--workload", default="cubic3d_24x4", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="mixed_fp32", choices=["mixed_fp32", "fp64"])
     ap.add_argument("--fp64-poles", type=int, default=8)
+    ap.add_argument("--forms", default="both", choices=["both", "head"],
+                    help="both: also time the FP64 form as the complex128 reference; head: only --precision")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run the plain copy kernel over GIB gibibytes (HBM counter calibration) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -117,6 +138,20 @@ def main():
     import paper_1005_0088_amd as nd
     from synth import BETA, CONFIGS, config_system
 
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 8
+        with nd.Context(0) as ctx:
+            a, b = ctx.device_buffer(n), ctx.device_buffer(n)
+            for _ in range(3):
+                t0 = time.perf_counter()
+                b.copy_from(a)
+                dt = time.perf_counter() - t0
+            print(json.dumps({"copy_bytes": 8 * n, "read_bytes": 8 * n, "write_bytes": 8 * n,
+                              "launches": 3, "GBs_read_plus_write": 2 * 8 * n / dt / 1e9}))
+            a.free()
+            b.free()
+        return
+
     name = args.workload
     n_poles = CONFIGS[name]["n_poles"]
     mu = 0.0
@@ -124,17 +159,24 @@ def main():
     n, nnz = sysd["n"], int(sysd["row_ptr"][-1])
     print("bench: %s n=%d nnz=%d poles=%d" % (name, n, nnz, n_poles), file=sys.stderr, flush=True)
 
-    # the plain FP64 form always runs: it is the complex128 reference of the error
-    r64, rho64 = run_form(nd, sysd, mu, BETA, n_poles, args.steps, args.warmup, "fp64", 0)
+    # the plain FP64 form is the complex128 reference of the error
+    r64 = rho64 = None
+    if args.forms == "both" or args.precision == "fp64":
+        r64, rho64 = run_form(nd, sysd, mu, BETA, n_poles, args.steps, args.warmup, "fp64", 0)
     if args.precision == "fp64":
         head, rho = r64, rho64
     else:
         head, rho = run_form(nd, sysd, mu, BETA, n_poles, args.steps, args.warmup, args.precision, args.fp64_poles)
     st, prof = head["stats"], head["prof"]
-    g = prof["gemm"]
+    # dominant kernel: the FP64 front GEMMs in the FP64 form, the FP32-product
+    # front GEMMs in the mixed form (peak of their own arithmetic)
+    if head["precision"] == "fp64":
+        g, peak, kname = prof["gemm"], FP64_MFMA_PEAK_TFLOPS, "k_zgemm (complex FP64 front-update GEMMs)"
+    else:
+        g, peak, kname = prof["gemm_f32"], FP32_MFMA_PEAK_TFLOPS, "k_cgemm32 (complex front-update GEMMs, FP32 products)"
     achieved = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
-    # the FP32 matrix-core GEMMs dominate the mixed form; their peak is the FP32 one
-    peak = FP64_MFMA_PEAK_TFLOPS if head["precision"] == "fp64" else FP32_MFMA_PEAK_TFLOPS
+    gemm_tf = {k: (v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0)
+               for k, v in prof.items() if k.startswith("gemm")}
 
     line = {
         "metric": "poles/sec (selected inversion) on 3D 24^3x4 at 1e-7 rho error; MFMA TFLOP/s",
@@ -154,15 +196,19 @@ def main():
                    "fp64_poles": st["n_fp64_poles"], "fronts": st["n_fronts"], "levels": st["n_levels"],
                    "root_j": st["root_j"], "pole_batch": st["pole_batch"]},
         "tflops_model": st["flops_per_pole"] * n_poles / (head["ms_per_step"] * 1e-3) / 1e12,
-        "max_abs_err_vs_complex128": float(np.max(np.abs(rho - rho64))),
+        "max_abs_err_vs_complex128": float(np.max(np.abs(rho - rho64))) if rho64 is not None else None,
         "max_abs_err_vs_oracle_sample": golden_error(name, rho, mu, n_poles),
-        "fp64_form": {"poles_per_s": r64["poles_per_s"], "ms_per_step": r64["ms_per_step"],
-                      "gemm_tflops": r64["prof"]["gemm"]["flops"] / (r64["prof"]["gemm"]["ms"] * 1e-3) / 1e12,
-                      "max_abs_err_vs_oracle_sample": golden_error(name, rho64, mu, n_poles)},
+        "fp64_form": None if r64 is None else {
+            "poles_per_s": r64["poles_per_s"], "ms_per_step": r64["ms_per_step"],
+            "gemm_tflops": r64["prof"]["gemm"]["flops"] / (r64["prof"]["gemm"]["ms"] * 1e-3) / 1e12,
+            "kernel_ms": {k: round(v["ms"], 3) for k, v in r64["prof"].items()},
+            "max_abs_err_vs_oracle_sample": golden_error(name, rho64, mu, n_poles)},
         "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
-        "roofline": {"kernel": "k_zgemm/k_cgemm32 (complex front GEMMs, all variants)", "bound": "mfma",
+        "gemm_tflops": gemm_tf,
+        "roofline": {"kernel": kname, "bound": "mfma",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(name, head["precision"]),
+                     "traffic_unit": "bytes per launch (calibrated HBM read + write)",
                      "launches": g["launches"], "avg_launch_ms": g["ms"] / max(1, g["launches"]),
                      "flops_per_step": g["flops"]},
     }

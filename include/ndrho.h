@@ -146,7 +146,9 @@ int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out);
 
 /* Kernel kinds reported by the profile below. */
 enum { NDRHO_K_EXTADD = 0, NDRHO_K_ASSEMBLE = 1, NDRHO_K_PIVOT_INV = 2, NDRHO_K_GEMM = 3, NDRHO_K_COPY = 4,
-       NDRHO_K_GATHER = 5, NDRHO_K_ACCUM = 6, NDRHO_K_COUNT = 7 };
+       NDRHO_K_GATHER = 5, NDRHO_K_ACCUM = 6, NDRHO_K_GEMM_PIVOT = 7, NDRHO_K_GEMM_F32 = 8, NDRHO_K_COUNT = 9 };
+/* NDRHO_K_GEMM: FP64 front-update GEMMs; NDRHO_K_GEMM_PIVOT: FP64 GEMMs of the
+ * recursive pivot-block inverse; NDRHO_K_GEMM_F32: FP32-product front updates. */
 
 /* enable != 0: from now on every launch is bracketed by HIP events on the
  * context stream and its duration is added to a per-kind total (clears the
@@ -166,6 +168,10 @@ int ndrho_profile_read(const ndrho_ctx* ctx, double* ms, double* flops, int64_t*
 int ndrho_device_alloc(ndrho_ctx* ctx, int64_t bytes, void** ptr);
 int ndrho_device_free(ndrho_ctx* ctx, void* ptr);
 int ndrho_device_to_host(ndrho_ctx* ctx, void* dst, const void* src, int64_t bytes);
+/* Plain device-to-device copy kernel of `bytes` (a multiple of 16) on the
+ * context stream, synchronised; also the reference for calibrating the HBM
+ * byte counters of a profiler (it reads and writes exactly `bytes`). */
+int ndrho_device_copy(ndrho_ctx* ctx, void* dst, const void* src, int64_t bytes);
 
 /* ---------------- host-only utilities (no device needed) ---------------- */
 

@@ -60,6 +60,7 @@ SIGNATURES = [
     ("ndrho_device_alloc", C.c_int, [_P, C.c_int64, C.POINTER(_P)]),
     ("ndrho_device_free", C.c_int, [_P, _P]),
     ("ndrho_device_to_host", C.c_int, [_P, _P, _P, C.c_int64]),
+    ("ndrho_device_copy", C.c_int, [_P, _P, _P, C.c_int64]),
     ("ndrho_cf_poles", C.c_int, [C.c_int32, _DP, _DP]),
     ("ndrho_plan_create", C.c_int, [C.c_int64, _I64P, _I32P, _DP, C.c_int32, C.POINTER(_P)]),
     ("ndrho_plan_destroy", C.c_int, [_P]),
@@ -197,6 +198,13 @@ class DeviceBuffer:
                                                            C.c_void_p(self.ptr), 8 * self.n))
         return out
 
+    def copy_from(self, other):
+        """Device-to-device copy of another buffer of the same size (plain copy kernel)."""
+        if other.n != self.n:
+            raise ValueError("size mismatch")
+        self.ctx._check(self.ctx._lib.ndrho_device_copy(self.ctx._h, C.c_void_p(self.ptr), C.c_void_p(other.ptr),
+                                                        8 * self.n))
+
     def free(self):
         if self.ptr and self.ctx._h:
             self.ctx._lib.ndrho_device_free(self.ctx._h, C.c_void_p(self.ptr))
@@ -297,7 +305,7 @@ class Context:
         self._check(self._lib.ndrho_stats(self._h, int(sid), C.byref(st)))
         return {k: getattr(st, k) for k, _ in Stats._fields_}
 
-    KINDS = ("extadd", "assemble", "pivot_inv", "gemm", "copy", "gather", "accum")
+    KINDS = ("extadd", "assemble", "pivot_inv", "gemm", "copy", "gather", "accum", "gemm_pivot", "gemm_f32")
 
     def profile(self, enable=True):
         self._check(self._lib.ndrho_profile(self._h, int(bool(enable))))

@@ -247,22 +247,25 @@ struct ndrho_ctx {
           d.gemm = S.gemm + op.begin;
           d.gemm_tiles = S.gemm_tiles + op.tile_begin;
           const bool split = !(op.flags & OP_PIVOT) && nhi < nb;
+          const int k64 = (op.flags & OP_PIVOT) ? NDRHO_K_GEMM_PIVOT : NDRHO_K_GEMM;
           if (!split) {
-            timed(NDRHO_K_GEMM, op.flops * nb, [&] { e = launch_gemm(d, stream); });
+            timed(k64, op.flops * nb, [&] { e = launch_gemm(d, stream); });
             break;
           }
           if (nhi > 0) {  // FP64 for the poles nearest the real axis
             DevOp h = d;
             h.npoles = nhi;
-            timed(NDRHO_K_GEMM, op.flops * nhi, [&] { e = launch_gemm(h, stream); });
+            timed(k64, op.flops * nhi, [&] { e = launch_gemm(h, stream); });
             if (e != hipSuccess) break;
           }
-          DevOp l = d;  // FP32 products for the others
+          DevOp l = d;  // FP32 products for the others, on 128x128 tiles
           l.fp32 = true;
+          l.gemm_tiles = S.gemm_tiles + op.tile128_begin;
+          l.tile_count = op.tile128_count;
           l.npoles = nb - nhi;
           l.a += nhi * l.sa, l.b += nhi * l.sb, l.c += nhi * l.sc;
           if (op.flags & G_BETA) l.c0 += nhi * l.sc0;
-          timed(NDRHO_K_GEMM, op.flops * (nb - nhi), [&] { e = launch_gemm(l, stream); });
+          timed(NDRHO_K_GEMM_F32, op.flops * (nb - nhi), [&] { e = launch_gemm(l, stream); });
           break;
         }
         case OP_COPY:
@@ -667,6 +670,16 @@ int ndrho_device_to_host(ndrho_ctx* ctx, void* dst, const void* src, int64_t byt
     if (!dst || !src || bytes < 0) fail(NDRHO_EINVAL, "invalid copy arguments");
     HIP_OK(hipSetDevice(ctx->device));
     HIP_OK(hipMemcpyAsync(dst, src, static_cast<size_t>(bytes), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+int ndrho_device_copy(ndrho_ctx* ctx, void* dst, const void* src, int64_t bytes) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    if (!dst || !src || bytes < 0 || bytes % 16) fail(NDRHO_EINVAL, "invalid copy arguments");
+    HIP_OK(hipSetDevice(ctx->device));
+    HIP_OK(launch_stream_copy(src, dst, bytes, ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));
   });
 }

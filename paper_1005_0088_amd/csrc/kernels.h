@@ -42,6 +42,7 @@ hipError_t launch_gather(const DevOp& o, hipStream_t st);
 hipError_t launch_accum(const int64_t* slot, int64_t count, const double2* panel, int64_t ps, const double* w,
                         int npoles, double* acc, hipStream_t st);
 hipError_t launch_init_acc(const double* m0, int64_t count, int add_m0, double* acc, int* status, hipStream_t st);
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
 hipError_t launch_scatter(const int32_t* entry, int64_t count, const double* acc, double* out, hipStream_t st);
 
 }  // namespace ndrho

@@ -4,6 +4,7 @@
 // every per-pole buffer is laid out as [pole][elements] with a pole stride.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -252,48 +253,56 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
       p3[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
-  double2 ra[4], rb[4];
-  const double2 zero = make_double2(0.0, 0.0);
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (!TA) {
-        const int m = tid & 63, k = (tid >> 6) + 4 * i;
-        const int gm = m0 + m, gk = k0 + k;
-        ra[i] = (gm < M && gk < K) ? Ap[gm + int64_t(gk) * pr.lda] : zero;
-      } else {
-        const int k = tid & 15, m = (tid >> 4) + 16 * i;
-        const int gm = m0 + m, gk = k0 + k;
-        ra[i] = (gm < M && gk < K) ? Ap[gk + int64_t(gm) * pr.lda] : zero;
-      }
-      if (!TB) {
-        const int k = tid & 15, n = (tid >> 4) + 16 * i;
-        const int gn = n0 + n, gk = k0 + k;
-        rb[i] = (gn < N && gk < K) ? Bp[gk + int64_t(gn) * pr.ldb] : zero;
-      } else {
-        const int n = tid & 63, k = (tid >> 6) + 4 * i;
-        const int gn = n0 + n, gk = k0 + k;
-        rb[i] = (gn < N && gk < K) ? Bp[gn + int64_t(gk) * pr.ldb] : zero;
-      }
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (!TA) As[buf][(tid >> 6) + 4 * i][tid & 63] = ra[i];
-      else As[buf][tid & 15][(tid >> 4) + 16 * i] = ra[i];
-      if (!TB) Bs[buf][tid & 15][(tid >> 4) + 16 * i] = rb[i];
-      else Bs[buf][(tid >> 6) + 4 * i][tid & 63] = rb[i];
-    }
-  };
+  double2 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+  // operand staging without local arrays (arrays captured by a lambda end up
+  // in scratch memory); element i of this thread's share of a 64x16 stage
+#define ZG_LDA(i, k0, dst)                                                             \
+  do {                                                                                 \
+    const int m_ = TA ? (tid >> 4) + 16 * (i) : (tid & 63);                           \
+    const int k_ = TA ? (tid & 15) : (tid >> 6) + 4 * (i);                            \
+    const int gm = m0 + m_, gk = (k0) + k_;                                            \
+    dst = (gm < M && gk < K) ? (TA ? Ap[gk + int64_t(gm) * pr.lda] : Ap[gm + int64_t(gk) * pr.lda]) : make_double2(0.0, 0.0); \
+  } while (0)
+#define ZG_LDB(i, k0, dst)                                                             \
+  do {                                                                                 \
+    const int n_ = TB ? (tid & 63) : (tid >> 4) + 16 * (i);                           \
+    const int k_ = TB ? (tid >> 6) + 4 * (i) : (tid & 15);                            \
+    const int gn = n0 + n_, gk = (k0) + k_;                                            \
+    dst = (gn < N && gk < K) ? (TB ? Bp[gn + int64_t(gk) * pr.ldb] : Bp[gk + int64_t(gn) * pr.ldb]) : make_double2(0.0, 0.0); \
+  } while (0)
+#define ZG_STA(buf, i, v) As[buf][TA ? (tid & 15) : (tid >> 6) + 4 * (i)][TA ? (tid >> 4) + 16 * (i) : (tid & 63)] = (v)
+#define ZG_STB(buf, i, v) Bs[buf][TB ? (tid >> 6) + 4 * (i) : (tid & 15)][TB ? (tid & 63) : (tid >> 4) + 16 * (i)] = (v)
+#define ZG_LOAD(k0)          \
+  do {                       \
+    ZG_LDA(0, k0, ra0);      \
+    ZG_LDA(1, k0, ra1);      \
+    ZG_LDA(2, k0, ra2);      \
+    ZG_LDA(3, k0, ra3);      \
+    ZG_LDB(0, k0, rb0);      \
+    ZG_LDB(1, k0, rb1);      \
+    ZG_LDB(2, k0, rb2);      \
+    ZG_LDB(3, k0, rb3);      \
+  } while (0)
+#define ZG_STORE(buf, CV)                                                                            \
+  do {                                                                                               \
+    ZG_STA(buf, 0, CV(ra0));                                                                         \
+    ZG_STA(buf, 1, CV(ra1));                                                                         \
+    ZG_STA(buf, 2, CV(ra2));                                                                         \
+    ZG_STA(buf, 3, CV(ra3));                                                                         \
+    ZG_STB(buf, 0, CV(rb0));                                                                         \
+    ZG_STB(buf, 1, CV(rb1));                                                                         \
+    ZG_STB(buf, 2, CV(rb2));                                                                         \
+    ZG_STB(buf, 3, CV(rb3));                                                                         \
+  } while (0)
+#define ZG_ID(v) (v)
 
   const int nk = (K + BK - 1) / BK;
-  load(0);
-  store(0);
+  ZG_LOAD(0);
+  ZG_STORE(0, ZG_ID);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * BK);
+    if (kt + 1 < nk) ZG_LOAD((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
@@ -322,7 +331,7 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
 #pragma unroll
         for (int j = 0; j < 2; ++j) p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bs[j], as[i], p3[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) store(cur ^ 1);
+    if (kt + 1 < nk) ZG_STORE(cur ^ 1, ZG_ID);
     __syncthreads();
   }
 
@@ -358,7 +367,10 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
 // away from the real axis.
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <int FLAGS>
+// WT x WT MFMA blocks of 16x16 per wave, 2 x 2 waves: the workgroup tile is
+// (32 WT) x (32 WT); WT = 4 gives 128 x 128 tiles (the default for this
+// kernel), WT = 2 the 64 x 64 tiles of the FP64 kernel.
+template <int FLAGS, int WT>
 __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__ probs,
                                                     const TileRef* __restrict__ tiles, int64_t ntiles,
                                                     int64_t npoles, const double2* __restrict__ A, int64_t sA,
@@ -366,8 +378,11 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
                                                     int64_t sC0, double2* C, int64_t sC) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
   constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
-  __shared__ float2 As[2][BK][BM + 1];
-  __shared__ float2 Bs[2][BK][BN + 1];
+  constexpr int TM = 32 * WT;          // workgroup tile edge
+  constexpr int NL = TM * BK / 256;    // operand elements per thread per stage
+  constexpr int RS = 256 / TM;         // k rows per pass of a non-transposed load
+  __shared__ float2 As[2][BK][TM + 1];
+  __shared__ float2 Bs[2][BK][TM + 1];
 
   const int64_t total = ntiles * npoles;
   const int64_t logical = xcd_remap(blockIdx.x, total);
@@ -377,102 +392,97 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
   const double2* Ap = A + pole * sA + pr.a_off;
   const double2* Bp = B + pole * sB + pr.b_off;
   const int M = pr.m, N = pr.n, K = pr.k;
-  const int m0 = tr.tm * BM, n0 = tr.tn * BN;
+  const int m0 = tr.tm * TM, n0 = tr.tn * TM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
-  f4 cre[2][2], cim[2][2];
+  f4 cre[WT][WT], cim[WT][WT];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < WT; ++j) {
       cre[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       cim[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     }
 
-  double2 ra[4], rb[4];
-  const double2 zero = make_double2(0.0, 0.0);
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (!TA) {
-        const int m = tid & 63, k = (tid >> 6) + 4 * i;
-        const int gm = m0 + m, gk = k0 + k;
-        ra[i] = (gm < M && gk < K) ? Ap[gm + int64_t(gk) * pr.lda] : zero;
-      } else {
-        const int k = tid & 15, m = (tid >> 4) + 16 * i;
-        const int gm = m0 + m, gk = k0 + k;
-        ra[i] = (gm < M && gk < K) ? Ap[gk + int64_t(gm) * pr.lda] : zero;
-      }
-      if (!TB) {
-        const int k = tid & 15, n = (tid >> 4) + 16 * i;
-        const int gn = n0 + n, gk = k0 + k;
-        rb[i] = (gn < N && gk < K) ? Bp[gk + int64_t(gn) * pr.ldb] : zero;
-      } else {
-        const int n = tid & 63, k = (tid >> 6) + 4 * i;
-        const int gn = n0 + n, gk = k0 + k;
-        rb[i] = (gn < N && gk < K) ? Bp[gn + int64_t(gk) * pr.ldb] : zero;
-      }
-    }
-  };
-  auto f2 = [](double2 v) { return make_float2(static_cast<float>(v.x), static_cast<float>(v.y)); };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (!TA) As[buf][(tid >> 6) + 4 * i][tid & 63] = f2(ra[i]);
-      else As[buf][tid & 15][(tid >> 4) + 16 * i] = f2(ra[i]);
-      if (!TB) Bs[buf][tid & 15][(tid >> 4) + 16 * i] = f2(rb[i]);
-      else Bs[buf][(tid >> 6) + 4 * i][tid & 63] = f2(rb[i]);
-    }
-  };
+  // operand staging: NL elements per thread, kept in named registers through
+  // a fully unrolled loop over a register array (no lambda captures, which
+  // would move the array to scratch memory)
+  double2 ra[NL], rb[NL];
+#define CG_LOAD(k0)                                                                              \
+  _Pragma("unroll") for (int i = 0; i < NL; ++i) {                                               \
+    {                                                                                            \
+      const int m_ = TA ? (tid >> 4) + 16 * i : tid % TM;                                        \
+      const int k_ = TA ? (tid & 15) : tid / TM + RS * i;                                        \
+      const int gm = m0 + m_, gk = (k0) + k_;                                                    \
+      ra[i] = (gm < M && gk < K) ? (TA ? Ap[gk + int64_t(gm) * pr.lda] : Ap[gm + int64_t(gk) * pr.lda]) : make_double2(0.0, 0.0); \
+    }                                                                                            \
+    {                                                                                            \
+      const int n_ = TB ? tid % TM : (tid >> 4) + 16 * i;                                        \
+      const int k_ = TB ? tid / TM + RS * i : (tid & 15);                                        \
+      const int gn = n0 + n_, gk = (k0) + k_;                                                    \
+      rb[i] = (gn < N && gk < K) ? (TB ? Bp[gn + int64_t(gk) * pr.ldb] : Bp[gk + int64_t(gn) * pr.ldb]) : make_double2(0.0, 0.0); \
+    }                                                                                            \
+  }
+#define CG_STORE(buf)                                                                                        \
+  _Pragma("unroll") for (int i = 0; i < NL; ++i) {                                                           \
+    As[buf][TA ? (tid & 15) : tid / TM + RS * i][TA ? (tid >> 4) + 16 * i : tid % TM] =                    \
+        make_float2(static_cast<float>(ra[i].x), static_cast<float>(ra[i].y));                               \
+    Bs[buf][TB ? tid / TM + RS * i : (tid & 15)][TB ? tid % TM : (tid >> 4) + 16 * i] =                    \
+        make_float2(static_cast<float>(rb[i].x), static_cast<float>(rb[i].y));                               \
+  }
 
   const int nk = (K + BK - 1) / BK;
-  load(0);
-  store(0);
+  CG_LOAD(0)
+  CG_STORE(0)
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * BK);
+    if (kt + 1 < nk) {
+      CG_LOAD((kt + 1) * BK)
+    }
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      float2 av[2], bv[2];
+      float2 av[WT], bv[WT];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        av[i] = As[cur][kr][wm * 32 + i * 16 + (lane & 15)];
-        bv[i] = Bs[cur][kr][wn * 32 + i * 16 + (lane & 15)];
+      for (int i = 0; i < WT; ++i) {
+        av[i] = As[cur][kr][wm * 16 * WT + i * 16 + (lane & 15)];
+        bv[i] = Bs[cur][kr][wn * 16 * WT + i * 16 + (lane & 15)];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j].x, av[i].x, cre[i][j], 0, 0, 0);
+        for (int j = 0; j < WT; ++j) cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j].x, av[i].x, cre[i][j], 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j].x, av[i].y, cim[i][j], 0, 0, 0);
+        for (int j = 0; j < WT; ++j) cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j].x, av[i].y, cim[i][j], 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-bv[j].y, av[i].y, cre[i][j], 0, 0, 0);
+        for (int j = 0; j < WT; ++j) cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-bv[j].y, av[i].y, cre[i][j], 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j].y, av[i].x, cim[i][j], 0, 0, 0);
+        for (int j = 0; j < WT; ++j) cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j].y, av[i].x, cim[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) store(cur ^ 1);
+    if (kt + 1 < nk) {
+      CG_STORE(cur ^ 1)
+    }
     __syncthreads();
   }
 
   const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WT; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 32 + i * 16 + (lane & 15);
-        const int n = n0 + wn * 32 + j * 16 + F32_DROW(r, lane);
+        const int m = m0 + wm * 16 * WT + i * 16 + (lane & 15);
+        const int n = n0 + wn * 16 * WT + j * 16 + F32_DROW(r, lane);
         if (m >= M || n >= N) continue;
         if (SYM && m < n) continue;
         double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
@@ -590,7 +600,23 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ ent
   if (k < count) out[entry[k]] = acc[k];
 }
 
+// Plain streaming copy (16-byte elements), the calibration reference for
+// HBM byte counters.
+__global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                     int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) dst[i] = src[i];
+}
+
 // ----------------------------------------------------------------- launchers
+
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t st) {
+  const int64_t n = bytes / 16;
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 256 * 64);
+  hipLaunchKernelGGL(k_stream_copy, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                     static_cast<const double2*>(src), static_cast<double2*>(dst), n);
+  return hipGetLastError();
+}
 
 static inline unsigned blocks_for(int64_t n, int per) { return static_cast<unsigned>((n + per - 1) / per); }
 
@@ -626,7 +652,7 @@ static void gemm_inst(const DevOp& o, hipStream_t st) {
 template <int F>
 static void gemm32_inst(const DevOp& o, hipStream_t st) {
   const int64_t total = o.tile_count * o.npoles;
-  hipLaunchKernelGGL(k_cgemm32<F>, dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
+  hipLaunchKernelGGL((k_cgemm32<F, 4>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
                      o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
 }
 

@@ -34,7 +34,7 @@ struct GemmProb {
   int32_t m, n, k, lda, ldb, ldc0, ldc, pad;
   int64_t a_off, b_off, c0_off, c_off;
 };
-struct TileRef {  // one 64x64 output tile of problem `prob`
+struct TileRef {  // one 64x64 (or 128x128) output tile of problem `prob`
   int32_t prob, tm, tn, pad;
 };
 struct InvDesc {  // in-place inverse of an n x n block (n <= 64)
@@ -88,6 +88,7 @@ struct Op {
   int buf_a = 0, buf_b = 0, buf_c0 = 0, buf_c = 0;  // for EXTADD: c = panel, a = child upd, b = own upd
   int64_t begin = 0, count = 0;          // descriptor range
   int64_t tile_begin = 0, tile_count = 0;
+  int64_t tile128_begin = 0, tile128_count = 0;  // 128x128 tiles (FP32-product GEMMs)
   int depth = 0;
   double flops = 0;          // useful flops per pole (GEMM)
 };
