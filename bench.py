@@ -24,6 +24,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
+    "multi2d_8x4": "8 uneven 2D lattices {32,40,48,56,64,72,80,96}^2 x 4, nn, one schedule, 100 poles",
     "chain1d_256x4": "1D chain 256 sites x 4 orbitals, nearest neighbours, N=1024, 60 poles",
     "square2d_64x4": "2D square lattice 64x64 sites x 4 orbitals, nn + 2nd neighbours, N=16384, 80 poles",
     "cubic3d_24x4": "3D cubic lattice 24^3 sites x 4 orbitals, nearest neighbours, N=55296, 80 poles",
@@ -83,34 +84,49 @@ def golden_error(name, rho, mu, n_poles):
     return float(np.max(np.abs(rho[np.asarray(g["entries"])] - np.asarray(g["values"]))))
 
 
-def run_form(nd, sysd, mu, beta, n_poles, steps, warmup, precision, fp64_poles):
-    """Time one precision form; returns (timing dict, rho on the host)."""
-    n, nnz = sysd["n"], int(sysd["row_ptr"][-1])
+def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_poles):
+    """Time one precision form on one system (density_matrix) or several
+    (density_matrix_batch: one schedule); returns (timing dict, rho list)."""
     ctx = nd.Context(0, precision=precision, fp64_poles=fp64_poles)
     t0 = time.time()
-    sid = ctx.set_structure(n, sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"])
+    sids = []
+    for sysd in systems:
+        sid = ctx.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"])
+        ctx.set_poles(sid, mu, beta, n_poles)
+        sids.append(sid)
+    if precision != "fp64":
+        ctx.autotune(sids)   # per-launch GEMM variant (untimed set-up, like the plan)
     setup_s = time.time() - t0
-    ctx.set_poles(sid, mu, beta, n_poles)
-    out = ctx.device_buffer(nnz)
+    outs = [ctx.device_buffer(int(sysd["row_ptr"][-1])) for sysd in systems]
+    multi = len(systems) > 1
+
+    def step():
+        if multi:
+            ctx.density_matrix_batch(sids, outs)
+        else:
+            ctx.density_matrix(sids[0], outs[0])
+
     for i in range(warmup):
-        ctx.density_matrix(sid, out)
+        step()
     # every density_matrix call ends with a stream synchronisation (it reads
     # the pivot status), so the host clock brackets complete device work
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.density_matrix(sid, out)
+        step()
     dt = time.perf_counter() - t0
-    st = ctx.stats(sid)
+    st = [ctx.stats(s) for s in sids]
     # one instrumented step: per-kind kernel time from HIP events on the library's stream
     ctx.profile(True)
-    ctx.density_matrix(sid, out)
+    step()
     prof = ctx.profile_read()
     ctx.profile(False)
-    rho = out.numpy()
-    out.free()
+    rho = [o.numpy() for o in outs]
+    for o in outs:
+        o.free()
     ctx.close()
     res = {"precision": precision, "setup_s": setup_s, "ms_per_step": 1e3 * dt / steps,
-           "poles_per_s": n_poles * steps / dt, "stats": st, "prof": prof}
+           "poles_per_s": n_poles * steps / dt, "stats": st, "prof": prof,
+           "flops_model_per_step": n_poles * sum(x["flops_per_pole"] for x in st)}
     print("bench: %s %.1f ms/step" % (precision, res["ms_per_step"]), file=sys.stderr, flush=True)
     return res, rho
 
@@ -155,19 +171,25 @@ def main():
     name = args.workload
     n_poles = CONFIGS[name]["n_poles"]
     mu = 0.0
-    sysd = config_system(name)
-    n, nnz = sysd["n"], int(sysd["row_ptr"][-1])
-    print("bench: %s n=%d nnz=%d poles=%d" % (name, n, nnz, n_poles), file=sys.stderr, flush=True)
+    if name == "multi2d_8x4":
+        systems = [config_system(name, i) for i in range(len(CONFIGS[name]["dims"]))]
+    else:
+        systems = [config_system(name)]
+    n = sum(x["n"] for x in systems)
+    nnz = sum(int(x["row_ptr"][-1]) for x in systems)
+    print("bench: %s structures=%d n=%d nnz=%d poles=%d" % (name, len(systems), n, nnz, n_poles), file=sys.stderr,
+          flush=True)
 
     # the plain FP64 form is the complex128 reference of the error
     r64 = rho64 = None
     if args.forms == "both" or args.precision == "fp64":
-        r64, rho64 = run_form(nd, sysd, mu, BETA, n_poles, args.steps, args.warmup, "fp64", 0)
+        r64, rho64 = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, "fp64", 0)
     if args.precision == "fp64":
         head, rho = r64, rho64
     else:
-        head, rho = run_form(nd, sysd, mu, BETA, n_poles, args.steps, args.warmup, args.precision, args.fp64_poles)
-    st, prof = head["stats"], head["prof"]
+        head, rho = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, args.precision,
+                             args.fp64_poles)
+    st, prof = head["stats"][0], head["prof"]
     # dominant kernel: the FP64 front GEMMs in the FP64 form, the FP32-product
     # front GEMMs in the mixed form (peak of their own arithmetic)
     if head["precision"] == "fp64":
@@ -191,18 +213,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head["precision"] == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": name, "description": WORKLOADS[name], "n": n, "nnz": nnz, "n_poles": n_poles,
-                   "kT_eV": 1.0 / BETA, "mu_eV": mu, "precision": head["precision"],
-                   "fp64_poles": st["n_fp64_poles"], "fronts": st["n_fronts"], "levels": st["n_levels"],
-                   "root_j": st["root_j"], "pole_batch": st["pole_batch"]},
-        "tflops_model": st["flops_per_pole"] * n_poles / (head["ms_per_step"] * 1e-3) / 1e12,
-        "max_abs_err_vs_complex128": float(np.max(np.abs(rho - rho64))) if rho64 is not None else None,
-        "max_abs_err_vs_oracle_sample": golden_error(name, rho, mu, n_poles),
+        "config": {"workload": name, "description": WORKLOADS[name], "structures": len(systems), "n": n,
+                   "nnz": nnz, "n_poles": n_poles, "kT_eV": 1.0 / BETA, "mu_eV": mu, "precision": head["precision"],
+                   "fp64_poles": st["n_fp64_poles"], "fronts": sum(x["n_fronts"] for x in head["stats"]),
+                   "levels": max(x["n_levels"] for x in head["stats"]), "root_j": st["root_j"],
+                   "pole_batch": st["pole_batch"]},
+        "pole_structures_per_s": head["poles_per_s"] * len(systems),
+        "tflops_model": head["flops_model_per_step"] / (head["ms_per_step"] * 1e-3) / 1e12,
+        "max_abs_err_vs_complex128": (max(float(np.max(np.abs(a - b))) for a, b in zip(rho, rho64))
+                                      if rho64 is not None else None),
+        "max_abs_err_vs_oracle_sample": golden_error(name, rho[0], mu, n_poles) if len(rho) == 1 else None,
         "fp64_form": None if r64 is None else {
             "poles_per_s": r64["poles_per_s"], "ms_per_step": r64["ms_per_step"],
+            "tflops_model": r64["flops_model_per_step"] / (r64["ms_per_step"] * 1e-3) / 1e12,
             "gemm_tflops": r64["prof"]["gemm"]["flops"] / (r64["prof"]["gemm"]["ms"] * 1e-3) / 1e12,
             "kernel_ms": {k: round(v["ms"], 3) for k, v in r64["prof"].items()},
-            "max_abs_err_vs_oracle_sample": golden_error(name, rho64, mu, n_poles)},
+            "max_abs_err_vs_oracle_sample": golden_error(name, rho64[0], mu, n_poles) if len(rho64) == 1 else None},
         "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
         "gemm_tflops": gemm_tf,
         "roofline": {"kernel": kname, "bound": "mfma",
@@ -213,7 +239,7 @@ def main():
                      "flops_per_step": g["flops"]},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(sysd, mu, BETA, n_poles, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(systems[-1], mu, BETA, n_poles, args.cpu_seconds)
     print(json.dumps(line))
 
 

@@ -66,6 +66,10 @@ typedef struct {
   int32_t verbose;      /* 0 = quiet */
   int32_t fp64_poles;   /* mixed mode: the fp64_poles shifts nearest the real axis stay FP64 (default 8) */
   double fp64_pole_im;  /* mixed mode: shifts with Im alpha < fp64_pole_im also stay FP64 (default 0.05) */
+  int32_t use_graph;    /* 1 (default): capture the launch sequence of an evaluation in a hipGraph and replay it */
+  int32_t gemm_variant; /* mixed mode, front-update GEMMs of the low poles: -1 (default) per-launch choice
+                           (heuristic, refined by ndrho_autotune); 0 FP64; 1 FP32 products on 64x64 tiles;
+                           2 FP32 products on 128x128 tiles */
 } ndrho_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -121,9 +125,27 @@ int ndrho_set_shifts(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double*
  * Errors: ESTATE (no poles set), ESINGULAR, EDEVICE, ENOMEM. */
 int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int32_t on_device);
 
-/* Same for k structures, in the order given. */
+/* rho for k distinct structures in one schedule: their front trees are
+ * joined into one forest (planned, uploaded and given its M0 on the first
+ * call for this list of ids, then cached), so every launch works on the
+ * fronts of all k structures at a depth and on all poles.  The members need
+ * the same shift count, weights and M0 flag (same n_poles and beta); mu, and
+ * with it alpha_p, may differ per structure.  rho_outs[i] receives
+ * structure struct_ids[i]'s nnz values (host or device, as on_device).
+ * Errors: EINVAL (repeated id, mismatched poles), ESTATE, ESINGULAR, ENOMEM. */
 int ndrho_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, double* const* rho_outs,
                                int32_t on_device);
+
+/* Autotuner of the front-update GEMM launches of one structure (k = 1) or of
+ * a batch of k structures (as run by ndrho_density_matrix_batch): for every
+ * launch it times, on one full evaluation of the current shifts each, FP64
+ * for all poles, FP32 products on 64x64 tiles and FP32 products on 128x128
+ * tiles (the FP32 variants apply only to the poles the precision mode puts
+ * in low precision), and keeps the fastest.  With cache_path non-NULL the
+ * choice is looked up in, or appended to, that text file under a key of the
+ * plan's shape, pole count and batch size.  FP64 mode: nothing to tune.
+ * Errors: EINVAL, ESTATE (no shifts set), EDEVICE. */
+int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const char* cache_path);
 
 typedef struct {
   int64_t n, nnz;

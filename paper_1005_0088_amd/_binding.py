@@ -24,7 +24,7 @@ class NdrhoError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("leaf_rows", C.c_int32), ("precision", C.c_int32), ("pole_batch", C.c_int32),
                 ("mem_fraction", C.c_double), ("verbose", C.c_int32), ("fp64_poles", C.c_int32),
-                ("fp64_pole_im", C.c_double)]
+                ("fp64_pole_im", C.c_double), ("use_graph", C.c_int32), ("gemm_variant", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -54,6 +54,7 @@ SIGNATURES = [
     ("ndrho_set_shifts", C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _DP, C.c_int32]),
     ("ndrho_density_matrix", C.c_int, [_P, C.c_int32, _P, C.c_int32]),
     ("ndrho_density_matrix_batch", C.c_int, [_P, _I32P, C.c_int32, C.POINTER(_P), C.c_int32]),
+    ("ndrho_autotune", C.c_int, [_P, _I32P, C.c_int32, C.c_char_p]),
     ("ndrho_stats", C.c_int, [_P, C.c_int32, C.POINTER(Stats)]),
     ("ndrho_profile", C.c_int, [_P, C.c_int32]),
     ("ndrho_profile_read", C.c_int, [_P, _DP, _DP, _I64P]),
@@ -219,7 +220,7 @@ class Context:
     """
 
     def __init__(self, device=0, stream=None, leaf_rows=32, pole_batch=0, mem_fraction=0.8, precision="fp64",
-                 fp64_poles=None, fp64_pole_im=None):
+                 fp64_poles=None, fp64_pole_im=None, use_graph=True, gemm_variant=-1):
         self._lib = load_library()
         opt = Options()
         self._lib.ndrho_default_options(C.byref(opt))
@@ -231,6 +232,8 @@ class Context:
             opt.fp64_poles = int(fp64_poles)
         if fp64_pole_im is not None:
             opt.fp64_pole_im = float(fp64_pole_im)
+        opt.use_graph = int(bool(use_graph))
+        opt.gemm_variant = int(gemm_variant)
         handle = None
         if stream is not None:
             handle = getattr(stream, "cuda_stream", stream)
@@ -292,13 +295,27 @@ class Context:
         return out
 
     def density_matrix_batch(self, sids, outs=None):
+        """rho of several structures in one schedule (see ndrho_density_matrix_batch).
+        outs: None (new numpy arrays), a list of numpy arrays, or a list of DeviceBuffers."""
         sids = [int(s) for s in sids]
         if outs is None:
             outs = [np.empty(self._nnz[s], dtype=np.float64) for s in sids]
+        on_dev = all(isinstance(o, DeviceBuffer) for o in outs)
+        for s, o in zip(sids, outs):
+            n = o.n if isinstance(o, DeviceBuffer) else o.size
+            if n != self._nnz[s] or (not on_dev and (o.dtype != np.float64 or not o.flags.c_contiguous)):
+                raise ValueError("each output must hold nnz float64 values of its structure")
         ids = np.asarray(sids, dtype=np.int32)
-        ptrs = (C.c_void_p * len(sids))(*[o.ctypes.data for o in outs])
-        self._check(self._lib.ndrho_density_matrix_batch(self._h, _ptr(ids, C.c_int32), len(sids), ptrs, 0))
+        ptrs = (C.c_void_p * len(sids))(*[o.ptr if on_dev else o.ctypes.data for o in outs])
+        self._check(self._lib.ndrho_density_matrix_batch(self._h, _ptr(ids, C.c_int32), len(sids), ptrs,
+                                                         int(on_dev)))
         return outs
+
+    def autotune(self, sids, cache_path=None):
+        """Pick the fastest GEMM variant per launch for one structure or a batch."""
+        ids = np.asarray([int(x) for x in (sids if hasattr(sids, "__len__") else [sids])], dtype=np.int32)
+        path = cache_path.encode() if cache_path else None
+        self._check(self._lib.ndrho_autotune(self._h, _ptr(ids, C.c_int32), int(ids.size), path))
 
     def stats(self, sid):
         st = Stats()

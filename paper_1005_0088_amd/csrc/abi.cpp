@@ -5,6 +5,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
+#include <fstream>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -48,6 +51,7 @@ struct DevStruct {
   int32_t* rel = nullptr;
   int64_t* asm_slot = nullptr;
   int32_t* asm_entry = nullptr;
+  int32_t* asm_sid = nullptr;
   int64_t* acc_slot = nullptr;
   int32_t* acc_entry = nullptr;
   // shifts and weights
@@ -56,6 +60,13 @@ struct DevStruct {
   bool add_m0 = true;
   double2* d_alpha = nullptr;
   double* d_w = nullptr;
+  std::vector<double> w_host;  // weights as set (batch compatibility checks)
+  // GEMM variant per program op (empty: default heuristic not yet applied)
+  std::vector<int8_t> variant;
+  int tune_gen = 0;
+  // captured launch sequence of a full evaluation, valid for `gkey`
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const void*> gkey;
 
   template <class T>
   T* put(const std::vector<T>& v, hipStream_t st) {
@@ -64,6 +75,8 @@ struct DevStruct {
     return p;
   }
   void release() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
     if (d_alpha) (void)hipFree(d_alpha);
@@ -75,6 +88,50 @@ struct DevStruct {
 
 thread_local std::string g_err;  // errors without a context (create, plan utilities)
 
+enum { V_FP64 = 0, V_F32_64 = 1, V_F32_128 = 2, V_COUNT = 3 };
+
+// Default GEMM variant per op before any tuning: FP32 products on 128x128
+// tiles where the op's largest problem fills several such tiles, plain FP64
+// for the small fronts of the deep levels (where FP32 does not pay).
+std::vector<int8_t> default_variants(const Plan& P) {
+  std::vector<int8_t> v;
+  auto pick = [&](const Op& op) {
+    if (op.kind != OP_GEMM || (op.flags & OP_PIVOT)) return int8_t(V_FP64);
+    int mx = 0;
+    for (int64_t i = 0; i < op.count; ++i) {
+      const GemmProb& g = P.gemm[op.begin + i];
+      mx = std::max(mx, std::min(g.m, g.n));
+    }
+    return int8_t(mx >= 256 ? V_F32_128 : V_FP64);
+  };
+  for (const Op& op : P.upward) v.push_back(pick(op));
+  for (const Op& op : P.downward) v.push_back(pick(op));
+  return v;
+}
+
+// Device copies of a plan's descriptor arrays and tables.
+void upload_plan(DevStruct& ds, hipStream_t st) {
+  const Plan& P = ds.plan;
+  ds.gemm = ds.put(P.gemm, st);
+  ds.gemm_tiles = ds.put(P.gemm_tiles, st);
+  ds.inv = ds.put(P.inv, st);
+  ds.copy = ds.put(P.copy, st);
+  ds.copy_tiles = ds.put(P.copy_tiles, st);
+  ds.ext = ds.put(P.ext, st);
+  ds.ext_child = ds.put(P.ext_child, st);
+  ds.ext_inv = ds.put(P.ext_inv, st);
+  ds.ext_tiles = ds.put(P.ext_tiles, st);
+  ds.gat = ds.put(P.gat, st);
+  ds.gat_tiles = ds.put(P.gat_tiles, st);
+  ds.rel = ds.put(P.rel_all, st);
+  ds.asm_slot = ds.put(P.asm_slot_sorted, st);
+  ds.asm_entry = ds.put(P.asm_entry_sorted, st);
+  ds.asm_sid = ds.put(P.asm_sid_sorted, st);
+  ds.acc_slot = ds.put(P.acc_slot, st);
+  ds.acc_entry = ds.put(P.acc_entry, st);
+  ds.variant = default_variants(P);
+}
+
 }  // namespace
 
 struct ndrho_ctx {
@@ -84,6 +141,8 @@ struct ndrho_ctx {
   ndrho_options opt{};
   std::string err;
   std::vector<std::unique_ptr<DevStruct>> structs;
+  // joined plans of structure batches, keyed by the list of structure ids
+  std::map<std::vector<int32_t>, std::unique_ptr<DevStruct>> unions;
   void* ws = nullptr;
   size_t ws_bytes = 0;
   double* acc = nullptr;
@@ -99,7 +158,10 @@ struct ndrho_ctx {
     int kind;
     size_t ev;
     double flops;
+    int op;  // program index of the launch (upward ops, then downward), -1 for the pole sum
   };
+  int cur_op = -1;
+  std::vector<double>* op_ms = nullptr;  // per-op milliseconds while autotuning
   std::vector<Rec> recs;
   double prof_ms[NDRHO_K_COUNT] = {0};
   double prof_flops[NDRHO_K_COUNT] = {0};
@@ -124,7 +186,7 @@ struct ndrho_ctx {
     HIP_OK(hipEventRecord(event(i), stream));
     launch();
     HIP_OK(hipEventRecord(event(i + 1), stream));
-    recs.push_back(Rec{kind, i, flops});
+    recs.push_back(Rec{kind, i, flops, cur_op});
   }
   // fold recorded events into the totals (stream must be complete)
   void fold_profile() {
@@ -134,6 +196,7 @@ struct ndrho_ctx {
       prof_ms[r.kind] += ms;
       prof_flops[r.kind] += r.flops;
       prof_n[r.kind] += 1;
+      if (op_ms && r.op >= 0 && r.op < static_cast<int>(op_ms->size())) (*op_ms)[r.op] += ms;
     }
     recs.clear();
   }
@@ -141,6 +204,7 @@ struct ndrho_ctx {
   ~ndrho_ctx() {
     for (auto& s : structs)
       if (s) s->release();
+    for (auto& u : unions) u.second->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     if (ws) (void)hipFree(ws);
     if (acc) (void)hipFree(acc);
@@ -197,8 +261,8 @@ struct ndrho_ctx {
   // One pass of the whole program over `nb` poles; the first `nhi` of them
   // take FP64 front updates, the rest the context's low precision (pivot
   // inverses are FP64 for all).
-  void run_pass(DevStruct& S, int nb, const double2* alpha, const double* w, double hcoef, int spd_check,
-                int nhi) {
+  void run_pass(DevStruct& S, int nb, const double2* alpha, int64_t astride, const double* w, double hcoef,
+                int spd_check, int nhi) {
     const Plan& P = S.plan;
     double2* base = static_cast<double2*>(ws);
     double2* bufs[BUF_COUNT];
@@ -237,7 +301,8 @@ struct ndrho_ctx {
         case OP_ASSEMBLE:
           d.slot = S.asm_slot + op.begin;
           d.entry = S.asm_entry + op.begin;
-          timed(NDRHO_K_ASSEMBLE, 0.0, [&] { e = launch_assemble(d, S.h, S.s, alpha, hcoef, stream); });
+          d.sid = S.asm_sid + op.begin;
+          timed(NDRHO_K_ASSEMBLE, 0.0, [&] { e = launch_assemble(d, S.h, S.s, alpha, astride, hcoef, stream); });
           break;
         case OP_SMALLINV:
           d.inv = S.inv + op.begin;
@@ -246,7 +311,11 @@ struct ndrho_ctx {
         case OP_GEMM: {
           d.gemm = S.gemm + op.begin;
           d.gemm_tiles = S.gemm_tiles + op.tile_begin;
-          const bool split = !(op.flags & OP_PIVOT) && nhi < nb;
+          // variant of a front-update GEMM: V_FP64 keeps every pole in FP64,
+          // V_F32_64 / V_F32_128 give the low poles FP32 products on 64x64
+          // or 128x128 tiles (chosen by heuristic or by the autotuner)
+          const int var = opt.gemm_variant >= 0 ? opt.gemm_variant : S.variant[cur_op];
+          const bool split = !(op.flags & OP_PIVOT) && nhi < nb && var != V_FP64;
           const int k64 = (op.flags & OP_PIVOT) ? NDRHO_K_GEMM_PIVOT : NDRHO_K_GEMM;
           if (!split) {
             timed(k64, op.flops * nb, [&] { e = launch_gemm(d, stream); });
@@ -258,10 +327,13 @@ struct ndrho_ctx {
             timed(k64, op.flops * nhi, [&] { e = launch_gemm(h, stream); });
             if (e != hipSuccess) break;
           }
-          DevOp l = d;  // FP32 products for the others, on 128x128 tiles
+          DevOp l = d;  // FP32 products for the others
           l.fp32 = true;
-          l.gemm_tiles = S.gemm_tiles + op.tile128_begin;
-          l.tile_count = op.tile128_count;
+          if (var == V_F32_128) {
+            l.tile128 = true;
+            l.gemm_tiles = S.gemm_tiles + op.tile128_begin;
+            l.tile_count = op.tile128_count;
+          }
           l.npoles = nb - nhi;
           l.a += nhi * l.sa, l.b += nhi * l.sb, l.c += nhi * l.sc;
           if (op.flags & G_BETA) l.c0 += nhi * l.sc0;
@@ -282,8 +354,16 @@ struct ndrho_ctx {
       }
       if (e != hipSuccess) fail(NDRHO_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     };
-    for (const Op& op : P.upward) run(op);
-    for (const Op& op : P.downward) run(op);
+    cur_op = 0;
+    for (const Op& op : P.upward) {
+      run(op);
+      ++cur_op;
+    }
+    for (const Op& op : P.downward) {
+      run(op);
+      ++cur_op;
+    }
+    cur_op = -1;
     hipError_t ea = hipSuccess;
     timed(NDRHO_K_ACCUM, 0.0,
           [&] { ea = launch_accum(S.acc_slot, P.nnz, bufs[BUF_PANEL], P.panel_total, w, nb, acc, stream); });
@@ -293,18 +373,55 @@ struct ndrho_ctx {
   // Full weighted sum over the structure's shifts into `acc` (sorted order).
   // The first n_hi shifts run with FP64 front updates, the rest in the
   // context's low precision; the sum is taken in shift order either way.
-  void evaluate(DevStruct& S, const double2* alpha, const double* w, int n, int n_hi, bool add_m0, double hcoef,
-                int spd_check) {
+  void evaluate(DevStruct& S, const double2* alpha, int64_t astride, const double* w, int n, int n_hi, bool add_m0,
+                double hcoef, int spd_check) {
     const Plan& P = S.plan;
     const int nb = batch_for(P, n);
     ensure_ws(P, nb);
     last_batch = nb;
-    HIP_OK(launch_init_acc(S.m0, P.nnz, add_m0 ? 1 : 0, acc, status, stream));
-    for (int p0 = 0; p0 < n; p0 += nb) {
-      const int cnt = std::min(nb, n - p0);
-      const int nhi = std::max(0, std::min(cnt, n_hi - p0));
-      run_pass(S, cnt, alpha + p0, w + p0, hcoef, spd_check, nhi);
+    auto record = [&] {
+      HIP_OK(launch_init_acc(S.m0, P.nnz, add_m0 ? 1 : 0, acc, status, stream));
+      for (int p0 = 0; p0 < n; p0 += nb) {
+        const int cnt = std::min(nb, n - p0);
+        const int nhi = std::max(0, std::min(cnt, n_hi - p0));
+        run_pass(S, cnt, alpha + p0, astride, w + p0, hcoef, spd_check, nhi);
+      }
+    };
+    if (!opt.use_graph || prof) {
+      record();
+      return;
     }
+    // The whole evaluation (hundreds of launches) is captured once into a
+    // hipGraph and replayed; anything that changes a launch argument (the
+    // workspace, the shift arrays, the batch size, the precision split)
+    // changes the key and triggers a new capture.
+    std::vector<const void*> key = {ws, acc, status, alpha, w, S.m0, reinterpret_cast<const void*>(astride),
+                                    reinterpret_cast<const void*>(static_cast<intptr_t>(S.tune_gen))};
+    key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(nb)));
+    key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(n)));
+    key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(n_hi)));
+    key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>((add_m0 ? 1 : 0) | (spd_check ? 2 : 0) |
+                                                                      (hcoef != 0.0 ? 4 : 0))));
+    if (!S.gexec || key != S.gkey) {
+      if (S.gexec) HIP_OK(hipGraphExecDestroy(S.gexec));
+      S.gexec = nullptr;
+      HIP_OK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      try {
+        record();
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      hipGraph_t g = nullptr;
+      HIP_OK(hipStreamEndCapture(stream, &g));
+      const hipError_t ie = hipGraphInstantiate(&S.gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIP_OK(ie);
+      S.gkey = key;
+    }
+    HIP_OK(hipGraphLaunch(S.gexec, stream));
   }
 
   void read_status(int* st) {
@@ -326,7 +443,7 @@ struct ndrho_ctx {
       S.allocs.push_back(S.m0);
     }
     try {
-      evaluate(S, da, dw, 1, 1, false, 0.0, 1);
+      evaluate(S, da, 0, dw, 1, 1, false, 0.0, 1);
       int st[2];
       read_status(st);
       if (st[0] || st[1]) fail(NDRHO_ENOTSPD, "S is not positive definite (a non-positive pivot of S)");
@@ -339,6 +456,83 @@ struct ndrho_ctx {
     }
     (void)hipFree(da);
     (void)hipFree(dw);
+  }
+
+  // Joined plan for a list of structures (built, uploaded and given its own
+  // M0 on first use; values are copied from the member structures).
+  DevStruct& get_union(const std::vector<int32_t>& ids) {
+    auto it = unions.find(ids);
+    if (it != unions.end()) return *it->second;
+    std::vector<const Plan*> parts;
+    for (int32_t id : ids) parts.push_back(&get(id).plan);
+    std::unique_ptr<DevStruct> ds(new DevStruct());
+    try {
+      join_plans(ds->plan, parts);
+      const Plan& P = ds->plan;
+      for (double** dst : {&ds->h, &ds->s}) {
+        if (hipMalloc(dst, P.nnz * sizeof(double)) != hipSuccess) fail(NDRHO_ENOMEM, "batch allocation failed");
+        ds->allocs.push_back(*dst);
+      }
+      for (size_t k = 0; k < ids.size(); ++k) {
+        const DevStruct& m = get(ids[k]);
+        const size_t bytes = m.plan.nnz * sizeof(double);
+        HIP_OK(hipMemcpyAsync(ds->h + P.struct_nnz_off[k], m.h, bytes, hipMemcpyDeviceToDevice, stream));
+        HIP_OK(hipMemcpyAsync(ds->s + P.struct_nnz_off[k], m.s, bytes, hipMemcpyDeviceToDevice, stream));
+      }
+      upload_plan(*ds, stream);
+      HIP_OK(hipStreamSynchronize(stream));
+      compute_m0(*ds);
+    } catch (...) {
+      ds->release();
+      throw;
+    }
+    DevStruct& ref = *ds;
+    unions[ids] = std::move(ds);
+    return ref;
+  }
+
+  // Validate a batch, get its joined plan and fill its shift table
+  // (per-structure alpha side by side with stride n_shifts, common weights).
+  DevStruct& prepare_batch(const std::vector<int32_t>& ids) {
+    const int32_t k = static_cast<int32_t>(ids.size());
+    {
+      std::vector<int32_t> sorted = ids;
+      std::sort(sorted.begin(), sorted.end());
+      if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        fail(NDRHO_EINVAL, "a structure appears twice in the batch");
+    }
+    const DevStruct& first = get(ids[0]);
+    for (int32_t id : ids) {
+      const DevStruct& m = get(id);
+      if (m.n_shifts < 1) fail(NDRHO_ESTATE, "set_poles (or set_shifts) has not been called for a batch member");
+      if (m.n_shifts != first.n_shifts || m.w_host != first.w_host || m.add_m0 != first.add_m0 ||
+          m.n_hi != first.n_hi)
+        fail(NDRHO_EINVAL, "batch members need the same number of poles, weights (beta) and M0 flag");
+    }
+    DevStruct& U = get_union(ids);
+    const int n = first.n_shifts;
+    if (U.n_shifts != n || !U.d_alpha) {
+      if (U.d_alpha) HIP_OK(hipFree(U.d_alpha));
+      if (U.d_w) HIP_OK(hipFree(U.d_w));
+      U.d_alpha = nullptr;
+      U.d_w = nullptr;
+      if (hipMalloc(&U.d_alpha, sizeof(double2) * n * k) != hipSuccess ||
+          hipMalloc(&U.d_w, sizeof(double) * n) != hipSuccess)
+        fail(NDRHO_ENOMEM, "batch shift allocation failed");
+      U.n_shifts = n;
+    }
+    for (int32_t i = 0; i < k; ++i)
+      HIP_OK(hipMemcpyAsync(U.d_alpha + int64_t(i) * n, get(ids[i]).d_alpha, sizeof(double2) * n,
+                            hipMemcpyDeviceToDevice, stream));
+    HIP_OK(hipMemcpyAsync(U.d_w, first.d_w, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+    U.n_hi = first.n_hi;
+    U.add_m0 = first.add_m0;
+    return U;
+  }
+
+  void drop_unions() {
+    for (auto& u : unions) u.second->release();
+    unions.clear();
   }
 
   void set_shifts(DevStruct& S, const std::vector<double2>& alpha, const std::vector<double>& w, bool add_m0) {
@@ -361,6 +555,7 @@ struct ndrho_ctx {
     HIP_OK(hipStreamSynchronize(stream));
     S.n_shifts = static_cast<int>(alpha.size());
     S.add_m0 = add_m0;
+    S.w_host = w;
   }
 };
 
@@ -403,6 +598,8 @@ int ndrho_default_options(ndrho_options* opt) {
   opt->verbose = 0;
   opt->fp64_poles = 8;
   opt->fp64_pole_im = 0.05;
+  opt->use_graph = 1;
+  opt->gemm_variant = -1;
   return NDRHO_OK;
 }
 
@@ -421,6 +618,7 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
     if (c->opt.precision != NDRHO_FP64 && c->opt.precision != NDRHO_MIXED_FP32)
       fail(NDRHO_EUNSUPPORTED, "precision must be NDRHO_FP64 or NDRHO_MIXED_FP32");
     if (c->opt.fp64_poles < 0 || !(c->opt.fp64_pole_im >= 0.0)) fail(NDRHO_EINVAL, "invalid FP64 pole rule");
+    if (c->opt.gemm_variant < -1 || c->opt.gemm_variant >= V_COUNT) fail(NDRHO_EINVAL, "invalid gemm_variant");
     if (c->opt.pole_batch < 0) fail(NDRHO_EINVAL, "pole_batch must be >= 0");
     if (!(c->opt.mem_fraction > 0.0 && c->opt.mem_fraction <= 1.0)) fail(NDRHO_EINVAL, "mem_fraction must be in (0, 1]");
     int count = 0;
@@ -472,22 +670,7 @@ int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const
       std::vector<double> hv(H, H + P.nnz), sv(S, S + P.nnz);
       ds->h = ds->put(hv, st);
       ds->s = ds->put(sv, st);
-      ds->gemm = ds->put(P.gemm, st);
-      ds->gemm_tiles = ds->put(P.gemm_tiles, st);
-      ds->inv = ds->put(P.inv, st);
-      ds->copy = ds->put(P.copy, st);
-      ds->copy_tiles = ds->put(P.copy_tiles, st);
-      ds->ext = ds->put(P.ext, st);
-      ds->ext_child = ds->put(P.ext_child, st);
-      ds->ext_inv = ds->put(P.ext_inv, st);
-      ds->ext_tiles = ds->put(P.ext_tiles, st);
-      ds->gat = ds->put(P.gat, st);
-      ds->gat_tiles = ds->put(P.gat_tiles, st);
-      ds->rel = ds->put(P.rel_all, st);
-      ds->asm_slot = ds->put(P.asm_slot_sorted, st);
-      ds->asm_entry = ds->put(P.asm_entry_sorted, st);
-      ds->acc_slot = ds->put(P.acc_slot, st);
-      ds->acc_entry = ds->put(P.acc_entry, st);
+      upload_plan(*ds, st);
       HIP_OK(hipStreamSynchronize(st));
       ctx->compute_m0(*ds);
     } catch (...) {
@@ -509,6 +692,7 @@ int ndrho_update_values(ndrho_ctx* ctx, int32_t struct_id, const double* H, cons
     HIP_OK(hipSetDevice(ctx->device));
     HIP_OK(hipMemcpyAsync(ds.h, H, P.nnz * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIP_OK(hipMemcpyAsync(ds.s, S, P.nnz * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    ctx->drop_unions();
     ctx->compute_m0(ds);
   });
 }
@@ -560,7 +744,7 @@ int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int
     HIP_OK(hipSetDevice(ctx->device));
     const auto t0 = std::chrono::steady_clock::now();
     const Plan& P = ds.plan;
-    ctx->evaluate(ds, ds.d_alpha, ds.d_w, ds.n_shifts, ds.n_hi, ds.add_m0, 1.0, 0);
+    ctx->evaluate(ds, ds.d_alpha, 0, ds.d_w, ds.n_shifts, ds.n_hi, ds.add_m0, 1.0, 0);
     double* dst = on_device ? rho_out : ctx->outbuf;
     HIP_OK(launch_scatter(ds.acc_entry, P.nnz, ctx->acc, dst, ctx->stream));
     int st[2];
@@ -577,17 +761,101 @@ int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int
 int ndrho_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, double* const* rho_outs,
                                int32_t on_device) {
   if (!ctx) return NDRHO_EINVAL;
-  if (k < 0 || (k > 0 && (!struct_ids || !rho_outs))) {
-    ctx->err = "invalid batch arguments";
-    return NDRHO_EINVAL;
-  }
-  const auto t0 = std::chrono::steady_clock::now();
-  for (int32_t i = 0; i < k; ++i) {
-    int rc = ndrho_density_matrix(ctx, struct_ids[i], rho_outs[i], on_device);
-    if (rc != NDRHO_OK) return rc;
-  }
-  ctx->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  return NDRHO_OK;
+  return guarded(ctx, [&] {
+    if (k < 1 || !struct_ids || !rho_outs) fail(NDRHO_EINVAL, "invalid batch arguments");
+    for (int32_t i = 0; i < k; ++i)
+      if (!rho_outs[i]) fail(NDRHO_EINVAL, "rho_outs has a NULL entry");
+    std::vector<int32_t> ids(struct_ids, struct_ids + k);
+    HIP_OK(hipSetDevice(ctx->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    DevStruct& U = ctx->prepare_batch(ids);
+    const Plan& P = U.plan;
+    const DevStruct& first = ctx->get(ids[0]);
+    const int n = first.n_shifts;
+    ctx->evaluate(U, U.d_alpha, n, U.d_w, n, first.n_hi, first.add_m0, 1.0, 0);
+    HIP_OK(launch_scatter(U.acc_entry, P.nnz, ctx->acc, ctx->outbuf, ctx->stream));
+    int st[2];
+    ctx->read_status(st);
+    if (st[0]) fail(NDRHO_ESINGULAR, "a zero, tiny or non-finite pivot occurred in alpha S - H");
+    for (int32_t i = 0; i < k; ++i) {
+      const int64_t cnt = ctx->get(ids[i]).plan.nnz;
+      HIP_OK(hipMemcpyAsync(rho_outs[i], ctx->outbuf + P.struct_nnz_off[i], cnt * sizeof(double),
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    ctx->last_batch = ctx->last_batch;
+    ctx->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  });
+}
+
+int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const char* cache_path) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    if (k < 1 || !struct_ids) fail(NDRHO_EINVAL, "invalid structure list");
+    HIP_OK(hipSetDevice(ctx->device));
+    std::vector<int32_t> ids(struct_ids, struct_ids + k);
+    DevStruct& T = k == 1 ? ctx->get(ids[0]) : ctx->prepare_batch(ids);
+    if (T.n_shifts < 1) fail(NDRHO_ESTATE, "set_poles (or set_shifts) has not been called");
+    const Plan& P = T.plan;
+    const int nops = static_cast<int>(P.upward.size() + P.downward.size());
+    const int nb = ctx->batch_for(P, T.n_shifts);
+    char keybuf[256];
+    std::snprintf(keybuf, sizeof(keybuf), "ndrho-tune-v1 n=%lld nnz=%lld fronts=%zu shifts=%d fp64=%d batch=%d ops=%d",
+                  static_cast<long long>(P.n), static_cast<long long>(P.nnz), P.fronts.size(), T.n_shifts, T.n_hi,
+                  nb, nops);
+    const std::string key(keybuf);
+    if (T.n_hi >= T.n_shifts || ctx->opt.gemm_variant >= 0) return;  // nothing to choose
+    if (cache_path) {
+      std::ifstream in(cache_path);
+      std::string line;
+      while (std::getline(in, line)) {
+        if (line.size() == key.size() + 1 + static_cast<size_t>(nops) && line.compare(0, key.size(), key) == 0) {
+          for (int i = 0; i < nops; ++i) T.variant[i] = static_cast<int8_t>(line[key.size() + 1 + i] - '0');
+          ++T.tune_gen;
+          return;
+        }
+      }
+    }
+    // time every variant of every front-update GEMM on one full evaluation each
+    std::vector<std::vector<double>> ms(V_COUNT, std::vector<double>(nops, 0.0));
+    const bool was_prof = ctx->prof;
+    const std::vector<int8_t> saved = T.variant;
+    const int64_t astride = k == 1 ? 0 : T.n_shifts;
+    try {
+      for (int v = 0; v < V_COUNT; ++v) {
+        for (int i = 0; i < nops; ++i) {
+          const Op& op = i < static_cast<int>(P.upward.size()) ? P.upward[i] : P.downward[i - P.upward.size()];
+          T.variant[i] = (op.kind == OP_GEMM && !(op.flags & OP_PIVOT)) ? static_cast<int8_t>(v) : int8_t(V_FP64);
+        }
+        ctx->prof = true;
+        ctx->op_ms = &ms[v];
+        ctx->evaluate(T, T.d_alpha, astride, T.d_w, T.n_shifts, T.n_hi, T.add_m0, 1.0, 0);
+        int st[2];
+        ctx->read_status(st);
+        ctx->op_ms = nullptr;
+      }
+    } catch (...) {
+      ctx->op_ms = nullptr;
+      ctx->prof = was_prof;
+      T.variant = saved;
+      throw;
+    }
+    ctx->prof = was_prof;
+    for (int k2 = 0; k2 < NDRHO_K_COUNT; ++k2) ctx->prof_ms[k2] = ctx->prof_flops[k2] = 0, ctx->prof_n[k2] = 0;
+    std::string choice;
+    for (int i = 0; i < nops; ++i) {
+      int best = V_FP64;
+      for (int v = 1; v < V_COUNT; ++v)
+        if (ms[v][i] < ms[best][i]) best = v;
+      T.variant[i] = static_cast<int8_t>(best);
+      choice.push_back(static_cast<char>('0' + best));
+    }
+    ++T.tune_gen;
+    if (cache_path) {
+      std::ofstream out(cache_path, std::ios::app);
+      out << key << ' ' << choice << '\n';
+    }
+  });
 }
 
 int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out) {

@@ -13,7 +13,8 @@ namespace ndrho {
 struct DevOp {
   int flags = 0;
   int npoles = 1;
-  bool fp32 = false;  // GEMM products on the FP32 matrix cores
+  bool fp32 = false;     // GEMM products on the FP32 matrix cores
+  bool tile128 = false;  // FP32 GEMM on 128x128 tiles (else 64x64)
   int64_t count = 0, tile_count = 0;
   const GemmProb* gemm = nullptr;
   const TileRef* gemm_tiles = nullptr;
@@ -28,13 +29,14 @@ struct DevOp {
   const int32_t* rel = nullptr;
   const int64_t* slot = nullptr;
   const int32_t* entry = nullptr;
+  const int32_t* sid = nullptr;
   double2 *a = nullptr, *b = nullptr, *c0 = nullptr, *c = nullptr;
   int64_t sa = 0, sb = 0, sc0 = 0, sc = 0;
 };
 
 hipError_t launch_extadd(const DevOp& o, hipStream_t st);
-hipError_t launch_assemble(const DevOp& o, const double* hv, const double* sv, const double2* alpha, double hcoef,
-                           hipStream_t st);
+hipError_t launch_assemble(const DevOp& o, const double* hv, const double* sv, const double2* alpha,
+                           int64_t astride, double hcoef, hipStream_t st);
 hipError_t launch_smallinv(const DevOp& o, int* status, int spd_check, hipStream_t st);
 hipError_t launch_gemm(const DevOp& o, hipStream_t st);
 hipError_t launch_copy(const DevOp& o, hipStream_t st);

@@ -98,18 +98,22 @@ __global__ __launch_bounds__(256) void k_extadd(const ExtAddDesc* __restrict__ d
 // ----------------------------------------------------------------- assembly
 //
 // X = alpha_p S - h H for every pole of the batch, added into the panels at
-// the table positions (each position receives at most one entry).
+// the table positions (each position receives at most one entry).  With
+// several structures in one plan, entry k belongs to structure sid[k] and
+// takes its shifts from alpha[sid[k] * astride + p].
 __global__ __launch_bounds__(256) void k_assemble(const int64_t* __restrict__ slot, const int32_t* __restrict__ entry,
-                                                  int64_t count, const double* __restrict__ hv,
-                                                  const double* __restrict__ sv, const double2* __restrict__ alpha,
-                                                  int npoles, double hcoef, double2* __restrict__ panel, int64_t ps) {
+                                                  const int32_t* __restrict__ sid, int64_t count,
+                                                  const double* __restrict__ hv, const double* __restrict__ sv,
+                                                  const double2* __restrict__ alpha, int64_t astride, int npoles,
+                                                  double hcoef, double2* __restrict__ panel, int64_t ps) {
   const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (k >= count) return;
   const int64_t sl = slot[k];
   const int32_t e = entry[k];
   const double h = hcoef * hv[e], s = sv[e];
+  const double2* al = alpha + int64_t(sid[k]) * astride;
   for (int p = 0; p < npoles; ++p) {
-    const double2 a = alpha[p];
+    const double2 a = al[p];
     double2* x = panel + int64_t(p) * ps + sl;
     double2 v = *x;
     v.x += a.x * s - h;
@@ -627,11 +631,11 @@ hipError_t launch_extadd(const DevOp& o, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_assemble(const DevOp& o, const double* hv, const double* sv, const double2* alpha, double hcoef,
-                           hipStream_t st) {
+hipError_t launch_assemble(const DevOp& o, const double* hv, const double* sv, const double2* alpha,
+                           int64_t astride, double hcoef, hipStream_t st) {
   if (o.count == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_assemble, dim3(blocks_for(o.count, 256)), dim3(256), 0, st, o.slot, o.entry, o.count, hv, sv,
-                     alpha, o.npoles, hcoef, o.c, o.sc);
+  hipLaunchKernelGGL(k_assemble, dim3(blocks_for(o.count, 256)), dim3(256), 0, st, o.slot, o.entry, o.sid, o.count,
+                     hv, sv, alpha, astride, o.npoles, hcoef, o.c, o.sc);
   return hipGetLastError();
 }
 
@@ -652,8 +656,12 @@ static void gemm_inst(const DevOp& o, hipStream_t st) {
 template <int F>
 static void gemm32_inst(const DevOp& o, hipStream_t st) {
   const int64_t total = o.tile_count * o.npoles;
-  hipLaunchKernelGGL((k_cgemm32<F, 4>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
-                     o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
+  if (o.tile128)
+    hipLaunchKernelGGL((k_cgemm32<F, 4>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
+                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
+  else
+    hipLaunchKernelGGL((k_cgemm32<F, 2>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
+                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
 }
 
 hipError_t launch_gemm(const DevOp& o, hipStream_t st) {

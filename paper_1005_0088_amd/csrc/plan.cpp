@@ -505,6 +505,21 @@ void build_plan(Plan& P, int64_t n, const int64_t* row_ptr, const int32_t* col, 
     }
   }
 
+  finalize_plan(P);
+}
+
+// Storage layout, the table of pattern positions and the launch program,
+// from the front tree and the CSR pattern held in P (one structure, or the
+// forest of several structures joined by join_plans).
+void finalize_plan(Plan& P) {
+  const int nf = static_cast<int>(P.fronts.size());
+  std::vector<int> owner(P.n, -1);
+  for (int f = 0; f < nf; ++f)
+    for (int64_t q = P.fronts[f].j0; q < P.fronts[f].j0 + P.fronts[f].nj; ++q) owner[q] = f;
+  P.flops_model = P.bytes_model = P.flops_exec = 0;
+  P.upd_total = P.temp_total = 0;
+  P.upward.clear();
+  P.downward.clear();
   // ---- storage offsets
   std::vector<std::vector<int>> by_depth(P.n_levels);
   for (int f = 0; f < nf; ++f) by_depth[P.fronts[f].depth].push_back(f);
@@ -538,9 +553,9 @@ void build_plan(Plan& P, int64_t n, const int64_t* row_ptr, const int32_t* col, 
   P.out_slot.resize(P.nnz);
   P.asm_slot.resize(P.nnz);
   std::vector<std::vector<std::pair<int64_t, int32_t>>> asm_by_depth(P.n_levels);
-  for (int64_t i = 0; i < n; ++i) {
-    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-      const int pi = P.iperm[i], pj = P.iperm[col[e]];
+  for (int64_t i = 0; i < P.n; ++i) {
+    for (int64_t e = P.row_ptr[i]; e < P.row_ptr[i + 1]; ++e) {
+      const int pi = P.iperm[i], pj = P.iperm[P.col[e]];
       const int a = std::min(pi, pj), b = std::max(pi, pj);
       const Front& F = P.fronts[owner[a]];
       const int64_t ld = F.nj + F.nu;
@@ -570,6 +585,12 @@ void build_plan(Plan& P, int64_t n, const int64_t* row_ptr, const int32_t* col, 
     }
   }
   P.asm_depth_begin[P.n_levels] = static_cast<int64_t>(P.asm_slot_sorted.size());
+  P.asm_sid_sorted.assign(P.asm_entry_sorted.size(), 0);
+  if (!P.struct_nnz_off.empty())
+    for (size_t k = 0; k < P.asm_entry_sorted.size(); ++k)
+      P.asm_sid_sorted[k] = static_cast<int32_t>(
+          std::upper_bound(P.struct_nnz_off.begin(), P.struct_nnz_off.end(), int64_t(P.asm_entry_sorted[k])) -
+          P.struct_nnz_off.begin() - 1);
   {
     std::vector<std::pair<int64_t, int32_t>> acc(P.nnz);
     for (int64_t e = 0; e < P.nnz; ++e) acc[e] = {P.out_slot[e], static_cast<int32_t>(e)};
@@ -706,6 +727,39 @@ void build_plan(Plan& P, int64_t n, const int64_t* row_ptr, const int32_t* col, 
     B.gemm(P.downward, G_TA | G_SYM | G_BETA | G_NEG, BUF_PANEL, BUF_TEMP, BUF_PANEL, BUF_PANEL, g4, d);
     B.copy(P.downward, false, BUF_TEMP, BUF_PANEL, c2, d);
   }
+}
+
+void join_plans(Plan& U, const std::vector<const Plan*>& parts) {
+  U = Plan();
+  int64_t rows = 0, nnz = 0;
+  int levels = 0;
+  U.row_ptr.push_back(0);
+  for (const Plan* p : parts) {
+    const int fbase = static_cast<int>(U.fronts.size());
+    U.struct_row_off.push_back(rows);
+    U.struct_nnz_off.push_back(nnz);
+    for (int64_t i = 0; i < p->n; ++i) U.row_ptr.push_back(nnz + p->row_ptr[i + 1]);
+    for (int64_t e = 0; e < p->nnz; ++e) U.col.push_back(static_cast<int32_t>(p->col[e] + rows));
+    for (int64_t i = 0; i < p->n; ++i) {
+      U.perm.push_back(static_cast<int32_t>(p->perm[i] + rows));
+      U.iperm.push_back(static_cast<int32_t>(p->iperm[i] + rows));
+    }
+    for (const Front& F0 : p->fronts) {
+      Front F = F0;
+      if (F.parent >= 0) F.parent += fbase;
+      for (int& c : F.children) c += fbase;
+      F.j0 += rows;
+      for (int& q : F.u) q += static_cast<int>(rows);
+      U.fronts.push_back(std::move(F));
+    }
+    rows += p->n;
+    nnz += p->nnz;
+    levels = std::max(levels, p->n_levels);
+  }
+  U.n = rows;
+  U.nnz = nnz;
+  U.n_levels = levels;
+  finalize_plan(U);
 }
 
 }  // namespace ndrho

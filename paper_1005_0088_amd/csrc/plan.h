@@ -128,6 +128,12 @@ struct Plan {
 
   double flops_model = 0, bytes_model = 0;    // per pole
   double flops_exec = 0;                      // flops of the program per pole
+
+  // several structures joined into one forest (empty for one structure):
+  // first row / first CSR entry of each structure, and the structure of
+  // every assembly entry (for per-structure shifts)
+  std::vector<int64_t> struct_row_off, struct_nnz_off;
+  std::vector<int32_t> asm_sid_sorted;
 };
 
 // Validate the CSR pattern (and values if given); throws Error(EINVAL).
@@ -135,5 +141,10 @@ void validate_csr(int64_t n, const int64_t* row_ptr, const int32_t* col, const d
 // Ordering + symbolic analysis + program.
 void build_plan(Plan& plan, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* coords,
                 int leaf_rows);
+// Layout, tables and program from P's fronts and CSR (called by build_plan).
+void finalize_plan(Plan& P);
+// One plan for several structures: their front trees side by side as a
+// forest over the block-diagonal union of their matrices.
+void join_plans(Plan& U, const std::vector<const Plan*>& parts);
 
 }  // namespace ndrho

@@ -203,12 +203,14 @@ def test_errors(ctx):
 
 # ------------------------------------------------------------- precision form
 
-def test_mixed_fp32_single_shift_close_to_dense():
-    # FP32 products with FP32 accumulation: relative error of G well below 1e-5
+@pytest.mark.parametrize("variant", [1, 2])
+def test_mixed_fp32_single_shift_close_to_dense(variant):
+    # FP32 products with FP32 accumulation (64x64 or 128x128 tiles): relative
+    # error of G well below 1e-5
     import paper_1005_0088_amd as nd
     sysd = lattice((7, 6, 5), "nn", 14)
     h, s, rows, cols = _dense(sysd)
-    with nd.Context(0, precision="mixed_fp32", fp64_poles=0, fp64_pole_im=0.0) as c:
+    with nd.Context(0, precision="mixed_fp32", fp64_poles=0, fp64_pole_im=0.0, gemm_variant=variant) as c:
         sid = _register(c, sysd)
         c.set_shifts(sid, np.array([0.2 + 0.5j]), np.array([1.0]), add_m0=False)
         got = c.density_matrix(sid)
@@ -272,3 +274,107 @@ def test_full_size_against_oracle_sample(name, precision, tol):
     order = np.argsort(key)
     pos = order[np.searchsorted(key[order], tkey)]
     assert np.max(np.abs(rho - rho[pos])) < tol
+
+
+# ------------------------------------------------------------- several structures, one schedule
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_batch_of_structures_matches_single_runs(precision):
+    import paper_1005_0088_amd as nd
+    systems = [lattice((9, 7), "nn", 30), lattice((12, 12), "nn", 31), lattice((5, 4, 6), "nn2", 32),
+               lattice((40,), "nn", 33)]
+    mus = [0.1, -0.2, 0.0, 0.3]
+    with nd.Context(0, precision=precision) as c:
+        sids = []
+        for sysd, mu in zip(systems, mus):
+            sid = _register(c, sysd)
+            c.set_poles(sid, mu, BETA, 50)
+            sids.append(sid)
+        singles = [c.density_matrix(s) for s in sids]
+        batch = c.density_matrix_batch(sids)
+        dev = [c.device_buffer(x.size) for x in singles]
+        c.density_matrix_batch(sids, dev)
+        batch_dev = [d.numpy() for d in dev]
+        for d in dev:
+            d.free()
+        # a different order and a subset give the same per-structure results
+        sub = c.density_matrix_batch([sids[2], sids[0]])
+    # FP64: the same arithmetic per front; mixed: a launch may pick another
+    # GEMM variant when fronts of several structures share it
+    tol = 1e-13 if precision == "fp64" else 2e-7
+    for a, b, d in zip(singles, batch, batch_dev):
+        assert np.max(np.abs(a - b)) < tol
+        assert np.array_equal(b, d)
+    assert np.max(np.abs(sub[0] - singles[2])) < tol and np.max(np.abs(sub[1] - singles[0])) < tol
+    # and each structure still matches the oracle
+    if precision == "fp64":
+        for sysd, mu, got in zip(systems, mus, batch):
+            h, s, rows, cols = _dense(sysd)
+            eps, cc = dense.eigen(h, s)
+            ref = dense.rho_cf_pattern(eps, cc, mu, BETA, 50, rows, cols)
+            assert np.max(np.abs(got - ref)) < 1e-10
+
+
+def test_batch_rejects_mismatched_poles(ctx):
+    import paper_1005_0088_amd as nd
+    a = _register(ctx, lattice((6, 6), "nn", 40))
+    b = _register(ctx, lattice((7, 5), "nn", 41))
+    ctx.set_poles(a, 0.0, BETA, 30)
+    ctx.set_poles(b, 0.0, BETA, 40)
+    with pytest.raises(nd.NdrhoError) as e:
+        ctx.density_matrix_batch([a, b])
+    assert e.value.name == "EINVAL"
+    with pytest.raises(nd.NdrhoError) as e:
+        ctx.density_matrix_batch([a, a])
+    assert e.value.name == "EINVAL"
+
+
+def test_graph_replay_matches_plain_launches():
+    # the captured graph is replayed several times with other work in
+    # between; every replay must equal the uncaptured result
+    import paper_1005_0088_amd as nd
+    sysd = lattice((8, 7, 6), "nn", 42)
+    with nd.Context(0, use_graph=False) as c0:
+        s0 = _register(c0, sysd)
+        c0.set_poles(s0, 0.05, BETA, 40)
+        ref = c0.density_matrix(s0)
+    with nd.Context(0, use_graph=True) as c1:
+        s1 = _register(c1, sysd)
+        other = _register(c1, lattice((9, 9), "nn", 43))
+        c1.set_poles(s1, 0.05, BETA, 40)
+        c1.set_poles(other, 0.0, BETA, 20)
+        for _ in range(3):
+            got = c1.density_matrix(s1)
+            assert np.array_equal(got, ref)
+            c1.density_matrix(other)
+
+
+def test_autotune_keeps_accuracy_and_caches(tmp_path):
+    import paper_1005_0088_amd as nd
+    sysd = lattice((10, 9, 8), "nn", 44)
+    cache = str(tmp_path / "tune.txt")
+    with nd.Context(0, precision="fp64") as c:
+        s0 = _register(c, sysd)
+        c.set_poles(s0, 0.0, BETA, 40)
+        ref = c.density_matrix(s0)
+        c.autotune([s0], cache)               # FP64: nothing to tune
+    with nd.Context(0, precision="mixed_fp32") as c:
+        s1 = _register(c, sysd)
+        c.set_poles(s1, 0.0, BETA, 40)
+        c.autotune([s1], cache)
+        got = c.density_matrix(s1)
+        again = c.density_matrix(s1)
+    assert np.max(np.abs(got - ref)) < 1e-7
+    assert np.array_equal(got, again)
+    with open(cache) as f:
+        lines = f.read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("ndrho-tune-v1 ")
+    choice = lines[0].split()[-1]
+    assert set(choice) <= set("012")
+    with nd.Context(0, precision="mixed_fp32") as c:   # cached choice is reused, not re-tuned
+        s2 = _register(c, sysd)
+        c.set_poles(s2, 0.0, BETA, 40)
+        c.autotune([s2], cache)
+        assert np.array_equal(c.density_matrix(s2), got)
+    with open(cache) as f:
+        assert len(f.read().splitlines()) == 1
