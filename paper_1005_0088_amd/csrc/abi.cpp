@@ -219,7 +219,9 @@ struct ndrho_ctx {
     return *structs[id];
   }
 
-  static int64_t per_pole_elems(const Plan& P) { return P.panel_total + 2 * P.upd_total + P.temp_total; }
+  static int64_t per_pole_elems(const Plan& P) {
+    return P.panel_total + 2 * P.upd_total + P.temp_total + P.l_total;
+  }
 
   // Workspace for `nb` poles of plan P (grown, never shrunk).
   void ensure_ws(const Plan& P, int nb) {
@@ -275,6 +277,8 @@ struct ndrho_ctx {
     strides[BUF_UPD1] = P.upd_total;
     bufs[BUF_TEMP] = bufs[BUF_UPD1] + P.upd_total * nb;
     strides[BUF_TEMP] = P.temp_total;
+    bufs[BUF_L] = bufs[BUF_TEMP] + P.temp_total * nb;
+    strides[BUF_L] = P.l_total;
     auto resolve = [&](const Op& op) {
       DevOp d;
       d.flags = op.flags & 0xff;

@@ -45,10 +45,12 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t total) {
 //
 // Pull form of the child-to-parent accumulation of Schur complements
 // (Eq. (32); the (B[C])^T bookkeeping of Eq. (28)): every element of the
-// parent's panel (columns in J) and of its own U x U block is written once
-// as the sum, in child order, of the children's update entries that map onto
-// it.  Writing (not adding) also clears the panel before assembly, so no
-// separate fill is needed and no two threads touch one target.
+// parent's panel (columns in J) and of the lower triangle of its own U x U
+// block is written once as the sum, in child order, of the children's update
+// entries that map onto it (update blocks are symmetric and stored as lower
+// triangles; the relative maps are increasing, so lower maps to lower).
+// Writing (not adding) also clears the panel before assembly, so no separate
+// fill is needed and no two threads touch one target.
 __global__ __launch_bounds__(256) void k_extadd(const ExtAddDesc* __restrict__ descs,
                                                 const ExtAddChild* __restrict__ kids,
                                                 const int32_t* __restrict__ inv, const ElemTile* __restrict__ tiles,
@@ -79,13 +81,14 @@ __global__ __launch_bounds__(256) void k_extadd(const ExtAddDesc* __restrict__ d
       r = d.nj + (e2 - q * d.nu);
       s = d.nj + q;
     }
+    if (e >= tp && r < s) continue;  // own U x U block: lower triangle only
     double2 sum = make_double2(0.0, 0.0);
     for (int c = 0; c < d.child_count; ++c) {
       const ExtAddChild k = kids[d.child_begin + c];
       const int32_t* im = inv + k.inv_off;
       const int32_t a = im[r], b = im[s];
-      if (a >= 0 && b >= 0) {
-        const double2 v = cu[k.upd_off + a + int64_t(b) * k.nu];
+      if (a >= 0 && b >= 0) {  // children store the lower triangle of their update
+        const double2 v = cu[k.upd_off + max(a, b) + int64_t(min(a, b)) * k.nu];
         sum.x += v.x;
         sum.y += v.y;
       }
@@ -232,6 +235,8 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
                                                   int64_t sC0, double2* C, int64_t sC) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
   constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
+  static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   __shared__ double2 As[2][BK][BM + 1];
   __shared__ double2 Bs[2][BK][BN + 1];
 
@@ -265,7 +270,10 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
     const int m_ = TA ? (tid >> 4) + 16 * (i) : (tid & 63);                           \
     const int k_ = TA ? (tid & 15) : (tid >> 6) + 4 * (i);                            \
     const int gm = m0 + m_, gk = (k0) + k_;                                            \
-    dst = (gm < M && gk < K) ? (TA ? Ap[gk + int64_t(gm) * pr.lda] : Ap[gm + int64_t(gk) * pr.lda]) : make_double2(0.0, 0.0); \
+    dst = (gm < M && gk < K) ? (TA ? Ap[gk + int64_t(gm) * pr.lda]                    \
+                                   : (SYMA && gm < gk) ? Ap[gk + int64_t(gm) * pr.lda]      \
+                                                       : Ap[gm + int64_t(gk) * pr.lda])     \
+                             : make_double2(0.0, 0.0);                                      \
   } while (0)
 #define ZG_LDB(i, k0, dst)                                                             \
   do {                                                                                 \
@@ -359,7 +367,7 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
           v.y += c0.y;
         }
         Cp[m + int64_t(n) * pr.ldc] = v;
-        if (SYM && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+        if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
       }
 }
 
@@ -382,6 +390,8 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
                                                     int64_t sC0, double2* C, int64_t sC) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
   constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
+  static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   constexpr int TM = 32 * WT;          // workgroup tile edge
   constexpr int NL = TM * BK / 256;    // operand elements per thread per stage
   constexpr int RS = 256 / TM;         // k rows per pass of a non-transposed load
@@ -419,7 +429,10 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
       const int m_ = TA ? (tid >> 4) + 16 * i : tid % TM;                                        \
       const int k_ = TA ? (tid & 15) : tid / TM + RS * i;                                        \
       const int gm = m0 + m_, gk = (k0) + k_;                                                    \
-      ra[i] = (gm < M && gk < K) ? (TA ? Ap[gk + int64_t(gm) * pr.lda] : Ap[gm + int64_t(gk) * pr.lda]) : make_double2(0.0, 0.0); \
+      ra[i] = (gm < M && gk < K) ? (TA ? Ap[gk + int64_t(gm) * pr.lda]                                 \
+                                       : (SYMA && gm < gk) ? Ap[gk + int64_t(gm) * pr.lda]                   \
+                                                           : Ap[gm + int64_t(gk) * pr.lda])                  \
+                                 : make_double2(0.0, 0.0);                                                   \
     }                                                                                            \
     {                                                                                            \
       const int n_ = TB ? tid % TM : (tid >> 4) + 16 * i;                                        \
@@ -497,7 +510,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
           v.y += c0.y;
         }
         Cp[m + int64_t(n) * pr.ldc] = v;
-        if (SYM && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+        if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
       }
 }
 
@@ -541,10 +554,10 @@ __global__ __launch_bounds__(256) void k_copy(const CopyDesc* __restrict__ descs
 
 // ----------------------------------------------------------------- gather G_UU
 //
-// Downward pass: the entries of G on U_f x U_f are read from the parent's
-// selected block, i.e. from its G_JJ and G_UJ panel (either orientation, G is
-// symmetric) or from the parent's own gathered G_UU (Eq. (38): the blocks
-// X^{-1}_{p,2n}, X^{-1}_{p,2n+1} needed by the next level).
+// Downward pass: the lower triangle of G on U_f x U_f is read from the
+// parent's selected block, i.e. from its G_JJ and G_UJ panel or from the
+// parent's own gathered G_UU (Eq. (38): the blocks X^{-1}_{p,2n},
+// X^{-1}_{p,2n+1} needed by the next level).
 __global__ __launch_bounds__(256) void k_gather(const GatherDesc* __restrict__ descs,
                                                 const int32_t* __restrict__ rel, const ElemTile* __restrict__ tiles,
                                                 const double2* __restrict__ pguu, int64_t gs,
@@ -564,11 +577,9 @@ __global__ __launch_bounds__(256) void k_gather(const GatherDesc* __restrict__ d
     const uint32_t e = uint32_t(t.e0) + threadIdx.x + 256 * i;
     if (e >= total) break;
     const uint32_t b = e / uint32_t(d.nu), a = e - b * uint32_t(d.nu);
-    const int r = rl[a], s = rl[b];
-    double2 v;
-    if (s < d.pnj) v = pan[r + int64_t(s) * pld];
-    else if (r < d.pnj) v = pan[s + int64_t(r) * pld];
-    else v = pg[(r - d.pnj) + int64_t(s - d.pnj) * d.pnu];
+    if (a < b) continue;  // G_UU is kept as its lower triangle
+    const int r = rl[a], s = rl[b];  // r >= s (increasing map)
+    const double2 v = s < d.pnj ? pan[r + int64_t(s) * pld] : pg[(r - d.pnj) + int64_t(s - d.pnj) * d.pnu];
     out[e] = v;
   }
 }
@@ -667,10 +678,10 @@ static void gemm32_inst(const DevOp& o, hipStream_t st) {
 hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
   if (o.tile_count == 0) return hipSuccess;
   if (o.fp32) {
-    switch (o.flags) {
+    switch (o.flags) {  // front updates only (pivot GEMMs are always FP64)
       case 0: gemm32_inst<0>(o, st); break;
-      case G_NEG: gemm32_inst<G_NEG>(o, st); break;
-      case G_TB | G_SYM | G_BETA | G_NEG: gemm32_inst<G_TB | G_SYM | G_BETA | G_NEG>(o, st); break;
+      case G_NEG | G_SYMA: gemm32_inst<G_NEG | G_SYMA>(o, st); break;
+      case G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR: gemm32_inst<G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR>(o, st); break;
       case G_TA | G_SYM | G_BETA | G_NEG: gemm32_inst<G_TA | G_SYM | G_BETA | G_NEG>(o, st); break;
       default: return hipErrorInvalidValue;
     }
@@ -679,6 +690,8 @@ hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
   switch (o.flags) {
     case 0: gemm_inst<0>(o, st); break;
     case G_NEG: gemm_inst<G_NEG>(o, st); break;
+    case G_NEG | G_SYMA: gemm_inst<G_NEG | G_SYMA>(o, st); break;
+    case G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR: gemm_inst<G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR>(o, st); break;
     case G_TB | G_SYM | G_BETA | G_NEG: gemm_inst<G_TB | G_SYM | G_BETA | G_NEG>(o, st); break;
     case G_TA | G_SYM | G_BETA | G_NEG: gemm_inst<G_TA | G_SYM | G_BETA | G_NEG>(o, st); break;
     default: return hipErrorInvalidValue;

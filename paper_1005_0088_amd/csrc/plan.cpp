@@ -534,6 +534,13 @@ void finalize_plan(Plan& P) {
     P.bytes_model += 16.0 * (2.0 * (double(F.nj) * F.nj + double(F.nu) * F.nj) + 3.0 * double(F.nu) * F.nu);
   }
   P.panel_total = po;
+  int64_t lo = 0;
+  for (int f = 0; f < nf; ++f) {
+    Front& F = P.fronts[f];
+    F.l_off = lo;
+    lo += int64_t(F.nu) * F.nj;
+  }
+  P.l_total = std::max<int64_t>(lo, 1);
   for (int d = 0; d < P.n_levels; ++d) {
     int64_t uo = 0, to = 0;
     for (int f : by_depth[d]) {
@@ -541,7 +548,7 @@ void finalize_plan(Plan& P) {
       F.upd_off = uo;
       uo += int64_t(F.nu) * F.nu;
       F.temp_off = to;
-      to += std::max<int64_t>(int64_t(F.nu) * F.nj, rec_temp(F.nj));
+      to += rec_temp(F.nj);
     }
     P.upd_total = std::max(P.upd_total, uo);
     P.temp_total = std::max(P.temp_total, to);
@@ -668,22 +675,19 @@ void finalize_plan(Plan& P) {
       B.smallinv(P.upward, small, d);
       for (auto& g : groups) B.inverse(P.upward, g.second, g.first, 0, 0, d);
     }
-    // L = B A^{-1};  Upd = Upd - L B^T;  B <- L
+    // L = B A^{-1} (into the L buffer);  Upd = Upd - L B^T (lower triangle)
     {
       std::vector<GemmProb> g1, g2;
-      std::vector<CopyDesc> c1;
       for (int f : fr) {
         const Front& F = P.fronts[f];
         if (F.nu == 0) continue;
         const int ld = F.nj + F.nu;
-        g1.push_back(GemmProb{F.nu, F.nj, F.nj, ld, ld, 0, F.nu, 0, F.panel_off + F.nj, F.panel_off, 0, F.temp_off});
-        g2.push_back(GemmProb{F.nu, F.nu, F.nj, F.nu, ld, F.nu, F.nu, 0, F.temp_off, F.panel_off + F.nj, F.upd_off,
+        g1.push_back(GemmProb{F.nu, F.nj, F.nj, ld, ld, 0, F.nu, 0, F.panel_off + F.nj, F.panel_off, 0, F.l_off});
+        g2.push_back(GemmProb{F.nu, F.nu, F.nj, F.nu, ld, F.nu, F.nu, 0, F.l_off, F.panel_off + F.nj, F.upd_off,
                               F.upd_off});
-        c1.push_back(CopyDesc{F.temp_off, F.panel_off + F.nj, F.nu, ld, F.nu, F.nj});
       }
-      B.gemm(P.upward, 0, BUF_PANEL, BUF_PANEL, 0, BUF_TEMP, g1, d);
-      B.gemm(P.upward, G_TB | G_SYM | G_BETA | G_NEG, BUF_TEMP, BUF_PANEL, ubuf, ubuf, g2, d);
-      B.copy(P.upward, false, BUF_TEMP, BUF_PANEL, c1, d);
+      B.gemm(P.upward, 0, BUF_PANEL, BUF_PANEL, 0, BUF_L, g1, d);
+      B.gemm(P.upward, G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR, BUF_L, BUF_PANEL, ubuf, ubuf, g2, d);
     }
   }
   for (int d = 1; d < P.n_levels; ++d) {
@@ -711,21 +715,18 @@ void finalize_plan(Plan& P) {
       if (op.count) P.downward.push_back(op);
     }
     std::vector<GemmProb> g3, g4;
-    std::vector<CopyDesc> c2;
     for (int f : fr) {
       const Front& F = P.fronts[f];
       if (F.nu == 0) continue;
       const int ld = F.nj + F.nu;
-      // T = -G_UU L
-      g3.push_back(GemmProb{F.nu, F.nj, F.nu, F.nu, ld, 0, F.nu, 0, F.upd_off, F.panel_off + F.nj, 0, F.temp_off});
-      // G_JJ = A^{-1} - L^T T
-      g4.push_back(GemmProb{F.nj, F.nj, F.nu, ld, F.nu, ld, ld, 0, F.panel_off + F.nj, F.temp_off, F.panel_off,
+      // G_UJ = -G_UU L, written over B in the panel (G_UU from its lower triangle)
+      g3.push_back(GemmProb{F.nu, F.nj, F.nu, F.nu, F.nu, 0, ld, 0, F.upd_off, F.l_off, 0, F.panel_off + F.nj});
+      // G_JJ = A^{-1} - L^T G_UJ
+      g4.push_back(GemmProb{F.nj, F.nj, F.nu, F.nu, ld, ld, ld, 0, F.l_off, F.panel_off + F.nj, F.panel_off,
                             F.panel_off});
-      c2.push_back(CopyDesc{F.temp_off, F.panel_off + F.nj, F.nu, ld, F.nu, F.nj});
     }
-    B.gemm(P.downward, G_NEG, ubuf, BUF_PANEL, 0, BUF_TEMP, g3, d);
-    B.gemm(P.downward, G_TA | G_SYM | G_BETA | G_NEG, BUF_PANEL, BUF_TEMP, BUF_PANEL, BUF_PANEL, g4, d);
-    B.copy(P.downward, false, BUF_TEMP, BUF_PANEL, c2, d);
+    B.gemm(P.downward, G_NEG | G_SYMA, ubuf, BUF_L, 0, BUF_PANEL, g3, d);
+    B.gemm(P.downward, G_TA | G_SYM | G_BETA | G_NEG, BUF_L, BUF_PANEL, BUF_PANEL, BUF_PANEL, g4, d);
   }
 }
 

@@ -26,7 +26,8 @@ struct Front {
   std::vector<int> children;
   int64_t panel_off = 0;      // column-major (nj+nu) x nj panel, per pole
   int64_t upd_off = 0;        // nu x nu update / gathered-G block in the depth's buffer
-  int64_t temp_off = 0;       // scratch region in the temp buffer
+  int64_t temp_off = 0;       // scratch region in the temp buffer (recursive pivot inverse)
+  int64_t l_off = 0;          // L_UJ = B A^{-1} (nu x nj, column-major, ld nu) in the L buffer
 };
 
 // Work descriptors shared with the device code (plain structs, 8-byte aligned).
@@ -73,11 +74,14 @@ struct GatherDesc {
   int32_t nu, pnj, pnu, pad;
 };
 
-enum BufId { BUF_PANEL = 0, BUF_UPD0 = 1, BUF_UPD1 = 2, BUF_TEMP = 3, BUF_COUNT = 4 };
+enum BufId { BUF_PANEL = 0, BUF_UPD0 = 1, BUF_UPD1 = 2, BUF_TEMP = 3, BUF_L = 4, BUF_COUNT = 5 };
 
 enum OpKind { OP_EXTADD, OP_ASSEMBLE, OP_SMALLINV, OP_GEMM, OP_COPY, OP_GATHER };
 
-enum GemmFlags { G_TA = 1, G_TB = 2, G_SYM = 4, G_BETA = 8, G_NEG = 16 };
+// G_SYMA: A is symmetric and only its lower triangle is stored (entry (m, k)
+// is read from (max, min)); G_NOMIRROR: with G_SYM, write the lower triangle
+// of C only.
+enum GemmFlags { G_TA = 1, G_TB = 2, G_SYM = 4, G_BETA = 8, G_NEG = 16, G_NOMIRROR = 32, G_SYMA = 64 };
 // Op-level marker (not a kernel flag): the GEMM belongs to a pivot-block
 // inverse and always runs in FP64.
 constexpr int OP_PIVOT = 1 << 8;
@@ -103,6 +107,7 @@ struct Plan {
   int64_t panel_total = 0;     // complex elements per pole
   int64_t upd_total = 0;       // per depth buffer, complex elements per pole (max over depths)
   int64_t temp_total = 0;
+  int64_t l_total = 0;         // complex elements per pole of the L buffer
   std::vector<int64_t> out_slot, asm_slot;   // per CSR entry
 
   // device program
