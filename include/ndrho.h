@@ -66,6 +66,8 @@ typedef struct {
   int32_t verbose;      /* 0 = quiet */
   int32_t fp64_poles;   /* mixed mode: the fp64_poles shifts nearest the real axis stay FP64 (default 8) */
   double fp64_pole_im;  /* mixed mode: shifts with Im alpha < fp64_pole_im also stay FP64 (default 0.05) */
+  int32_t fp64_far_poles; /* mixed mode: the fp64_far_poles shifts farthest from the axis stay FP64 too
+                             (default 8): their residues are as large as those of the nearest ones */
   int32_t use_graph;    /* 1 (default): capture the launch sequence of an evaluation in a hipGraph and replay it */
   int32_t gemm_variant; /* mixed mode, front-update GEMMs of the low poles: -1 (default) per-launch choice
                            (heuristic, refined by ndrho_autotune); 0 FP64; 1 FP32 products on 64x64 tiles;

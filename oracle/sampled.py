@@ -63,3 +63,35 @@ def rho_columns(h, s, mu, beta, n_poles, cols, pool=None):
     for wp, g in zip(w, cols_g):
         out += wp * g.real
     return out
+
+
+def _gmres_block(h, s, alpha, cols, rtol):
+    return np.stack([green_column_gmres(h, s, alpha, j, rtol) for j in cols], axis=1)
+
+
+def s_inverse_columns_cg(s, cols, rtol=1e-14):
+    """S^{-1}[:, cols] by conjugate gradients (S is symmetric positive definite)."""
+    out = np.empty((s.shape[0], len(cols)))
+    for k, j in enumerate(cols):
+        b = np.zeros(s.shape[0])
+        b[j] = 1.0
+        x, info = spl.cg(s, b, rtol=rtol, atol=0.0, maxiter=2000)
+        if info != 0:
+            raise RuntimeError("CG did not converge (info=%d)" % info)
+        out[:, k] = x
+    return out
+
+
+def rho_columns_gmres(h, s, mu, beta, n_poles, cols, pool=None, rtol=1e-13):
+    """Columns `cols` of rho (Eq. (8)) with GMRES solves per pole and column
+    (for systems whose sparse LU is too large); M0 columns by CG on S.
+    Accurate to about rtol times the condition number of each shifted matrix."""
+    z, r = cf_poles(n_poles)
+    alphas = mu + 1j * z / beta
+    w = -(4.0 / beta) * r
+    out = s_inverse_columns_cg(s, cols).copy()
+    args = [(h, s, a, cols, rtol) for a in alphas]
+    cols_g = pool.starmap(_gmres_block, args) if pool is not None else [_gmres_block(*a) for a in args]
+    for wp, g in zip(w, cols_g):
+        out += wp * g.real
+    return out

@@ -24,7 +24,8 @@ class NdrhoError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("leaf_rows", C.c_int32), ("precision", C.c_int32), ("pole_batch", C.c_int32),
                 ("mem_fraction", C.c_double), ("verbose", C.c_int32), ("fp64_poles", C.c_int32),
-                ("fp64_pole_im", C.c_double), ("use_graph", C.c_int32), ("gemm_variant", C.c_int32)]
+                ("fp64_pole_im", C.c_double), ("fp64_far_poles", C.c_int32), ("use_graph", C.c_int32),
+                ("gemm_variant", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -220,7 +221,7 @@ class Context:
     """
 
     def __init__(self, device=0, stream=None, leaf_rows=32, pole_batch=0, mem_fraction=0.8, precision="fp64",
-                 fp64_poles=None, fp64_pole_im=None, use_graph=True, gemm_variant=-1):
+                 fp64_poles=None, fp64_pole_im=None, use_graph=True, gemm_variant=-1, fp64_far_poles=None):
         self._lib = load_library()
         opt = Options()
         self._lib.ndrho_default_options(C.byref(opt))
@@ -232,6 +233,8 @@ class Context:
             opt.fp64_poles = int(fp64_poles)
         if fp64_pole_im is not None:
             opt.fp64_pole_im = float(fp64_pole_im)
+        if fp64_far_poles is not None:
+            opt.fp64_far_poles = int(fp64_far_poles)
         opt.use_graph = int(bool(use_graph))
         opt.gemm_variant = int(gemm_variant)
         handle = None

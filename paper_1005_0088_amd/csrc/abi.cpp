@@ -539,15 +539,37 @@ struct ndrho_ctx {
     unions.clear();
   }
 
-  void set_shifts(DevStruct& S, const std::vector<double2>& alpha, const std::vector<double>& w, bool add_m0) {
-    // shifts kept in FP64 in mixed mode: the leading run of shifts that are
-    // among the fp64_poles nearest the real axis or below fp64_pole_im
-    int hi = static_cast<int>(alpha.size());
+  void set_shifts(DevStruct& S, const std::vector<double2>& alpha_in, const std::vector<double>& w_in,
+                  bool add_m0) {
+    // Mixed mode keeps in FP64 the fp64_poles shifts nearest the real axis,
+    // the fp64_far_poles farthest from it, and any with |Im alpha| below
+    // fp64_pole_im.  Those are moved to the front (stable order otherwise):
+    // the pole sum is still taken in one fixed order.
+    const int n = static_cast<int>(alpha_in.size());
+    std::vector<double2> alpha = alpha_in;
+    std::vector<double> w = w_in;
+    int hi = n;
     if (opt.precision == NDRHO_MIXED_FP32) {
+      std::vector<int> by_im(n);
+      for (int i = 0; i < n; ++i) by_im[i] = i;
+      std::stable_sort(by_im.begin(), by_im.end(),
+                       [&](int a, int b) { return std::fabs(alpha_in[a].y) < std::fabs(alpha_in[b].y); });
+      std::vector<char> keep(n, 0);
+      for (int r = 0; r < n; ++r) {
+        const int i = by_im[r];
+        if (r < opt.fp64_poles || r >= n - opt.fp64_far_poles || std::fabs(alpha_in[i].y) < opt.fp64_pole_im)
+          keep[i] = 1;
+      }
+      alpha.clear();
+      w.clear();
+      for (int pass = 1; pass >= 0; --pass)
+        for (int i = 0; i < n; ++i)
+          if (keep[i] == pass) {
+            alpha.push_back(alpha_in[i]);
+            w.push_back(w_in[i]);
+          }
       hi = 0;
-      while (hi < static_cast<int>(alpha.size()) &&
-             (hi < opt.fp64_poles || std::fabs(alpha[hi].y) < opt.fp64_pole_im))
-        ++hi;
+      for (int i = 0; i < n; ++i) hi += keep[i];
     }
     S.n_hi = hi;
     if (S.d_alpha) HIP_OK(hipFree(S.d_alpha));
@@ -602,6 +624,7 @@ int ndrho_default_options(ndrho_options* opt) {
   opt->verbose = 0;
   opt->fp64_poles = 8;
   opt->fp64_pole_im = 0.05;
+  opt->fp64_far_poles = 8;
   opt->use_graph = 1;
   opt->gemm_variant = -1;
   return NDRHO_OK;
@@ -621,7 +644,8 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
     if (c->opt.leaf_rows < 1) fail(NDRHO_EINVAL, "leaf_rows must be >= 1");
     if (c->opt.precision != NDRHO_FP64 && c->opt.precision != NDRHO_MIXED_FP32)
       fail(NDRHO_EUNSUPPORTED, "precision must be NDRHO_FP64 or NDRHO_MIXED_FP32");
-    if (c->opt.fp64_poles < 0 || !(c->opt.fp64_pole_im >= 0.0)) fail(NDRHO_EINVAL, "invalid FP64 pole rule");
+    if (c->opt.fp64_poles < 0 || c->opt.fp64_far_poles < 0 || !(c->opt.fp64_pole_im >= 0.0))
+      fail(NDRHO_EINVAL, "invalid FP64 pole rule");
     if (c->opt.gemm_variant < -1 || c->opt.gemm_variant >= V_COUNT) fail(NDRHO_EINVAL, "invalid gemm_variant");
     if (c->opt.pole_batch < 0) fail(NDRHO_EINVAL, "pole_batch must be >= 0");
     if (!(c->opt.mem_fraction > 0.0 && c->opt.mem_fraction <= 1.0)) fail(NDRHO_EINVAL, "mem_fraction must be in (0, 1]");

@@ -210,7 +210,8 @@ def test_mixed_fp32_single_shift_close_to_dense(variant):
     import paper_1005_0088_amd as nd
     sysd = lattice((7, 6, 5), "nn", 14)
     h, s, rows, cols = _dense(sysd)
-    with nd.Context(0, precision="mixed_fp32", fp64_poles=0, fp64_pole_im=0.0, gemm_variant=variant) as c:
+    with nd.Context(0, precision="mixed_fp32", fp64_poles=0, fp64_pole_im=0.0, fp64_far_poles=0,
+                    gemm_variant=variant) as c:
         sid = _register(c, sysd)
         c.set_shifts(sid, np.array([0.2 + 0.5j]), np.array([1.0]), add_m0=False)
         got = c.density_matrix(sid)
@@ -223,17 +224,19 @@ def test_mixed_fp32_single_shift_close_to_dense(variant):
 @pytest.mark.parametrize("dims,nb,fp64_poles,tol", [((9, 9, 9), "nn", 8, 1e-7), ((9, 9, 9), "nn", 0, 1e-6),
                                                     ((20, 18), "nn2", 8, 1e-7)])
 def test_mixed_rho_against_oracle(dims, nb, fp64_poles, tol):
+    # fp64_poles shifts nearest and as many farthest from the real axis in FP64
     import paper_1005_0088_amd as nd
     sysd = lattice(dims, nb, 15)
     h, s, rows, cols = _dense(sysd)
     eps, c = dense.eigen(h, s)
     mu = dense.mu_for_count(eps, BETA, float(sysd["n"]))
     ref = dense.rho_cf_pattern(eps, c, mu, BETA, 80, rows, cols)
-    with nd.Context(0, precision="mixed_fp32", fp64_poles=fp64_poles, fp64_pole_im=0.05) as cx:
+    with nd.Context(0, precision="mixed_fp32", fp64_poles=fp64_poles, fp64_far_poles=fp64_poles,
+                    fp64_pole_im=0.05, gemm_variant=2) as cx:
         sid = _register(cx, sysd)
         cx.set_poles(sid, mu, BETA, 80)
         got = cx.density_matrix(sid)
-        assert cx.stats(sid)["n_fp64_poles"] == fp64_poles
+        assert cx.stats(sid)["n_fp64_poles"] == 2 * fp64_poles
     err = np.max(np.abs(got - ref))
     print("mixed fp64_poles=%d err=%.3e" % (fp64_poles, err))
     assert err < tol
