@@ -127,82 +127,93 @@ __global__ __launch_bounds__(256) void k_assemble(const int64_t* __restrict__ sl
 
 // ----------------------------------------------------------------- pivot inverse
 //
-// In-place inverse of an n x n (n <= 64) pivot block by Gauss-Jordan
-// elimination without pivoting, one workgroup per (block, pole), the block
-// held in registers (each thread owns up to 16 entries) with row k and column
-// k broadcast through LDS.  The pivots met are the D of the block's LDL^T
-// (Eq. (18)), so they are checked here: |d| <= 1e-14 max|a_ii| or non-finite
+// In-place inverse of an n x n (n <= 64) symmetric pivot block by
+// Gauss-Jordan elimination without pivoting, one workgroup per (block, pole).
+// Thread t owns row r = t % 64 and the columns c = t / 64 + 4 i (i < 16) in
+// registers.  Step k publishes row k through LDS; column k is not needed
+// separately: for a symmetric start, after the pivots 0..k-1 have been
+// eliminated an entry between an eliminated and a remaining index equals
+// minus its transpose and all others equal their transpose, so
+// a_rk = -a_kr for r < k and a_rk = a_kr otherwise.  The pivots met are the
+// D of the block's LDL^T (Eq. (18)): |d| <= 1e-14 max|a_ii| or non-finite
 // counts as singular; with spd_check a pivot with d <= 0 or Im d != 0 counts
-// as "not positive definite" (used for the real factorization of S).  The
-// result is written symmetrized from its lower triangle.
+// as "not positive definite" (the real factorization of S).  The result is
+// written symmetrized from its lower triangle.
 __global__ __launch_bounds__(256) void k_smallinv(const InvDesc* __restrict__ descs, double2* __restrict__ panel,
                                                   int64_t ps, int* __restrict__ status, int spd_check) {
-  __shared__ double2 colk[2][64];
   __shared__ double2 rowk[2][64];
-  __shared__ double sdiag;
+  __shared__ double dmag[64];
   const InvDesc d = descs[blockIdx.x];
   const int n = d.n;
   const int64_t ld = d.ld;
   double2* a = panel + int64_t(blockIdx.y) * ps + d.off;
   const int tid = threadIdx.x;
-  const int nn = n * n;
+  const int r = tid & 63, cg = tid >> 6;
+  const bool live = r < n;
   double2 v[16];
-  int rr[16], cc[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const int e = tid + 256 * i;
-    rr[i] = e < nn ? e % n : -1;
-    cc[i] = e < nn ? e / n : -1;
-    v[i] = e < nn ? a[rr[i] + cc[i] * ld] : make_double2(0.0, 0.0);
+    const int c = cg + 4 * i;
+    v[i] = make_double2(0.0, 0.0);
+    if (live && c < n) v[i] = a[r + int64_t(c) * ld];
   }
-  if (tid == 0) {
-    double m = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double2 x = a[i + i * ld];
-      m = fmax(m, fabs(x.x) + fabs(x.y));
-    }
-    sdiag = m;
+  if (tid < n) {
+    const double2 x = a[tid + int64_t(tid) * ld];
+    dmag[tid] = fabs(x.x) + fabs(x.y);
   }
+  __syncthreads();
+  double sdiag = 0.0;
+  if (tid == 0)
+    for (int i = 0; i < n; ++i) sdiag = fmax(sdiag, dmag[i]);
   int bad_sing = 0, bad_spd = 0;
   for (int k = 0; k < n; ++k) {
     const int b = k & 1;
+    if (r == k) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      if (cc[i] == k) colk[b][rr[i]] = v[i];
-      if (rr[i] == k) rowk[b][cc[i]] = v[i];
+      for (int i = 0; i < 16; ++i) {
+        const int c = cg + 4 * i;
+        if (c < n) rowk[b][c] = v[i];
+      }
     }
     __syncthreads();
-    const double2 p = colk[b][k];
+    const double2 p = rowk[b][k];
     if (tid == 0) {
       const double mag = fabs(p.x) + fabs(p.y);
       if (!(mag > 1e-14 * sdiag) || !isfinite(p.x) || !isfinite(p.y)) bad_sing = 1;
       if (spd_check && !(p.x > 0.0 && p.y == 0.0)) bad_spd = 1;
     }
     const double2 pinv = cinv(p);
+    const double2 akr = rowk[b][r];
+    const double sg = r < k ? -1.0 : 1.0;  // a_rk = sg * a_kr
+    const double2 f = cmul(make_double2(sg * akr.x, sg * akr.y), pinv);  // a_rk / a_kk
+    const bool prow = r == k;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int r = rr[i], c = cc[i];
-      if (r < 0) continue;
-      if (r == k && c == k) {
-        v[i] = pinv;
-      } else if (r == k) {
-        v[i] = cmul(rowk[b][c], pinv);
-      } else if (c == k) {
-        const double2 t = cmul(colk[b][r], pinv);
-        v[i] = make_double2(-t.x, -t.y);
-      } else {
-        const double2 t = cmul(cmul(colk[b][r], pinv), rowk[b][c]);
-        v[i].x -= t.x;
-        v[i].y -= t.y;
-      }
+      const int c = cg + 4 * i;
+      const double2 rk = rowk[b][c & 63];
+      // row k: scaled by the pivot; column k: -a_rk / a_kk; else rank-1 update
+      // (selects on scalars: a select of double2 values goes through memory)
+      double ux = v[i].x - (f.x * rk.x - f.y * rk.y);
+      double uy = v[i].y - (f.x * rk.y + f.y * rk.x);
+      const double sx = rk.x * pinv.x - rk.y * pinv.y, sy = rk.x * pinv.y + rk.y * pinv.x;
+      const bool ck = c == k;
+      ux = ck ? -f.x : ux;
+      uy = ck ? -f.y : uy;
+      ux = prow ? (ck ? pinv.x : sx) : ux;
+      uy = prow ? (ck ? pinv.y : sy) : uy;
+      const bool act = live && c < n;
+      v[i].x = act ? ux : v[i].x;
+      v[i].y = act ? uy : v[i].y;
     }
   }
+  // symmetrized write-back from the lower triangle
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const int r = rr[i], c = cc[i];
-    if (r < 0 || r < c) continue;
-    a[r + c * ld] = v[i];
-    if (r != c) a[c + r * ld] = v[i];
+    const int c = cg + 4 * i;
+    if (live && c < n && r >= c) {
+      a[r + int64_t(c) * ld] = v[i];
+      if (r != c) a[c + int64_t(r) * ld] = v[i];
+    }
   }
   if (tid == 0) {
     if (bad_sing) atomicAdd(&status[0], 1);

@@ -347,46 +347,58 @@ struct Builder {
     prog.push_back(op);
   }
 
-  // In-place inverse of the leading nj x nj block of each front in `grp`
-  // (all with the same nj), by the block form of Eq. (21) applied
+  // In-place inverse of the leading n_f x n_f block (at row/column r0_f) of
+  // each front f in `grp`, by the block form of Eq. (21) applied
   // recursively: A11^{-1}; L = A21 A11^{-1}; S = A22 - L A21^T; S^{-1};
-  // G21 = -S^{-1} L; G11 = A11^{-1} - L^T G21; G12 = G21^T.
-  void inverse(std::vector<Op>& prog, const std::vector<int>& grp, int n, int r0, int64_t tstack, int depth) {
-    if (n <= 64) {
+  // G21 = -S^{-1} L; G11 = A11^{-1} - L^T G21; G12 = G21^T.  All blocks of a
+  // group span the same number of 64-row blocks, so they share one split
+  // (n1 = 64 ceil(blocks/2)) and every launch of the recursion serves the
+  // whole group, each problem with its own sizes.
+  void inverse(std::vector<Op>& prog, const std::vector<int>& grp, const std::vector<int>& n,
+               const std::vector<int>& r0, const std::vector<int64_t>& tstack, int depth) {
+    const int nb = (n[0] + 63) / 64;
+    if (nb <= 1) {
       std::vector<InvDesc> d;
-      for (int f : grp) {
-        const Front& F = P.fronts[f];
+      for (size_t g = 0; g < grp.size(); ++g) {
+        const Front& F = P.fronts[grp[g]];
         const int ld = F.nj + F.nu;
-        d.push_back(InvDesc{F.panel_off + r0 + int64_t(r0) * ld, ld, n});
+        d.push_back(InvDesc{F.panel_off + r0[g] + int64_t(r0[g]) * ld, ld, n[g]});
       }
       smallinv(prog, d, depth);
       return;
     }
-    const int nb = (n + 63) / 64;
-    const int n1 = 64 * ((nb + 1) / 2), n2 = n - n1;
-    inverse(prog, grp, n1, r0, tstack, depth);
+    const int n1 = 64 * ((nb + 1) / 2);
+    std::vector<int> n1v(grp.size(), n1), n2v(grp.size()), r1v(grp.size());
+    std::vector<int64_t> t2v(grp.size());
+    for (size_t g = 0; g < grp.size(); ++g) {
+      n2v[g] = n[g] - n1;
+      r1v[g] = r0[g] + n1;
+      t2v[g] = tstack[g] + int64_t(n2v[g]) * n1;
+    }
+    inverse(prog, grp, n1v, r0, tstack, depth);
     auto at = [&](const Front& F, int r, int c) { return F.panel_off + r + int64_t(c) * (F.nj + F.nu); };
     std::vector<GemmProb> ga, gb, gc, gd;
     std::vector<CopyDesc> ct;
-    for (int f : grp) {
-      const Front& F = P.fronts[f];
+    for (size_t g = 0; g < grp.size(); ++g) {
+      const Front& F = P.fronts[grp[g]];
       const int ld = F.nj + F.nu;
-      const int64_t t = F.temp_off + tstack;
+      const int n2 = n2v[g], a = r0[g];
+      const int64_t t = F.temp_off + tstack[g];
       // L = A21 A11^{-1}   (n2 x n1)
-      ga.push_back(GemmProb{n2, n1, n1, ld, ld, 0, n2, 0, at(F, r0 + n1, r0), at(F, r0, r0), 0, t});
+      ga.push_back(GemmProb{n2, n1, n1, ld, ld, 0, n2, 0, at(F, a + n1, a), at(F, a, a), 0, t});
       // A22 <- A22 - L A21^T
-      gb.push_back(GemmProb{n2, n2, n1, n2, ld, ld, ld, 0, t, at(F, r0 + n1, r0), at(F, r0 + n1, r0 + n1),
-                            at(F, r0 + n1, r0 + n1)});
+      gb.push_back(GemmProb{n2, n2, n1, n2, ld, ld, ld, 0, t, at(F, a + n1, a), at(F, a + n1, a + n1),
+                            at(F, a + n1, a + n1)});
       // A21 <- -S^{-1} L
-      gc.push_back(GemmProb{n2, n1, n2, ld, n2, 0, ld, 0, at(F, r0 + n1, r0 + n1), t, 0, at(F, r0 + n1, r0)});
+      gc.push_back(GemmProb{n2, n1, n2, ld, n2, 0, ld, 0, at(F, a + n1, a + n1), t, 0, at(F, a + n1, a)});
       // A11 <- A11^{-1} - L^T G21
-      gd.push_back(GemmProb{n1, n1, n2, n2, ld, ld, ld, 0, t, at(F, r0 + n1, r0), at(F, r0, r0), at(F, r0, r0)});
+      gd.push_back(GemmProb{n1, n1, n2, n2, ld, ld, ld, 0, t, at(F, a + n1, a), at(F, a, a), at(F, a, a)});
       // A12 <- G21^T
-      ct.push_back(CopyDesc{at(F, r0 + n1, r0), at(F, r0, r0 + n1), ld, ld, n1, n2});
+      ct.push_back(CopyDesc{at(F, a + n1, a), at(F, a, a + n1), ld, ld, n1, n2});
     }
     gemm(prog, OP_PIVOT, BUF_PANEL, BUF_PANEL, 0, BUF_TEMP, ga, depth);
     gemm(prog, OP_PIVOT | G_TB | G_SYM | G_BETA | G_NEG, BUF_TEMP, BUF_PANEL, BUF_PANEL, BUF_PANEL, gb, depth);
-    inverse(prog, grp, n2, r0 + n1, tstack + int64_t(n2) * n1, depth);
+    inverse(prog, grp, n2v, r1v, t2v, depth);
     gemm(prog, OP_PIVOT | G_NEG, BUF_PANEL, BUF_TEMP, 0, BUF_PANEL, gc, depth);
     gemm(prog, OP_PIVOT | G_TA | G_SYM | G_BETA | G_NEG, BUF_TEMP, BUF_PANEL, BUF_PANEL, BUF_PANEL, gd, depth);
     copy(prog, true, BUF_PANEL, BUF_PANEL, ct, depth);
@@ -663,17 +675,23 @@ void finalize_plan(Plan& P) {
       op.depth = d;
       P.upward.push_back(op);
     }
-    // pivot-block inverses
+    // pivot-block inverses: blocks of <= 64 rows in one launch, larger ones
+    // grouped by their number of 64-row blocks
     {
       std::vector<InvDesc> small;
       std::map<int, std::vector<int>> groups;
       for (int f : fr) {
         const Front& F = P.fronts[f];
         if (F.nj <= 64) small.push_back(InvDesc{F.panel_off, F.nj + F.nu, F.nj});
-        else groups[F.nj].push_back(f);
+        else groups[(F.nj + 63) / 64].push_back(f);
       }
       B.smallinv(P.upward, small, d);
-      for (auto& g : groups) B.inverse(P.upward, g.second, g.first, 0, 0, d);
+      for (auto& g : groups) {
+        std::vector<int> nv, r0(g.second.size(), 0);
+        std::vector<int64_t> t0(g.second.size(), 0);
+        for (int f : g.second) nv.push_back(P.fronts[f].nj);
+        B.inverse(P.upward, g.second, nv, r0, t0, d);
+      }
     }
     // L = B A^{-1} (into the L buffer);  Upd = Upd - L B^T (lower triangle)
     {

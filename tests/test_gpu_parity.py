@@ -381,3 +381,22 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
         assert np.array_equal(c.density_matrix(s2), got)
     with open(cache) as f:
         assert len(f.read().splitlines()) == 1
+
+
+def test_large_3d_fp64_against_oracle_sample():
+    # 40^3 sites x 4 (N = 256 000), 100 poles, 10 poles per device pass.  The
+    # stored values come from GMRES solves (rtol 1e-13) per pole and column,
+    # whose own error (about rtol times the conditioning, summed over poles)
+    # sets the tolerance here.
+    import paper_1005_0088_amd as nd
+    from synth import config_system
+    g = _golden("cubic3d_40x4")
+    sysd = config_system("cubic3d_40x4")
+    with nd.Context(0) as c:
+        sid = _register(c, sysd)
+        c.set_poles(sid, g["mu"], g["beta"], g["n_poles"])
+        rho = c.density_matrix(sid)
+        assert c.stats(sid)["pole_batch"] < g["n_poles"]     # several passes over pole batches
+    err = np.max(np.abs(rho[np.asarray(g["entries"])] - np.asarray(g["values"])))
+    print("cubic3d_40x4 fp64 max err on %d sampled entries: %.3e" % (len(g["entries"]), err))
+    assert err < 1e-9
