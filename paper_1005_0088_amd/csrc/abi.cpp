@@ -310,6 +310,8 @@ struct ndrho_ctx {
           break;
         case OP_SMALLINV:
           d.inv = S.inv + op.begin;
+          d.count16 = op.inv16;
+          d.count32 = op.inv32;
           timed(NDRHO_K_PIVOT_INV, 0.0, [&] { e = launch_smallinv(d, status, spd_check, stream); });
           break;
         case OP_GEMM: {

@@ -16,6 +16,7 @@ struct DevOp {
   bool fp32 = false;     // GEMM products on the FP32 matrix cores
   bool tile128 = false;  // FP32 GEMM on 128x128 tiles (else 64x64)
   int64_t count = 0, tile_count = 0;
+  int64_t count16 = 0, count32 = 0;  // pivot inverse: blocks of the n <= 16 and n <= 32 classes
   const GemmProb* gemm = nullptr;
   const TileRef* gemm_tiles = nullptr;
   const InvDesc* inv = nullptr;

@@ -127,10 +127,11 @@ __global__ __launch_bounds__(256) void k_assemble(const int64_t* __restrict__ sl
 
 // ----------------------------------------------------------------- pivot inverse
 //
-// In-place inverse of an n x n (n <= 64) symmetric pivot block by
+// In-place inverse of an n x n (n <= NMAX) symmetric pivot block by
 // Gauss-Jordan elimination without pivoting, one workgroup per (block, pole).
-// Thread t owns row r = t % 64 and the columns c = t / 64 + 4 i (i < 16) in
-// registers.  Step k publishes row k through LDS; column k is not needed
+// Size classes: NMAX = 64 on 512 threads, 32 on 128 and 16 on one wave.
+// Thread t owns row r = t % NMAX and the columns c = t / NMAX + CG i
+// (CG = THREADS / NMAX column groups, i < NMAX / CG) in registers.  Step k publishes row k through LDS; column k is not needed
 // separately: for a symmetric start, after the pivots 0..k-1 have been
 // eliminated an entry between an eliminated and a remaining index equals
 // minus its transpose and all others equal their transpose, so
@@ -139,21 +140,24 @@ __global__ __launch_bounds__(256) void k_assemble(const int64_t* __restrict__ sl
 // counts as singular; with spd_check a pivot with d <= 0 or Im d != 0 counts
 // as "not positive definite" (the real factorization of S).  The result is
 // written symmetrized from its lower triangle.
-__global__ __launch_bounds__(256) void k_smallinv(const InvDesc* __restrict__ descs, double2* __restrict__ panel,
-                                                  int64_t ps, int* __restrict__ status, int spd_check) {
-  __shared__ double2 rowk[2][64];
-  __shared__ double dmag[64];
+template <int NMAX, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_smallinv(const InvDesc* __restrict__ descs, double2* __restrict__ panel,
+                                                      int64_t ps, int* __restrict__ status, int spd_check) {
+  constexpr int CG = THREADS / NMAX, COLS = NMAX / CG;
+  static_assert(CG * NMAX == THREADS && CG * COLS == NMAX, "size class");
+  __shared__ double2 rowk[2][NMAX];
+  __shared__ double dmag[NMAX];
   const InvDesc d = descs[blockIdx.x];
   const int n = d.n;
   const int64_t ld = d.ld;
   double2* a = panel + int64_t(blockIdx.y) * ps + d.off;
   const int tid = threadIdx.x;
-  const int r = tid & 63, cg = tid >> 6;
+  const int r = tid % NMAX, cg = tid / NMAX;
   const bool live = r < n;
-  double2 v[16];
+  double2 v[COLS];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int c = cg + 4 * i;
+  for (int i = 0; i < COLS; ++i) {
+    const int c = cg + CG * i;
     v[i] = make_double2(0.0, 0.0);
     if (live && c < n) v[i] = a[r + int64_t(c) * ld];
   }
@@ -170,8 +174,8 @@ __global__ __launch_bounds__(256) void k_smallinv(const InvDesc* __restrict__ de
     const int b = k & 1;
     if (r == k) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int c = cg + 4 * i;
+      for (int i = 0; i < COLS; ++i) {
+        const int c = cg + CG * i;
         if (c < n) rowk[b][c] = v[i];
       }
     }
@@ -188,9 +192,9 @@ __global__ __launch_bounds__(256) void k_smallinv(const InvDesc* __restrict__ de
     const double2 f = cmul(make_double2(sg * akr.x, sg * akr.y), pinv);  // a_rk / a_kk
     const bool prow = r == k;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int c = cg + 4 * i;
-      const double2 rk = rowk[b][c & 63];
+    for (int i = 0; i < COLS; ++i) {
+      const int c = cg + CG * i;
+      const double2 rk = rowk[b][c];
       // row k: scaled by the pivot; column k: -a_rk / a_kk; else rank-1 update
       // (selects on scalars: a select of double2 values goes through memory)
       double ux = v[i].x - (f.x * rk.x - f.y * rk.y);
@@ -208,8 +212,8 @@ __global__ __launch_bounds__(256) void k_smallinv(const InvDesc* __restrict__ de
   }
   // symmetrized write-back from the lower triangle
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int c = cg + 4 * i;
+  for (int i = 0; i < COLS; ++i) {
+    const int c = cg + CG * i;
     if (live && c < n && r >= c) {
       a[r + int64_t(c) * ld] = v[i];
       if (r != c) a[c + int64_t(r) * ld] = v[i];
@@ -661,10 +665,19 @@ hipError_t launch_assemble(const DevOp& o, const double* hv, const double* sv, c
   return hipGetLastError();
 }
 
+// The op's descriptors come sorted by size class: count16 blocks with n <= 16,
+// then count32 with n <= 32, then the rest (n <= 64).
 hipError_t launch_smallinv(const DevOp& o, int* status, int spd_check, hipStream_t st) {
-  if (o.count == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_smallinv, dim3(static_cast<unsigned>(o.count), o.npoles), dim3(256), 0, st, o.inv, o.c, o.sc,
-                     status, spd_check);
+  const int64_t n16 = o.count16, n32 = o.count32, n64 = o.count - n16 - n32;
+  if (n16 > 0)
+    hipLaunchKernelGGL((k_smallinv<16, 64>), dim3(static_cast<unsigned>(n16), o.npoles), dim3(64), 0, st, o.inv, o.c,
+                       o.sc, status, spd_check);
+  if (n32 > 0)
+    hipLaunchKernelGGL((k_smallinv<32, 128>), dim3(static_cast<unsigned>(n32), o.npoles), dim3(128), 0, st,
+                       o.inv + n16, o.c, o.sc, status, spd_check);
+  if (n64 > 0)
+    hipLaunchKernelGGL((k_smallinv<64, 512>), dim3(static_cast<unsigned>(n64), o.npoles), dim3(512), 0, st,
+                       o.inv + n16 + n32, o.c, o.sc, status, spd_check);
   return hipGetLastError();
 }
 

@@ -340,10 +340,17 @@ struct Builder {
     op.begin = static_cast<int64_t>(P.inv.size());
     op.count = static_cast<int64_t>(descs.size());
     op.depth = depth;
-    for (const InvDesc& d : descs) {
-      P.inv.push_back(d);
-      P.flops_exec += 8.0 * double(d.n) * d.n * d.n;
-    }
+    // sorted by size class (n <= 16, n <= 32, n <= 64), each on its own kernel
+    for (int cls = 0; cls < 3; ++cls)
+      for (const InvDesc& d : descs) {
+        if (d.n < 1 || d.n > 64) throw Error(NDRHO_EINVAL, "pivot block size out of range");
+        const int dc = d.n <= 16 ? 0 : d.n <= 32 ? 1 : 2;
+        if (dc != cls) continue;
+        P.inv.push_back(d);
+        P.flops_exec += 8.0 * double(d.n) * d.n * d.n;
+        if (cls == 0) ++op.inv16;
+        if (cls == 1) ++op.inv32;
+      }
     prog.push_back(op);
   }
 

@@ -93,6 +93,7 @@ struct Op {
   int64_t begin = 0, count = 0;          // descriptor range
   int64_t tile_begin = 0, tile_count = 0;
   int64_t tile128_begin = 0, tile128_count = 0;  // 128x128 tiles (FP32-product GEMMs)
+  int64_t inv16 = 0, inv32 = 0;  // SMALLINV: leading descriptors with n <= 16, then n <= 32
   int depth = 0;
   double flops = 0;          // useful flops per pole (GEMM)
 };
