@@ -21,6 +21,10 @@ sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+# split-BF16 front updates: 4 real products x 6 slice products of 2 flops per
+# complex multiply-add (8 useful flops)
+BF16X3_EXEC_PER_USEFUL = 48.0 / 8.0
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -61,7 +65,7 @@ def measured_traffic(name, precision):
     summary (calibrated FETCH_SIZE + WRITE_SIZE), or None when it is missing
     or the kernels have changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (name, "mixed" if precision != "fp64" else "fp64"))
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (name, precision))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -137,7 +141,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cubic3d_24x4", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="mixed_fp32", choices=["mixed_fp32", "fp64"])
+    ap.add_argument("--precision", default="mixed_fp32", choices=["mixed_fp32", "mixed_bf16x3", "fp64"])
     ap.add_argument("--fp64-poles", type=int, default=8)
     ap.add_argument("--forms", default="both", choices=["both", "head"],
                     help="both: also time the FP64 form as the complex128 reference; head: only --precision")
@@ -193,11 +197,17 @@ def main():
     st, prof = head["stats"][0], head["prof"]
     # dominant kernel: the FP64 front GEMMs in the FP64 form, the FP32-product
     # front GEMMs in the mixed form (peak of their own arithmetic)
+    exec_per_useful = 1.0
     if head["precision"] == "fp64":
         g, peak, kname = prof["gemm"], FP64_MFMA_PEAK_TFLOPS, "k_zgemm (complex FP64 front-update GEMMs)"
+    elif head["precision"] == "mixed_bf16x3":
+        g, peak, kname = (prof["gemm_bf16x3"], BF16_MFMA_PEAK_TFLOPS,
+                          "k_cgemm_bf3 (complex front-update GEMMs, split-BF16 products; executed BF16 flops)")
+        exec_per_useful = BF16X3_EXEC_PER_USEFUL
     else:
         g, peak, kname = prof["gemm_f32"], FP32_MFMA_PEAK_TFLOPS, "k_cgemm32 (complex front-update GEMMs, FP32 products)"
-    achieved = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    useful = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    achieved = useful * exec_per_useful
     gemm_tf = {k: (v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0)
                for k, v in prof.items() if k.startswith("gemm")}
 
@@ -212,7 +222,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head["precision"] == "fp64" else "f64+f32",
+        "dtype": {"fp64": "f64", "mixed_fp32": "f64+f32", "mixed_bf16x3": "f64+bf16x3"}[head["precision"]],
         "data": "synthetic",
         "config": {"workload": name, "description": WORKLOADS[name], "structures": len(systems), "n": n,
                    "nnz": nnz, "n_poles": n_poles, "kT_eV": 1.0 / BETA, "mu_eV": mu, "precision": head["precision"],
@@ -234,7 +244,8 @@ def main():
         "gemm_tflops": gemm_tf,
         "roofline": {"kernel": kname, "bound": "mfma",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(name, head["precision"]),
+                     "frac": achieved / peak, "useful_complex_tflops": useful,
+                     "traffic": measured_traffic(name, head["precision"]),
                      "traffic_unit": "bytes per launch (calibrated HBM read + write)",
                      "launches": g["launches"], "avg_launch_ms": g["ms"] / max(1, g["launches"]),
                      "flops_per_step": g["flops"]},

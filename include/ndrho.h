@@ -55,12 +55,17 @@ enum {
  *   NDRHO_MIXED_FP32: for poles away from the real axis (see fp64_poles,
  *                     fp64_pole_im) the four front-update GEMMs (L = B A^{-1},
  *                     Schur update, G_UJ, G_JJ) take FP32 products with FP32
- *                     accumulation, results summed into FP64 storage. */
-enum { NDRHO_FP64 = 0, NDRHO_MIXED_FP32 = 1 };
+ *                     accumulation, results summed into FP64 storage.
+ *   NDRHO_MIXED_BF16X3: the same GEMMs as compensated split-BF16 products:
+ *                     each FP64 operand is split into three bfloat16 slices
+ *                     and the six leading slice products run on the BF16
+ *                     matrix cores with FP32 accumulation (accuracy of an
+ *                     FP32 GEMM). */
+enum { NDRHO_FP64 = 0, NDRHO_MIXED_FP32 = 1, NDRHO_MIXED_BF16X3 = 2 };
 
 typedef struct {
   int32_t leaf_rows;    /* nested dissection stops at domains of <= leaf_rows rows (default 32) */
-  int32_t precision;    /* NDRHO_FP64 (default) or NDRHO_MIXED_FP32 */
+  int32_t precision;    /* NDRHO_FP64 (default), NDRHO_MIXED_FP32 or NDRHO_MIXED_BF16X3 */
   int32_t pole_batch;   /* poles per device pass; 0 = largest that fits the memory budget */
   double mem_fraction;  /* fraction of free device memory the workspace may use (default 0.8) */
   int32_t verbose;      /* 0 = quiet */
@@ -71,7 +76,7 @@ typedef struct {
   int32_t use_graph;    /* 1 (default): capture the launch sequence of an evaluation in a hipGraph and replay it */
   int32_t gemm_variant; /* mixed mode, front-update GEMMs of the low poles: -1 (default) per-launch choice
                            (heuristic, refined by ndrho_autotune); 0 FP64; 1 FP32 products on 64x64 tiles;
-                           2 FP32 products on 128x128 tiles */
+                           2 FP32 products on 128x128 tiles; 3 split-BF16 products on 128x128 tiles */
 } ndrho_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -170,9 +175,11 @@ int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out);
 
 /* Kernel kinds reported by the profile below. */
 enum { NDRHO_K_EXTADD = 0, NDRHO_K_ASSEMBLE = 1, NDRHO_K_PIVOT_INV = 2, NDRHO_K_GEMM = 3, NDRHO_K_COPY = 4,
-       NDRHO_K_GATHER = 5, NDRHO_K_ACCUM = 6, NDRHO_K_GEMM_PIVOT = 7, NDRHO_K_GEMM_F32 = 8, NDRHO_K_COUNT = 9 };
+       NDRHO_K_GATHER = 5, NDRHO_K_ACCUM = 6, NDRHO_K_GEMM_PIVOT = 7, NDRHO_K_GEMM_F32 = 8,
+       NDRHO_K_GEMM_BF16X3 = 9, NDRHO_K_COUNT = 10 };
 /* NDRHO_K_GEMM: FP64 front-update GEMMs; NDRHO_K_GEMM_PIVOT: FP64 GEMMs of the
- * recursive pivot-block inverse; NDRHO_K_GEMM_F32: FP32-product front updates. */
+ * recursive pivot-block inverse; NDRHO_K_GEMM_F32: FP32-product front updates;
+ * NDRHO_K_GEMM_BF16X3: split-BF16 front updates. */
 
 /* enable != 0: from now on every launch is bracketed by HIP events on the
  * context stream and its duration is added to a per-kind total (clears the

@@ -7,8 +7,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libndrho.so")
 
-FP64, MIXED_FP32 = 0, 1
-PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32}
+FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16x3": MIXED_BF16X3}
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTSPD", -4: "ESINGULAR", -5: "EDEVICE",
                 -6: "ESTATE", -7: "EUNSUPPORTED"}
@@ -325,7 +325,7 @@ class Context:
         self._check(self._lib.ndrho_stats(self._h, int(sid), C.byref(st)))
         return {k: getattr(st, k) for k, _ in Stats._fields_}
 
-    KINDS = ("extadd", "assemble", "pivot_inv", "gemm", "copy", "gather", "accum", "gemm_pivot", "gemm_f32")
+    KINDS = ("extadd", "assemble", "pivot_inv", "gemm", "copy", "gather", "accum", "gemm_pivot", "gemm_f32", "gemm_bf16x3")
 
     def profile(self, enable=True):
         self._check(self._lib.ndrho_profile(self._h, int(bool(enable))))

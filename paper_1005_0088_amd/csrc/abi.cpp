@@ -88,12 +88,21 @@ struct DevStruct {
 
 thread_local std::string g_err;  // errors without a context (create, plan utilities)
 
-enum { V_FP64 = 0, V_F32_64 = 1, V_F32_128 = 2, V_COUNT = 3 };
+enum { V_FP64 = 0, V_F32_64 = 1, V_F32_128 = 2, V_BF3 = 3, V_COUNT = 4 };
 
-// Default GEMM variant per op before any tuning: FP32 products on 128x128
-// tiles where the op's largest problem fills several such tiles, plain FP64
-// for the small fronts of the deep levels (where FP32 does not pay).
-std::vector<int8_t> default_variants(const Plan& P) {
+// Low-precision variants a precision mode may choose from (besides V_FP64).
+static bool variant_allowed(int precision, int v) {
+  if (v == V_FP64) return true;
+  if (precision == NDRHO_MIXED_FP32) return v == V_F32_64 || v == V_F32_128;
+  if (precision == NDRHO_MIXED_BF16X3) return v == V_BF3;
+  return false;
+}
+
+// Default GEMM variant per op before any tuning: low-precision products on
+// 128x128 tiles where the op's largest problem fills several such tiles,
+// plain FP64 for the small fronts of the deep levels (where they do not pay).
+std::vector<int8_t> default_variants(const Plan& P, int precision) {
+  const int8_t low = precision == NDRHO_MIXED_BF16X3 ? int8_t(V_BF3) : int8_t(V_F32_128);
   std::vector<int8_t> v;
   auto pick = [&](const Op& op) {
     if (op.kind != OP_GEMM || (op.flags & OP_PIVOT)) return int8_t(V_FP64);
@@ -102,7 +111,7 @@ std::vector<int8_t> default_variants(const Plan& P) {
       const GemmProb& g = P.gemm[op.begin + i];
       mx = std::max(mx, std::min(g.m, g.n));
     }
-    return int8_t(mx >= 256 ? V_F32_128 : V_FP64);
+    return mx >= 256 ? low : int8_t(V_FP64);
   };
   for (const Op& op : P.upward) v.push_back(pick(op));
   for (const Op& op : P.downward) v.push_back(pick(op));
@@ -110,7 +119,7 @@ std::vector<int8_t> default_variants(const Plan& P) {
 }
 
 // Device copies of a plan's descriptor arrays and tables.
-void upload_plan(DevStruct& ds, hipStream_t st) {
+void upload_plan(DevStruct& ds, hipStream_t st, int precision) {
   const Plan& P = ds.plan;
   ds.gemm = ds.put(P.gemm, st);
   ds.gemm_tiles = ds.put(P.gemm_tiles, st);
@@ -129,7 +138,7 @@ void upload_plan(DevStruct& ds, hipStream_t st) {
   ds.asm_sid = ds.put(P.asm_sid_sorted, st);
   ds.acc_slot = ds.put(P.acc_slot, st);
   ds.acc_entry = ds.put(P.acc_entry, st);
-  ds.variant = default_variants(P);
+  ds.variant = default_variants(P, precision);
 }
 
 }  // namespace
@@ -219,6 +228,7 @@ struct ndrho_ctx {
     return *structs[id];
   }
 
+  // complex elements per pole of the workspace
   static int64_t per_pole_elems(const Plan& P) {
     return P.panel_total + 2 * P.upd_total + P.temp_total + P.l_total;
   }
@@ -333,9 +343,10 @@ struct ndrho_ctx {
             timed(k64, op.flops * nhi, [&] { e = launch_gemm(h, stream); });
             if (e != hipSuccess) break;
           }
-          DevOp l = d;  // FP32 products for the others
-          l.fp32 = true;
-          if (var == V_F32_128) {
+          DevOp l = d;  // low-precision products for the others
+          l.fp32 = var == V_F32_64 || var == V_F32_128;
+          l.bf3 = var == V_BF3;
+          if (var == V_F32_128 || var == V_BF3) {
             l.tile128 = true;
             l.gemm_tiles = S.gemm_tiles + op.tile128_begin;
             l.tile_count = op.tile128_count;
@@ -343,7 +354,8 @@ struct ndrho_ctx {
           l.npoles = nb - nhi;
           l.a += nhi * l.sa, l.b += nhi * l.sb, l.c += nhi * l.sc;
           if (op.flags & G_BETA) l.c0 += nhi * l.sc0;
-          timed(NDRHO_K_GEMM_F32, op.flops * (nb - nhi), [&] { e = launch_gemm(l, stream); });
+          timed(l.bf3 ? NDRHO_K_GEMM_BF16X3 : NDRHO_K_GEMM_F32, op.flops * (nb - nhi),
+                [&] { e = launch_gemm(l, stream); });
           break;
         }
         case OP_COPY:
@@ -485,7 +497,7 @@ struct ndrho_ctx {
         HIP_OK(hipMemcpyAsync(ds->h + P.struct_nnz_off[k], m.h, bytes, hipMemcpyDeviceToDevice, stream));
         HIP_OK(hipMemcpyAsync(ds->s + P.struct_nnz_off[k], m.s, bytes, hipMemcpyDeviceToDevice, stream));
       }
-      upload_plan(*ds, stream);
+      upload_plan(*ds, stream, opt.precision);
       HIP_OK(hipStreamSynchronize(stream));
       compute_m0(*ds);
     } catch (...) {
@@ -551,7 +563,7 @@ struct ndrho_ctx {
     std::vector<double2> alpha = alpha_in;
     std::vector<double> w = w_in;
     int hi = n;
-    if (opt.precision == NDRHO_MIXED_FP32) {
+    if (opt.precision != NDRHO_FP64) {
       std::vector<int> by_im(n);
       for (int i = 0; i < n; ++i) by_im[i] = i;
       std::stable_sort(by_im.begin(), by_im.end(),
@@ -644,11 +656,14 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
     ndrho_default_options(&c->opt);
     if (opt) c->opt = *opt;
     if (c->opt.leaf_rows < 1) fail(NDRHO_EINVAL, "leaf_rows must be >= 1");
-    if (c->opt.precision != NDRHO_FP64 && c->opt.precision != NDRHO_MIXED_FP32)
-      fail(NDRHO_EUNSUPPORTED, "precision must be NDRHO_FP64 or NDRHO_MIXED_FP32");
+    if (c->opt.precision != NDRHO_FP64 && c->opt.precision != NDRHO_MIXED_FP32 &&
+        c->opt.precision != NDRHO_MIXED_BF16X3)
+      fail(NDRHO_EUNSUPPORTED, "precision must be NDRHO_FP64, NDRHO_MIXED_FP32 or NDRHO_MIXED_BF16X3");
     if (c->opt.fp64_poles < 0 || c->opt.fp64_far_poles < 0 || !(c->opt.fp64_pole_im >= 0.0))
       fail(NDRHO_EINVAL, "invalid FP64 pole rule");
-    if (c->opt.gemm_variant < -1 || c->opt.gemm_variant >= V_COUNT) fail(NDRHO_EINVAL, "invalid gemm_variant");
+    if (c->opt.gemm_variant < -1 || c->opt.gemm_variant >= V_COUNT ||
+        (c->opt.gemm_variant >= 0 && !variant_allowed(c->opt.precision, c->opt.gemm_variant)))
+      fail(NDRHO_EINVAL, "invalid gemm_variant for this precision");
     if (c->opt.pole_batch < 0) fail(NDRHO_EINVAL, "pole_batch must be >= 0");
     if (!(c->opt.mem_fraction > 0.0 && c->opt.mem_fraction <= 1.0)) fail(NDRHO_EINVAL, "mem_fraction must be in (0, 1]");
     int count = 0;
@@ -700,7 +715,7 @@ int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const
       std::vector<double> hv(H, H + P.nnz), sv(S, S + P.nnz);
       ds->h = ds->put(hv, st);
       ds->s = ds->put(sv, st);
-      upload_plan(*ds, st);
+      upload_plan(*ds, st, ctx->opt.precision);
       HIP_OK(hipStreamSynchronize(st));
       ctx->compute_m0(*ds);
     } catch (...) {
@@ -830,9 +845,10 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
     const int nops = static_cast<int>(P.upward.size() + P.downward.size());
     const int nb = ctx->batch_for(P, T.n_shifts);
     char keybuf[256];
-    std::snprintf(keybuf, sizeof(keybuf), "ndrho-tune-v1 n=%lld nnz=%lld fronts=%zu shifts=%d fp64=%d batch=%d ops=%d",
+    std::snprintf(keybuf, sizeof(keybuf),
+                  "ndrho-tune-v2 n=%lld nnz=%lld fronts=%zu shifts=%d fp64=%d batch=%d prec=%d ops=%d",
                   static_cast<long long>(P.n), static_cast<long long>(P.nnz), P.fronts.size(), T.n_shifts, T.n_hi,
-                  nb, nops);
+                  nb, ctx->opt.precision, nops);
     const std::string key(keybuf);
     if (T.n_hi >= T.n_shifts || ctx->opt.gemm_variant >= 0) return;  // nothing to choose
     if (cache_path) {
@@ -853,6 +869,7 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
     const int64_t astride = k == 1 ? 0 : T.n_shifts;
     try {
       for (int v = 0; v < V_COUNT; ++v) {
+        if (!variant_allowed(ctx->opt.precision, v)) continue;
         for (int i = 0; i < nops; ++i) {
           const Op& op = i < static_cast<int>(P.upward.size()) ? P.upward[i] : P.downward[i - P.upward.size()];
           T.variant[i] = (op.kind == OP_GEMM && !(op.flags & OP_PIVOT)) ? static_cast<int8_t>(v) : int8_t(V_FP64);
@@ -876,7 +893,7 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
     for (int i = 0; i < nops; ++i) {
       int best = V_FP64;
       for (int v = 1; v < V_COUNT; ++v)
-        if (ms[v][i] < ms[best][i]) best = v;
+        if (variant_allowed(ctx->opt.precision, v) && ms[v][i] < ms[best][i]) best = v;
       T.variant[i] = static_cast<int8_t>(best);
       choice.push_back(static_cast<char>('0' + best));
     }

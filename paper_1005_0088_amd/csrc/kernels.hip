@@ -529,6 +529,213 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
       }
 }
 
+// Same contraction with compensated split-BF16 products.  Operands are
+// staged into LDS as FP32 (the only rounding of the operands, as in the FP32
+// kernel); when a lane picks up its MFMA operand (8 consecutive k of one
+// row) it splits every FP32 value x exactly into three bfloat16 numbers,
+// x = h + m + l (h = bf16(x), m = bf16(x - h), l = x - h - m: 8 + 8 + 8
+// significand bits, the differences exact in FP32), and the six products
+// h.h, h.m, m.h, h.l, m.m, l.h of each real product run on the BF16 matrix
+// cores (v_mfma_f32_16x16x32_bf16), which form bf16 x bf16 products exactly
+// and accumulate in FP32.  The dropped products m.l, l.m, l.l are O(2^-24)
+// relative, so the result has the accuracy of an FP32 GEMM for a quarter of
+// its matrix-core cycles; the split runs on the vector ALUs beside them.
+// 128 x 128 output tiles on eight waves (2 x 4 waves of 64 x 32), K in steps
+// of 32 through double-buffered LDS (re and im planes of FP32, rows padded
+// to 36 floats so that the 16 rows read by one MFMA operand hit distinct
+// banks).
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int B3_TM = 128;               // workgroup tile edge (M and N)
+constexpr int B3_BK = 32;                // K per stage
+constexpr int B3_LD = B3_BK + 4;         // LDS row stride (floats)
+constexpr int B3_PLANE = B3_TM * B3_LD;  // floats per plane
+
+// exact split of 8 FP32 values into three bf16 vectors
+__device__ __forceinline__ void split8(const f4& x0, const f4& x1, bf8& h, bf8& m, bf8& l) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const float x = q < 4 ? x0[q] : x1[q - 4];
+    const __bf16 hq = static_cast<__bf16>(x);
+    const float r1 = x - static_cast<float>(hq);
+    const __bf16 mq = static_cast<__bf16>(r1);
+    const float r2 = r1 - static_cast<float>(mq);
+    h[q] = hq;
+    m[q] = mq;
+    l[q] = static_cast<__bf16>(r2);
+  }
+}
+
+template <int FLAGS>
+__global__ __launch_bounds__(512) void k_cgemm_bf3(const GemmProb* __restrict__ probs,
+                                                   const TileRef* __restrict__ tiles, int64_t ntiles,
+                                                   int64_t npoles, const double2* __restrict__ A, int64_t sA,
+                                                   const double2* __restrict__ B, int64_t sB, const double2* C0,
+                                                   int64_t sC0, double2* C, int64_t sC) {
+  constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
+  static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
+  // [buffer][A re, A im, B re, B im][row][k]
+  __shared__ __attribute__((aligned(16))) float lds[2][4 * B3_PLANE];
+
+  const int64_t total = ntiles * npoles;
+  const int64_t logical = xcd_remap(blockIdx.x, total);
+  const int64_t pole = logical / ntiles;
+  const TileRef tr = tiles[logical % ntiles];
+  const GemmProb pr = probs[tr.prob];
+  const double2* Ap = A + pole * sA + pr.a_off;
+  const double2* Bp = B + pole * sB + pr.b_off;
+  const int M = pr.m, N = pr.n, K = pr.k;
+  const int m0 = tr.tm * B3_TM, n0 = tr.tn * B3_TM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;   // wave tile: rows 64 wm.., columns 32 wn..
+
+  f4 cre[4][2], cim[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      cim[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  // Staging: each thread moves two groups of four consecutive k of one row
+  // per operand.  Row-contiguous storage (A untransposed, B transposed) puts
+  // consecutive threads on consecutive rows; k-contiguous storage (A
+  // transposed, B untransposed) puts eight threads on the 32 k of a row.
+  // The next stage goes through registers in two halves (A, then B) so that
+  // fewer of them are held across the products.
+  double2 rs[8];
+#define B3_AROW(g) (TA ? tid / 8 + 64 * (g) : tid % 128)
+#define B3_AK(g) (TA ? 4 * (tid % 8) : 4 * (tid / 128 + 4 * (g)))
+#define B3_BROW(g) (TB ? tid % 128 : tid / 8 + 64 * (g))
+#define B3_BK4(g) (TB ? 4 * (tid / 128 + 4 * (g)) : 4 * (tid % 8))
+#define B3_LOADA(k0)                                                                                    \
+  _Pragma("unroll") for (int g = 0; g < 2; ++g) {                                                       \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                     \
+      const int gm = m0 + B3_AROW(g), gk = (k0) + B3_AK(g) + q;                                         \
+      rs[4 * g + q] = (gm < M && gk < K) ? ((TA || (SYMA && gm < gk)) ? Ap[gk + int64_t(gm) * pr.lda]      \
+                                                                      : Ap[gm + int64_t(gk) * pr.lda])     \
+                                         : make_double2(0.0, 0.0);                                      \
+    }                                                                                                   \
+  }
+#define B3_LOADB(k0)                                                                                    \
+  _Pragma("unroll") for (int g = 0; g < 2; ++g) {                                                       \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                     \
+      const int gn = n0 + B3_BROW(g), gk = (k0) + B3_BK4(g) + q;                                        \
+      rs[4 * g + q] = (gn < N && gk < K) ? (TB ? Bp[gn + int64_t(gk) * pr.ldb] : Bp[gk + int64_t(gn) * pr.ldb]) \
+                                         : make_double2(0.0, 0.0);                                      \
+    }                                                                                                   \
+  }
+#define B3_PUT(buf, plane, row, kk, v)                                                                  \
+  do {                                                                                                  \
+    float* d_ = &lds[buf][(plane) * B3_PLANE + (row) * B3_LD + (kk)];                                   \
+    *reinterpret_cast<f4*>(d_) = f4{static_cast<float>((v)[0].x), static_cast<float>((v)[1].x),          \
+                                    static_cast<float>((v)[2].x), static_cast<float>((v)[3].x)};        \
+    *reinterpret_cast<f4*>(d_ + B3_PLANE) = f4{static_cast<float>((v)[0].y), static_cast<float>((v)[1].y), \
+                                               static_cast<float>((v)[2].y), static_cast<float>((v)[3].y)}; \
+  } while (0)
+#define B3_STOREA(buf) _Pragma("unroll") for (int g = 0; g < 2; ++g) B3_PUT(buf, 0, B3_AROW(g), B3_AK(g), rs + 4 * g);
+#define B3_STOREB(buf) _Pragma("unroll") for (int g = 0; g < 2; ++g) B3_PUT(buf, 2, B3_BROW(g), B3_BK4(g), rs + 4 * g);
+
+  const int nk = (K + B3_BK - 1) / B3_BK;
+  B3_LOADA(0)
+  B3_STOREA(0)
+  B3_LOADB(0)
+  B3_STOREB(0)
+  __syncthreads();
+  const int orow = lane & 15, ok = 8 * (lane >> 4);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) {
+      B3_LOADA((kt + 1) * B3_BK)
+    }
+    const float* L = lds[cur];
+    bf8 b[2][6];   // [j][2 slice + part]
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const float* br = L + 2 * B3_PLANE + (wn * 32 + j * 16 + orow) * B3_LD + ok;
+      split8(*reinterpret_cast<const f4*>(br), *reinterpret_cast<const f4*>(br + 4), b[j][0], b[j][2], b[j][4]);
+      split8(*reinterpret_cast<const f4*>(br + B3_PLANE), *reinterpret_cast<const f4*>(br + B3_PLANE + 4), b[j][1],
+             b[j][3], b[j][5]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float* ar = L + (wm * 64 + i * 16 + orow) * B3_LD + ok;
+      bf8 a[6], na[3];
+      split8(*reinterpret_cast<const f4*>(ar), *reinterpret_cast<const f4*>(ar + 4), a[0], a[2], a[4]);
+      split8(*reinterpret_cast<const f4*>(ar + B3_PLANE), *reinterpret_cast<const f4*>(ar + B3_PLANE + 4), a[1], a[3],
+             a[5]);
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) {  // -Im(A) slices: sign flip of the bf16 bits
+        typedef unsigned u4v __attribute__((ext_vector_type(4)));
+        na[sl] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, a[2 * sl + 1]) ^ 0x80008000u);
+      }
+      // slice pairs (sa, sb) with sa + sb <= 2; re += Ar Br - Ai Bi,
+      // im += Ai Br + Ar Bi (B tile as the first operand)
+#pragma unroll
+      for (int sa = 0; sa < 3; ++sa)
+#pragma unroll
+        for (int sb = 0; sb + sa < 3; ++sb) {
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb], a[2 * sa], cre[i][j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb], a[2 * sa + 1], cim[i][j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb + 1], na[sa], cre[i][j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb + 1], a[2 * sa], cim[i][j], 0, 0, 0);
+        }
+      if (i == 1 && more) {  // halfway: the next A block to LDS, fetch the next B block
+        B3_STOREA(cur ^ 1)
+        B3_LOADB((kt + 1) * B3_BK)
+      }
+    }
+    if (more) {
+      B3_STOREB(cur ^ 1)
+    }
+    __syncthreads();
+  }
+#undef B3_AROW
+#undef B3_AK
+#undef B3_BROW
+#undef B3_BK4
+#undef B3_LOADA
+#undef B3_LOADB
+#undef B3_PUT
+#undef B3_STOREA
+#undef B3_STOREB
+
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
+  double2* Cp = C + pole * sC + pr.c_off;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + i * 16 + (lane & 15);
+        const int n = n0 + wn * 32 + j * 16 + F32_DROW(r, lane);
+        if (m >= M || n >= N) continue;
+        if (SYM && m < n) continue;
+        double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
+        if (NEG) v = make_double2(-v.x, -v.y);
+        if (BETA) {
+          const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
+          v.x += c0.x;
+          v.y += c0.y;
+        }
+        Cp[m + int64_t(n) * pr.ldc] = v;
+        if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+      }
+}
+
 // ----------------------------------------------------------------- copy
 //
 // dst (rows x cols) <- src, or <- src^T through an LDS tile so that both the
@@ -699,8 +906,25 @@ static void gemm32_inst(const DevOp& o, hipStream_t st) {
                        o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
 }
 
+template <int F>
+static void gemm_bf3_inst(const DevOp& o, hipStream_t st) {
+  const int64_t total = o.tile_count * o.npoles;
+  hipLaunchKernelGGL(k_cgemm_bf3<F>, dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm, o.gemm_tiles,
+                     o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
+}
+
 hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
   if (o.tile_count == 0) return hipSuccess;
+  if (o.bf3) {
+    switch (o.flags) {  // front updates only, on 128x128 tiles
+      case 0: gemm_bf3_inst<0>(o, st); break;
+      case G_NEG | G_SYMA: gemm_bf3_inst<G_NEG | G_SYMA>(o, st); break;
+      case G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR: gemm_bf3_inst<G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR>(o, st); break;
+      case G_TA | G_SYM | G_BETA | G_NEG: gemm_bf3_inst<G_TA | G_SYM | G_BETA | G_NEG>(o, st); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   if (o.fp32) {
     switch (o.flags) {  // front updates only (pivot GEMMs are always FP64)
       case 0: gemm32_inst<0>(o, st); break;

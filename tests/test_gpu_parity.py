@@ -203,14 +203,15 @@ def test_errors(ctx):
 
 # ------------------------------------------------------------- precision form
 
-@pytest.mark.parametrize("variant", [1, 2])
-def test_mixed_fp32_single_shift_close_to_dense(variant):
-    # FP32 products with FP32 accumulation (64x64 or 128x128 tiles): relative
-    # error of G well below 1e-5
+@pytest.mark.parametrize("precision,variant", [("mixed_fp32", 1), ("mixed_fp32", 2), ("mixed_bf16x3", 3)])
+def test_mixed_single_shift_close_to_dense(precision, variant):
+    # FP32 products with FP32 accumulation (64x64 or 128x128 tiles), or
+    # split-BF16 products with FP32 accumulation: relative error of G well
+    # below 1e-5
     import paper_1005_0088_amd as nd
     sysd = lattice((7, 6, 5), "nn", 14)
     h, s, rows, cols = _dense(sysd)
-    with nd.Context(0, precision="mixed_fp32", fp64_poles=0, fp64_pole_im=0.0, fp64_far_poles=0,
+    with nd.Context(0, precision=precision, fp64_poles=0, fp64_pole_im=0.0, fp64_far_poles=0,
                     gemm_variant=variant) as c:
         sid = _register(c, sysd)
         c.set_shifts(sid, np.array([0.2 + 0.5j]), np.array([1.0]), add_m0=False)
@@ -218,12 +219,15 @@ def test_mixed_fp32_single_shift_close_to_dense(variant):
         assert c.stats(sid)["n_fp64_poles"] == 0
     g = dense.green_dense(h, s, 0.2 + 0.5j)
     err = np.max(np.abs(got - g[rows, cols].real)) / np.abs(g).max()
-    assert 1e-12 < err < 1e-5          # the FP32 path really ran, and is FP32-accurate
+    print("%s variant %d relative err %.3e" % (precision, variant, err))
+    assert 1e-12 < err < 1e-5          # the low-precision path really ran, and is FP32-accurate
 
 
-@pytest.mark.parametrize("dims,nb,fp64_poles,tol", [((9, 9, 9), "nn", 8, 1e-7), ((9, 9, 9), "nn", 0, 1e-6),
-                                                    ((20, 18), "nn2", 8, 1e-7)])
-def test_mixed_rho_against_oracle(dims, nb, fp64_poles, tol):
+@pytest.mark.parametrize("dims,nb,fp64_poles,tol,precision,variant",
+                         [((9, 9, 9), "nn", 8, 1e-7, "mixed_fp32", 2), ((9, 9, 9), "nn", 0, 1e-6, "mixed_fp32", 2),
+                          ((20, 18), "nn2", 8, 1e-7, "mixed_fp32", 2), ((9, 9, 9), "nn", 8, 1e-7, "mixed_bf16x3", 3),
+                          ((9, 9, 9), "nn", 0, 1e-6, "mixed_bf16x3", 3), ((20, 18), "nn2", 8, 1e-7, "mixed_bf16x3", 3)])
+def test_mixed_rho_against_oracle(dims, nb, fp64_poles, tol, precision, variant):
     # fp64_poles shifts nearest and as many farthest from the real axis in FP64
     import paper_1005_0088_amd as nd
     sysd = lattice(dims, nb, 15)
@@ -231,14 +235,14 @@ def test_mixed_rho_against_oracle(dims, nb, fp64_poles, tol):
     eps, c = dense.eigen(h, s)
     mu = dense.mu_for_count(eps, BETA, float(sysd["n"]))
     ref = dense.rho_cf_pattern(eps, c, mu, BETA, 80, rows, cols)
-    with nd.Context(0, precision="mixed_fp32", fp64_poles=fp64_poles, fp64_far_poles=fp64_poles,
-                    fp64_pole_im=0.05, gemm_variant=2) as cx:
+    with nd.Context(0, precision=precision, fp64_poles=fp64_poles, fp64_far_poles=fp64_poles,
+                    fp64_pole_im=0.05, gemm_variant=variant) as cx:
         sid = _register(cx, sysd)
         cx.set_poles(sid, mu, BETA, 80)
         got = cx.density_matrix(sid)
         assert cx.stats(sid)["n_fp64_poles"] == 2 * fp64_poles
     err = np.max(np.abs(got - ref))
-    print("mixed fp64_poles=%d err=%.3e" % (fp64_poles, err))
+    print("%s fp64_poles=%d err=%.3e" % (precision, fp64_poles, err))
     assert err < tol
 
 
@@ -253,7 +257,9 @@ def _golden(name):
 
 
 @pytest.mark.parametrize("name,precision,tol", [("cubic3d_24x4", "fp64", 1e-10), ("cubic3d_24x4", "mixed_fp32", 1e-7),
-                                                ("square2d_64x4", "fp64", 1e-10), ("square2d_64x4", "mixed_fp32", 1e-7)])
+                                                ("cubic3d_24x4", "mixed_bf16x3", 1e-7),
+                                                ("square2d_64x4", "fp64", 1e-10), ("square2d_64x4", "mixed_fp32", 1e-7),
+                                                ("square2d_64x4", "mixed_bf16x3", 1e-7)])
 def test_full_size_against_oracle_sample(name, precision, tol):
     # the configuration the benchmark times, in the same launch configuration
     import paper_1005_0088_amd as nd
@@ -281,7 +287,7 @@ def test_full_size_against_oracle_sample(name, precision, tol):
 
 # ------------------------------------------------------------- several structures, one schedule
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32", "mixed_bf16x3"])
 def test_batch_of_structures_matches_single_runs(precision):
     import paper_1005_0088_amd as nd
     systems = [lattice((9, 7), "nn", 30), lattice((12, 12), "nn", 31), lattice((5, 4, 6), "nn2", 32),
@@ -371,7 +377,7 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
     assert np.array_equal(got, again)
     with open(cache) as f:
         lines = f.read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("ndrho-tune-v1 ")
+    assert len(lines) == 1 and lines[0].startswith("ndrho-tune-v2 ")
     choice = lines[0].split()[-1]
     assert set(choice) <= set("012")
     with nd.Context(0, precision="mixed_fp32") as c:   # cached choice is reused, not re-tuned
@@ -381,6 +387,14 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
         assert np.array_equal(c.density_matrix(s2), got)
     with open(cache) as f:
         assert len(f.read().splitlines()) == 1
+    with nd.Context(0, precision="mixed_bf16x3") as c:  # its own key; FP64 or split-BF16 per launch
+        s3 = _register(c, sysd)
+        c.set_poles(s3, 0.0, BETA, 40)
+        c.autotune([s3], cache)
+        assert np.max(np.abs(c.density_matrix(s3) - ref)) < 1e-7
+    with open(cache) as f:
+        lines = f.read().splitlines()
+    assert len(lines) == 2 and set(lines[1].split()[-1]) <= set("03")
 
 
 def test_large_3d_fp64_against_oracle_sample():
