@@ -551,19 +551,29 @@ constexpr int B3_BK = 32;                // K per stage
 constexpr int B3_LD = B3_BK + 4;         // LDS row stride (floats)
 constexpr int B3_PLANE = B3_TM * B3_LD;  // floats per plane
 
-// exact split of 8 FP32 values into three bf16 vectors
+// exact split of 8 FP32 values into three bf16 vectors, two values per
+// packed conversion (v_cvt_pk_bf16_f32 rounds to nearest even)
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void split2(f2 x, unsigned& h, unsigned& m, unsigned& l) {
+  const b2 hh = __builtin_convertvector(x, b2);
+  const f2 r1 = x - __builtin_convertvector(hh, f2);
+  const b2 mm = __builtin_convertvector(r1, b2);
+  const f2 r2 = r1 - __builtin_convertvector(mm, f2);
+  h = __builtin_bit_cast(unsigned, hh);
+  m = __builtin_bit_cast(unsigned, mm);
+  l = __builtin_bit_cast(unsigned, __builtin_convertvector(r2, b2));
+}
 __device__ __forceinline__ void split8(const f4& x0, const f4& x1, bf8& h, bf8& m, bf8& l) {
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const float x = q < 4 ? x0[q] : x1[q - 4];
-    const __bf16 hq = static_cast<__bf16>(x);
-    const float r1 = x - static_cast<float>(hq);
-    const __bf16 mq = static_cast<__bf16>(r1);
-    const float r2 = r1 - static_cast<float>(mq);
-    h[q] = hq;
-    m[q] = mq;
-    l[q] = static_cast<__bf16>(r2);
-  }
+  unsigned h0, h1, h2, h3, m0, m1, m2, m3, l0, l1, l2, l3;
+  split2(f2{x0[0], x0[1]}, h0, m0, l0);
+  split2(f2{x0[2], x0[3]}, h1, m1, l1);
+  split2(f2{x1[0], x1[1]}, h2, m2, l2);
+  split2(f2{x1[2], x1[3]}, h3, m3, l3);
+  h = __builtin_bit_cast(bf8, u4v{h0, h1, h2, h3});
+  m = __builtin_bit_cast(bf8, u4v{m0, m1, m2, m3});
+  l = __builtin_bit_cast(bf8, u4v{l0, l1, l2, l3});
 }
 
 template <int FLAGS>
@@ -611,22 +621,37 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3(const GemmProb* __restrict__ 
 #define B3_AK(g) (TA ? 4 * (tid % 8) : 4 * (tid / 128 + 4 * (g)))
 #define B3_BROW(g) (TB ? tid % 128 : tid / 8 + 64 * (g))
 #define B3_BK4(g) (TB ? 4 * (tid / 128 + 4 * (g)) : 4 * (tid % 8))
+  // whole 128 x 32 blocks inside the matrix load without per-element guards
+  const bool afull = m0 + B3_TM <= M, bfull = n0 + B3_TM <= N;
+#define B3_AIDX(gm, gk) ((TA || (SYMA && (gm) < (gk))) ? (gk) + int64_t(gm) * pr.lda : (gm) + int64_t(gk) * pr.lda)
+#define B3_BIDX(gn, gk) (TB ? (gn) + int64_t(gk) * pr.ldb : (gk) + int64_t(gn) * pr.ldb)
 #define B3_LOADA(k0)                                                                                    \
-  _Pragma("unroll") for (int g = 0; g < 2; ++g) {                                                       \
-    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                     \
-      const int gm = m0 + B3_AROW(g), gk = (k0) + B3_AK(g) + q;                                         \
-      rs[4 * g + q] = (gm < M && gk < K) ? ((TA || (SYMA && gm < gk)) ? Ap[gk + int64_t(gm) * pr.lda]      \
-                                                                      : Ap[gm + int64_t(gk) * pr.lda])     \
-                                         : make_double2(0.0, 0.0);                                      \
-    }                                                                                                   \
+  if (afull && (k0) + B3_BK <= K) {                                                                     \
+    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
+        const int gm = m0 + B3_AROW(g), gk = (k0) + B3_AK(g) + q;                                       \
+        rs[4 * g + q] = Ap[B3_AIDX(gm, gk)];                                                            \
+      }                                                                                                 \
+  } else {                                                                                              \
+    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
+        const int gm = m0 + B3_AROW(g), gk = (k0) + B3_AK(g) + q;                                       \
+        rs[4 * g + q] = (gm < M && gk < K) ? Ap[B3_AIDX(gm, gk)] : make_double2(0.0, 0.0);              \
+      }                                                                                                 \
   }
 #define B3_LOADB(k0)                                                                                    \
-  _Pragma("unroll") for (int g = 0; g < 2; ++g) {                                                       \
-    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                     \
-      const int gn = n0 + B3_BROW(g), gk = (k0) + B3_BK4(g) + q;                                        \
-      rs[4 * g + q] = (gn < N && gk < K) ? (TB ? Bp[gn + int64_t(gk) * pr.ldb] : Bp[gk + int64_t(gn) * pr.ldb]) \
-                                         : make_double2(0.0, 0.0);                                      \
-    }                                                                                                   \
+  if (bfull && (k0) + B3_BK <= K) {                                                                     \
+    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
+        const int gn = n0 + B3_BROW(g), gk = (k0) + B3_BK4(g) + q;                                      \
+        rs[4 * g + q] = Bp[B3_BIDX(gn, gk)];                                                            \
+      }                                                                                                 \
+  } else {                                                                                              \
+    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
+        const int gn = n0 + B3_BROW(g), gk = (k0) + B3_BK4(g) + q;                                      \
+        rs[4 * g + q] = (gn < N && gk < K) ? Bp[B3_BIDX(gn, gk)] : make_double2(0.0, 0.0);              \
+      }                                                                                                 \
   }
 #define B3_PUT(buf, plane, row, kk, v)                                                                  \
   do {                                                                                                  \
@@ -670,7 +695,6 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3(const GemmProb* __restrict__ 
              a[5]);
 #pragma unroll
       for (int sl = 0; sl < 3; ++sl) {  // -Im(A) slices: sign flip of the bf16 bits
-        typedef unsigned u4v __attribute__((ext_vector_type(4)));
         na[sl] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, a[2 * sl + 1]) ^ 0x80008000u);
       }
       // slice pairs (sa, sb) with sa + sb <= 2; re += Ar Br - Ai Bi,
@@ -706,6 +730,8 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3(const GemmProb* __restrict__ 
 #undef B3_AK
 #undef B3_BROW
 #undef B3_BK4
+#undef B3_AIDX
+#undef B3_BIDX
 #undef B3_LOADA
 #undef B3_LOADB
 #undef B3_PUT
