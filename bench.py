@@ -141,10 +141,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cubic3d_24x4", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="mixed_fp32", choices=["mixed_fp32", "mixed_bf16x3", "fp64"])
+    ap.add_argument("--precision", default="mixed_bf16x3", choices=["mixed_bf16x3", "mixed_fp32", "fp64"],
+                    help="form of the headline number")
     ap.add_argument("--fp64-poles", type=int, default=8)
-    ap.add_argument("--forms", default="both", choices=["both", "head"],
-                    help="both: also time the FP64 form as the complex128 reference; head: only --precision")
+    ap.add_argument("--forms", default="all", choices=["all", "both", "head"],
+                    help="all: every precision form (FP64 is the complex128 reference of the error); "
+                         "both: --precision and FP64; head: only --precision")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run the plain copy kernel over GIB gibibytes (HBM counter calibration) and exit")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default per-launch GEMM variants")
@@ -187,8 +189,19 @@ def main():
 
     # the plain FP64 form is the complex128 reference of the error
     r64 = rho64 = None
-    if args.forms == "both" or args.precision == "fp64":
+    if args.forms != "head" or args.precision == "fp64":
         r64, rho64 = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, "fp64", 0)
+    others = {}
+    if args.forms == "all":
+        for form in ("mixed_fp32", "mixed_bf16x3"):
+            if form != args.precision:
+                r, rr = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, form, args.fp64_poles,
+                                 not args.no_autotune)
+                others[form] = {
+                    "poles_per_s": r["poles_per_s"], "ms_per_step": r["ms_per_step"],
+                    "kernel_ms": {k: round(v["ms"], 3) for k, v in r["prof"].items()},
+                    "max_abs_err_vs_complex128": max(float(np.max(np.abs(a - b))) for a, b in zip(rr, rho64)),
+                    "max_abs_err_vs_oracle_sample": golden_error(name, rr[0], mu, n_poles) if len(rr) == 1 else None}
     if args.precision == "fp64":
         head, rho = r64, rho64
     else:
@@ -240,6 +253,7 @@ def main():
             "gemm_tflops": r64["prof"]["gemm"]["flops"] / (r64["prof"]["gemm"]["ms"] * 1e-3) / 1e12,
             "kernel_ms": {k: round(v["ms"], 3) for k, v in r64["prof"].items()},
             "max_abs_err_vs_oracle_sample": golden_error(name, rho64[0], mu, n_poles) if len(rho64) == 1 else None},
+        "other_forms": others,
         "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
         "gemm_tflops": gemm_tf,
         "roofline": {"kernel": kname, "bound": "mfma",
