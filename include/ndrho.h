@@ -57,10 +57,11 @@ enum {
  *                     Schur update, G_UJ, G_JJ) take FP32 products with FP32
  *                     accumulation, results summed into FP64 storage.
  *   NDRHO_MIXED_BF16X3: the same GEMMs as compensated split-BF16 products:
- *                     each FP64 operand is split into three bfloat16 slices
- *                     and the six leading slice products run on the BF16
- *                     matrix cores with FP32 accumulation (accuracy of an
- *                     FP32 GEMM). */
+ *                     operands rounded to FP32 are split exactly into three
+ *                     bfloat16 slices and the six leading slice products run
+ *                     on the BF16 matrix cores with FP32 accumulation
+ *                     (accuracy of an FP32 GEMM); a launch that runs faster
+ *                     with FP32 products (small fronts) takes those. */
 enum { NDRHO_FP64 = 0, NDRHO_MIXED_FP32 = 1, NDRHO_MIXED_BF16X3 = 2 };
 
 typedef struct {
@@ -76,7 +77,9 @@ typedef struct {
   int32_t use_graph;    /* 1 (default): capture the launch sequence of an evaluation in a hipGraph and replay it */
   int32_t gemm_variant; /* mixed mode, front-update GEMMs of the low poles: -1 (default) per-launch choice
                            (heuristic, refined by ndrho_autotune); 0 FP64; 1 FP32 products on 64x64 tiles;
-                           2 FP32 products on 128x128 tiles; 3 split-BF16 products on 128x128 tiles */
+                           2 FP32 products on 128x128 tiles; 3 split-BF16 products on 128x128 tiles;
+                           4 split-BF16 products on 64x64 tiles.  FP32 mode accepts 0-2, split-BF16
+                           mode 0-4 */
 } ndrho_options;
 
 /* Fill *opt with the defaults listed above. */

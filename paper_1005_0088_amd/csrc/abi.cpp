@@ -88,13 +88,15 @@ struct DevStruct {
 
 thread_local std::string g_err;  // errors without a context (create, plan utilities)
 
-enum { V_FP64 = 0, V_F32_64 = 1, V_F32_128 = 2, V_BF3 = 3, V_COUNT = 4 };
+enum { V_FP64 = 0, V_F32_64 = 1, V_F32_128 = 2, V_BF3_128 = 3, V_BF3_64 = 4, V_COUNT = 5 };
 
-// Low-precision variants a precision mode may choose from (besides V_FP64).
+// Variants a precision mode may choose from: FP32 mode its FP32 products;
+// split-BF16 mode its split-BF16 products and, where a launch runs faster
+// so, FP32 products (the two have the same operand rounding and accuracy).
 static bool variant_allowed(int precision, int v) {
   if (v == V_FP64) return true;
   if (precision == NDRHO_MIXED_FP32) return v == V_F32_64 || v == V_F32_128;
-  if (precision == NDRHO_MIXED_BF16X3) return v == V_BF3;
+  if (precision == NDRHO_MIXED_BF16X3) return v != V_FP64;
   return false;
 }
 
@@ -102,7 +104,7 @@ static bool variant_allowed(int precision, int v) {
 // 128x128 tiles where the op's largest problem fills several such tiles,
 // plain FP64 for the small fronts of the deep levels (where they do not pay).
 std::vector<int8_t> default_variants(const Plan& P, int precision) {
-  const int8_t low = precision == NDRHO_MIXED_BF16X3 ? int8_t(V_BF3) : int8_t(V_F32_128);
+  const int8_t low = precision == NDRHO_MIXED_BF16X3 ? int8_t(V_BF3_128) : int8_t(V_F32_128);
   std::vector<int8_t> v;
   auto pick = [&](const Op& op) {
     if (op.kind != OP_GEMM || (op.flags & OP_PIVOT)) return int8_t(V_FP64);
@@ -345,8 +347,8 @@ struct ndrho_ctx {
           }
           DevOp l = d;  // low-precision products for the others
           l.fp32 = var == V_F32_64 || var == V_F32_128;
-          l.bf3 = var == V_BF3;
-          if (var == V_F32_128 || var == V_BF3) {
+          l.bf3 = var == V_BF3_64 || var == V_BF3_128;
+          if (var == V_F32_128 || var == V_BF3_128) {
             l.tile128 = true;
             l.gemm_tiles = S.gemm_tiles + op.tile128_begin;
             l.tile_count = op.tile128_count;

@@ -540,16 +540,14 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
 // and accumulate in FP32.  The dropped products m.l, l.m, l.l are O(2^-24)
 // relative, so the result has the accuracy of an FP32 GEMM for a quarter of
 // its matrix-core cycles; the split runs on the vector ALUs beside them.
-// 128 x 128 output tiles on eight waves (2 x 4 waves of 64 x 32), K in steps
-// of 32 through double-buffered LDS (re and im planes of FP32, rows padded
-// to 36 floats so that the 16 rows read by one MFMA operand hit distinct
-// banks).
+// TM x TM output tiles: TM = 128 on eight waves (2 x 4 waves of 64 x 32),
+// TM = 64 on four (2 x 2 waves of 32 x 32); K in steps of 32 through
+// double-buffered LDS (re and im planes of FP32, rows padded to 36 floats so
+// that the 16 rows read by one MFMA operand hit distinct banks).
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int B3_TM = 128;               // workgroup tile edge (M and N)
 constexpr int B3_BK = 32;                // K per stage
 constexpr int B3_LD = B3_BK + 4;         // LDS row stride (floats)
-constexpr int B3_PLANE = B3_TM * B3_LD;  // floats per plane
 
 // exact split of 8 FP32 values into three bf16 vectors, two values per
 // packed conversion (v_cvt_pk_bf16_f32 rounds to nearest even)
@@ -576,8 +574,8 @@ __device__ __forceinline__ void split8(const f4& x0, const f4& x1, bf8& h, bf8& 
   l = __builtin_bit_cast(bf8, u4v{l0, l1, l2, l3});
 }
 
-template <int FLAGS>
-__global__ __launch_bounds__(512) void k_cgemm_bf3(const GemmProb* __restrict__ probs,
+template <int FLAGS, int B3_TM>
+__global__ __launch_bounds__(B3_TM * 4) void k_cgemm_bf3(const GemmProb* __restrict__ probs,
                                                    const TileRef* __restrict__ tiles, int64_t ntiles,
                                                    int64_t npoles, const double2* __restrict__ A, int64_t sA,
                                                    const double2* __restrict__ B, int64_t sB, const double2* C0,
@@ -586,6 +584,10 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3(const GemmProb* __restrict__ 
   constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
   constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
+  constexpr int NT = B3_TM * 4;            // threads
+  constexpr int IB = B3_TM / 32;           // 16-row blocks of a wave's A rows (wave tile TM/2 x 32)
+  constexpr int RPT = NT / 8;              // rows per pass of a k-contiguous load
+  constexpr int B3_PLANE = B3_TM * B3_LD;  // floats per plane
   // [buffer][A re, A im, B re, B im][row][k]
   __shared__ __attribute__((aligned(16))) float lds[2][4 * B3_PLANE];
 
@@ -599,11 +601,11 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3(const GemmProb* __restrict__ 
   const int M = pr.m, N = pr.n, K = pr.k;
   const int m0 = tr.tm * B3_TM, n0 = tr.tn * B3_TM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;   // wave tile: rows 64 wm.., columns 32 wn..
+  const int wm = wave & 1, wn = wave >> 1;   // wave tile: rows TM/2 wm.., columns 32 wn..
 
-  f4 cre[4][2], cim[4][2];
+  f4 cre[IB][2], cim[IB][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < IB; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       cre[i][j] = f4{0.f, 0.f, 0.f, 0.f};
@@ -617,10 +619,10 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3(const GemmProb* __restrict__ 
   // The next stage goes through registers in two halves (A, then B) so that
   // fewer of them are held across the products.
   double2 rs[8];
-#define B3_AROW(g) (TA ? tid / 8 + 64 * (g) : tid % 128)
-#define B3_AK(g) (TA ? 4 * (tid % 8) : 4 * (tid / 128 + 4 * (g)))
-#define B3_BROW(g) (TB ? tid % 128 : tid / 8 + 64 * (g))
-#define B3_BK4(g) (TB ? 4 * (tid / 128 + 4 * (g)) : 4 * (tid % 8))
+#define B3_AROW(g) (TA ? tid / 8 + RPT * (g) : tid % B3_TM)
+#define B3_AK(g) (TA ? 4 * (tid % 8) : 4 * (tid / B3_TM + 4 * (g)))
+#define B3_BROW(g) (TB ? tid % B3_TM : tid / 8 + RPT * (g))
+#define B3_BK4(g) (TB ? 4 * (tid / B3_TM + 4 * (g)) : 4 * (tid % 8))
   // whole 128 x 32 blocks inside the matrix load without per-element guards
   const bool afull = m0 + B3_TM <= M, bfull = n0 + B3_TM <= N;
 #define B3_AIDX(gm, gk) ((TA || (SYMA && (gm) < (gk))) ? (gk) + int64_t(gm) * pr.lda : (gm) + int64_t(gk) * pr.lda)
@@ -687,8 +689,8 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3(const GemmProb* __restrict__ 
              b[j][3], b[j][5]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float* ar = L + (wm * 64 + i * 16 + orow) * B3_LD + ok;
+    for (int i = 0; i < IB; ++i) {
+      const float* ar = L + (wm * (B3_TM / 2) + i * 16 + orow) * B3_LD + ok;
       bf8 a[6], na[3];
       split8(*reinterpret_cast<const f4*>(ar), *reinterpret_cast<const f4*>(ar + 4), a[0], a[2], a[4]);
       split8(*reinterpret_cast<const f4*>(ar + B3_PLANE), *reinterpret_cast<const f4*>(ar + B3_PLANE + 4), a[1], a[3],
@@ -716,7 +718,7 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3(const GemmProb* __restrict__ 
           for (int j = 0; j < 2; ++j)
             cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb + 1], a[2 * sa], cim[i][j], 0, 0, 0);
         }
-      if (i == 1 && more) {  // halfway: the next A block to LDS, fetch the next B block
+      if (i == IB / 2 - 1 && more) {  // halfway: the next A block to LDS, fetch the next B block
         B3_STOREA(cur ^ 1)
         B3_LOADB((kt + 1) * B3_BK)
       }
@@ -741,12 +743,12 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3(const GemmProb* __restrict__ 
   const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < IB; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 64 + i * 16 + (lane & 15);
+        const int m = m0 + wm * (B3_TM / 2) + i * 16 + (lane & 15);
         const int n = n0 + wn * 32 + j * 16 + F32_DROW(r, lane);
         if (m >= M || n >= N) continue;
         if (SYM && m < n) continue;
@@ -935,14 +937,20 @@ static void gemm32_inst(const DevOp& o, hipStream_t st) {
 template <int F>
 static void gemm_bf3_inst(const DevOp& o, hipStream_t st) {
   const int64_t total = o.tile_count * o.npoles;
-  hipLaunchKernelGGL(k_cgemm_bf3<F>, dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm, o.gemm_tiles,
-                     o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
+  if (o.tile128)
+    hipLaunchKernelGGL((k_cgemm_bf3<F, 128>), dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm,
+                       o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
+                       o.c, o.sc);
+  else
+    hipLaunchKernelGGL((k_cgemm_bf3<F, 64>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm,
+                       o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
+                       o.c, o.sc);
 }
 
 hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
   if (o.tile_count == 0) return hipSuccess;
   if (o.bf3) {
-    switch (o.flags) {  // front updates only, on 128x128 tiles
+    switch (o.flags) {  // front updates only
       case 0: gemm_bf3_inst<0>(o, st); break;
       case G_NEG | G_SYMA: gemm_bf3_inst<G_NEG | G_SYMA>(o, st); break;
       case G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR: gemm_bf3_inst<G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR>(o, st); break;

@@ -99,6 +99,24 @@ def test_pole_sum_by_dense_inverse_matches_closed_form_chain(n, a, b, s, mu, n_p
     assert np.max(np.abs(got - ref)) < 2e-13
 
 
+@pytest.mark.parametrize("route", ["lu", "gmres"])
+def test_sampled_columns_match_closed_form_chain(route):
+    # the sampled-column routes of Eq. (8) (sparse LU per pole, or GMRES per
+    # pole with CG for S^-1) reproduce the closed-form rho on the columns
+    import scipy.sparse as sp
+    from oracle import sampled
+    n, a, b, s, mu, beta, n_poles = 50, 0.2, -1.0, 0.1, 0.05, 10.0, 60
+    h, sm = chain.chain_matrices(n, a, b, s)
+    hs, ss = sp.csr_matrix(h), sp.csr_matrix(sm)
+    cols = np.array([0, 7, 31, 49])
+    if route == "lu":
+        got = sampled.rho_columns(hs, ss, mu, beta, n_poles, cols)
+    else:
+        got = sampled.rho_columns_gmres(hs, ss, mu, beta, n_poles, cols)
+    ref = chain.chain_rho(n, a, b, s, mu, beta)[:, cols]
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
 def test_green_dense_matches_closed_form_chain():
     n, a, b, s = 17, 0.1, -0.8, 0.15
     h, sm = chain.chain_matrices(n, a, b, s)
