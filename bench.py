@@ -88,17 +88,18 @@ def golden_error(name, rho, mu, n_poles):
     return float(np.max(np.abs(rho[np.asarray(g["entries"])] - np.asarray(g["values"]))))
 
 
-def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_poles, autotune=True):
+def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_poles, autotune=True, gemm_variant=-1):
     """Time one precision form on one system (density_matrix) or several
     (density_matrix_batch: one schedule); returns (timing dict, rho list)."""
-    ctx = nd.Context(0, precision=precision, fp64_poles=fp64_poles)
+    variant = gemm_variant if precision != "fp64" else -1
+    ctx = nd.Context(0, precision=precision, fp64_poles=fp64_poles, fp64_far_poles=fp64_poles, gemm_variant=variant)
     t0 = time.time()
     sids = []
     for sysd in systems:
         sid = ctx.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"])
         ctx.set_poles(sid, mu, beta, n_poles)
         sids.append(sid)
-    if precision != "fp64" and autotune:
+    if precision != "fp64" and autotune and variant < 0:
         ctx.autotune(sids)   # per-launch GEMM variant (untimed set-up, like the plan)
     setup_s = time.time() - t0
     outs = [ctx.device_buffer(int(sysd["row_ptr"][-1])) for sysd in systems]
@@ -150,6 +151,8 @@ def main():
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run the plain copy kernel over GIB gibibytes (HBM counter calibration) and exit")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default per-launch GEMM variants")
+    ap.add_argument("--gemm-variant", type=int, default=-1,
+                    help="force one GEMM variant on every low-precision front update (see ndrho_options)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -206,7 +209,7 @@ def main():
         head, rho = r64, rho64
     else:
         head, rho = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, args.precision,
-                             args.fp64_poles, not args.no_autotune)
+                             args.fp64_poles, not args.no_autotune, args.gemm_variant)
     st, prof = head["stats"][0], head["prof"]
     # dominant kernel: the FP64 front GEMMs in the FP64 form, the FP32-product
     # front GEMMs in the mixed form (peak of their own arithmetic)

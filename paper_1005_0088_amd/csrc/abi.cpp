@@ -347,7 +347,7 @@ struct ndrho_ctx {
           }
           DevOp l = d;  // low-precision products for the others
           l.fp32 = var == V_F32_64 || var == V_F32_128;
-          l.bf3 = var == V_BF3_64 || var == V_BF3_128;
+          l.bf3 = var == V_BF3_128 ? 1 : var == V_BF3_64 ? 2 : 0;
           if (var == V_F32_128 || var == V_BF3_128) {
             l.tile128 = true;
             l.gemm_tiles = S.gemm_tiles + op.tile128_begin;

@@ -540,8 +540,8 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
 // and accumulate in FP32.  The dropped products m.l, l.m, l.l are O(2^-24)
 // relative, so the result has the accuracy of an FP32 GEMM for a quarter of
 // its matrix-core cycles; the split runs on the vector ALUs beside them.
-// TM x TM output tiles: TM = 128 on eight waves (2 x 4 waves of 64 x 32),
-// TM = 64 on four (2 x 2 waves of 32 x 32); K in steps of 32 through
+// TM x TM output tiles on NW waves in two rows: TM = 128 on eight waves
+// (64 x 32 each), TM = 64 on four (32 x 32 each); K in steps of 32 through
 // double-buffered LDS (re and im planes of FP32, rows padded to 36 floats so
 // that the 16 rows read by one MFMA operand hit distinct banks).
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -574,8 +574,8 @@ __device__ __forceinline__ void split8(const f4& x0, const f4& x1, bf8& h, bf8& 
   l = __builtin_bit_cast(bf8, u4v{l0, l1, l2, l3});
 }
 
-template <int FLAGS, int B3_TM>
-__global__ __launch_bounds__(B3_TM * 4) void k_cgemm_bf3(const GemmProb* __restrict__ probs,
+template <int FLAGS, int B3_TM, int NW>
+__global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restrict__ probs,
                                                    const TileRef* __restrict__ tiles, int64_t ntiles,
                                                    int64_t npoles, const double2* __restrict__ A, int64_t sA,
                                                    const double2* __restrict__ B, int64_t sB, const double2* C0,
@@ -584,8 +584,12 @@ __global__ __launch_bounds__(B3_TM * 4) void k_cgemm_bf3(const GemmProb* __restr
   constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
   constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
-  constexpr int NT = B3_TM * 4;            // threads
-  constexpr int IB = B3_TM / 32;           // 16-row blocks of a wave's A rows (wave tile TM/2 x 32)
+  constexpr int NT = NW * 64;              // threads
+  constexpr int IB = B3_TM / 32;           // 16-row blocks of a wave's A rows (wave tile TM/2 x WCOL)
+  constexpr int WCOL = 2 * B3_TM / NW;     // columns of a wave's tile
+  constexpr int JB = WCOL / 16;            // 16-column blocks of a wave's B columns
+  constexpr int GPT = B3_TM * 8 / NT;      // groups of 4 k per thread and operand in a stage
+  constexpr int KGS = NT / B3_TM;          // k-group stride of a row-contiguous load
   constexpr int RPT = NT / 8;              // rows per pass of a k-contiguous load
   constexpr int B3_PLANE = B3_TM * B3_LD;  // floats per plane
   // [buffer][A re, A im, B re, B im][row][k]
@@ -601,13 +605,13 @@ __global__ __launch_bounds__(B3_TM * 4) void k_cgemm_bf3(const GemmProb* __restr
   const int M = pr.m, N = pr.n, K = pr.k;
   const int m0 = tr.tm * B3_TM, n0 = tr.tn * B3_TM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;   // wave tile: rows TM/2 wm.., columns 32 wn..
+  const int wm = wave & 1, wn = wave >> 1;   // wave tile: rows TM/2 wm.., columns WCOL wn..
 
-  f4 cre[IB][2], cim[IB][2];
+  f4 cre[IB][JB], cim[IB][JB];
 #pragma unroll
   for (int i = 0; i < IB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < JB; ++j) {
       cre[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       cim[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     }
@@ -618,24 +622,24 @@ __global__ __launch_bounds__(B3_TM * 4) void k_cgemm_bf3(const GemmProb* __restr
   // transposed, B untransposed) puts eight threads on the 32 k of a row.
   // The next stage goes through registers in two halves (A, then B) so that
   // fewer of them are held across the products.
-  double2 rs[8];
+  double2 rs[4 * GPT];
 #define B3_AROW(g) (TA ? tid / 8 + RPT * (g) : tid % B3_TM)
-#define B3_AK(g) (TA ? 4 * (tid % 8) : 4 * (tid / B3_TM + 4 * (g)))
+#define B3_AK(g) (TA ? 4 * (tid % 8) : 4 * (tid / B3_TM + KGS * (g)))
 #define B3_BROW(g) (TB ? tid % B3_TM : tid / 8 + RPT * (g))
-#define B3_BK4(g) (TB ? 4 * (tid / B3_TM + 4 * (g)) : 4 * (tid % 8))
+#define B3_BK4(g) (TB ? 4 * (tid / B3_TM + KGS * (g)) : 4 * (tid % 8))
   // whole 128 x 32 blocks inside the matrix load without per-element guards
   const bool afull = m0 + B3_TM <= M, bfull = n0 + B3_TM <= N;
 #define B3_AIDX(gm, gk) ((TA || (SYMA && (gm) < (gk))) ? (gk) + int64_t(gm) * pr.lda : (gm) + int64_t(gk) * pr.lda)
 #define B3_BIDX(gn, gk) (TB ? (gn) + int64_t(gk) * pr.ldb : (gk) + int64_t(gn) * pr.ldb)
 #define B3_LOADA(k0)                                                                                    \
   if (afull && (k0) + B3_BK <= K) {                                                                     \
-    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+    _Pragma("unroll") for (int g = 0; g < GPT; ++g)                                                     \
       _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
         const int gm = m0 + B3_AROW(g), gk = (k0) + B3_AK(g) + q;                                       \
         rs[4 * g + q] = Ap[B3_AIDX(gm, gk)];                                                            \
       }                                                                                                 \
   } else {                                                                                              \
-    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+    _Pragma("unroll") for (int g = 0; g < GPT; ++g)                                                     \
       _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
         const int gm = m0 + B3_AROW(g), gk = (k0) + B3_AK(g) + q;                                       \
         rs[4 * g + q] = (gm < M && gk < K) ? Ap[B3_AIDX(gm, gk)] : make_double2(0.0, 0.0);              \
@@ -643,13 +647,13 @@ __global__ __launch_bounds__(B3_TM * 4) void k_cgemm_bf3(const GemmProb* __restr
   }
 #define B3_LOADB(k0)                                                                                    \
   if (bfull && (k0) + B3_BK <= K) {                                                                     \
-    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+    _Pragma("unroll") for (int g = 0; g < GPT; ++g)                                                     \
       _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
         const int gn = n0 + B3_BROW(g), gk = (k0) + B3_BK4(g) + q;                                      \
         rs[4 * g + q] = Bp[B3_BIDX(gn, gk)];                                                            \
       }                                                                                                 \
   } else {                                                                                              \
-    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+    _Pragma("unroll") for (int g = 0; g < GPT; ++g)                                                     \
       _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
         const int gn = n0 + B3_BROW(g), gk = (k0) + B3_BK4(g) + q;                                      \
         rs[4 * g + q] = (gn < N && gk < K) ? Bp[B3_BIDX(gn, gk)] : make_double2(0.0, 0.0);              \
@@ -663,8 +667,8 @@ __global__ __launch_bounds__(B3_TM * 4) void k_cgemm_bf3(const GemmProb* __restr
     *reinterpret_cast<f4*>(d_ + B3_PLANE) = f4{static_cast<float>((v)[0].y), static_cast<float>((v)[1].y), \
                                                static_cast<float>((v)[2].y), static_cast<float>((v)[3].y)}; \
   } while (0)
-#define B3_STOREA(buf) _Pragma("unroll") for (int g = 0; g < 2; ++g) B3_PUT(buf, 0, B3_AROW(g), B3_AK(g), rs + 4 * g);
-#define B3_STOREB(buf) _Pragma("unroll") for (int g = 0; g < 2; ++g) B3_PUT(buf, 2, B3_BROW(g), B3_BK4(g), rs + 4 * g);
+#define B3_STOREA(buf) _Pragma("unroll") for (int g = 0; g < GPT; ++g) B3_PUT(buf, 0, B3_AROW(g), B3_AK(g), rs + 4 * g);
+#define B3_STOREB(buf) _Pragma("unroll") for (int g = 0; g < GPT; ++g) B3_PUT(buf, 2, B3_BROW(g), B3_BK4(g), rs + 4 * g);
 
   const int nk = (K + B3_BK - 1) / B3_BK;
   B3_LOADA(0)
@@ -680,10 +684,10 @@ __global__ __launch_bounds__(B3_TM * 4) void k_cgemm_bf3(const GemmProb* __restr
       B3_LOADA((kt + 1) * B3_BK)
     }
     const float* L = lds[cur];
-    bf8 b[2][6];   // [j][2 slice + part]
+    bf8 b[JB][6];   // [j][2 slice + part]
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const float* br = L + 2 * B3_PLANE + (wn * 32 + j * 16 + orow) * B3_LD + ok;
+    for (int j = 0; j < JB; ++j) {
+      const float* br = L + 2 * B3_PLANE + (wn * WCOL + j * 16 + orow) * B3_LD + ok;
       split8(*reinterpret_cast<const f4*>(br), *reinterpret_cast<const f4*>(br + 4), b[j][0], b[j][2], b[j][4]);
       split8(*reinterpret_cast<const f4*>(br + B3_PLANE), *reinterpret_cast<const f4*>(br + B3_PLANE + 4), b[j][1],
              b[j][3], b[j][5]);
@@ -706,16 +710,16 @@ __global__ __launch_bounds__(B3_TM * 4) void k_cgemm_bf3(const GemmProb* __restr
 #pragma unroll
         for (int sb = 0; sb + sa < 3; ++sb) {
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+          for (int j = 0; j < JB; ++j)
             cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb], a[2 * sa], cre[i][j], 0, 0, 0);
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+          for (int j = 0; j < JB; ++j)
             cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb], a[2 * sa + 1], cim[i][j], 0, 0, 0);
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+          for (int j = 0; j < JB; ++j)
             cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb + 1], na[sa], cre[i][j], 0, 0, 0);
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+          for (int j = 0; j < JB; ++j)
             cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb + 1], a[2 * sa], cim[i][j], 0, 0, 0);
         }
       if (i == IB / 2 - 1 && more) {  // halfway: the next A block to LDS, fetch the next B block
@@ -745,11 +749,11 @@ __global__ __launch_bounds__(B3_TM * 4) void k_cgemm_bf3(const GemmProb* __restr
 #pragma unroll
   for (int i = 0; i < IB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm * (B3_TM / 2) + i * 16 + (lane & 15);
-        const int n = n0 + wn * 32 + j * 16 + F32_DROW(r, lane);
+        const int n = n0 + wn * WCOL + j * 16 + F32_DROW(r, lane);
         if (m >= M || n >= N) continue;
         if (SYM && m < n) continue;
         double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
@@ -937,12 +941,12 @@ static void gemm32_inst(const DevOp& o, hipStream_t st) {
 template <int F>
 static void gemm_bf3_inst(const DevOp& o, hipStream_t st) {
   const int64_t total = o.tile_count * o.npoles;
-  if (o.tile128)
-    hipLaunchKernelGGL((k_cgemm_bf3<F, 128>), dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm,
+  if (o.bf3 == 1)
+    hipLaunchKernelGGL((k_cgemm_bf3<F, 128, 8>), dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm,
                        o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
                        o.c, o.sc);
   else
-    hipLaunchKernelGGL((k_cgemm_bf3<F, 64>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm,
+    hipLaunchKernelGGL((k_cgemm_bf3<F, 64, 4>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm,
                        o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
                        o.c, o.sc);
 }
