@@ -124,6 +124,7 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
     ctx.profile(True)
     step()
     prof = ctx.profile_read()
+    by_depth = ctx.profile_read_depth()
     ctx.profile(False)
     rho = [o.numpy() for o in outs]
     for o in outs:
@@ -131,6 +132,7 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
     ctx.close()
     res = {"precision": precision, "setup_s": setup_s, "ms_per_step": 1e3 * dt / steps,
            "poles_per_s": n_poles * steps / dt, "stats": st, "prof": prof,
+           "ms_by_depth": {k: [round(float(x), 3) for x in v] for k, v in by_depth.items() if v.any()},
            "flops_model_per_step": n_poles * sum(x["flops_per_pole"] for x in st)}
     print("bench: %s %.1f ms/step" % (precision, res["ms_per_step"]), file=sys.stderr, flush=True)
     return res, rho
@@ -258,6 +260,7 @@ def main():
             "max_abs_err_vs_oracle_sample": golden_error(name, rho64[0], mu, n_poles) if len(rho64) == 1 else None},
         "other_forms": others,
         "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
+        "kernel_ms_by_depth": head["ms_by_depth"],
         "gemm_tflops": gemm_tf,
         "roofline": {"kernel": kname, "bound": "mfma",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",

@@ -78,8 +78,8 @@ typedef struct {
   int32_t gemm_variant; /* mixed mode, front-update GEMMs of the low poles: -1 (default) per-launch choice
                            (heuristic, refined by ndrho_autotune); 0 FP64; 1 FP32 products on 64x64 tiles;
                            2 FP32 products on 128x128 tiles; 3 split-BF16 products on 128x128 tiles;
-                           4 split-BF16 products on 64x64 tiles.  FP32 mode accepts 0-2, split-BF16
-                           mode 0-4 */
+                           4 split-BF16 products on 64x64 tiles; 5 split-BF16 products on 128x128 tiles,
+                           each element split once per stage.  FP32 mode accepts 0-2, split-BF16 mode 0-5 */
 } ndrho_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -192,6 +192,13 @@ int ndrho_profile(ndrho_ctx* ctx, int32_t enable);
  * flops (complex GEMMs: 8 real flops per complex multiply-add, symmetric
  * outputs counted once), and launch counts; arrays of NDRHO_K_COUNT. */
 int ndrho_profile_read(const ndrho_ctx* ctx, double* ms, double* flops, int64_t* launches);
+/* The same milliseconds split by dissection-tree depth of the launch:
+ * ms[kind * NDRHO_PROFILE_DEPTHS + depth] (row-major, NDRHO_K_COUNT rows,
+ * caller-owned, fully written); depths >= NDRHO_PROFILE_DEPTHS - 2 share the
+ * second-to-last column, and launches outside the tree (pole sum, M0 set-up)
+ * use the last.  EINVAL for NULL arguments. */
+enum { NDRHO_PROFILE_DEPTHS = 32 };
+int ndrho_profile_read_depth(const ndrho_ctx* ctx, double* ms);
 
 /* Device memory on the context's device for callers without their own
  * allocator (e.g. a device-resident rho_out).  ndrho_device_alloc returns

@@ -59,6 +59,7 @@ SIGNATURES = [
     ("ndrho_stats", C.c_int, [_P, C.c_int32, C.POINTER(Stats)]),
     ("ndrho_profile", C.c_int, [_P, C.c_int32]),
     ("ndrho_profile_read", C.c_int, [_P, _DP, _DP, _I64P]),
+    ("ndrho_profile_read_depth", C.c_int, [_P, _DP]),
     ("ndrho_device_alloc", C.c_int, [_P, C.c_int64, C.POINTER(_P)]),
     ("ndrho_device_free", C.c_int, [_P, _P]),
     ("ndrho_device_to_host", C.c_int, [_P, _P, _P, C.c_int64]),
@@ -339,6 +340,15 @@ class Context:
                                                  _ptr(nl, C.c_int64)))
         return {name: {"ms": float(ms[i]), "flops": float(fl[i]), "launches": int(nl[i])}
                 for i, name in enumerate(self.KINDS)}
+
+    def profile_read_depth(self):
+        """Profiled milliseconds per kernel kind and tree depth: {kind: array over depths}
+        (the last column holds launches outside the tree)."""
+        nd_ = 32
+        ms = np.zeros(len(self.KINDS) * nd_)
+        self._check(self._lib.ndrho_profile_read_depth(self._h, _ptr(ms, C.c_double)))
+        ms = ms.reshape(len(self.KINDS), nd_)
+        return {name: ms[i].copy() for i, name in enumerate(self.KINDS)}
 
     def close(self):
         h = getattr(self, "_h", None)

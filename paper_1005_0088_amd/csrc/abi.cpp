@@ -88,7 +88,7 @@ struct DevStruct {
 
 thread_local std::string g_err;  // errors without a context (create, plan utilities)
 
-enum { V_FP64 = 0, V_F32_64 = 1, V_F32_128 = 2, V_BF3_128 = 3, V_BF3_64 = 4, V_COUNT = 5 };
+enum { V_FP64 = 0, V_F32_64 = 1, V_F32_128 = 2, V_BF3_128 = 3, V_BF3_64 = 4, V_BF3S_128 = 5, V_COUNT = 6 };
 
 // Variants a precision mode may choose from: FP32 mode its FP32 products;
 // split-BF16 mode its split-BF16 products and, where a launch runs faster
@@ -170,13 +170,20 @@ struct ndrho_ctx {
     size_t ev;
     double flops;
     int op;  // program index of the launch (upward ops, then downward), -1 for the pole sum
+    int depth;
   };
   int cur_op = -1;
+  int cur_depth = -1;
   std::vector<double>* op_ms = nullptr;  // per-op milliseconds while autotuning
   std::vector<Rec> recs;
   double prof_ms[NDRHO_K_COUNT] = {0};
   double prof_flops[NDRHO_K_COUNT] = {0};
   int64_t prof_n[NDRHO_K_COUNT] = {0};
+  double prof_depth_ms[NDRHO_K_COUNT * NDRHO_PROFILE_DEPTHS] = {0};
+  void clear_profile() {
+    for (int k = 0; k < NDRHO_K_COUNT; ++k) prof_ms[k] = prof_flops[k] = 0, prof_n[k] = 0;
+    for (double& x : prof_depth_ms) x = 0;
+  }
 
   hipEvent_t event(size_t i) {
     while (events.size() <= i) {
@@ -197,7 +204,7 @@ struct ndrho_ctx {
     HIP_OK(hipEventRecord(event(i), stream));
     launch();
     HIP_OK(hipEventRecord(event(i + 1), stream));
-    recs.push_back(Rec{kind, i, flops, cur_op});
+    recs.push_back(Rec{kind, i, flops, cur_op, cur_depth});
   }
   // fold recorded events into the totals (stream must be complete)
   void fold_profile() {
@@ -207,6 +214,8 @@ struct ndrho_ctx {
       prof_ms[r.kind] += ms;
       prof_flops[r.kind] += r.flops;
       prof_n[r.kind] += 1;
+      const int d = r.depth < 0 ? NDRHO_PROFILE_DEPTHS - 1 : std::min(r.depth, NDRHO_PROFILE_DEPTHS - 2);
+      prof_depth_ms[r.kind * NDRHO_PROFILE_DEPTHS + d] += ms;
       if (op_ms && r.op >= 0 && r.op < static_cast<int>(op_ms->size())) (*op_ms)[r.op] += ms;
     }
     recs.clear();
@@ -347,8 +356,8 @@ struct ndrho_ctx {
           }
           DevOp l = d;  // low-precision products for the others
           l.fp32 = var == V_F32_64 || var == V_F32_128;
-          l.bf3 = var == V_BF3_128 ? 1 : var == V_BF3_64 ? 2 : 0;
-          if (var == V_F32_128 || var == V_BF3_128) {
+          l.bf3 = var == V_BF3_128 ? 1 : var == V_BF3_64 ? 2 : var == V_BF3S_128 ? 3 : 0;
+          if (var == V_F32_128 || var == V_BF3_128 || var == V_BF3S_128) {
             l.tile128 = true;
             l.gemm_tiles = S.gemm_tiles + op.tile128_begin;
             l.tile_count = op.tile128_count;
@@ -376,14 +385,17 @@ struct ndrho_ctx {
     };
     cur_op = 0;
     for (const Op& op : P.upward) {
+      cur_depth = op.depth;
       run(op);
       ++cur_op;
     }
     for (const Op& op : P.downward) {
+      cur_depth = op.depth;
       run(op);
       ++cur_op;
     }
     cur_op = -1;
+    cur_depth = -1;
     hipError_t ea = hipSuccess;
     timed(NDRHO_K_ACCUM, 0.0,
           [&] { ea = launch_accum(S.acc_slot, P.nnz, bufs[BUF_PANEL], P.panel_total, w, nb, acc, stream); });
@@ -890,7 +902,7 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
       throw;
     }
     ctx->prof = was_prof;
-    for (int k2 = 0; k2 < NDRHO_K_COUNT; ++k2) ctx->prof_ms[k2] = ctx->prof_flops[k2] = 0, ctx->prof_n[k2] = 0;
+    ctx->clear_profile();
     std::string choice;
     for (int i = 0; i < nops; ++i) {
       int best = V_FP64;
@@ -943,8 +955,7 @@ int ndrho_profile(ndrho_ctx* ctx, int32_t enable) {
     HIP_OK(hipStreamSynchronize(ctx->stream));
     if (!ctx->recs.empty()) ctx->fold_profile();
     ctx->prof = enable != 0;
-    if (ctx->prof)
-      for (int k = 0; k < NDRHO_K_COUNT; ++k) ctx->prof_ms[k] = ctx->prof_flops[k] = 0, ctx->prof_n[k] = 0;
+    if (ctx->prof) ctx->clear_profile();
   });
 }
 
@@ -955,6 +966,12 @@ int ndrho_profile_read(const ndrho_ctx* ctx, double* ms, double* flops, int64_t*
     if (flops) flops[k] = ctx->prof_flops[k];
     if (launches) launches[k] = ctx->prof_n[k];
   }
+  return NDRHO_OK;
+}
+
+int ndrho_profile_read_depth(const ndrho_ctx* ctx, double* ms) {
+  if (!ctx || !ms) return NDRHO_EINVAL;
+  for (int i = 0; i < NDRHO_K_COUNT * NDRHO_PROFILE_DEPTHS; ++i) ms[i] = ctx->prof_depth_ms[i];
   return NDRHO_OK;
 }
 

@@ -553,6 +553,7 @@ constexpr int B3_LD = B3_BK + 4;         // LDS row stride (floats)
 // packed conversion (v_cvt_pk_bf16_f32 rounds to nearest even)
 typedef float f2 __attribute__((ext_vector_type(2)));
 typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
 typedef unsigned u4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void split2(f2 x, unsigned& h, unsigned& m, unsigned& l) {
   const b2 hh = __builtin_convertvector(x, b2);
@@ -768,6 +769,193 @@ __global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restric
       }
 }
 
+// Variant of k_cgemm_bf3 (128 x 128 tiles, eight waves of 64 x 32) that
+// splits every element once per stage instead of once per wave that reads
+// it: the next stage's FP64 values are fetched into registers while the
+// matrix cores work, and between the two barriers of a step each thread
+// rounds its share to FP32, splits it and stores the twelve bf16 planes
+// (A and B, 3 slices x re/im; rows padded to 40 bf16) that the MFMA operands
+// are read from directly.
+constexpr int B3S_TM = 128;
+constexpr int B3S_LD = B3_BK + 8;            // bf16 per plane row
+constexpr int B3S_PLANE = B3S_TM * B3S_LD;   // bf16 per plane
+
+template <int FLAGS>
+__global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__ probs,
+                                                    const TileRef* __restrict__ tiles, int64_t ntiles,
+                                                    int64_t npoles, const double2* __restrict__ A, int64_t sA,
+                                                    const double2* __restrict__ B, int64_t sB, const double2* C0,
+                                                    int64_t sC0, double2* C, int64_t sC) {
+  constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
+  static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
+  // planes: [operand A/B][2 slice + part][row][k]
+  __shared__ __attribute__((aligned(16))) unsigned short lds[12 * B3S_PLANE];
+
+  const int64_t total = ntiles * npoles;
+  const int64_t logical = xcd_remap(blockIdx.x, total);
+  const int64_t pole = logical / ntiles;
+  const TileRef tr = tiles[logical % ntiles];
+  const GemmProb pr = probs[tr.prob];
+  const double2* Ap = A + pole * sA + pr.a_off;
+  const double2* Bp = B + pole * sB + pr.b_off;
+  const int M = pr.m, N = pr.n, K = pr.k;
+  const int m0 = tr.tm * B3S_TM, n0 = tr.tn * B3S_TM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;   // wave tile: rows 64 wm.., columns 32 wn..
+
+  f4 cre[4][2], cim[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      cim[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  // staging map as in k_cgemm_bf3: two groups of four consecutive k of one
+  // row per thread and operand
+  double2 ra[8], rb[8];
+  const bool afull = m0 + B3S_TM <= M, bfull = n0 + B3S_TM <= N;
+#define S3_AROW(g) (TA ? tid / 8 + 64 * (g) : tid % 128)
+#define S3_AK(g) (TA ? 4 * (tid % 8) : 4 * (tid / 128 + 4 * (g)))
+#define S3_BROW(g) (TB ? tid % 128 : tid / 8 + 64 * (g))
+#define S3_BK4(g) (TB ? 4 * (tid / 128 + 4 * (g)) : 4 * (tid % 8))
+#define S3_AIDX(gm, gk) ((TA || (SYMA && (gm) < (gk))) ? (gk) + int64_t(gm) * pr.lda : (gm) + int64_t(gk) * pr.lda)
+#define S3_BIDX(gn, gk) (TB ? (gn) + int64_t(gk) * pr.ldb : (gk) + int64_t(gn) * pr.ldb)
+#define S3_LOAD(k0)                                                                                     \
+  if (afull && (k0) + B3_BK <= K) {                                                                     \
+    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
+        const int gm = m0 + S3_AROW(g), gk = (k0) + S3_AK(g) + q;                                       \
+        ra[4 * g + q] = Ap[S3_AIDX(gm, gk)];                                                            \
+      }                                                                                                 \
+  } else {                                                                                              \
+    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
+        const int gm = m0 + S3_AROW(g), gk = (k0) + S3_AK(g) + q;                                       \
+        ra[4 * g + q] = (gm < M && gk < K) ? Ap[S3_AIDX(gm, gk)] : make_double2(0.0, 0.0);              \
+      }                                                                                                 \
+  }                                                                                                     \
+  if (bfull && (k0) + B3_BK <= K) {                                                                     \
+    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
+        const int gn = n0 + S3_BROW(g), gk = (k0) + S3_BK4(g) + q;                                      \
+        rb[4 * g + q] = Bp[S3_BIDX(gn, gk)];                                                            \
+      }                                                                                                 \
+  } else {                                                                                              \
+    _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
+        const int gn = n0 + S3_BROW(g), gk = (k0) + S3_BK4(g) + q;                                      \
+        rb[4 * g + q] = (gn < N && gk < K) ? Bp[S3_BIDX(gn, gk)] : make_double2(0.0, 0.0);              \
+      }                                                                                                 \
+  }
+  // split four complex values (one group) and store them into the six planes of an operand
+#define S3_PUT(base, row, kk, v)                                                                        \
+  do {                                                                                                  \
+    unsigned h0, h1, m0_, m1, l0, l1;                                                                   \
+    unsigned short* d_ = lds + (base) + (row) * B3S_LD + (kk);                                          \
+    split2(f2{static_cast<float>((v)[0].x), static_cast<float>((v)[1].x)}, h0, m0_, l0);                \
+    split2(f2{static_cast<float>((v)[2].x), static_cast<float>((v)[3].x)}, h1, m1, l1);                 \
+    *reinterpret_cast<u2v*>(d_) = u2v{h0, h1};                                                          \
+    *reinterpret_cast<u2v*>(d_ + 2 * B3S_PLANE) = u2v{m0_, m1};                                         \
+    *reinterpret_cast<u2v*>(d_ + 4 * B3S_PLANE) = u2v{l0, l1};                                          \
+    split2(f2{static_cast<float>((v)[0].y), static_cast<float>((v)[1].y)}, h0, m0_, l0);                \
+    split2(f2{static_cast<float>((v)[2].y), static_cast<float>((v)[3].y)}, h1, m1, l1);                 \
+    *reinterpret_cast<u2v*>(d_ + B3S_PLANE) = u2v{h0, h1};                                              \
+    *reinterpret_cast<u2v*>(d_ + 3 * B3S_PLANE) = u2v{m0_, m1};                                         \
+    *reinterpret_cast<u2v*>(d_ + 5 * B3S_PLANE) = u2v{l0, l1};                                          \
+  } while (0)
+#define S3_STORE()                                                                                      \
+  _Pragma("unroll") for (int g = 0; g < 2; ++g) {                                                       \
+    S3_PUT(0, S3_AROW(g), S3_AK(g), ra + 4 * g);                                                        \
+    S3_PUT(6 * B3S_PLANE, S3_BROW(g), S3_BK4(g), rb + 4 * g);                                           \
+  }
+
+  const int nk = (K + B3_BK - 1) / B3_BK;
+  S3_LOAD(0)
+  S3_STORE()
+  __syncthreads();
+  const int orow = lane & 15, ok = 8 * (lane >> 4);
+  for (int kt = 0; kt < nk; ++kt) {
+    const bool more = kt + 1 < nk;
+    if (more) {
+      S3_LOAD((kt + 1) * B3_BK)
+    }
+    bf8 b[2][6];   // [j][2 slice + part]
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        b[j][pl] = *reinterpret_cast<const bf8*>(lds + (6 + pl) * B3S_PLANE + (wn * 32 + j * 16 + orow) * B3S_LD + ok);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bf8 a[6], na[3];
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        a[pl] = *reinterpret_cast<const bf8*>(lds + pl * B3S_PLANE + (wm * 64 + i * 16 + orow) * B3S_LD + ok);
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl)  // -Im(A) slices: sign flip of the bf16 bits
+        na[sl] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, a[2 * sl + 1]) ^ 0x80008000u);
+#pragma unroll
+      for (int sa = 0; sa < 3; ++sa)
+#pragma unroll
+        for (int sb = 0; sb + sa < 3; ++sb) {
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb], a[2 * sa], cre[i][j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb], a[2 * sa + 1], cim[i][j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb + 1], na[sa], cre[i][j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j][2 * sb + 1], a[2 * sa], cim[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    if (more) {
+      S3_STORE()
+    }
+    __syncthreads();
+  }
+#undef S3_AROW
+#undef S3_AK
+#undef S3_BROW
+#undef S3_BK4
+#undef S3_AIDX
+#undef S3_BIDX
+#undef S3_LOAD
+#undef S3_PUT
+#undef S3_STORE
+
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
+  double2* Cp = C + pole * sC + pr.c_off;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 64 + i * 16 + (lane & 15);
+        const int n = n0 + wn * 32 + j * 16 + F32_DROW(r, lane);
+        if (m >= M || n >= N) continue;
+        if (SYM && m < n) continue;
+        double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
+        if (NEG) v = make_double2(-v.x, -v.y);
+        if (BETA) {
+          const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
+          v.x += c0.x;
+          v.y += c0.y;
+        }
+        Cp[m + int64_t(n) * pr.ldc] = v;
+        if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+      }
+}
+
 // ----------------------------------------------------------------- copy
 //
 // dst (rows x cols) <- src, or <- src^T through an LDS tile so that both the
@@ -945,10 +1133,13 @@ static void gemm_bf3_inst(const DevOp& o, hipStream_t st) {
     hipLaunchKernelGGL((k_cgemm_bf3<F, 128, 8>), dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm,
                        o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
                        o.c, o.sc);
-  else
+  else if (o.bf3 == 2)
     hipLaunchKernelGGL((k_cgemm_bf3<F, 64, 4>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm,
                        o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
                        o.c, o.sc);
+  else
+    hipLaunchKernelGGL(k_cgemm_bf3s<F>, dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm, o.gemm_tiles,
+                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
 }
 
 hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
