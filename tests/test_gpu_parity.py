@@ -130,6 +130,57 @@ def test_rho_against_dense_eigen_oracle(ctx, dims, nb, n_poles, coords):
     assert dense.trace_rho_s(got, sysd["s"]) == pytest.approx(sysd["n"], abs=1e-8)
 
 
+@pytest.mark.parametrize("n,with_coords", [(1, True), (1, False), (37, True), (37, False)])
+def test_diagonal_systems_closed_form(ctx, n, with_coords):
+    # no couplings: every row is its own front (a forest of one-row roots);
+    # rho_ii = 2 f(beta (h_i/s_i - mu)) / s_i
+    from oracle import poles
+    rng = np.random.default_rng(50 + n)
+    h = rng.normal(0.0, 1.0, n)
+    s = rng.uniform(0.5, 2.0, n)
+    row_ptr = np.arange(n + 1)
+    col = np.arange(n)
+    coords = np.stack([np.arange(n, dtype=float), np.zeros(n), np.zeros(n)], 1) if with_coords else None
+    print("case: diagonal n=%d coords=%s" % (n, with_coords), flush=True)
+    sid = ctx.set_structure(n, row_ptr, col, h, s, coords)
+    mu = 0.1
+    ctx.set_poles(sid, mu, BETA, 60)
+    got = ctx.density_matrix(sid)
+    ref = 2.0 * poles.fermi(BETA * (h / s - mu)) / s
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("dims,n_poles", [((2, 2), 40), ((2, 2, 2), 1), ((5, 5), 1)])
+def test_single_front_and_single_pole(ctx, dims, n_poles):
+    # n <= leaf rows (one front, the root only) and a one-pole fraction
+    sysd = lattice(dims, "nn", 60)
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    sid = _register(ctx, sysd)
+    ctx.set_poles(sid, 0.05, BETA, n_poles)
+    got = ctx.density_matrix(sid)
+    ref = dense.rho_cf_pattern(eps, c, 0.05, BETA, n_poles, rows, cols)
+    assert np.max(np.abs(got - ref)) < 1e-11
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16x3"])
+def test_mixed_mode_with_every_pole_fp64_equals_fp64_form(precision):
+    # when the FP64 set covers every pole no low-precision launch runs and
+    # the result is the FP64 form's, bit for bit
+    import paper_1005_0088_amd as nd
+    sysd = lattice((8, 7, 6), "nn", 61)
+    with nd.Context(0) as c:
+        sid = _register(c, sysd)
+        c.set_poles(sid, 0.0, BETA, 20)
+        ref = c.density_matrix(sid)
+    with nd.Context(0, precision=precision, fp64_poles=10, fp64_far_poles=10) as c:
+        sid = _register(c, sysd)
+        c.set_poles(sid, 0.0, BETA, 20)
+        got = c.density_matrix(sid)
+        assert c.stats(sid)["n_fp64_poles"] == 20
+    assert np.array_equal(got, ref)
+
+
 def test_batched_equals_unbatched_bitwise():
     import paper_1005_0088_amd as nd
     sysd = lattice((6, 5, 5), "nn2", 9)
