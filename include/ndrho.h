@@ -80,6 +80,9 @@ typedef struct {
                            2 FP32 products on 128x128 tiles; 3 split-BF16 products on 128x128 tiles;
                            4 split-BF16 products on 64x64 tiles; 5 split-BF16 products on 128x128 tiles,
                            each element split once per stage.  FP32 mode accepts 0-2, split-BF16 mode 0-5 */
+  int32_t fp64_small_tiles; /* FP64 GEMM launches: -1 (default) one wave per 32x32 output tile where the
+                               launch's problems would fill less than half of the 64x64 tiles; 0 never;
+                               1 always */
 } ndrho_options;
 
 /* Fill *opt with the defaults listed above. */

@@ -25,7 +25,7 @@ class Options(C.Structure):
     _fields_ = [("leaf_rows", C.c_int32), ("precision", C.c_int32), ("pole_batch", C.c_int32),
                 ("mem_fraction", C.c_double), ("verbose", C.c_int32), ("fp64_poles", C.c_int32),
                 ("fp64_pole_im", C.c_double), ("fp64_far_poles", C.c_int32), ("use_graph", C.c_int32),
-                ("gemm_variant", C.c_int32)]
+                ("gemm_variant", C.c_int32), ("fp64_small_tiles", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -222,7 +222,8 @@ class Context:
     """
 
     def __init__(self, device=0, stream=None, leaf_rows=32, pole_batch=0, mem_fraction=0.8, precision="fp64",
-                 fp64_poles=None, fp64_pole_im=None, use_graph=True, gemm_variant=-1, fp64_far_poles=None):
+                 fp64_poles=None, fp64_pole_im=None, use_graph=True, gemm_variant=-1, fp64_far_poles=None,
+                 fp64_small_tiles=-1):
         self._lib = load_library()
         opt = Options()
         self._lib.ndrho_default_options(C.byref(opt))
@@ -238,6 +239,7 @@ class Context:
             opt.fp64_far_poles = int(fp64_far_poles)
         opt.use_graph = int(bool(use_graph))
         opt.gemm_variant = int(gemm_variant)
+        opt.fp64_small_tiles = int(fp64_small_tiles)
         handle = None
         if stream is not None:
             handle = getattr(stream, "cuda_stream", stream)

@@ -344,12 +344,23 @@ struct ndrho_ctx {
           const int var = opt.gemm_variant >= 0 ? opt.gemm_variant : S.variant[cur_op];
           const bool split = !(op.flags & OP_PIVOT) && nhi < nb && var != V_FP64;
           const int k64 = (op.flags & OP_PIVOT) ? NDRHO_K_GEMM_PIVOT : NDRHO_K_GEMM;
+          // FP64 launches of small problems: one wave per 32x32 tile
+          const bool small = opt.fp64_small_tiles < 0 ? op.small : opt.fp64_small_tiles != 0;
+          auto fp64_launch = [&](DevOp x) {
+            if (small) {
+              x.small = true;
+              x.gemm_tiles = S.gemm_tiles + op.tile32_begin;
+              x.tile_count = op.tile32_count;
+            }
+            return x;
+          };
           if (!split) {
-            timed(k64, op.flops * nb, [&] { e = launch_gemm(d, stream); });
+            const DevOp h = fp64_launch(d);
+            timed(k64, op.flops * nb, [&] { e = launch_gemm(h, stream); });
             break;
           }
           if (nhi > 0) {  // FP64 for the poles nearest the real axis
-            DevOp h = d;
+            DevOp h = fp64_launch(d);
             h.npoles = nhi;
             timed(k64, op.flops * nhi, [&] { e = launch_gemm(h, stream); });
             if (e != hipSuccess) break;
@@ -655,6 +666,7 @@ int ndrho_default_options(ndrho_options* opt) {
   opt->fp64_far_poles = 8;
   opt->use_graph = 1;
   opt->gemm_variant = -1;
+  opt->fp64_small_tiles = -1;
   return NDRHO_OK;
 }
 
@@ -675,6 +687,7 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
       fail(NDRHO_EUNSUPPORTED, "precision must be NDRHO_FP64, NDRHO_MIXED_FP32 or NDRHO_MIXED_BF16X3");
     if (c->opt.fp64_poles < 0 || c->opt.fp64_far_poles < 0 || !(c->opt.fp64_pole_im >= 0.0))
       fail(NDRHO_EINVAL, "invalid FP64 pole rule");
+    if (c->opt.fp64_small_tiles < -1 || c->opt.fp64_small_tiles > 1) fail(NDRHO_EINVAL, "invalid fp64_small_tiles");
     if (c->opt.gemm_variant < -1 || c->opt.gemm_variant >= V_COUNT ||
         (c->opt.gemm_variant >= 0 && !variant_allowed(c->opt.precision, c->opt.gemm_variant)))
       fail(NDRHO_EINVAL, "invalid gemm_variant for this precision");

@@ -15,6 +15,7 @@ struct DevOp {
   int npoles = 1;
   bool fp32 = false;     // GEMM products on the FP32 matrix cores
   bool tile128 = false;  // FP32 GEMM on 128x128 tiles (else 64x64)
+  bool small = false;    // FP64 GEMM with one wave per 32x32 tile
   int bf3 = 0;           // split-BF16 products: 0 no; 1 128x128 tiles on 8 waves; 2 64x64 tiles on 4;
                          // 3 128x128 tiles, one split per element and stage
   int64_t count = 0, tile_count = 0;

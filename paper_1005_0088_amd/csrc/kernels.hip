@@ -386,6 +386,109 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
       }
 }
 
+// The same FP64 contraction for small problems: one wave per 32 x 32
+// output tile (four waves per workgroup, independent), operands read from
+// global memory straight into the MFMA operand registers: no LDS and no
+// barriers, so a tile whose problem is much smaller than 64 x 64 costs
+// little.  K advances by 8 (two MFMA k-steps), all loads of a step issued
+// before its products; an element outside the problem is read from the
+// operand's first element and replaced by zero (no branches around loads).
+template <int FLAGS>
+__global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__ probs,
+                                                 const TileRef* __restrict__ tiles, int64_t ntiles, int64_t npoles,
+                                                 const double2* __restrict__ A, int64_t sA,
+                                                 const double2* __restrict__ B, int64_t sB, const double2* C0,
+                                                 int64_t sC0, double2* C, int64_t sC) {
+  constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
+  static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
+  const int64_t total = ntiles * npoles;
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (w >= total) return;  // the whole wave; nothing here synchronises waves
+  const int lane = threadIdx.x & 63;
+  const int64_t pole = w / ntiles;
+  const TileRef tr = tiles[w % ntiles];
+  const GemmProb pr = probs[tr.prob];
+  const double2* Ap = A + pole * sA + pr.a_off;
+  const double2* Bp = B + pole * sB + pr.b_off;
+  const int M = pr.m, N = pr.n, K = pr.k;
+  const int m0 = tr.tm * 32, n0 = tr.tn * 32;
+  const int r = lane & 15, kq = lane >> 4;
+
+  d4 p1[2][2], p2[2][2], p3[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      p1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      p2[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      p3[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    double2 a[2][2], b[2][2];
+    bool oa[2][2], ob[2][2];
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int gk = k0 + 4 * st + kq;
+        const int gm = m0 + 16 * i + r;
+        oa[st][i] = gm < M && gk < K;
+        const int64_t ia = (TA || (SYMA && gm < gk)) ? gk + int64_t(gm) * pr.lda : gm + int64_t(gk) * pr.lda;
+        a[st][i] = Ap[oa[st][i] ? ia : int64_t(0)];
+        const int gn = n0 + 16 * i + r;
+        ob[st][i] = gn < N && gk < K;
+        const int64_t ib = TB ? gn + int64_t(gk) * pr.ldb : gk + int64_t(gn) * pr.ldb;
+        b[st][i] = Bp[ob[st][i] ? ib : int64_t(0)];
+      }
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      double ar[2], ai[2], as[2], br[2], bi[2], bs[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = oa[st][i] ? a[st][i].x : 0.0;
+        ai[i] = oa[st][i] ? a[st][i].y : 0.0;
+        br[i] = ob[st][i] ? b[st][i].x : 0.0;
+        bi[i] = ob[st][i] ? b[st][i].y : 0.0;
+        as[i] = ar[i] + ai[i];
+        bs[i] = br[i] + bi[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[j], ar[i], p1[i][j], 0, 0, 0);
+          p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bi[j], ai[i], p2[i][j], 0, 0, 0);
+          p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bs[j], as[i], p3[i][j], 0, 0, 0);
+        }
+    }
+  }
+
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
+  double2* Cp = C + pole * sC + pr.c_off;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + i * 16 + (lane & 15);
+        const int n = n0 + j * 16 + F64_DROW(q, lane);
+        if (m >= M || n >= N) continue;
+        if (SYM && m < n) continue;
+        double2 v = make_double2(p1[i][j][q] - p2[i][j][q], p3[i][j][q] - p1[i][j][q] - p2[i][j][q]);
+        if (NEG) v = make_double2(-v.x, -v.y);
+        if (BETA) {
+          const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
+          v.x += c0.x;
+          v.y += c0.y;
+        }
+        Cp[m + int64_t(n) * pr.ldc] = v;
+        if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+      }
+}
+
 // Same contraction with the products on the FP32 matrix cores
 // (v_mfma_f32_16x16x4f32) and FP32 accumulation: FP64 operands are rounded
 // to FP32 when staged into LDS, the four real products of each complex one
@@ -1111,8 +1214,13 @@ hipError_t launch_smallinv(const DevOp& o, int* status, int spd_check, hipStream
 template <int F>
 static void gemm_inst(const DevOp& o, hipStream_t st) {
   const int64_t total = o.tile_count * o.npoles;
-  hipLaunchKernelGGL(k_zgemm<F>, dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
-                     o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
+  if (o.small)  // one wave per 32x32 tile, four per workgroup
+    hipLaunchKernelGGL(k_zgemm_w<F>, dim3(static_cast<unsigned>((total + 3) / 4)), dim3(256), 0, st, o.gemm,
+                       o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
+                       o.c, o.sc);
+  else
+    hipLaunchKernelGGL(k_zgemm<F>, dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
+                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
 }
 
 template <int F>

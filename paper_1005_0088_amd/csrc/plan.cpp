@@ -307,6 +307,20 @@ struct Builder {
       }
     }
     op.tile128_count = static_cast<int64_t>(P.gemm_tiles.size()) - op.tile128_begin;
+    op.tile32_begin = static_cast<int64_t>(P.gemm_tiles.size());
+    double area = 0;
+    for (size_t i = 0; i < probs.size(); ++i) {
+      const GemmProb& g = probs[i];
+      const int tm = (g.m + 31) / 32, tn = (g.n + 31) / 32;
+      for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tn; ++b) {
+          if ((flags & G_SYM) && b > a) continue;
+          P.gemm_tiles.push_back(TileRef{static_cast<int32_t>(i), a, b, 0});
+        }
+      area += (flags & G_SYM) ? double(g.n) * (g.n + 1) / 2 : double(g.m) * g.n;
+    }
+    op.tile32_count = static_cast<int64_t>(P.gemm_tiles.size()) - op.tile32_begin;
+    op.small = double(op.tile_count) * 64 * 64 > 2.0 * area;
     op.flops = fl;
     P.flops_exec += fl;
     prog.push_back(op);

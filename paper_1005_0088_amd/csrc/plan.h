@@ -35,7 +35,7 @@ struct GemmProb {
   int32_t m, n, k, lda, ldb, ldc0, ldc, pad;
   int64_t a_off, b_off, c0_off, c_off;
 };
-struct TileRef {  // one 64x64 (or 128x128) output tile of problem `prob`
+struct TileRef {  // one 64x64 (or 128x128, or 32x32) output tile of problem `prob`
   int32_t prob, tm, tn, pad;
 };
 struct InvDesc {  // in-place inverse of an n x n block (n <= 64)
@@ -93,6 +93,9 @@ struct Op {
   int64_t begin = 0, count = 0;          // descriptor range
   int64_t tile_begin = 0, tile_count = 0;
   int64_t tile128_begin = 0, tile128_count = 0;  // 128x128 tiles (FP32-product GEMMs)
+  int64_t tile32_begin = 0, tile32_count = 0;    // 32x32 tiles (FP64 GEMM of small problems)
+  bool small = false;        // GEMM: FP64 launches on 32x32 tiles by default (more than half of
+                             // the 64x64 tile area would lie outside the problems)
   int64_t inv16 = 0, inv32 = 0;  // SMALLINV: leading descriptors with n <= 16, then n <= 32
   int depth = 0;
   double flops = 0;          // useful flops per pole (GEMM)

@@ -181,6 +181,26 @@ def test_mixed_mode_with_every_pole_fp64_equals_fp64_form(precision):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("dims,nb", [((9, 9, 9), "nn"), ((20, 18), "nn2"), ((300,), "nn")])
+def test_fp64_small_tile_kernel_matches(dims, nb):
+    # every FP64 GEMM on one-wave 32x32 tiles, on 64x64 tiles, or chosen by
+    # problem size: all three agree with the oracle
+    import paper_1005_0088_amd as nd
+    sysd = lattice(dims, nb, 62)
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    mu = dense.mu_for_count(eps, BETA, float(sysd["n"]))
+    ref = dense.rho_cf_pattern(eps, c, mu, BETA, 40, rows, cols)
+    got = {}
+    for mode in (1, 0, -1):
+        with nd.Context(0, fp64_small_tiles=mode) as cx:
+            sid = _register(cx, sysd)
+            cx.set_poles(sid, mu, BETA, 40)
+            got[mode] = cx.density_matrix(sid)
+        assert np.max(np.abs(got[mode] - ref)) < 1e-10
+    assert np.max(np.abs(got[1] - got[0])) < 1e-12
+
+
 def test_batched_equals_unbatched_bitwise():
     import paper_1005_0088_amd as nd
     sysd = lattice((6, 5, 5), "nn2", 9)
