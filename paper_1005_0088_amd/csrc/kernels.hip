@@ -189,25 +189,26 @@ __global__ __launch_bounds__(THREADS) void k_smallinv(const InvDesc* __restrict_
     const double2 pinv = cinv(p);
     const double2 akr = rowk[b][r];
     const double sg = r < k ? -1.0 : 1.0;  // a_rk = sg * a_kr
-    const double2 f = cmul(make_double2(sg * akr.x, sg * akr.y), pinv);  // a_rk / a_kk
     const bool prow = r == k;
+    // every element takes a_rc <- keep a_rc - f_r a_kc: off the pivot row
+    // keep = 1 and f_r = a_rk / a_kk (the rank-1 update); on it keep = 0 and
+    // f_k = -1/a_kk, which is the scaling of the pivot row by 1/a_kk.  The
+    // column k becomes -f_r (1/a_kk on the pivot row).  Rows r >= n and
+    // columns c >= n compute garbage that is never stored or published.
+    const double2 fr = cmul(make_double2(sg * akr.x, sg * akr.y), pinv);
+    const double2 f = prow ? make_double2(-pinv.x, -pinv.y) : fr;
+    const double keep = prow ? 0.0 : 1.0;
+    const double2 colk = prow ? pinv : make_double2(-fr.x, -fr.y);
 #pragma unroll
     for (int i = 0; i < COLS; ++i) {
       const int c = cg + CG * i;
       const double2 rk = rowk[b][c];
-      // row k: scaled by the pivot; column k: -a_rk / a_kk; else rank-1 update
       // (selects on scalars: a select of double2 values goes through memory)
-      double ux = v[i].x - (f.x * rk.x - f.y * rk.y);
-      double uy = v[i].y - (f.x * rk.y + f.y * rk.x);
-      const double sx = rk.x * pinv.x - rk.y * pinv.y, sy = rk.x * pinv.y + rk.y * pinv.x;
+      const double ux = keep * v[i].x - (f.x * rk.x - f.y * rk.y);
+      const double uy = keep * v[i].y - (f.x * rk.y + f.y * rk.x);
       const bool ck = c == k;
-      ux = ck ? -f.x : ux;
-      uy = ck ? -f.y : uy;
-      ux = prow ? (ck ? pinv.x : sx) : ux;
-      uy = prow ? (ck ? pinv.y : sy) : uy;
-      const bool act = live && c < n;
-      v[i].x = act ? ux : v[i].x;
-      v[i].y = act ? uy : v[i].y;
+      v[i].x = ck ? colk.x : ux;
+      v[i].y = ck ? colk.y : uy;
     }
   }
   // symmetrized write-back from the lower triangle
