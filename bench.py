@@ -88,7 +88,8 @@ def golden_error(name, rho, mu, n_poles):
     return float(np.max(np.abs(rho[np.asarray(g["entries"])] - np.asarray(g["values"]))))
 
 
-def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_poles, autotune=True, gemm_variant=-1):
+def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_poles, autotune=True, gemm_variant=-1,
+             tune_cache=None):
     """Time one precision form on one system (density_matrix) or several
     (density_matrix_batch: one schedule); returns (timing dict, rho list)."""
     variant = gemm_variant if precision != "fp64" else -1
@@ -100,7 +101,7 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
         ctx.set_poles(sid, mu, beta, n_poles)
         sids.append(sid)
     if precision != "fp64" and autotune and variant < 0:
-        ctx.autotune(sids)   # per-launch GEMM variant (untimed set-up, like the plan)
+        ctx.autotune(sids, tune_cache)   # per-launch GEMM variant (untimed set-up, like the plan)
     setup_s = time.time() - t0
     outs = [ctx.device_buffer(int(sysd["row_ptr"][-1])) for sysd in systems]
     multi = len(systems) > 1
@@ -153,6 +154,7 @@ def main():
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run the plain copy kernel over GIB gibibytes (HBM counter calibration) and exit")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default per-launch GEMM variants")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (read and appended)")
     ap.add_argument("--gemm-variant", type=int, default=-1,
                     help="force one GEMM variant on every low-precision front update (see ndrho_options)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -201,7 +203,7 @@ def main():
         for form in ("mixed_fp32", "mixed_bf16x3"):
             if form != args.precision:
                 r, rr = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, form, args.fp64_poles,
-                                 not args.no_autotune)
+                                 not args.no_autotune, -1, args.tune_cache)
                 others[form] = {
                     "poles_per_s": r["poles_per_s"], "ms_per_step": r["ms_per_step"],
                     "kernel_ms": {k: round(v["ms"], 3) for k, v in r["prof"].items()},
@@ -211,7 +213,7 @@ def main():
         head, rho = r64, rho64
     else:
         head, rho = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, args.precision,
-                             args.fp64_poles, not args.no_autotune, args.gemm_variant)
+                             args.fp64_poles, not args.no_autotune, args.gemm_variant, args.tune_cache)
     st, prof = head["stats"][0], head["prof"]
     # dominant kernel: the FP64 front GEMMs in the FP64 form, the FP32-product
     # front GEMMs in the mixed form (peak of their own arithmetic)

@@ -337,6 +337,9 @@ struct ndrho_ctx {
           break;
         case OP_GEMM: {
           d.gemm = S.gemm + op.begin;
+          d.ext = S.ext;  // G_EXTC0: the children of each problem's front
+          d.ext_child = S.ext_child;
+          d.ext_inv = S.ext_inv;
           d.gemm_tiles = S.gemm_tiles + op.tile_begin;
           // variant of a front-update GEMM: V_FP64 keeps every pole in FP64,
           // V_F32_64 / V_F32_128 give the low poles FP32 products on 64x64
@@ -375,7 +378,7 @@ struct ndrho_ctx {
           }
           l.npoles = nb - nhi;
           l.a += nhi * l.sa, l.b += nhi * l.sb, l.c += nhi * l.sc;
-          if (op.flags & G_BETA) l.c0 += nhi * l.sc0;
+          if (op.flags & (G_BETA | G_EXTC0)) l.c0 += nhi * l.sc0;
           timed(l.bf3 ? NDRHO_K_GEMM_BF16X3 : NDRHO_K_GEMM_F32, op.flops * (nb - nhi),
                 [&] { e = launch_gemm(l, stream); });
           break;

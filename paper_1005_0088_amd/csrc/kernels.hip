@@ -41,47 +41,56 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t total) {
   return x * q + (x < r ? x : r) + local;
 }
 
+// C0 of a front's update block formed from its children (G_EXTC0): the sum,
+// in child order, of the children's lower-stored update entries that map
+// onto the front's U x U entry (m, n), m >= n (the same sum the extend-add
+// forms for the panel).
+__device__ __forceinline__ double2 ext_c0(const ExtAddDesc& e, const ExtAddChild* __restrict__ kids,
+                                          const int32_t* __restrict__ inv, const double2* __restrict__ cu, int m,
+                                          int n) {
+  double2 sum = make_double2(0.0, 0.0);
+  for (int c = 0; c < e.child_count; ++c) {
+    const ExtAddChild k = kids[e.child_begin + c];
+    const int32_t* im = inv + k.inv_off;
+    const int32_t a = im[e.nj + m], b = im[e.nj + n];
+    if (a >= 0 && b >= 0) {
+      const double2 v = cu[k.upd_off + max(a, b) + int64_t(min(a, b)) * k.nu];
+      sum.x += v.x;
+      sum.y += v.y;
+    }
+  }
+  return sum;
+}
+
 // ----------------------------------------------------------------- extend-add
 //
 // Pull form of the child-to-parent accumulation of Schur complements
 // (Eq. (32); the (B[C])^T bookkeeping of Eq. (28)): every element of the
-// parent's panel (columns in J) and of the lower triangle of its own U x U
-// block is written once as the sum, in child order, of the children's update
-// entries that map onto it (update blocks are symmetric and stored as lower
-// triangles; the relative maps are increasing, so lower maps to lower).
-// Writing (not adding) also clears the panel before assembly, so no separate
-// fill is needed and no two threads touch one target.
+// parent's panel (columns in J) is written once as the sum, in child order,
+// of the children's update entries that map onto it (update blocks are
+// symmetric and stored as lower triangles; the relative maps are increasing,
+// so lower maps to lower).  Writing (not adding) also clears the panel
+// before assembly, so no separate fill is needed and no two threads touch
+// one target.  The parent's own U x U block takes the same sum in the
+// epilogue of its Schur-update GEMM (G_EXTC0).
 __global__ __launch_bounds__(256) void k_extadd(const ExtAddDesc* __restrict__ descs,
                                                 const ExtAddChild* __restrict__ kids,
                                                 const int32_t* __restrict__ inv, const ElemTile* __restrict__ tiles,
                                                 int64_t ntiles, double2* __restrict__ panel, int64_t ps,
-                                                const double2* __restrict__ cupd, int64_t cs,
-                                                double2* __restrict__ upd, int64_t us) {
+                                                const double2* __restrict__ cupd, int64_t cs) {
   const int64_t pole = blockIdx.y;
   const ElemTile t = tiles[blockIdx.x];
   const ExtAddDesc d = descs[t.desc];
   // per-front element counts stay far below 2^31: 32-bit index arithmetic
   const uint32_t ld = d.nj + d.nu;
   const uint32_t tp = ld * d.nj;
-  const uint32_t total = tp + uint32_t(d.nu) * d.nu;
   double2* pan = panel + pole * ps + d.panel_off;
-  double2* own = upd + pole * us + d.upd_off;
   const double2* cu = cupd + pole * cs;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint32_t e = uint32_t(t.e0) + threadIdx.x + 256 * i;
-    if (e >= total) break;
-    uint32_t r, s;
-    if (e < tp) {
-      s = e / ld;
-      r = e - s * ld;
-    } else {
-      const uint32_t e2 = e - tp;
-      const uint32_t q = e2 / d.nu;
-      r = d.nj + (e2 - q * d.nu);
-      s = d.nj + q;
-    }
-    if (e >= tp && r < s) continue;  // own U x U block: lower triangle only
+    if (e >= tp) break;
+    const uint32_t s = e / ld, r = e - s * ld;
     double2 sum = make_double2(0.0, 0.0);
     for (int c = 0; c < d.child_count; ++c) {
       const ExtAddChild k = kids[d.child_begin + c];
@@ -93,8 +102,7 @@ __global__ __launch_bounds__(256) void k_extadd(const ExtAddDesc* __restrict__ d
         sum.y += v.y;
       }
     }
-    if (e < tp) pan[r + int64_t(s) * ld] = sum;
-    else own[(r - d.nj) + int64_t(s - d.nj) * d.nu] = sum;
+    pan[r + int64_t(s) * ld] = sum;
   }
 }
 
@@ -248,9 +256,10 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
                                                   const TileRef* __restrict__ tiles, int64_t ntiles, int64_t npoles,
                                                   const double2* __restrict__ A, int64_t sA,
                                                   const double2* __restrict__ B, int64_t sB, const double2* C0,
-                                                  int64_t sC0, double2* C, int64_t sC) {
+                                                  int64_t sC0, double2* C, int64_t sC,
+    const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
   constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   __shared__ double2 As[2][BK][BM + 1];
@@ -363,7 +372,8 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
     __syncthreads();
   }
 
-  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
+  const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -377,8 +387,8 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
         if (SYM && m < n) continue;
         double2 v = make_double2(p1[i][j][r] - p2[i][j][r], p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
         if (NEG) v = make_double2(-v.x, -v.y);
-        if (BETA) {
-          const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
+        if (BETA || EXTC0) {
+          const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
           v.x += c0.x;
           v.y += c0.y;
         }
@@ -399,9 +409,10 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__
                                                  const TileRef* __restrict__ tiles, int64_t ntiles, int64_t npoles,
                                                  const double2* __restrict__ A, int64_t sA,
                                                  const double2* __restrict__ B, int64_t sB, const double2* C0,
-                                                 int64_t sC0, double2* C, int64_t sC) {
+                                                 int64_t sC0, double2* C, int64_t sC,
+    const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
   constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   const int64_t total = ntiles * npoles;
@@ -466,7 +477,8 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__
     }
   }
 
-  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
+  const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -480,8 +492,8 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__
         if (SYM && m < n) continue;
         double2 v = make_double2(p1[i][j][q] - p2[i][j][q], p3[i][j][q] - p1[i][j][q] - p2[i][j][q]);
         if (NEG) v = make_double2(-v.x, -v.y);
-        if (BETA) {
-          const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
+        if (BETA || EXTC0) {
+          const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
           v.x += c0.x;
           v.y += c0.y;
         }
@@ -506,9 +518,10 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
                                                     const TileRef* __restrict__ tiles, int64_t ntiles,
                                                     int64_t npoles, const double2* __restrict__ A, int64_t sA,
                                                     const double2* __restrict__ B, int64_t sB, const double2* C0,
-                                                    int64_t sC0, double2* C, int64_t sC) {
+                                                    int64_t sC0, double2* C, int64_t sC,
+    const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
   constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   constexpr int TM = 32 * WT;          // workgroup tile edge
@@ -609,7 +622,8 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
     __syncthreads();
   }
 
-  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
+  const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < WT; ++i)
@@ -623,8 +637,8 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
         if (SYM && m < n) continue;
         double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
         if (NEG) v = make_double2(-v.x, -v.y);
-        if (BETA) {
-          const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
+        if (BETA || EXTC0) {
+          const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
           v.x += c0.x;
           v.y += c0.y;
         }
@@ -684,9 +698,10 @@ __global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restric
                                                    const TileRef* __restrict__ tiles, int64_t ntiles,
                                                    int64_t npoles, const double2* __restrict__ A, int64_t sA,
                                                    const double2* __restrict__ B, int64_t sB, const double2* C0,
-                                                   int64_t sC0, double2* C, int64_t sC) {
+                                                   int64_t sC0, double2* C, int64_t sC,
+    const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
   constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   constexpr int NT = NW * 64;              // threads
@@ -849,7 +864,8 @@ __global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restric
 #undef B3_STOREA
 #undef B3_STOREB
 
-  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
+  const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < IB; ++i)
@@ -863,8 +879,8 @@ __global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restric
         if (SYM && m < n) continue;
         double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
         if (NEG) v = make_double2(-v.x, -v.y);
-        if (BETA) {
-          const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
+        if (BETA || EXTC0) {
+          const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
           v.x += c0.x;
           v.y += c0.y;
         }
@@ -889,9 +905,10 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__
                                                     const TileRef* __restrict__ tiles, int64_t ntiles,
                                                     int64_t npoles, const double2* __restrict__ A, int64_t sA,
                                                     const double2* __restrict__ B, int64_t sB, const double2* C0,
-                                                    int64_t sC0, double2* C, int64_t sC) {
+                                                    int64_t sC0, double2* C, int64_t sC,
+    const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
   constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   // planes: [operand A/B][2 slice + part][row][k]
@@ -1036,7 +1053,8 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__
 #undef S3_PUT
 #undef S3_STORE
 
-  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : nullptr;
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
+  const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -1050,8 +1068,8 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__
         if (SYM && m < n) continue;
         double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
         if (NEG) v = make_double2(-v.x, -v.y);
-        if (BETA) {
-          const double2 c0 = C0p[m + int64_t(n) * pr.ldc0];
+        if (BETA || EXTC0) {
+          const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
           v.x += c0.x;
           v.y += c0.y;
         }
@@ -1184,7 +1202,7 @@ static inline unsigned blocks_for(int64_t n, int per) { return static_cast<unsig
 hipError_t launch_extadd(const DevOp& o, hipStream_t st) {
   if (o.tile_count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_extadd, dim3(static_cast<unsigned>(o.tile_count), o.npoles), dim3(256), 0, st, o.ext, o.ext_child,
-                     o.ext_inv, o.elem_tiles, o.tile_count, o.c, o.sc, o.a, o.sa, o.b, o.sb);
+                     o.ext_inv, o.elem_tiles, o.tile_count, o.c, o.sc, o.a, o.sa);
   return hipGetLastError();
 }
 
@@ -1218,10 +1236,10 @@ static void gemm_inst(const DevOp& o, hipStream_t st) {
   if (o.small)  // one wave per 32x32 tile, four per workgroup
     hipLaunchKernelGGL(k_zgemm_w<F>, dim3(static_cast<unsigned>((total + 3) / 4)), dim3(256), 0, st, o.gemm,
                        o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
-                       o.c, o.sc);
+                       o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
   else
     hipLaunchKernelGGL(k_zgemm<F>, dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
-                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
+                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
 }
 
 template <int F>
@@ -1229,10 +1247,10 @@ static void gemm32_inst(const DevOp& o, hipStream_t st) {
   const int64_t total = o.tile_count * o.npoles;
   if (o.tile128)
     hipLaunchKernelGGL((k_cgemm32<F, 4>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
-                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
+                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
   else
     hipLaunchKernelGGL((k_cgemm32<F, 2>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
-                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
+                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
 }
 
 template <int F>
@@ -1241,14 +1259,14 @@ static void gemm_bf3_inst(const DevOp& o, hipStream_t st) {
   if (o.bf3 == 1)
     hipLaunchKernelGGL((k_cgemm_bf3<F, 128, 8>), dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm,
                        o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
-                       o.c, o.sc);
+                       o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
   else if (o.bf3 == 2)
     hipLaunchKernelGGL((k_cgemm_bf3<F, 64, 4>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm,
                        o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
-                       o.c, o.sc);
+                       o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
   else
     hipLaunchKernelGGL(k_cgemm_bf3s<F>, dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm, o.gemm_tiles,
-                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc);
+                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
 }
 
 hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
@@ -1257,7 +1275,7 @@ hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
     switch (o.flags) {  // front updates only
       case 0: gemm_bf3_inst<0>(o, st); break;
       case G_NEG | G_SYMA: gemm_bf3_inst<G_NEG | G_SYMA>(o, st); break;
-      case G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR: gemm_bf3_inst<G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR>(o, st); break;
+      case G_TB | G_SYM | G_EXTC0 | G_NEG | G_NOMIRROR: gemm_bf3_inst<G_TB | G_SYM | G_EXTC0 | G_NEG | G_NOMIRROR>(o, st); break;
       case G_TA | G_SYM | G_BETA | G_NEG: gemm_bf3_inst<G_TA | G_SYM | G_BETA | G_NEG>(o, st); break;
       default: return hipErrorInvalidValue;
     }
@@ -1267,7 +1285,7 @@ hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
     switch (o.flags) {  // front updates only (pivot GEMMs are always FP64)
       case 0: gemm32_inst<0>(o, st); break;
       case G_NEG | G_SYMA: gemm32_inst<G_NEG | G_SYMA>(o, st); break;
-      case G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR: gemm32_inst<G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR>(o, st); break;
+      case G_TB | G_SYM | G_EXTC0 | G_NEG | G_NOMIRROR: gemm32_inst<G_TB | G_SYM | G_EXTC0 | G_NEG | G_NOMIRROR>(o, st); break;
       case G_TA | G_SYM | G_BETA | G_NEG: gemm32_inst<G_TA | G_SYM | G_BETA | G_NEG>(o, st); break;
       default: return hipErrorInvalidValue;
     }
@@ -1277,7 +1295,7 @@ hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
     case 0: gemm_inst<0>(o, st); break;
     case G_NEG: gemm_inst<G_NEG>(o, st); break;
     case G_NEG | G_SYMA: gemm_inst<G_NEG | G_SYMA>(o, st); break;
-    case G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR: gemm_inst<G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR>(o, st); break;
+    case G_TB | G_SYM | G_EXTC0 | G_NEG | G_NOMIRROR: gemm_inst<G_TB | G_SYM | G_EXTC0 | G_NEG | G_NOMIRROR>(o, st); break;
     case G_TB | G_SYM | G_BETA | G_NEG: gemm_inst<G_TB | G_SYM | G_BETA | G_NEG>(o, st); break;
     case G_TA | G_SYM | G_BETA | G_NEG: gemm_inst<G_TA | G_SYM | G_BETA | G_NEG>(o, st); break;
     default: return hipErrorInvalidValue;

@@ -657,7 +657,9 @@ void finalize_plan(Plan& P) {
     const std::vector<int>& fr = by_depth[d];
     const int ubuf = (d % 2 == 0) ? BUF_UPD0 : BUF_UPD1;
     const int cbuf = (d % 2 == 0) ? BUF_UPD1 : BUF_UPD0;
-    // extend-add (writes every panel element and the U x U block)
+    // extend-add into the panels (writes every panel element); the U x U
+    // blocks take theirs in the epilogue of the Schur-update GEMM below
+    std::vector<int32_t> ext_index(P.fronts.size(), -1);
     {
       Op op;
       op.kind = OP_EXTADD;
@@ -678,8 +680,9 @@ void finalize_plan(Plan& P) {
           P.ext_child.push_back(ch);
         }
         const int32_t di = static_cast<int32_t>(P.ext.size() - op.begin);
+        ext_index[f] = static_cast<int32_t>(P.ext.size());
         P.ext.push_back(ds);
-        const int64_t total = int64_t(F.nj + F.nu) * F.nj + int64_t(F.nu) * F.nu;
+        const int64_t total = int64_t(F.nj + F.nu) * F.nj;
         for (int64_t e0 = 0; e0 < total; e0 += kTile) P.ext_tiles.push_back(ElemTile{di, 0, e0});
       }
       op.count = static_cast<int64_t>(P.ext.size()) - op.begin;
@@ -722,11 +725,12 @@ void finalize_plan(Plan& P) {
         if (F.nu == 0) continue;
         const int ld = F.nj + F.nu;
         g1.push_back(GemmProb{F.nu, F.nj, F.nj, ld, ld, 0, F.nu, 0, F.panel_off + F.nj, F.panel_off, 0, F.l_off});
-        g2.push_back(GemmProb{F.nu, F.nu, F.nj, F.nu, ld, F.nu, F.nu, 0, F.l_off, F.panel_off + F.nj, F.upd_off,
+        g2.push_back(GemmProb{F.nu, F.nu, F.nj, F.nu, ld, 0, F.nu, ext_index[f], F.l_off, F.panel_off + F.nj, 0,
                               F.upd_off});
       }
       B.gemm(P.upward, 0, BUF_PANEL, BUF_PANEL, 0, BUF_L, g1, d);
-      B.gemm(P.upward, G_TB | G_SYM | G_BETA | G_NEG | G_NOMIRROR, BUF_L, BUF_PANEL, ubuf, ubuf, g2, d);
+      // C0 of the update is the children's extend-add, read from the deeper buffer
+      B.gemm(P.upward, G_TB | G_SYM | G_EXTC0 | G_NEG | G_NOMIRROR, BUF_L, BUF_PANEL, cbuf, ubuf, g2, d);
     }
   }
   for (int d = 1; d < P.n_levels; ++d) {

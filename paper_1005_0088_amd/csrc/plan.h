@@ -32,7 +32,8 @@ struct Front {
 
 // Work descriptors shared with the device code (plain structs, 8-byte aligned).
 struct GemmProb {
-  int32_t m, n, k, lda, ldb, ldc0, ldc, pad;
+  int32_t m, n, k, lda, ldb, ldc0, ldc;
+  int32_t ext;  // G_EXTC0: index of the front's extend-add descriptor (its children)
   int64_t a_off, b_off, c0_off, c_off;
 };
 struct TileRef {  // one 64x64 (or 128x128, or 32x32) output tile of problem `prob`
@@ -80,8 +81,11 @@ enum OpKind { OP_EXTADD, OP_ASSEMBLE, OP_SMALLINV, OP_GEMM, OP_COPY, OP_GATHER }
 
 // G_SYMA: A is symmetric and only its lower triangle is stored (entry (m, k)
 // is read from (max, min)); G_NOMIRROR: with G_SYM, write the lower triangle
-// of C only.
-enum GemmFlags { G_TA = 1, G_TB = 2, G_SYM = 4, G_BETA = 8, G_NEG = 16, G_NOMIRROR = 32, G_SYMA = 64 };
+// of C only; G_EXTC0: C0 is not read but formed in the epilogue as the sum of
+// the children's update entries that map onto (m, n) (the extend-add of the
+// front's own U x U block, children in order).
+enum GemmFlags { G_TA = 1, G_TB = 2, G_SYM = 4, G_BETA = 8, G_NEG = 16, G_NOMIRROR = 32, G_SYMA = 64,
+                 G_EXTC0 = 128 };
 // Op-level marker (not a kernel flag): the GEMM belongs to a pivot-block
 // inverse and always runs in FP64.
 constexpr int OP_PIVOT = 1 << 8;
