@@ -93,7 +93,8 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
     """Time one precision form on one system (density_matrix) or several
     (density_matrix_batch: one schedule); returns (timing dict, rho list)."""
     variant = gemm_variant if precision != "fp64" else -1
-    ctx = nd.Context(0, precision=precision, fp64_poles=fp64_poles, fp64_far_poles=fp64_poles, gemm_variant=variant)
+    ctx = nd.Context(0, precision=precision, fp64_poles=fp64_poles, fp64_far_poles=fp64_poles, gemm_variant=variant,
+                     verbose=1)
     t0 = time.time()
     sids = []
     for sysd in systems:

@@ -69,7 +69,7 @@ typedef struct {
   int32_t precision;    /* NDRHO_FP64 (default), NDRHO_MIXED_FP32 or NDRHO_MIXED_BF16X3 */
   int32_t pole_batch;   /* poles per device pass; 0 = largest that fits the memory budget */
   double mem_fraction;  /* fraction of free device memory the workspace may use (default 0.8) */
-  int32_t verbose;      /* 0 = quiet */
+  int32_t verbose;      /* 0 = quiet; 1: ndrho_autotune reports each timed variant on stderr */
   int32_t fp64_poles;   /* mixed mode: the fp64_poles shifts nearest the real axis stay FP64 (default 8) */
   double fp64_pole_im;  /* mixed mode: shifts with Im alpha < fp64_pole_im also stay FP64 (default 0.05) */
   int32_t fp64_far_poles; /* mixed mode: the fp64_far_poles shifts farthest from the axis stay FP64 too

@@ -223,7 +223,7 @@ class Context:
 
     def __init__(self, device=0, stream=None, leaf_rows=32, pole_batch=0, mem_fraction=0.8, precision="fp64",
                  fp64_poles=None, fp64_pole_im=None, use_graph=True, gemm_variant=-1, fp64_far_poles=None,
-                 fp64_small_tiles=-1):
+                 fp64_small_tiles=-1, verbose=0):
         self._lib = load_library()
         opt = Options()
         self._lib.ndrho_default_options(C.byref(opt))
@@ -240,6 +240,7 @@ class Context:
         opt.use_graph = int(bool(use_graph))
         opt.gemm_variant = int(gemm_variant)
         opt.fp64_small_tiles = int(fp64_small_tiles)
+        opt.verbose = int(verbose)
         handle = None
         if stream is not None:
             handle = getattr(stream, "cuda_stream", stream)

@@ -910,6 +910,11 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
         int st[2];
         ctx->read_status(st);
         ctx->op_ms = nullptr;
+        if (ctx->opt.verbose) {
+          double tot = 0;
+          for (double x : ms[v]) tot += x;
+          std::fprintf(stderr, "ndrho_autotune: variant %d timed, %.1f ms of launches\n", v, tot);
+        }
       }
     } catch (...) {
       ctx->op_ms = nullptr;
