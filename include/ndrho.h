@@ -52,8 +52,9 @@ enum {
 /* Arithmetic of the front updates.  Storage, pivot-block inverses, the
  * assembly and the pole sum are FP64 (complex128) in every mode.
  *   NDRHO_FP64:       every GEMM on the FP64 matrix cores.
- *   NDRHO_MIXED_FP32: for poles away from the real axis (see fp64_poles,
- *                     fp64_pole_im) the four front-update GEMMs (L = B A^{-1},
+ *   NDRHO_MIXED_FP32: for poles away from the real axis (all but those kept
+ *                     by fp64_poles, fp64_far_poles and fp64_pole_im) the
+ *                     four front-update GEMMs (L = B A^{-1},
  *                     Schur update, G_UJ, G_JJ) take FP32 products with FP32
  *                     accumulation, results summed into FP64 storage.
  *   NDRHO_MIXED_BF16X3: the same GEMMs as compensated split-BF16 products:
@@ -151,13 +152,16 @@ int ndrho_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_
 
 /* Autotuner of the front-update GEMM launches of one structure (k = 1) or of
  * a batch of k structures (as run by ndrho_density_matrix_batch): for every
- * launch it times, on one full evaluation of the current shifts each, FP64
- * for all poles, FP32 products on 64x64 tiles and FP32 products on 128x128
- * tiles (the FP32 variants apply only to the poles the precision mode puts
- * in low precision), and keeps the fastest.  With cache_path non-NULL the
- * choice is looked up in, or appended to, that text file under a key of the
- * plan's shape, pole count and batch size.  FP64 mode: nothing to tune.
- * Errors: EINVAL, ESTATE (no shifts set), EDEVICE. */
+ * launch it times, on one full evaluation of the current shifts per variant,
+ * each gemm_variant the precision mode accepts (FP64 for all poles; FP32
+ * products on 64x64 or 128x128 tiles; in split-BF16 mode also split-BF16
+ * products on 128x128 tiles, on 64x64 tiles, and on 128x128 tiles with one
+ * split per element and stage; the low-precision variants apply only to the
+ * poles the mode puts in low precision) and keeps the fastest.  With
+ * cache_path non-NULL the choice is looked up in, or appended to, that text
+ * file under a key of the plan's shape, pole count, batch size and precision.
+ * FP64 mode: nothing to tune.  With opt.verbose each timed variant is
+ * reported on stderr.  Errors: EINVAL, ESTATE (no shifts set), EDEVICE. */
 int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const char* cache_path);
 
 typedef struct {

@@ -876,7 +876,7 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
     const int nb = ctx->batch_for(P, T.n_shifts);
     char keybuf[256];
     std::snprintf(keybuf, sizeof(keybuf),
-                  "ndrho-tune-v2 n=%lld nnz=%lld fronts=%zu shifts=%d fp64=%d batch=%d prec=%d ops=%d",
+                  "ndrho-tune-v3 n=%lld nnz=%lld fronts=%zu shifts=%d fp64=%d batch=%d prec=%d ops=%d",
                   static_cast<long long>(P.n), static_cast<long long>(P.nnz), P.fronts.size(), T.n_shifts, T.n_hi,
                   nb, ctx->opt.precision, nops);
     const std::string key(keybuf);

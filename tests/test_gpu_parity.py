@@ -451,7 +451,7 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
     assert np.array_equal(got, again)
     with open(cache) as f:
         lines = f.read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("ndrho-tune-v2 ")
+    assert len(lines) == 1 and lines[0].startswith("ndrho-tune-v3 ")
     choice = lines[0].split()[-1]
     assert set(choice) <= set("012")
     with nd.Context(0, precision="mixed_fp32") as c:   # cached choice is reused, not re-tuned
