@@ -341,9 +341,10 @@ struct ndrho_ctx {
           d.ext_child = S.ext_child;
           d.ext_inv = S.ext_inv;
           d.gemm_tiles = S.gemm_tiles + op.tile_begin;
-          // variant of a front-update GEMM: V_FP64 keeps every pole in FP64,
-          // V_F32_64 / V_F32_128 give the low poles FP32 products on 64x64
-          // or 128x128 tiles (chosen by heuristic or by the autotuner)
+          // variant of a front-update GEMM (chosen by heuristic or by the
+          // autotuner, or forced by gemm_variant): V_FP64 keeps every pole in
+          // FP64; the others give the low poles FP32 products (V_F32_64,
+          // V_F32_128) or split-BF16 products (V_BF3_128, V_BF3_64, V_BF3S_128)
           const int var = opt.gemm_variant >= 0 ? opt.gemm_variant : S.variant[cur_op];
           const bool split = !(op.flags & OP_PIVOT) && nhi < nb && var != V_FP64;
           const int k64 = (op.flags & OP_PIVOT) ? NDRHO_K_GEMM_PIVOT : NDRHO_K_GEMM;

@@ -295,7 +295,7 @@ struct Builder {
     }
     op.tile_count = static_cast<int64_t>(P.gemm_tiles.size()) - op.tile_begin;
     op.tile128_begin = static_cast<int64_t>(P.gemm_tiles.size());
-    if (!(flags & OP_PIVOT)) {  // front updates may run as FP32-product GEMMs on 128x128 tiles
+    if (!(flags & OP_PIVOT)) {  // front updates may run as low-precision GEMMs on 128x128 tiles
       for (size_t i = 0; i < probs.size(); ++i) {
         const GemmProb& g = probs[i];
         const int tm = (g.m + 127) / 128, tn = (g.n + 127) / 128;

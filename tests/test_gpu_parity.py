@@ -201,6 +201,26 @@ def test_fp64_small_tile_kernel_matches(dims, nb):
     assert np.max(np.abs(got[1] - got[0])) < 1e-12
 
 
+def test_profile_by_depth_adds_up(ctx):
+    # the per-depth split of the profile sums to the per-kind totals, and the
+    # launches of the tree land at depths below the tree's level count
+    sysd = lattice((8, 8, 6), "nn", 63)
+    sid = _register(ctx, sysd)
+    ctx.set_poles(sid, 0.0, BETA, 20)
+    ctx.density_matrix(sid)
+    ctx.profile(True)
+    ctx.density_matrix(sid)
+    kinds = ctx.profile_read()
+    depth = ctx.profile_read_depth()
+    ctx.profile(False)
+    levels = ctx.stats(sid)["n_levels"]
+    for k, v in kinds.items():
+        assert abs(depth[k].sum() - v["ms"]) <= 1e-6 * max(1.0, v["ms"])
+        assert not depth[k][levels:-1].any()
+    assert kinds["gemm"]["ms"] > 0 and depth["gemm"][:levels].sum() > 0
+    assert depth["accum"][-1] > 0              # the pole sum sits outside the tree
+
+
 def test_batched_equals_unbatched_bitwise():
     import paper_1005_0088_amd as nd
     sysd = lattice((6, 5, 5), "nn2", 9)
