@@ -62,6 +62,25 @@ __device__ __forceinline__ double2 ext_c0(const ExtAddDesc& e, const ExtAddChild
   return sum;
 }
 
+// One element of a GEMM result, C = [C0 +] (+/-) product: negate, add C0
+// (read from memory with G_BETA, formed from the children with G_EXTC0),
+// store, and with a mirrored symmetric output store the transpose too.
+template <int FLAGS>
+__device__ __forceinline__ void store_elem(double2 v, int m, int n, const GemmProb& pr, const double2* C0p,
+                                           double2* Cp, const ExtAddDesc& xd, const ExtAddChild* __restrict__ xk,
+                                           const int32_t* __restrict__ xi) {
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
+  constexpr bool MIRROR = (FLAGS & G_SYM) && !(FLAGS & G_NOMIRROR);
+  if (NEG) v = make_double2(-v.x, -v.y);
+  if (BETA || EXTC0) {
+    const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
+    v.x += c0.x;
+    v.y += c0.y;
+  }
+  Cp[m + int64_t(n) * pr.ldc] = v;
+  if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+}
+
 // ----------------------------------------------------------------- extend-add
 //
 // Pull form of the child-to-parent accumulation of Schur complements
@@ -259,8 +278,8 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
                                                   int64_t sC0, double2* C, int64_t sC,
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   __shared__ double2 As[2][BK][BM + 1];
   __shared__ double2 Bs[2][BK][BN + 1];
@@ -386,14 +405,7 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
         if (m >= M || n >= N) continue;
         if (SYM && m < n) continue;
         double2 v = make_double2(p1[i][j][r] - p2[i][j][r], p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
-        if (NEG) v = make_double2(-v.x, -v.y);
-        if (BETA || EXTC0) {
-          const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
-          v.x += c0.x;
-          v.y += c0.y;
-        }
-        Cp[m + int64_t(n) * pr.ldc] = v;
-        if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+        store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
       }
 }
 
@@ -412,8 +424,8 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__
                                                  int64_t sC0, double2* C, int64_t sC,
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   const int64_t total = ntiles * npoles;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
@@ -491,14 +503,7 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__
         if (m >= M || n >= N) continue;
         if (SYM && m < n) continue;
         double2 v = make_double2(p1[i][j][q] - p2[i][j][q], p3[i][j][q] - p1[i][j][q] - p2[i][j][q]);
-        if (NEG) v = make_double2(-v.x, -v.y);
-        if (BETA || EXTC0) {
-          const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
-          v.x += c0.x;
-          v.y += c0.y;
-        }
-        Cp[m + int64_t(n) * pr.ldc] = v;
-        if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+        store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
       }
 }
 
@@ -521,8 +526,8 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
                                                     int64_t sC0, double2* C, int64_t sC,
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   constexpr int TM = 32 * WT;          // workgroup tile edge
   constexpr int NL = TM * BK / 256;    // operand elements per thread per stage
@@ -636,14 +641,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
         if (m >= M || n >= N) continue;
         if (SYM && m < n) continue;
         double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
-        if (NEG) v = make_double2(-v.x, -v.y);
-        if (BETA || EXTC0) {
-          const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
-          v.x += c0.x;
-          v.y += c0.y;
-        }
-        Cp[m + int64_t(n) * pr.ldc] = v;
-        if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+        store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
       }
 }
 
@@ -701,8 +699,8 @@ __global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restric
                                                    int64_t sC0, double2* C, int64_t sC,
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   constexpr int NT = NW * 64;              // threads
   constexpr int IB = B3_TM / 32;           // 16-row blocks of a wave's A rows (wave tile TM/2 x WCOL)
@@ -878,14 +876,7 @@ __global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restric
         if (m >= M || n >= N) continue;
         if (SYM && m < n) continue;
         double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
-        if (NEG) v = make_double2(-v.x, -v.y);
-        if (BETA || EXTC0) {
-          const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
-          v.x += c0.x;
-          v.y += c0.y;
-        }
-        Cp[m + int64_t(n) * pr.ldc] = v;
-        if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+        store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
       }
 }
 
@@ -908,8 +899,8 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__
                                                     int64_t sC0, double2* C, int64_t sC,
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool MIRROR = SYM && !(FLAGS & G_NOMIRROR), SYMA = (FLAGS & G_SYMA) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   // planes: [operand A/B][2 slice + part][row][k]
   __shared__ __attribute__((aligned(16))) unsigned short lds[12 * B3S_PLANE];
@@ -1067,14 +1058,7 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__
         if (m >= M || n >= N) continue;
         if (SYM && m < n) continue;
         double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
-        if (NEG) v = make_double2(-v.x, -v.y);
-        if (BETA || EXTC0) {
-          const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
-          v.x += c0.x;
-          v.y += c0.y;
-        }
-        Cp[m + int64_t(n) * pr.ldc] = v;
-        if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
+        store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
       }
 }
 
