@@ -80,7 +80,10 @@ typedef struct {
                            (heuristic, refined by ndrho_autotune); 0 FP64; 1 FP32 products on 64x64 tiles;
                            2 FP32 products on 128x128 tiles; 3 split-BF16 products on 128x128 tiles;
                            4 split-BF16 products on 64x64 tiles; 5 split-BF16 products on 128x128 tiles,
-                           each element split once per stage.  FP32 mode accepts 0-2, split-BF16 mode 0-5 */
+                           each element split once per stage; 6 split-BF16 products on 128x128 tiles, K by
+                           16 through double-buffered bf16 planes on the 32x32x16 matrix-core shape (a
+                           launch whose operands span 2^31 bytes or more runs variant 3 instead).  FP32
+                           mode accepts 0-2, split-BF16 mode 0-6 */
   int32_t fp64_small_tiles; /* FP64 GEMM launches: -1 (default) one wave per 32x32 output tile where the
                                launch's problems would fill less than half of the 64x64 tiles; 0 never;
                                1 always */
@@ -155,8 +158,9 @@ int ndrho_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_
  * launch it times, on one full evaluation of the current shifts per variant,
  * each gemm_variant the precision mode accepts (FP64 for all poles; FP32
  * products on 64x64 or 128x128 tiles; in split-BF16 mode also split-BF16
- * products on 128x128 tiles, on 64x64 tiles, and on 128x128 tiles with one
- * split per element and stage; the low-precision variants apply only to the
+ * products on 128x128 tiles, on 64x64 tiles, on 128x128 tiles with one
+ * split per element and stage, and on 128x128 tiles with K staged by 16 in
+ * double-buffered bf16 planes; the low-precision variants apply only to the
  * poles the mode puts in low precision) and keeps the fastest.  With
  * cache_path non-NULL the choice is looked up in, or appended to, that text
  * file under a key of the plan's shape, pole count, batch size and precision.

@@ -1062,6 +1062,192 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__
       }
 }
 
+// Variant of the split-BF16 contraction that splits every operand element
+// once, as it is staged, and never per wave: K advances 16 at a time, each
+// stage holding the twelve bf16 planes of the A and B blocks (3 slices x
+// re/im x 128 rows x 16 k, rows padded to 24 bf16), double-buffered in LDS,
+// so that the next stage is fetched, rounded to FP32, split and stored while
+// the matrix cores work on the current one, with one barrier per stage.  The
+// products run on v_mfma_f32_32x32x16_bf16 (the 16-k bf16 shape at full rate
+// on this matrix core): eight waves, each a 64 x 32 piece of the 128 x 128
+// tile as two 32 x 32 blocks.
+typedef float f16v __attribute__((ext_vector_type(16)));
+constexpr int B3P_TM = 128;                  // tile edge
+constexpr int B3P_BK = 16;                   // K per stage
+constexpr int B3P_LD = B3P_BK + 8;           // bf16 per plane row
+constexpr int B3P_PLANE = B3P_TM * B3P_LD;   // bf16 per plane
+constexpr int B3P_STAGE = 12 * B3P_PLANE;    // A planes 0..5, B planes 6..11
+constexpr uint32_t B3P_OOB = 0x7FFFFFF0u;    // descriptor range in bytes; offsets at or beyond it read zero
+
+template <int FLAGS>
+__global__ __launch_bounds__(512) void k_cgemm_bf3p(const GemmProb* __restrict__ probs,
+                                                    const TileRef* __restrict__ tiles, int64_t ntiles,
+                                                    int64_t npoles, const double2* __restrict__ A, int64_t sA,
+                                                    const double2* __restrict__ B, int64_t sB, const double2* C0,
+                                                    int64_t sC0, double2* C, int64_t sC,
+    const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
+  constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
+  static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
+  // [stage][plane = 6 operand + 2 slice + part][row][k]
+  __shared__ __attribute__((aligned(16))) unsigned short lds[2 * B3P_STAGE];
+
+  const int64_t total = ntiles * npoles;
+  const int64_t logical = xcd_remap(blockIdx.x, total);
+  const int64_t pole = logical / ntiles;
+  const TileRef tr = tiles[logical % ntiles];
+  const GemmProb pr = probs[tr.prob];
+  const double2* Ap = A + pole * sA + pr.a_off;
+  const double2* Bp = B + pole * sB + pr.b_off;
+  const int M = pr.m, N = pr.n, K = pr.k;
+  const int m0 = tr.tm * B3P_TM, n0 = tr.tn * B3P_TM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;   // wave piece: rows 64 wm.., columns 32 wn..
+
+  f16v cre[2], cim[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      cre[i][r] = 0.f;
+      cim[i][r] = 0.f;
+    }
+
+  // Staging: every thread moves four consecutive k of one row per operand
+  // and stage.  Row-contiguous storage (A untransposed, B transposed) puts
+  // consecutive threads on consecutive rows; k-contiguous storage puts four
+  // threads on the 16 k of a row.
+  const int arow = TA ? tid / 4 : tid % B3P_TM, ak = TA ? 4 * (tid % 4) : 4 * (tid / B3P_TM);
+  const int brow = TB ? tid % B3P_TM : tid / 4, bk = TB ? 4 * (tid / B3P_TM) : 4 * (tid % 4);
+  double2 ra0[4], rb0[4], ra1[4], rb1[4];   // two stages in flight
+  // Branch-free fetches through buffer descriptors: an element outside the
+  // problem gets an offset beyond the descriptor's range, which the hardware
+  // answers with zeros, so no load is guarded by a branch and the waits for
+  // one stage's loads do not cover the next stage's.  Byte offsets are
+  // 32-bit: every operand region of a problem spans less than B3P_OOB bytes
+  // (the launcher checks this before choosing the kernel).
+  const __amdgpu_buffer_rsrc_t arsrc =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double2*>(Ap), static_cast<short>(0), B3P_OOB, 0x00020000);
+  const __amdgpu_buffer_rsrc_t brsrc =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double2*>(Bp), static_cast<short>(0), B3P_OOB, 0x00020000);
+  const uint32_t ulda = static_cast<uint32_t>(pr.lda), uldb = static_cast<uint32_t>(pr.ldb);
+  const uint32_t gm = static_cast<uint32_t>(m0 + arow), gn = static_cast<uint32_t>(n0 + brow);
+  const uint32_t uM = static_cast<uint32_t>(M), uN = static_cast<uint32_t>(N), uK = static_cast<uint32_t>(K);
+#define P3_LOAD(k0, ra, rb)                                                                             \
+  {                                                                                                     \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                     \
+      const uint32_t gk = static_cast<uint32_t>((k0) + ak + q);                                         \
+      const uint32_t o = (TA || (SYMA && gm < gk)) ? gk + gm * ulda : gm + gk * ulda;                   \
+      ra[q] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(                        \
+                                              arsrc, (gm < uM && gk < uK) ? o * 16u : B3P_OOB, 0, 0));  \
+    }                                                                                                   \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                     \
+      const uint32_t gk = static_cast<uint32_t>((k0) + bk + q);                                         \
+      const uint32_t o = TB ? gn + gk * uldb : gk + gn * uldb;                                          \
+      rb[q] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(                        \
+                                              brsrc, (gn < uN && gk < uK) ? o * 16u : B3P_OOB, 0, 0));  \
+    }                                                                                                   \
+  }
+  // round four complex values to FP32, split them and store the six planes of one operand row
+#define P3_PUT(base, row, kk, v)                                                                        \
+  do {                                                                                                  \
+    unsigned h0, h1, m0_, m1, l0, l1;                                                                   \
+    unsigned short* d_ = lds + (base) + (row) * B3P_LD + (kk);                                          \
+    split2(f2{static_cast<float>((v)[0].x), static_cast<float>((v)[1].x)}, h0, m0_, l0);                \
+    split2(f2{static_cast<float>((v)[2].x), static_cast<float>((v)[3].x)}, h1, m1, l1);                 \
+    *reinterpret_cast<u2v*>(d_) = u2v{h0, h1};                                                          \
+    *reinterpret_cast<u2v*>(d_ + 2 * B3P_PLANE) = u2v{m0_, m1};                                         \
+    *reinterpret_cast<u2v*>(d_ + 4 * B3P_PLANE) = u2v{l0, l1};                                          \
+    split2(f2{static_cast<float>((v)[0].y), static_cast<float>((v)[1].y)}, h0, m0_, l0);                \
+    split2(f2{static_cast<float>((v)[2].y), static_cast<float>((v)[3].y)}, h1, m1, l1);                 \
+    *reinterpret_cast<u2v*>(d_ + B3P_PLANE) = u2v{h0, h1};                                              \
+    *reinterpret_cast<u2v*>(d_ + 3 * B3P_PLANE) = u2v{m0_, m1};                                         \
+    *reinterpret_cast<u2v*>(d_ + 5 * B3P_PLANE) = u2v{l0, l1};                                          \
+  } while (0)
+#define P3_STORE(stage, ra, rb)                                                                         \
+  {                                                                                                     \
+    /* the fetched values enter the split here and not earlier, so that their */                       \
+    /* wait is placed here, a whole stage after the fetch */                                            \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                     \
+      asm volatile("" : "+v"(ra[q].x), "+v"(ra[q].y), "+v"(rb[q].x), "+v"(rb[q].y));                   \
+    }                                                                                                   \
+    P3_PUT((stage) * B3P_STAGE, arow, ak, ra);                                                          \
+    P3_PUT((stage) * B3P_STAGE + 6 * B3P_PLANE, brow, bk, rb);                                          \
+  }
+
+  // Stage kt + 2 is fetched while stage kt is multiplied and stage kt + 1
+  // (fetched one step earlier) is split into the other LDS buffer.  The loop
+  // is unrolled by two so that the two register sets keep fixed names, and
+  // its body has no branch: the stage count is rounded up to even and the
+  // fetches past K read zeros, so the compiler's wait for one stage's loads
+  // leaves the next stage's in flight.
+  const int nk = (K + B3P_BK - 1) / B3P_BK, nk2 = nk + (nk & 1);
+  P3_LOAD(0, ra0, rb0)
+  P3_STORE(0, ra0, rb0)
+  P3_LOAD(B3P_BK, ra1, rb1)
+  __syncthreads();
+  // MFMA operand of lane l: row l % 32 of its 32-row block, k = 8 (l / 32) .. + 7
+  const int orow = lane & 31, ok = 8 * (lane >> 5);
+#define P3_STEP(kt, rnow, bnow, rnext, bnext)                                                           \
+  {                                                                                                     \
+    P3_LOAD(((kt) + 2) * B3P_BK, rnow, bnow)                                                            \
+    asm volatile("" ::: "memory"); /* keeps the fetches here, ahead of their use */                     \
+    P3_MMA((kt) & 1)                                                                                    \
+    P3_STORE(((kt) & 1) ^ 1, rnext, bnext)                                                              \
+    __syncthreads();                                                                                    \
+  }
+#define P3_MMA(cur)                                                                                     \
+  {                                                                                                     \
+    const unsigned short* L = lds + (cur) * B3P_STAGE;                                                  \
+    bf8 b[6];                                                                                           \
+    _Pragma("unroll") for (int pl = 0; pl < 6; ++pl)                                                    \
+      b[pl] = *reinterpret_cast<const bf8*>(L + (6 + pl) * B3P_PLANE + (wn * 32 + orow) * B3P_LD + ok); \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                                     \
+      bf8 a[6], na[3];                                                                                  \
+      _Pragma("unroll") for (int pl = 0; pl < 6; ++pl)                                                  \
+        a[pl] = *reinterpret_cast<const bf8*>(L + pl * B3P_PLANE + (wm * 64 + i * 32 + orow) * B3P_LD + ok); \
+      _Pragma("unroll") for (int sl = 0; sl < 3; ++sl)                                                  \
+        na[sl] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, a[2 * sl + 1]) ^ 0x80008000u);         \
+      _Pragma("unroll") for (int sa = 0; sa < 3; ++sa)                                                  \
+        _Pragma("unroll") for (int sb = 0; sb + sa < 3; ++sb) {                                         \
+          cre[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2 * sb], a[2 * sa], cre[i], 0, 0, 0);      \
+          cim[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2 * sb], a[2 * sa + 1], cim[i], 0, 0, 0);  \
+          cre[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2 * sb + 1], na[sa], cre[i], 0, 0, 0);     \
+          cim[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2 * sb + 1], a[2 * sa], cim[i], 0, 0, 0);  \
+        }                                                                                               \
+    }                                                                                                   \
+  }
+  // -Im(A) slices by a sign flip of the bf16 bits; slice pairs (sa, sb) with
+  // sa + sb <= 2; re += Ar Br - Ai Bi, im += Ai Br + Ar Bi (B block first)
+  for (int kt = 0; kt < nk2; kt += 2) {
+    P3_STEP(kt, ra0, rb0, ra1, rb1)
+    P3_STEP(kt + 1, ra1, rb1, ra0, rb0)
+  }
+#undef P3_STEP
+#undef P3_MMA
+#undef P3_LOAD
+#undef P3_PUT
+#undef P3_STORE
+
+  // accumulator register r of lane l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]:
+  // row = column n of the tile (B block first), column = row m
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
+  const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
+  double2* Cp = C + pole * sC + pr.c_off;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = m0 + wm * 64 + i * 32 + (lane & 31);
+      const int n = n0 + wn * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (m >= M || n >= N) continue;
+      if (SYM && m < n) continue;
+      double2 v = make_double2(static_cast<double>(cre[i][r]), static_cast<double>(cim[i][r]));
+      store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
+    }
+}
+
 // ----------------------------------------------------------------- copy
 //
 // dst (rows x cols) <- src, or <- src^T through an LDS tile so that both the
@@ -1248,8 +1434,11 @@ static void gemm_bf3_inst(const DevOp& o, hipStream_t st) {
     hipLaunchKernelGGL((k_cgemm_bf3<F, 64, 4>), dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm,
                        o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
                        o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
-  else
+  else if (o.bf3 == 3)
     hipLaunchKernelGGL(k_cgemm_bf3s<F>, dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm, o.gemm_tiles,
+                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
+  else
+    hipLaunchKernelGGL(k_cgemm_bf3p<F>, dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm, o.gemm_tiles,
                        o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
 }
 

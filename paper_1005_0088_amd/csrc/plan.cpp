@@ -321,6 +321,11 @@ struct Builder {
     }
     op.tile32_count = static_cast<int64_t>(P.gemm_tiles.size()) - op.tile32_begin;
     op.small = double(op.tile_count) * 64 * 64 > 2.0 * area;
+    for (const GemmProb& g : probs) {  // largest byte offset of an operand element, either storage order
+      const double ea = 16.0 * double(std::max(g.m, g.k)) * (double(g.lda) + 1.0);
+      const double eb = 16.0 * double(std::max(g.n, g.k)) * (double(g.ldb) + 1.0);
+      if (std::max(ea, eb) >= 2147483632.0) op.off32 = false;
+    }
     op.flops = fl;
     P.flops_exec += fl;
     prog.push_back(op);

@@ -100,6 +100,8 @@ struct Op {
   int64_t tile32_begin = 0, tile32_count = 0;    // 32x32 tiles (FP64 GEMM of small problems)
   bool small = false;        // GEMM: FP64 launches on 32x32 tiles by default (more than half of
                              // the 64x64 tile area would lie outside the problems)
+  bool off32 = true;         // GEMM: every operand element of every problem lies within 2^31 - 16
+                             // bytes of the problem's operand origin (32-bit offsets suffice)
   int64_t inv16 = 0, inv32 = 0;  // SMALLINV: leading descriptors with n <= 16, then n <= 32
   int depth = 0;
   double flops = 0;          // useful flops per pole (GEMM)

@@ -295,7 +295,7 @@ def test_errors(ctx):
 # ------------------------------------------------------------- precision form
 
 @pytest.mark.parametrize("precision,variant", [("mixed_fp32", 1), ("mixed_fp32", 2), ("mixed_bf16x3", 3),
-                                               ("mixed_bf16x3", 4), ("mixed_bf16x3", 5)])
+                                               ("mixed_bf16x3", 4), ("mixed_bf16x3", 5), ("mixed_bf16x3", 6)])
 def test_mixed_single_shift_close_to_dense(precision, variant):
     # FP32 products with FP32 accumulation (64x64 or 128x128 tiles), or
     # split-BF16 products with FP32 accumulation: relative error of G well
@@ -320,7 +320,9 @@ def test_mixed_single_shift_close_to_dense(precision, variant):
                           ((20, 18), "nn2", 8, 1e-7, "mixed_fp32", 2), ((9, 9, 9), "nn", 8, 1e-7, "mixed_bf16x3", 3),
                           ((9, 9, 9), "nn", 0, 1e-6, "mixed_bf16x3", 3), ((20, 18), "nn2", 8, 1e-7, "mixed_bf16x3", 3),
                           ((9, 9, 9), "nn", 8, 1e-7, "mixed_bf16x3", 4), ((20, 18), "nn2", 8, 1e-7, "mixed_bf16x3", 4),
-                          ((9, 9, 9), "nn", 8, 1e-7, "mixed_bf16x3", 5), ((20, 18), "nn2", 8, 1e-7, "mixed_bf16x3", 5)])
+                          ((9, 9, 9), "nn", 8, 1e-7, "mixed_bf16x3", 5), ((20, 18), "nn2", 8, 1e-7, "mixed_bf16x3", 5),
+                          ((9, 9, 9), "nn", 8, 1e-7, "mixed_bf16x3", 6), ((20, 18), "nn2", 8, 1e-7, "mixed_bf16x3", 6),
+                          ((9, 9, 9), "nn", 0, 1e-6, "mixed_bf16x3", 6)])
 def test_mixed_rho_against_oracle(dims, nb, fp64_poles, tol, precision, variant):
     # fp64_poles shifts nearest and as many farthest from the real axis in FP64
     import paper_1005_0088_amd as nd
@@ -350,17 +352,23 @@ def _golden(name):
         return json.load(f)
 
 
-@pytest.mark.parametrize("name,precision,tol", [("cubic3d_24x4", "fp64", 1e-10), ("cubic3d_24x4", "mixed_fp32", 1e-7),
-                                                ("cubic3d_24x4", "mixed_bf16x3", 1e-7),
-                                                ("square2d_64x4", "fp64", 1e-10), ("square2d_64x4", "mixed_fp32", 1e-7),
-                                                ("square2d_64x4", "mixed_bf16x3", 1e-7)])
-def test_full_size_against_oracle_sample(name, precision, tol):
+@pytest.mark.parametrize("name,precision,tol,variant", [("cubic3d_24x4", "fp64", 1e-10, -1),
+                                                        ("cubic3d_24x4", "mixed_fp32", 1e-7, -1),
+                                                        ("cubic3d_24x4", "mixed_bf16x3", 1e-7, -1),
+                                                        ("cubic3d_24x4", "mixed_bf16x3", 1e-7, 6),
+                                                        ("square2d_64x4", "fp64", 1e-10, -1),
+                                                        ("square2d_64x4", "mixed_fp32", 1e-7, -1),
+                                                        ("square2d_64x4", "mixed_bf16x3", 1e-7, -1),
+                                                        ("square2d_64x4", "mixed_bf16x3", 1e-7, 6)])
+def test_full_size_against_oracle_sample(name, precision, tol, variant):
     # the configuration the benchmark times, in the same launch configuration
+    # (variant -1: the per-launch default; 6: every low-precision front
+    # update on the K-by-16 staged split-BF16 kernel)
     import paper_1005_0088_amd as nd
     from synth import config_system
     g = _golden(name)
     sysd = config_system(name)
-    with nd.Context(0, precision=precision) as c:
+    with nd.Context(0, precision=precision, gemm_variant=variant) as c:
         sid = _register(c, sysd)
         c.set_poles(sid, g["mu"], g["beta"], g["n_poles"])
         out = c.device_buffer(int(sysd["row_ptr"][-1]))
@@ -471,7 +479,7 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
     assert np.array_equal(got, again)
     with open(cache) as f:
         lines = f.read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("ndrho-tune-v3 ")
+    assert len(lines) == 1 and lines[0].startswith("ndrho-tune-v4 ")
     choice = lines[0].split()[-1]
     assert set(choice) <= set("012")
     with nd.Context(0, precision="mixed_fp32") as c:   # cached choice is reused, not re-tuned
@@ -488,7 +496,7 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
         assert np.max(np.abs(c.density_matrix(s3) - ref)) < 1e-7
     with open(cache) as f:
         lines = f.read().splitlines()
-    assert len(lines) == 2 and set(lines[1].split()[-1]) <= set("012345")
+    assert len(lines) == 2 and set(lines[1].split()[-1]) <= set("0123456")
 
 
 def test_large_3d_fp64_against_oracle_sample():
