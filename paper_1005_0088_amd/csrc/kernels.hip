@@ -91,7 +91,10 @@ __device__ __forceinline__ void store_elem(double2 v, int m, int n, const GemmPr
 // so lower maps to lower).  Writing (not adding) also clears the panel
 // before assembly, so no separate fill is needed and no two threads touch
 // one target.  The parent's own U x U block takes the same sum in the
-// epilogue of its Schur-update GEMM (G_EXTC0).
+// epilogue of its Schur-update GEMM (G_EXTC0).  Elements of the pivot block
+// above its diagonal 64 x 64 blocks are skipped: the recursive pivot inverse
+// reads only the lower part and the diagonal blocks, and writes the rest
+// (as the mirror of its lower part) before anything reads it.
 __global__ __launch_bounds__(256) void k_extadd(const ExtAddDesc* __restrict__ descs,
                                                 const ExtAddChild* __restrict__ kids,
                                                 const int32_t* __restrict__ inv, const ElemTile* __restrict__ tiles,
@@ -110,6 +113,7 @@ __global__ __launch_bounds__(256) void k_extadd(const ExtAddDesc* __restrict__ d
     const uint32_t e = uint32_t(t.e0) + threadIdx.x + 256 * i;
     if (e >= tp) break;
     const uint32_t s = e / ld, r = e - s * ld;
+    if (r < (s & ~63u)) continue;  // above the diagonal 64 x 64 blocks of the pivot block
     double2 sum = make_double2(0.0, 0.0);
     for (int c = 0; c < d.child_count; ++c) {
       const ExtAddChild k = kids[d.child_begin + c];

@@ -662,8 +662,9 @@ void finalize_plan(Plan& P) {
     const std::vector<int>& fr = by_depth[d];
     const int ubuf = (d % 2 == 0) ? BUF_UPD0 : BUF_UPD1;
     const int cbuf = (d % 2 == 0) ? BUF_UPD1 : BUF_UPD0;
-    // extend-add into the panels (writes every panel element); the U x U
-    // blocks take theirs in the epilogue of the Schur-update GEMM below
+    // extend-add into the panels (every element the pivot inverse and the
+    // update GEMMs read); the U x U blocks take theirs in the epilogue of the
+    // Schur-update GEMM below
     std::vector<int32_t> ext_index(P.fronts.size(), -1);
     {
       Op op;
@@ -687,8 +688,14 @@ void finalize_plan(Plan& P) {
         const int32_t di = static_cast<int32_t>(P.ext.size() - op.begin);
         ext_index[f] = static_cast<int32_t>(P.ext.size());
         P.ext.push_back(ds);
-        const int64_t total = int64_t(F.nj + F.nu) * F.nj;
-        for (int64_t e0 = 0; e0 < total; e0 += kTile) P.ext_tiles.push_back(ElemTile{di, 0, e0});
+        // tiles lying wholly above the diagonal 64 x 64 blocks of the pivot
+        // block are left out (the extend-add skips those elements, below)
+        const int64_t ld = F.nj + F.nu, total = ld * F.nj;
+        for (int64_t e0 = 0; e0 < total; e0 += kTile) {
+          const int64_t s0 = e0 / ld;
+          if (e0 + kTile <= s0 * ld + 64 * (s0 / 64)) continue;
+          P.ext_tiles.push_back(ElemTile{di, 0, e0});
+        }
       }
       op.count = static_cast<int64_t>(P.ext.size()) - op.begin;
       op.tile_count = static_cast<int64_t>(P.ext_tiles.size()) - op.tile_begin;
