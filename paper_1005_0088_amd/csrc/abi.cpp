@@ -935,6 +935,7 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
       choice.push_back(static_cast<char>('0' + best));
     }
     ++T.tune_gen;
+    if (ctx->opt.verbose) std::fprintf(stderr, "ndrho_autotune: choice per launch %s\n", choice.c_str());
     if (cache_path) {
       std::ofstream out(cache_path, std::ios::app);
       out << key << ' ' << choice << '\n';
