@@ -280,7 +280,6 @@ struct ndrho_ctx {
     return fit >= static_cast<double>(n_shifts) ? n_shifts : static_cast<int>(fit);
   }
 
-  // One pass of the whole program over `nb` poles.
   // One pass of the whole program over `nb` poles; the first `nhi` of them
   // take FP64 front updates, the rest the context's low precision (pivot
   // inverses are FP64 for all).
@@ -928,9 +927,11 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
     ctx->clear_profile();
     std::string choice;
     for (int i = 0; i < nops; ++i) {
-      int best = V_FP64;
-      for (int v = 1; v < V_COUNT; ++v)
-        if (variant_allowed(ctx->opt.precision, v) && ms[v][i] < ms[best][i]) best = v;
+      const Op& op = i < static_cast<int>(P.upward.size()) ? P.upward[i] : P.downward[i - P.upward.size()];
+      int best = V_FP64;  // only front-update GEMMs have variants
+      if (op.kind == OP_GEMM && !(op.flags & OP_PIVOT))
+        for (int v = 1; v < V_COUNT; ++v)
+          if (variant_allowed(ctx->opt.precision, v) && ms[v][i] < ms[best][i]) best = v;
       T.variant[i] = static_cast<int8_t>(best);
       choice.push_back(static_cast<char>('0' + best));
     }

@@ -41,44 +41,61 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t total) {
   return x * q + (x < r ? x : r) + local;
 }
 
-// C0 of a front's update block formed from its children (G_EXTC0): the sum,
-// in child order, of the children's lower-stored update entries that map
-// onto the front's U x U entry (m, n), m >= n (the same sum the extend-add
-// forms for the panel).
-__device__ __forceinline__ double2 ext_c0(const ExtAddDesc& e, const ExtAddChild* __restrict__ kids,
-                                          const int32_t* __restrict__ inv, const double2* __restrict__ cu, int m,
-                                          int n) {
-  double2 sum = make_double2(0.0, 0.0);
-  for (int c = 0; c < e.child_count; ++c) {
-    const ExtAddChild k = kids[e.child_begin + c];
-    const int32_t* im = inv + k.inv_off;
-    const int32_t a = im[e.nj + m], b = im[e.nj + n];
-    if (a >= 0 && b >= 0) {
-      const double2 v = cu[k.upd_off + max(a, b) + int64_t(min(a, b)) * k.nu];
-      sum.x += v.x;
-      sum.y += v.y;
+// Epilogue of a chunk of NE result elements held by one thread,
+// C = [C0 +] (+/-) product: negate, add C0 (read from memory with G_BETA,
+// formed from the children with G_EXTC0), store, and with a mirrored
+// symmetric output store the transpose too.  Elements outside the problem, or
+// above the diagonal of a symmetric output, are skipped.  With G_EXTC0 the C0
+// of an element of a front's U x U update is the sum, in child order, of the
+// children's lower-stored update entries that map onto it (the same sum the
+// extend-add forms for the panel); the map reads of the whole chunk are issued
+// before any of its value reads, so that a thread waits twice per child and
+// not twice per element and child.
+template <int FLAGS, int NE>
+__device__ __forceinline__ void store_chunk(double2 (&v)[NE], const int (&m)[NE], const int (&n)[NE],
+                                            const GemmProb& pr, const double2* C0p, double2* Cp,
+                                            const ExtAddDesc& xd, const ExtAddChild* __restrict__ xk,
+                                            const int32_t* __restrict__ xi) {
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
+  constexpr bool SYM = (FLAGS & G_SYM) != 0, MIRROR = SYM && !(FLAGS & G_NOMIRROR);
+  bool live[NE];
+#pragma unroll
+  for (int q = 0; q < NE; ++q) live[q] = m[q] < pr.m && n[q] < pr.n && !(SYM && m[q] < n[q]);
+  double2 c0[NE];
+  if (EXTC0) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) c0[q] = make_double2(0.0, 0.0);
+    for (int c = 0; c < xd.child_count; ++c) {
+      const ExtAddChild k = xk[xd.child_begin + c];
+      const int32_t* im = xi + k.inv_off + xd.nj;
+      int32_t a[NE], b[NE];
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        a[q] = live[q] ? im[m[q]] : -1;
+        b[q] = live[q] ? im[n[q]] : -1;
+      }
+#pragma unroll
+      for (int q = 0; q < NE; ++q)
+        if (a[q] >= 0 && b[q] >= 0) {  // the children store the lower triangle of their update
+          const double2 x = C0p[k.upd_off + max(a[q], b[q]) + int64_t(min(a[q], b[q])) * k.nu];
+          c0[q].x += x.x;
+          c0[q].y += x.y;
+        }
     }
   }
-  return sum;
-}
-
-// One element of a GEMM result, C = [C0 +] (+/-) product: negate, add C0
-// (read from memory with G_BETA, formed from the children with G_EXTC0),
-// store, and with a mirrored symmetric output store the transpose too.
-template <int FLAGS>
-__device__ __forceinline__ void store_elem(double2 v, int m, int n, const GemmProb& pr, const double2* C0p,
-                                           double2* Cp, const ExtAddDesc& xd, const ExtAddChild* __restrict__ xk,
-                                           const int32_t* __restrict__ xi) {
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool MIRROR = (FLAGS & G_SYM) && !(FLAGS & G_NOMIRROR);
-  if (NEG) v = make_double2(-v.x, -v.y);
-  if (BETA || EXTC0) {
-    const double2 c0 = BETA ? C0p[m + int64_t(n) * pr.ldc0] : ext_c0(xd, xk, xi, C0p, m, n);
-    v.x += c0.x;
-    v.y += c0.y;
+#pragma unroll
+  for (int q = 0; q < NE; ++q) {
+    if (!live[q]) continue;
+    double2 x = v[q];
+    if (NEG) x = make_double2(-x.x, -x.y);
+    if (BETA || EXTC0) {
+      const double2 y = BETA ? C0p[m[q] + int64_t(n[q]) * pr.ldc0] : c0[q];
+      x.x += y.x;
+      x.y += y.y;
+    }
+    Cp[m[q] + int64_t(n[q]) * pr.ldc] = x;
+    if (MIRROR && m[q] != n[q]) Cp[n[q] + int64_t(m[q]) * pr.ldc] = x;
   }
-  Cp[m + int64_t(n) * pr.ldc] = v;
-  if (MIRROR && m != n) Cp[n + int64_t(m) * pr.ldc] = v;
 }
 
 // ----------------------------------------------------------------- extend-add
@@ -399,18 +416,19 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i) {
+    double2 v[8];
+    int mm[8], nn[8];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 32 + i * 16 + (lane & 15);
-        const int n = n0 + wn * 32 + j * 16 + F64_DROW(r, lane);
-        if (m >= M || n >= N) continue;
-        if (SYM && m < n) continue;
-        double2 v = make_double2(p1[i][j][r] - p2[i][j][r], p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
-        store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
+        mm[4 * j + r] = m0 + wm * 32 + i * 16 + (lane & 15);
+        nn[4 * j + r] = n0 + wn * 32 + j * 16 + F64_DROW(r, lane);
+        v[4 * j + r] = make_double2(p1[i][j][r] - p2[i][j][r], p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
       }
+    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
+  }
 }
 
 // The same FP64 contraction for small problems: one wave per 32 x 32
@@ -497,18 +515,19 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i) {
+    double2 v[8];
+    int mm[8], nn[8];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = m0 + i * 16 + (lane & 15);
-        const int n = n0 + j * 16 + F64_DROW(q, lane);
-        if (m >= M || n >= N) continue;
-        if (SYM && m < n) continue;
-        double2 v = make_double2(p1[i][j][q] - p2[i][j][q], p3[i][j][q] - p1[i][j][q] - p2[i][j][q]);
-        store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
+        mm[4 * j + q] = m0 + i * 16 + (lane & 15);
+        nn[4 * j + q] = n0 + j * 16 + F64_DROW(q, lane);
+        v[4 * j + q] = make_double2(p1[i][j][q] - p2[i][j][q], p3[i][j][q] - p1[i][j][q] - p2[i][j][q]);
       }
+    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
+  }
 }
 
 // Same contraction with the products on the FP32 matrix cores
@@ -637,16 +656,19 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
 #pragma unroll
   for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < WT; ++j)
+    for (int j0 = 0; j0 < WT; j0 += 2) {  // chunks of two 16-column blocks
+      double2 v[8];
+      int mm[8], nn[8];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 16 * WT + i * 16 + (lane & 15);
-        const int n = n0 + wn * 16 * WT + j * 16 + F32_DROW(r, lane);
-        if (m >= M || n >= N) continue;
-        if (SYM && m < n) continue;
-        double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
-        store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
-      }
+      for (int j = j0; j < j0 + 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          mm[4 * (j - j0) + r] = m0 + wm * 16 * WT + i * 16 + (lane & 15);
+          nn[4 * (j - j0) + r] = n0 + wn * 16 * WT + j * 16 + F32_DROW(r, lane);
+          v[4 * (j - j0) + r] = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
+        }
+      store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
+    }
 }
 
 // Same contraction with compensated split-BF16 products.  Operands are
@@ -870,18 +892,19 @@ __global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restric
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
-  for (int i = 0; i < IB; ++i)
+  for (int i = 0; i < IB; ++i) {
+    double2 v[4 * JB];
+    int mm[4 * JB], nn[4 * JB];
 #pragma unroll
     for (int j = 0; j < JB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * (B3_TM / 2) + i * 16 + (lane & 15);
-        const int n = n0 + wn * WCOL + j * 16 + F32_DROW(r, lane);
-        if (m >= M || n >= N) continue;
-        if (SYM && m < n) continue;
-        double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
-        store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
+        mm[4 * j + r] = m0 + wm * (B3_TM / 2) + i * 16 + (lane & 15);
+        nn[4 * j + r] = n0 + wn * WCOL + j * 16 + F32_DROW(r, lane);
+        v[4 * j + r] = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
       }
+    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
+  }
 }
 
 // Variant of k_cgemm_bf3 (128 x 128 tiles, eight waves of 64 x 32) that
@@ -1052,18 +1075,19 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 4; ++i) {
+    double2 v[8];
+    int mm[8], nn[8];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 64 + i * 16 + (lane & 15);
-        const int n = n0 + wn * 32 + j * 16 + F32_DROW(r, lane);
-        if (m >= M || n >= N) continue;
-        if (SYM && m < n) continue;
-        double2 v = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
-        store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
+        mm[4 * j + r] = m0 + wm * 64 + i * 16 + (lane & 15);
+        nn[4 * j + r] = n0 + wn * 32 + j * 16 + F32_DROW(r, lane);
+        v[4 * j + r] = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
       }
+    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
+  }
 }
 
 // Variant of the split-BF16 contraction that splits every operand element
@@ -1242,13 +1266,17 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3p(const GemmProb* __restrict__
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = m0 + wm * 64 + i * 32 + (lane & 31);
-      const int n = n0 + wn * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      if (m >= M || n >= N) continue;
-      if (SYM && m < n) continue;
-      double2 v = make_double2(static_cast<double>(cre[i][r]), static_cast<double>(cim[i][r]));
-      store_elem<FLAGS>(v, m, n, pr, C0p, Cp, xd, xk, xi);
+    for (int h = 0; h < 2; ++h) {  // chunks of eight registers
+      double2 v[8];
+      int mm[8], nn[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int r = 8 * h + t;
+        mm[t] = m0 + wm * 64 + i * 32 + (lane & 31);
+        nn[t] = n0 + wn * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        v[t] = make_double2(static_cast<double>(cre[i][r]), static_cast<double>(cim[i][r]));
+      }
+      store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
     }
 }
 
