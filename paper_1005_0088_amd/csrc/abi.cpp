@@ -311,6 +311,16 @@ struct ndrho_ctx {
       d.c = bufs[op.buf_c], d.sc = strides[op.buf_c];
       return d;
     };
+    // G_UU of the low-precision poles is kept as FP32 complex at the depths
+    // where its only consumer, the G_UJ = -G_UU L launch, runs those poles in
+    // low precision (its products round the operand to FP32 in any case)
+    std::vector<char> guu32(P.n_levels + 1, 0);
+    for (size_t i = 0; i < P.downward.size(); ++i) {
+      const Op& op = P.downward[i];
+      if (op.kind != OP_GEMM || op.flags != (G_NEG | G_SYMA)) continue;
+      const int var = opt.gemm_variant >= 0 ? opt.gemm_variant : S.variant[P.upward.size() + i];
+      guu32[op.depth] = nhi < nb && var != V_FP64;
+    }
     auto run = [&](const Op& op) {
       DevOp d = resolve(op);
       hipError_t e = hipSuccess;
@@ -378,6 +388,7 @@ struct ndrho_ctx {
             l.tile_count = op.tile128_count;
           }
           l.npoles = nb - nhi;
+          l.a32 = op.flags == (G_NEG | G_SYMA) && guu32[op.depth];
           l.a += nhi * l.sa, l.b += nhi * l.sb, l.c += nhi * l.sc;
           if (op.flags & (G_BETA | G_EXTC0)) l.c0 += nhi * l.sc0;
           timed(l.bf3 ? NDRHO_K_GEMM_BF16X3 : NDRHO_K_GEMM_F32, op.flops * (nb - nhi),
@@ -393,6 +404,9 @@ struct ndrho_ctx {
           d.gat = S.gat + op.begin;
           d.rel = S.rel;
           d.elem_tiles = S.gat_tiles + op.tile_begin;
+          d.nhi = nhi;
+          d.gat_out32 = guu32[op.depth];
+          d.gat_in32 = op.depth > 0 ? guu32[op.depth - 1] : 0;
           timed(NDRHO_K_GATHER, 0.0, [&] { e = launch_gather(d, stream); });
           break;
       }

@@ -13,6 +13,10 @@ namespace ndrho {
 struct DevOp {
   int flags = 0;
   int npoles = 1;
+  bool a32 = false;      // GEMM: A operand stored as FP32 complex (G_A32)
+  int64_t nhi = 0;       // GATHER: the first nhi poles keep FP64 G_UU
+  int gat_in32 = 0;      // GATHER: the parent's G_UU of the other poles is FP32
+  int gat_out32 = 0;     // GATHER: write the G_UU of the other poles as FP32
   bool fp32 = false;     // GEMM products on the FP32 matrix cores
   bool tile128 = false;  // FP32 GEMM on 128x128 tiles (else 64x64)
   bool small = false;    // FP64 GEMM with one wave per 32x32 tile

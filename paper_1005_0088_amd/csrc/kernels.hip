@@ -33,6 +33,17 @@ __device__ __forceinline__ double2 cinv(double2 p) {
   return make_double2(xr / d, -xi / d);
 }
 
+// Element i of a GEMM's A operand: FP64 complex, or FP32 complex widened
+// exactly (G_A32; the low-precision products round it to FP32 in any case).
+template <bool A32>
+__device__ __forceinline__ double2 a_elem(const double2* Ap, int64_t i) {
+  if (A32) {
+    const float2 x = reinterpret_cast<const float2*>(Ap)[i];
+    return make_double2(static_cast<double>(x.x), static_cast<double>(x.y));
+  }
+  return Ap[i];
+}
+
 // Blocks of a launch are dealt to the 8 XCDs round-robin by linear id; this
 // remap gives every XCD one contiguous range of logical work items, so the
 // tiles of one pole (which share operand panels) meet in one L2.
@@ -300,8 +311,9 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
   constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0, A32 = (FLAGS & G_A32) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
+  static_assert(!A32, "the FP64 kernels read FP64 operands");
   __shared__ double2 As[2][BK][BM + 1];
   __shared__ double2 Bs[2][BK][BN + 1];
 
@@ -447,8 +459,9 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
   constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0, A32 = (FLAGS & G_A32) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
+  static_assert(!A32, "the FP64 kernels read FP64 operands");
   const int64_t total = ntiles * npoles;
   const int64_t w = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (w >= total) return;  // the whole wave; nothing here synchronises waves
@@ -550,7 +563,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
   constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0, A32 = (FLAGS & G_A32) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   constexpr int TM = 32 * WT;          // workgroup tile edge
   constexpr int NL = TM * BK / 256;    // operand elements per thread per stage
@@ -589,9 +602,12 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
       const int m_ = TA ? (tid >> 4) + 16 * i : tid % TM;                                        \
       const int k_ = TA ? (tid & 15) : tid / TM + RS * i;                                        \
       const int gm = m0 + m_, gk = (k0) + k_;                                                    \
-      ra[i] = (gm < M && gk < K) ? (TA ? Ap[gk + int64_t(gm) * pr.lda]                                 \
-                                       : (SYMA && gm < gk) ? Ap[gk + int64_t(gm) * pr.lda]                   \
-                                                           : Ap[gm + int64_t(gk) * pr.lda])                  \
+      ra[i] = (gm < M && gk < K)                                                                             \
+                  ? (A32 ? ((SYMA && gm < gk) ? a_elem<true>(Ap, gk + int64_t(gm) * pr.lda)                 \
+                                                  : a_elem<true>(Ap, gm + int64_t(gk) * pr.lda))             \
+                         : TA ? Ap[gk + int64_t(gm) * pr.lda]                                                 \
+                         : (SYMA && gm < gk) ? Ap[gk + int64_t(gm) * pr.lda]                                  \
+                                             : Ap[gm + int64_t(gk) * pr.lda])                                 \
                                  : make_double2(0.0, 0.0);                                                   \
     }                                                                                            \
     {                                                                                            \
@@ -726,7 +742,7 @@ __global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restric
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
   constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0, A32 = (FLAGS & G_A32) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   constexpr int NT = NW * 64;              // threads
   constexpr int IB = B3_TM / 32;           // 16-row blocks of a wave's A rows (wave tile TM/2 x WCOL)
@@ -780,13 +796,13 @@ __global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restric
     _Pragma("unroll") for (int g = 0; g < GPT; ++g)                                                     \
       _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
         const int gm = m0 + B3_AROW(g), gk = (k0) + B3_AK(g) + q;                                       \
-        rs[4 * g + q] = Ap[B3_AIDX(gm, gk)];                                                            \
+        rs[4 * g + q] = a_elem<A32>(Ap, B3_AIDX(gm, gk));                                               \
       }                                                                                                 \
   } else {                                                                                              \
     _Pragma("unroll") for (int g = 0; g < GPT; ++g)                                                     \
       _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
         const int gm = m0 + B3_AROW(g), gk = (k0) + B3_AK(g) + q;                                       \
-        rs[4 * g + q] = (gm < M && gk < K) ? Ap[B3_AIDX(gm, gk)] : make_double2(0.0, 0.0);              \
+        rs[4 * g + q] = (gm < M && gk < K) ? a_elem<A32>(Ap, B3_AIDX(gm, gk)) : make_double2(0.0, 0.0); \
       }                                                                                                 \
   }
 #define B3_LOADB(k0)                                                                                    \
@@ -927,7 +943,7 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
   constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0, A32 = (FLAGS & G_A32) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   // planes: [operand A/B][2 slice + part][row][k]
   __shared__ __attribute__((aligned(16))) unsigned short lds[12 * B3S_PLANE];
@@ -968,13 +984,13 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__
     _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
       _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
         const int gm = m0 + S3_AROW(g), gk = (k0) + S3_AK(g) + q;                                       \
-        ra[4 * g + q] = Ap[S3_AIDX(gm, gk)];                                                            \
+        ra[4 * g + q] = a_elem<A32>(Ap, S3_AIDX(gm, gk));                                               \
       }                                                                                                 \
   } else {                                                                                              \
     _Pragma("unroll") for (int g = 0; g < 2; ++g)                                                       \
       _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                   \
         const int gm = m0 + S3_AROW(g), gk = (k0) + S3_AK(g) + q;                                       \
-        ra[4 * g + q] = (gm < M && gk < K) ? Ap[S3_AIDX(gm, gk)] : make_double2(0.0, 0.0);              \
+        ra[4 * g + q] = (gm < M && gk < K) ? a_elem<A32>(Ap, S3_AIDX(gm, gk)) : make_double2(0.0, 0.0); \
       }                                                                                                 \
   }                                                                                                     \
   if (bfull && (k0) + B3_BK <= K) {                                                                     \
@@ -1116,7 +1132,7 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3p(const GemmProb* __restrict__
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
   constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool SYMA = (FLAGS & G_SYMA) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0, A32 = (FLAGS & G_A32) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   // [stage][plane = 6 operand + 2 slice + part][row][k]
   __shared__ __attribute__((aligned(16))) unsigned short lds[2 * B3P_STAGE];
@@ -1167,8 +1183,14 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3p(const GemmProb* __restrict__
     _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                     \
       const uint32_t gk = static_cast<uint32_t>((k0) + ak + q);                                         \
       const uint32_t o = (TA || (SYMA && gm < gk)) ? gk + gm * ulda : gm + gk * ulda;                   \
-      ra[q] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(                        \
-                                              arsrc, (gm < uM && gk < uK) ? o * 16u : B3P_OOB, 0, 0));  \
+      if (A32) {                                                                                        \
+        const float2 x_ = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(               \
+                                              arsrc, (gm < uM && gk < uK) ? o * 8u : B3P_OOB, 0, 0));   \
+        ra[q] = make_double2(static_cast<double>(x_.x), static_cast<double>(x_.y));                     \
+      } else {                                                                                          \
+        ra[q] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(                      \
+                                                arsrc, (gm < uM && gk < uK) ? o * 16u : B3P_OOB, 0, 0)); \
+      }                                                                                                 \
     }                                                                                                   \
     _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                                     \
       const uint32_t gk = static_cast<uint32_t>((k0) + bk + q);                                         \
@@ -1328,8 +1350,13 @@ __global__ __launch_bounds__(256) void k_gather(const GatherDesc* __restrict__ d
                                                 const int32_t* __restrict__ rel, const ElemTile* __restrict__ tiles,
                                                 const double2* __restrict__ pguu, int64_t gs,
                                                 const double2* __restrict__ panel, int64_t ps,
-                                                double2* __restrict__ guu, int64_t us) {
+                                                double2* __restrict__ guu, int64_t us, int64_t nhi, int in32,
+                                                int out32) {
   const int64_t pole = blockIdx.y;
+  // poles from nhi on: the parent's G_UU is FP32 complex (in32), and so is
+  // the output (out32) when its only consumer, G_UJ = -G_UU L, runs in low
+  // precision (it rounds the operand to FP32 in any case)
+  const bool lo = pole >= nhi, rd32 = lo && in32 != 0, wr32 = lo && out32 != 0;
   const ElemTile t = tiles[blockIdx.x];
   const GatherDesc d = descs[t.desc];
   const uint32_t total = uint32_t(d.nu) * d.nu;
@@ -1345,8 +1372,12 @@ __global__ __launch_bounds__(256) void k_gather(const GatherDesc* __restrict__ d
     const uint32_t b = e / uint32_t(d.nu), a = e - b * uint32_t(d.nu);
     if (a < b) continue;  // G_UU is kept as its lower triangle
     const int r = rl[a], s = rl[b];  // r >= s (increasing map)
-    const double2 v = s < d.pnj ? pan[r + int64_t(s) * pld] : pg[(r - d.pnj) + int64_t(s - d.pnj) * d.pnu];
-    out[e] = v;
+    const int64_t gi = (r - d.pnj) + int64_t(s - d.pnj) * d.pnu;
+    const double2 v = s < d.pnj ? pan[r + int64_t(s) * pld] : rd32 ? a_elem<true>(pg, gi) : pg[gi];
+    if (wr32)
+      reinterpret_cast<float2*>(out)[e] = make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+    else
+      out[e] = v;
   }
 }
 
@@ -1476,10 +1507,14 @@ static void gemm_bf3_inst(const DevOp& o, hipStream_t st) {
 
 hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
   if (o.tile_count == 0) return hipSuccess;
+  if (o.a32 && (o.flags != (G_NEG | G_SYMA) || !(o.bf3 || o.fp32))) return hipErrorInvalidValue;
   if (o.bf3) {
     switch (o.flags) {  // front updates only
       case 0: gemm_bf3_inst<0>(o, st); break;
-      case G_NEG | G_SYMA: gemm_bf3_inst<G_NEG | G_SYMA>(o, st); break;
+      case G_NEG | G_SYMA:
+        if (o.a32) gemm_bf3_inst<G_NEG | G_SYMA | G_A32>(o, st);
+        else gemm_bf3_inst<G_NEG | G_SYMA>(o, st);
+        break;
       case G_TB | G_SYM | G_EXTC0 | G_NEG | G_NOMIRROR: gemm_bf3_inst<G_TB | G_SYM | G_EXTC0 | G_NEG | G_NOMIRROR>(o, st); break;
       case G_TA | G_SYM | G_BETA | G_NEG: gemm_bf3_inst<G_TA | G_SYM | G_BETA | G_NEG>(o, st); break;
       default: return hipErrorInvalidValue;
@@ -1489,7 +1524,10 @@ hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
   if (o.fp32) {
     switch (o.flags) {  // front updates only (pivot GEMMs are always FP64)
       case 0: gemm32_inst<0>(o, st); break;
-      case G_NEG | G_SYMA: gemm32_inst<G_NEG | G_SYMA>(o, st); break;
+      case G_NEG | G_SYMA:
+        if (o.a32) gemm32_inst<G_NEG | G_SYMA | G_A32>(o, st);
+        else gemm32_inst<G_NEG | G_SYMA>(o, st);
+        break;
       case G_TB | G_SYM | G_EXTC0 | G_NEG | G_NOMIRROR: gemm32_inst<G_TB | G_SYM | G_EXTC0 | G_NEG | G_NOMIRROR>(o, st); break;
       case G_TA | G_SYM | G_BETA | G_NEG: gemm32_inst<G_TA | G_SYM | G_BETA | G_NEG>(o, st); break;
       default: return hipErrorInvalidValue;
@@ -1522,7 +1560,7 @@ hipError_t launch_copy(const DevOp& o, hipStream_t st) {
 hipError_t launch_gather(const DevOp& o, hipStream_t st) {
   if (o.tile_count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather, dim3(static_cast<unsigned>(o.tile_count), o.npoles), dim3(256), 0, st, o.gat, o.rel,
-                     o.elem_tiles, o.a, o.sa, o.b, o.sb, o.c, o.sc);
+                     o.elem_tiles, o.a, o.sa, o.b, o.sb, o.c, o.sc, o.nhi, o.gat_in32, o.gat_out32);
   return hipGetLastError();
 }
 

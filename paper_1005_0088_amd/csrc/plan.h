@@ -85,7 +85,8 @@ enum OpKind { OP_EXTADD, OP_ASSEMBLE, OP_SMALLINV, OP_GEMM, OP_COPY, OP_GATHER }
 // the children's update entries that map onto (m, n) (the extend-add of the
 // front's own U x U block, children in order).
 enum GemmFlags { G_TA = 1, G_TB = 2, G_SYM = 4, G_BETA = 8, G_NEG = 16, G_NOMIRROR = 32, G_SYMA = 64,
-                 G_EXTC0 = 128 };
+                 G_EXTC0 = 128,
+                 G_A32 = 512 };  // set at launch: the A operand is stored as FP32 complex (low-precision poles)
 // Op-level marker (not a kernel flag): the GEMM belongs to a pivot-block
 // inverse and always runs in FP64.
 constexpr int OP_PIVOT = 1 << 8;
