@@ -762,8 +762,13 @@ void finalize_plan(Plan& P) {
         const Front& Pa = P.fronts[F.parent];
         const int32_t di = static_cast<int32_t>(P.gat.size() - op.begin);
         P.gat.push_back(GatherDesc{F.upd_off, rel_off[f], Pa.panel_off, Pa.upd_off, F.nu, Pa.nj, Pa.nu, 0});
+        // G_UU is kept as its lower triangle: tiles wholly above it are left out
         const int64_t total = int64_t(F.nu) * F.nu;
-        for (int64_t e0 = 0; e0 < total; e0 += kTile) P.gat_tiles.push_back(ElemTile{di, 0, e0});
+        for (int64_t e0 = 0; e0 < total; e0 += kTile) {
+          const int64_t b0 = e0 / F.nu;
+          if (e0 + kTile <= b0 * (F.nu + 1)) continue;
+          P.gat_tiles.push_back(ElemTile{di, 0, e0});
+        }
       }
       op.count = static_cast<int64_t>(P.gat.size()) - op.begin;
       op.tile_count = static_cast<int64_t>(P.gat_tiles.size()) - op.tile_begin;
