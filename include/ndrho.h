@@ -20,7 +20,7 @@
  *   - all device work is ordered on the context's HIP stream;
  *   - input arrays are copied; the caller keeps ownership of all its buffers.
  *
- * CSR input format (set_structure): 0-based, n rows, row_ptr[n+1] (int64,
+ * CSR input format (set_structure): 0-based, n rows (1 <= n <= 2^31 - 2), row_ptr[n+1] (int64,
  * row_ptr[0] = 0, non-decreasing), col_idx[nnz] (int32, strictly increasing
  * within each row), the diagonal present in every row, the pattern
  * structurally symmetric, values H and S real symmetric on it (|a_ij - a_ji|

@@ -137,6 +137,19 @@ def test_chain_dissection_has_one_atom_separators():
     assert sorted([top_atom, n - 1 - top_atom]) == [4, 5]
 
 
+def test_plan_empty_and_disconnected():
+    # an empty structure is rejected; a pattern with no off-diagonal entries
+    # (n disconnected rows) is one front holding every row, with no update
+    with pytest.raises(nd.NdrhoError) as e:
+        nd.Plan(0, np.array([0], dtype=np.int64), np.array([], dtype=np.int32), None, 8)
+    assert e.value.name == "EINVAL"
+    p = nd.Plan(3, np.array([0, 1, 2, 3], dtype=np.int64), np.array([0, 1, 2], dtype=np.int32), None, 8)
+    ex = p.export()
+    assert p.n_fronts == 1 and p.n_levels == 1
+    assert int(ex["nj"][0]) == 3 and int(ex["nu"][0]) == 0
+    assert sorted(int(x) for x in ex["perm"]) == [0, 1, 2]
+
+
 def test_plan_rejects_bad_csr():
     sysd = lattice((4, 3), "nn", 0)
     col = sysd["col"].copy()
