@@ -499,20 +499,22 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
     assert len(lines) == 2 and set(lines[1].split()[-1]) <= set("0123456")
 
 
-def test_large_3d_fp64_against_oracle_sample():
+@pytest.mark.parametrize("precision,fp64_poles,tol", [("fp64", 0, 1e-9), ("mixed_bf16x3", 12, 1e-7)])
+def test_large_3d_against_oracle_sample(precision, fp64_poles, tol):
     # 40^3 sites x 4 (N = 256 000), 100 poles, 10 poles per device pass.  The
     # stored values come from GMRES solves (rtol 1e-13) per pole and column,
     # whose own error (about rtol times the conditioning, summed over poles)
-    # sets the tolerance here.
+    # sets the FP64 tolerance here; the mixed form keeps 12 + 12 poles in FP64
+    # (the setting that holds 1e-7 at this size) on the default launch variants.
     import paper_1005_0088_amd as nd
     from synth import config_system
     g = _golden("cubic3d_40x4")
     sysd = config_system("cubic3d_40x4")
-    with nd.Context(0) as c:
+    with nd.Context(0, precision=precision, fp64_poles=fp64_poles, fp64_far_poles=fp64_poles) as c:
         sid = _register(c, sysd)
         c.set_poles(sid, g["mu"], g["beta"], g["n_poles"])
         rho = c.density_matrix(sid)
         assert c.stats(sid)["pole_batch"] < g["n_poles"]     # several passes over pole batches
     err = np.max(np.abs(rho[np.asarray(g["entries"])] - np.asarray(g["values"])))
-    print("cubic3d_40x4 fp64 max err on %d sampled entries: %.3e" % (len(g["entries"]), err))
-    assert err < 1e-9
+    print("cubic3d_40x4 %s max err on %d sampled entries: %.3e" % (precision, len(g["entries"]), err))
+    assert err < tol
