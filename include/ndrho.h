@@ -163,7 +163,8 @@ int ndrho_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_
  * double-buffered bf16 planes; the low-precision variants apply only to the
  * poles the mode puts in low precision) and keeps the fastest.  With
  * cache_path non-NULL the choice is looked up in, or appended to, that text
- * file under a key of the plan's shape, pole count, batch size and precision.
+ * file under a key of the plan's shape, pole count, batch size and precision
+ * (a line whose choice names a variant the mode does not accept is ignored).
  * FP64 mode: nothing to tune.  With opt.verbose each timed variant and the
  * choice (one digit per launch of the program) are reported on stderr.  Errors: EINVAL, ESTATE (no shifts set), EDEVICE. */
 int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const char* cache_path);

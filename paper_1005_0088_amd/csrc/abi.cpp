@@ -900,11 +900,21 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
       std::ifstream in(cache_path);
       std::string line;
       while (std::getline(in, line)) {
-        if (line.size() == key.size() + 1 + static_cast<size_t>(nops) && line.compare(0, key.size(), key) == 0) {
-          for (int i = 0; i < nops; ++i) T.variant[i] = static_cast<int8_t>(line[key.size() + 1 + i] - '0');
-          ++T.tune_gen;
-          return;
+        if (line.size() != key.size() + 1 + static_cast<size_t>(nops) || line.compare(0, key.size(), key) != 0 ||
+            line[key.size()] != ' ')
+          continue;
+        // a line is used only if every digit is a variant this precision mode accepts
+        std::vector<int8_t> v(nops);
+        bool ok = true;
+        for (int i = 0; i < nops && ok; ++i) {
+          const int d = line[key.size() + 1 + i] - '0';
+          ok = d >= 0 && d < V_COUNT && variant_allowed(ctx->opt.precision, d);
+          v[i] = static_cast<int8_t>(d);
         }
+        if (!ok) continue;
+        T.variant = v;
+        ++T.tune_gen;
+        return;
       }
     }
     // time every variant of every front-update GEMM on one full evaluation each

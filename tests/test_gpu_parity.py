@@ -497,6 +497,18 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
     with open(cache) as f:
         lines = f.read().splitlines()
     assert len(lines) == 2 and set(lines[1].split()[-1]) <= set("0123456")
+    # a cached choice naming variants the mode does not accept is ignored and tuned again
+    bad = lines[0].rsplit(" ", 1)[0] + " " + "9" * len(lines[0].split()[-1])
+    with open(cache, "w") as f:
+        f.write(bad + "\n")
+    with nd.Context(0, precision="mixed_fp32") as c:
+        s4 = _register(c, sysd)
+        c.set_poles(s4, 0.0, BETA, 40)
+        c.autotune([s4], cache)
+        assert np.max(np.abs(c.density_matrix(s4) - ref)) < 1e-7
+    with open(cache) as f:
+        lines = f.read().splitlines()
+    assert len(lines) == 2 and lines[0] == bad and set(lines[1].split()[-1]) <= set("012")
 
 
 @pytest.mark.parametrize("precision,fp64_poles,tol", [("fp64", 0, 1e-9), ("mixed_bf16x3", 12, 1e-7)])
