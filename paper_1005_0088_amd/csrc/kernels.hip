@@ -136,25 +136,40 @@ __global__ __launch_bounds__(256) void k_extadd(const ExtAddDesc* __restrict__ d
   const uint32_t tp = ld * d.nj;
   double2* pan = panel + pole * ps + d.panel_off;
   const double2* cu = cupd + pole * cs;
+  // four elements per thread; the map reads of all four are issued before
+  // any value read, child by child (the sums keep the child order)
+  uint32_t r[4], s[4];
+  bool live[4];
+  double2 sum[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint32_t e = uint32_t(t.e0) + threadIdx.x + 256 * i;
-    if (e >= tp) break;
-    const uint32_t s = e / ld, r = e - s * ld;
-    if (r < (s & ~63u)) continue;  // above the diagonal 64 x 64 blocks of the pivot block
-    double2 sum = make_double2(0.0, 0.0);
-    for (int c = 0; c < d.child_count; ++c) {
-      const ExtAddChild k = kids[d.child_begin + c];
-      const int32_t* im = inv + k.inv_off;
-      const int32_t a = im[r], b = im[s];
-      if (a >= 0 && b >= 0) {  // children store the lower triangle of their update
-        const double2 v = cu[k.upd_off + max(a, b) + int64_t(min(a, b)) * k.nu];
-        sum.x += v.x;
-        sum.y += v.y;
-      }
-    }
-    pan[r + int64_t(s) * ld] = sum;
+    s[i] = e / ld;
+    r[i] = e - s[i] * ld;
+    // skipped: past the panel, or above the diagonal 64 x 64 blocks of the pivot block
+    live[i] = e < tp && r[i] >= (s[i] & ~63u);
+    sum[i] = make_double2(0.0, 0.0);
   }
+  for (int c = 0; c < d.child_count; ++c) {
+    const ExtAddChild k = kids[d.child_begin + c];
+    const int32_t* im = inv + k.inv_off;
+    int32_t a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = live[i] ? im[r[i]] : -1;
+      b[i] = live[i] ? im[s[i]] : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (a[i] >= 0 && b[i] >= 0) {  // children store the lower triangle of their update
+        const double2 v = cu[k.upd_off + max(a[i], b[i]) + int64_t(min(a[i], b[i])) * k.nu];
+        sum[i].x += v.x;
+        sum[i].y += v.y;
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (live[i]) pan[r[i] + int64_t(s[i]) * ld] = sum[i];
 }
 
 // ----------------------------------------------------------------- assembly
