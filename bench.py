@@ -95,12 +95,12 @@ def golden_error(name, rho, mu, n_poles):
 
 
 def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_poles, autotune=True, gemm_variant=-1,
-             tune_cache=None):
+             tune_cache=None, split_streams=1):
     """Time one precision form on one system (density_matrix) or several
     (density_matrix_batch: one schedule); returns (timing dict, rho list)."""
     variant = gemm_variant if precision != "fp64" else -1
     ctx = nd.Context(0, precision=precision, fp64_poles=fp64_poles, fp64_far_poles=fp64_poles, gemm_variant=variant,
-                     verbose=1)
+                     split_streams=split_streams, verbose=1)
     t0 = time.time()
     sids = []
     for sysd in systems:
@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--gemm-variant", type=int, default=-1,
                     help="force one GEMM variant on every low-precision front update (see ndrho_options)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--split-streams", type=int, default=1,
+                    help="mixed forms: launch chains beside the main one (0 = one chain; see ndrho_options)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -213,7 +215,7 @@ def main():
         for form in ("mixed_fp32", "mixed_bf16x3"):
             if form != args.precision:
                 r, rr = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, form, args.fp64_poles,
-                                 not args.no_autotune, -1, args.tune_cache)
+                                 not args.no_autotune, -1, args.tune_cache, args.split_streams)
                 others[form] = {
                     "poles_per_s": r["poles_per_s"], "ms_per_step": r["ms_per_step"],
                     "kernel_ms": {k: round(v["ms"], 3) for k, v in r["prof"].items()},
@@ -223,7 +225,8 @@ def main():
         head, rho = r64, rho64
     else:
         head, rho = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, args.precision,
-                             args.fp64_poles, not args.no_autotune, args.gemm_variant, args.tune_cache)
+                             args.fp64_poles, not args.no_autotune, args.gemm_variant, args.tune_cache,
+                             args.split_streams)
     st, prof = head["stats"][0], head["prof"]
     # dominant kernel: the FP64 front GEMMs in the FP64 form, the FP32-product
     # front GEMMs in the mixed form (peak of their own arithmetic)

@@ -87,6 +87,11 @@ typedef struct {
   int32_t fp64_small_tiles; /* FP64 GEMM launches: -1 (default) one wave per 32x32 output tile where the
                                launch's problems would fill less than half of the 64x64 tiles; 0 never;
                                1 always */
+  int32_t split_streams; /* mixed mode, 0-4: k >= 1 (default 1) runs the FP64 poles of a pass and its
+                            low-precision poles, divided into k parts, as k + 1 independent launch chains
+                            on further streams that the context creates (default priority), joined back
+                            before the pole sum; 0 runs one chain.  Results are identical either way.
+                            Profiling (ndrho_profile, ndrho_autotune) always runs one chain */
 } ndrho_options;
 
 /* Fill *opt with the defaults listed above. */

@@ -25,7 +25,8 @@ class Options(C.Structure):
     _fields_ = [("leaf_rows", C.c_int32), ("precision", C.c_int32), ("pole_batch", C.c_int32),
                 ("mem_fraction", C.c_double), ("verbose", C.c_int32), ("fp64_poles", C.c_int32),
                 ("fp64_pole_im", C.c_double), ("fp64_far_poles", C.c_int32), ("use_graph", C.c_int32),
-                ("gemm_variant", C.c_int32), ("fp64_small_tiles", C.c_int32)]
+                ("gemm_variant", C.c_int32), ("fp64_small_tiles", C.c_int32),
+                ("split_streams", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -223,7 +224,7 @@ class Context:
 
     def __init__(self, device=0, stream=None, leaf_rows=32, pole_batch=0, mem_fraction=0.8, precision="fp64",
                  fp64_poles=None, fp64_pole_im=None, use_graph=True, gemm_variant=-1, fp64_far_poles=None,
-                 fp64_small_tiles=-1, verbose=0):
+                 fp64_small_tiles=-1, split_streams=1, verbose=0):
         self._lib = load_library()
         opt = Options()
         self._lib.ndrho_default_options(C.byref(opt))
@@ -240,6 +241,7 @@ class Context:
         opt.use_graph = int(bool(use_graph))
         opt.gemm_variant = int(gemm_variant)
         opt.fp64_small_tiles = int(fp64_small_tiles)
+        opt.split_streams = int(split_streams)
         opt.verbose = int(verbose)
         handle = None
         if stream is not None:

@@ -149,6 +149,12 @@ struct ndrho_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // further streams of a split pass (FP64 poles and parts of the
+  // low-precision ones beside `stream`), the event that forks them from
+  // `stream` and one per stream that joins it back
+  static constexpr int kMaxChains = 4;
+  hipStream_t side[kMaxChains] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kMaxChains] = {};
   ndrho_options opt{};
   std::string err;
   std::vector<std::unique_ptr<DevStruct>> structs;
@@ -230,6 +236,11 @@ struct ndrho_ctx {
     if (acc) (void)hipFree(acc);
     if (outbuf) (void)hipFree(outbuf);
     if (status) (void)hipFree(status);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    for (int i = 0; i < kMaxChains; ++i) {
+      if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
+      if (side[i]) (void)hipStreamDestroy(side[i]);
+    }
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
@@ -280,25 +291,36 @@ struct ndrho_ctx {
     return fit >= static_cast<double>(n_shifts) ? n_shifts : static_cast<int>(fit);
   }
 
-  // One pass of the whole program over `nb` poles; the first `nhi` of them
-  // take FP64 front updates, the rest the context's low precision (pivot
-  // inverses are FP64 for all).
-  void run_pass(DevStruct& S, int nb, const double2* alpha, int64_t astride, const double* w, double hcoef,
-                int spd_check, int nhi) {
-    const Plan& P = S.plan;
+  // Workspace regions of a batch of `nlay` poles: each buffer kind holds
+  // its poles one after another, `strides` elements apart.
+  void layout(const Plan& P, int nlay, double2** bufs, int64_t* strides) const {
     double2* base = static_cast<double2*>(ws);
-    double2* bufs[BUF_COUNT];
-    int64_t strides[BUF_COUNT];
     bufs[BUF_PANEL] = base;
     strides[BUF_PANEL] = P.panel_total;
-    bufs[BUF_UPD0] = base + P.panel_total * nb;
+    bufs[BUF_UPD0] = base + P.panel_total * nlay;
     strides[BUF_UPD0] = P.upd_total;
-    bufs[BUF_UPD1] = bufs[BUF_UPD0] + P.upd_total * nb;
+    bufs[BUF_UPD1] = bufs[BUF_UPD0] + P.upd_total * nlay;
     strides[BUF_UPD1] = P.upd_total;
-    bufs[BUF_TEMP] = bufs[BUF_UPD1] + P.upd_total * nb;
+    bufs[BUF_TEMP] = bufs[BUF_UPD1] + P.upd_total * nlay;
     strides[BUF_TEMP] = P.temp_total;
-    bufs[BUF_L] = bufs[BUF_TEMP] + P.temp_total * nb;
+    bufs[BUF_L] = bufs[BUF_TEMP] + P.temp_total * nlay;
     strides[BUF_L] = P.l_total;
+  }
+
+  // One pass of the whole program (assembly, upward and downward sweeps;
+  // the pole sum is left to the caller) over `nb` poles held at positions
+  // q0 .. q0 + nb - 1 of a workspace laid out for `nlay` poles, launched on
+  // `st`; the first `nhi` of them take FP64 front updates, the rest the
+  // context's low precision (pivot inverses are FP64 for all).  Passes over
+  // disjoint position ranges share no memory but the pivot status counters,
+  // which are updated atomically.
+  void run_pass(DevStruct& S, int nlay, int q0, int nb, const double2* alpha, int64_t astride, double hcoef,
+                int spd_check, int nhi, hipStream_t st) {
+    const Plan& P = S.plan;
+    double2* bufs[BUF_COUNT];
+    int64_t strides[BUF_COUNT];
+    layout(P, nlay, bufs, strides);
+    for (int b = 0; b < BUF_COUNT; ++b) bufs[b] += q0 * strides[b];
     auto resolve = [&](const Op& op) {
       DevOp d;
       d.flags = op.flags & 0xff;
@@ -330,19 +352,19 @@ struct ndrho_ctx {
           d.ext_child = S.ext_child;
           d.ext_inv = S.ext_inv;
           d.elem_tiles = S.ext_tiles + op.tile_begin;
-          timed(NDRHO_K_EXTADD, 0.0, [&] { e = launch_extadd(d, stream); });
+          timed(NDRHO_K_EXTADD, 0.0, [&] { e = launch_extadd(d, st); });
           break;
         case OP_ASSEMBLE:
           d.slot = S.asm_slot + op.begin;
           d.entry = S.asm_entry + op.begin;
           d.sid = S.asm_sid + op.begin;
-          timed(NDRHO_K_ASSEMBLE, 0.0, [&] { e = launch_assemble(d, S.h, S.s, alpha, astride, hcoef, stream); });
+          timed(NDRHO_K_ASSEMBLE, 0.0, [&] { e = launch_assemble(d, S.h, S.s, alpha, astride, hcoef, st); });
           break;
         case OP_SMALLINV:
           d.inv = S.inv + op.begin;
           d.count16 = op.inv16;
           d.count32 = op.inv32;
-          timed(NDRHO_K_PIVOT_INV, 0.0, [&] { e = launch_smallinv(d, status, spd_check, stream); });
+          timed(NDRHO_K_PIVOT_INV, 0.0, [&] { e = launch_smallinv(d, status, spd_check, st); });
           break;
         case OP_GEMM: {
           d.gemm = S.gemm + op.begin;
@@ -370,13 +392,13 @@ struct ndrho_ctx {
           };
           if (!split) {
             const DevOp h = fp64_launch(d);
-            timed(k64, op.flops * nb, [&] { e = launch_gemm(h, stream); });
+            timed(k64, op.flops * nb, [&] { e = launch_gemm(h, st); });
             break;
           }
           if (nhi > 0) {  // FP64 for the poles nearest the real axis
             DevOp h = fp64_launch(d);
             h.npoles = nhi;
-            timed(k64, op.flops * nhi, [&] { e = launch_gemm(h, stream); });
+            timed(k64, op.flops * nhi, [&] { e = launch_gemm(h, st); });
             if (e != hipSuccess) break;
           }
           DevOp l = d;  // low-precision products for the others
@@ -392,13 +414,13 @@ struct ndrho_ctx {
           l.a += nhi * l.sa, l.b += nhi * l.sb, l.c += nhi * l.sc;
           if (op.flags & (G_BETA | G_EXTC0)) l.c0 += nhi * l.sc0;
           timed(l.bf3 ? NDRHO_K_GEMM_BF16X3 : NDRHO_K_GEMM_F32, op.flops * (nb - nhi),
-                [&] { e = launch_gemm(l, stream); });
+                [&] { e = launch_gemm(l, st); });
           break;
         }
         case OP_COPY:
           d.copy = S.copy + op.begin;
           d.copy_tiles = S.copy_tiles + op.tile_begin;
-          timed(NDRHO_K_COPY, 0.0, [&] { e = launch_copy(d, stream); });
+          timed(NDRHO_K_COPY, 0.0, [&] { e = launch_copy(d, st); });
           break;
         case OP_GATHER:
           d.gat = S.gat + op.begin;
@@ -407,7 +429,7 @@ struct ndrho_ctx {
           d.nhi = nhi;
           d.gat_out32 = guu32[op.depth];
           d.gat_in32 = op.depth > 0 ? guu32[op.depth - 1] : 0;
-          timed(NDRHO_K_GATHER, 0.0, [&] { e = launch_gather(d, stream); });
+          timed(NDRHO_K_GATHER, 0.0, [&] { e = launch_gather(d, st); });
           break;
       }
       if (e != hipSuccess) fail(NDRHO_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -425,10 +447,16 @@ struct ndrho_ctx {
     }
     cur_op = -1;
     cur_depth = -1;
-    hipError_t ea = hipSuccess;
-    timed(NDRHO_K_ACCUM, 0.0,
-          [&] { ea = launch_accum(S.acc_slot, P.nnz, bufs[BUF_PANEL], P.panel_total, w, nb, acc, stream); });
-    HIP_OK(ea);
+  }
+
+  // Create the first `k` further streams and their events on first use.
+  void ensure_side(int k) {
+    if (!ev_fork) HIP_OK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    for (int i = 0; i < k; ++i) {
+      if (side[i]) continue;
+      HIP_OK(hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking));
+      HIP_OK(hipEventCreateWithFlags(&ev_join[i], hipEventDisableTiming));
+    }
   }
 
   // Full weighted sum over the structure's shifts into `acc` (sorted order).
@@ -445,7 +473,36 @@ struct ndrho_ctx {
       for (int p0 = 0; p0 < n; p0 += nb) {
         const int cnt = std::min(nb, n - p0);
         const int nhi = std::max(0, std::min(cnt, n_hi - p0));
-        run_pass(S, cnt, alpha + p0, astride, w + p0, hcoef, spd_check, nhi);
+        if (opt.split_streams > 0 && !prof && nhi > 0 && nhi < cnt) {
+          // the FP64 poles and the low-precision poles (in split_streams
+          // parts) as independent launch chains: launches that leave compute
+          // units idle (small fronts, memory-bound steps) overlap work of the
+          // other chains
+          const int parts = std::min(opt.split_streams, cnt - nhi);
+          ensure_side(parts);
+          HIP_OK(hipEventRecord(ev_fork, stream));
+          for (int i = 0; i < parts; ++i) HIP_OK(hipStreamWaitEvent(side[i], ev_fork, 0));
+          run_pass(S, cnt, 0, nhi, alpha + p0, astride, hcoef, spd_check, nhi, side[0]);
+          for (int i = 0; i < parts; ++i) {
+            const int q0 = nhi + static_cast<int>(int64_t(cnt - nhi) * i / parts);
+            const int q1 = nhi + static_cast<int>(int64_t(cnt - nhi) * (i + 1) / parts);
+            run_pass(S, cnt, q0, q1 - q0, alpha + p0 + q0, astride, hcoef, spd_check, 0, i == 0 ? stream : side[i]);
+          }
+          for (int i = 0; i < parts; ++i) {
+            HIP_OK(hipEventRecord(ev_join[i], side[i]));
+            HIP_OK(hipStreamWaitEvent(stream, ev_join[i], 0));
+          }
+        } else {
+          run_pass(S, cnt, 0, cnt, alpha + p0, astride, hcoef, spd_check, nhi, stream);
+        }
+        // pole sum over the batch, in shift order
+        double2* bufs[BUF_COUNT];
+        int64_t strides[BUF_COUNT];
+        layout(P, cnt, bufs, strides);
+        hipError_t ea = hipSuccess;
+        timed(NDRHO_K_ACCUM, 0.0,
+              [&] { ea = launch_accum(S.acc_slot, P.nnz, bufs[BUF_PANEL], P.panel_total, w + p0, cnt, acc, stream); });
+        HIP_OK(ea);
       }
     };
     if (!opt.use_graph || prof) {
@@ -685,6 +742,7 @@ int ndrho_default_options(ndrho_options* opt) {
   opt->use_graph = 1;
   opt->gemm_variant = -1;
   opt->fp64_small_tiles = -1;
+  opt->split_streams = 1;
   return NDRHO_OK;
 }
 
@@ -706,6 +764,8 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
     if (c->opt.fp64_poles < 0 || c->opt.fp64_far_poles < 0 || !(c->opt.fp64_pole_im >= 0.0))
       fail(NDRHO_EINVAL, "invalid FP64 pole rule");
     if (c->opt.fp64_small_tiles < -1 || c->opt.fp64_small_tiles > 1) fail(NDRHO_EINVAL, "invalid fp64_small_tiles");
+    if (c->opt.split_streams < 0 || c->opt.split_streams > ndrho_ctx::kMaxChains)
+      fail(NDRHO_EINVAL, "invalid split_streams");
     if (c->opt.gemm_variant < -1 || c->opt.gemm_variant >= V_COUNT ||
         (c->opt.gemm_variant >= 0 && !variant_allowed(c->opt.precision, c->opt.gemm_variant)))
       fail(NDRHO_EINVAL, "invalid gemm_variant for this precision");

@@ -460,6 +460,33 @@ def test_graph_replay_matches_plain_launches():
             c1.density_matrix(other)
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_split_streams_identical(use_graph):
+    # the FP64 poles and parts of the low-precision ones on further streams
+    # run the same kernels per pole as one launch chain: results must be
+    # bit-identical, over pole batches that hold only FP64 poles, both kinds,
+    # or only low ones, on replays of the captured graph, and for a
+    # structure batch
+    import paper_1005_0088_amd as nd
+    a = lattice((9, 8, 7), "nn", 45)
+    b = lattice((12, 11), "nn", 46)
+    out = {}
+    for split in (0, 1, 3):
+        with nd.Context(0, precision="mixed_bf16x3", pole_batch=12, fp64_poles=6, fp64_far_poles=4,
+                        use_graph=use_graph, split_streams=split) as c:
+            sa, sb = _register(c, a), _register(c, b)
+            c.set_poles(sa, 0.05, BETA, 40)
+            c.set_poles(sb, 0.0, BETA, 40)
+            reps = [c.density_matrix(sa) for _ in range(3)]
+            for r in reps[1:]:
+                assert np.array_equal(r, reps[0])
+            out[split] = (reps[0], c.density_matrix_batch([sa, sb]))
+    for split in (1, 3):
+        assert np.array_equal(out[split][0], out[0][0])
+        for x, y in zip(out[split][1], out[0][1]):
+            assert np.array_equal(x, y)
+
+
 def test_autotune_keeps_accuracy_and_caches(tmp_path):
     import paper_1005_0088_amd as nd
     sysd = lattice((10, 9, 8), "nn", 44)
