@@ -90,7 +90,8 @@ typedef struct {
   int32_t split_streams; /* mixed mode, 0-4: k >= 1 (default 1) runs the FP64 poles of a pass and its
                             low-precision poles, divided into k parts, as k + 1 independent launch chains
                             on further streams that the context creates (default priority), joined back
-                            before the pole sum; 0 runs one chain.  Results are identical either way.
+                            before the pole sum, in passes of at least 1e10 modelled flops (smaller ones
+                            run one chain); 0 runs one chain.  Results are identical either way.
                             Profiling (ndrho_profile, ndrho_autotune) always runs one chain */
 } ndrho_options;
 
@@ -189,6 +190,8 @@ typedef struct {
   int64_t launches_per_pass;       /* kernel launches of one pass over a pole batch */
   int32_t n_fp64_poles;            /* leading shifts run with FP64 front updates */
   int32_t precision;               /* the context's precision mode */
+  int32_t split_passes;            /* passes of the structure's last evaluation that ran as several
+                                      launch chains (split_streams) */
 } ndrho_stats_t;
 
 int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out);

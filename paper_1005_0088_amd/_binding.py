@@ -36,7 +36,7 @@ class Stats(C.Structure):
                 ("flops_exec_per_pole", C.c_double), ("bytes_per_pole", C.c_double),
                 ("factor_bytes_per_pole", C.c_double), ("workspace_bytes", C.c_double),
                 ("last_ms", C.c_double), ("launches_per_pass", C.c_int64), ("n_fp64_poles", C.c_int32),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("split_passes", C.c_int32)]
 
 
 _P = C.c_void_p

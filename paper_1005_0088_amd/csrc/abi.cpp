@@ -36,6 +36,7 @@ T* upload(const std::vector<T>& v, hipStream_t st) {
 
 struct DevStruct {
   Plan plan;
+  int32_t split_passes = 0;  // passes of the last recorded evaluation run as several chains
   std::vector<void*> allocs;
   double *h = nullptr, *s = nullptr, *m0 = nullptr;
   GemmProb* gemm = nullptr;
@@ -449,6 +450,12 @@ struct ndrho_ctx {
     cur_depth = -1;
   }
 
+  // Passes of less work than this run as one chain: there the fork and join
+  // cost more than the chains overlap (measured: 0.1 ms lost on a 256-site
+  // chain with 4 orbitals per site and 60 poles, 5e8 flops per pass; 1.4 ms
+  // gained on a 64 x 64-site square lattice with 4 orbitals, 3e11 flops).
+  static constexpr double kSplitMinFlops = 1e10;
+
   // Create the first `k` further streams and their events on first use.
   void ensure_side(int k) {
     if (!ev_fork) HIP_OK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
@@ -470,15 +477,17 @@ struct ndrho_ctx {
     last_batch = nb;
     auto record = [&] {
       HIP_OK(launch_init_acc(S.m0, P.nnz, add_m0 ? 1 : 0, acc, status, stream));
+      S.split_passes = 0;
       for (int p0 = 0; p0 < n; p0 += nb) {
         const int cnt = std::min(nb, n - p0);
         const int nhi = std::max(0, std::min(cnt, n_hi - p0));
-        if (opt.split_streams > 0 && !prof && nhi > 0 && nhi < cnt) {
+        if (opt.split_streams > 0 && !prof && nhi > 0 && nhi < cnt && P.flops_exec * cnt >= kSplitMinFlops) {
           // the FP64 poles and the low-precision poles (in split_streams
           // parts) as independent launch chains: launches that leave compute
           // units idle (small fronts, memory-bound steps) overlap work of the
           // other chains
           const int parts = std::min(opt.split_streams, cnt - nhi);
+          ++S.split_passes;
           ensure_side(parts);
           HIP_OK(hipEventRecord(ev_fork, stream));
           for (int i = 0; i < parts; ++i) HIP_OK(hipStreamWaitEvent(side[i], ev_fork, 0));
@@ -933,7 +942,6 @@ int ndrho_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_
                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
     }
     HIP_OK(hipStreamSynchronize(ctx->stream));
-    ctx->last_batch = ctx->last_batch;
     ctx->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   });
 }
@@ -1054,6 +1062,7 @@ int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out) {
     out->last_ms = c->last_ms;
     out->launches_per_pass = static_cast<int64_t>(P.upward.size() + P.downward.size() + 1);
     out->n_fp64_poles = ds.n_hi;
+    out->split_passes = ds.split_passes;
     out->precision = c->opt.precision;
   });
 }

@@ -468,11 +468,14 @@ def test_split_streams_identical(use_graph):
     # or only low ones, on replays of the captured graph, and for a
     # structure batch
     import paper_1005_0088_amd as nd
-    a = lattice((9, 8, 7), "nn", 45)
+    # (40 poles, 16 of them FP64, 12 per pass: FP64 only, 4 + 8, low only,
+    # low only; passes of this lattice are above the library's minimum work
+    # for a split)
+    a = lattice((12, 11, 10), "nn", 45)
     b = lattice((12, 11), "nn", 46)
     out = {}
     for split in (0, 1, 3):
-        with nd.Context(0, precision="mixed_bf16x3", pole_batch=12, fp64_poles=6, fp64_far_poles=4,
+        with nd.Context(0, precision="mixed_bf16x3", pole_batch=12, fp64_poles=8, fp64_far_poles=8,
                         use_graph=use_graph, split_streams=split) as c:
             sa, sb = _register(c, a), _register(c, b)
             c.set_poles(sa, 0.05, BETA, 40)
@@ -480,6 +483,9 @@ def test_split_streams_identical(use_graph):
             reps = [c.density_matrix(sa) for _ in range(3)]
             for r in reps[1:]:
                 assert np.array_equal(r, reps[0])
+            assert c.stats(sa)["split_passes"] == (1 if split else 0)
+            c.density_matrix(sb)   # too little work per pass for a split
+            assert c.stats(sb)["split_passes"] == 0
             out[split] = (reps[0], c.density_matrix_batch([sa, sb]))
     for split in (1, 3):
         assert np.array_equal(out[split][0], out[0][0])
