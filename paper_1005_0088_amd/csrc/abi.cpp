@@ -532,6 +532,7 @@ struct ndrho_ctx {
     if (!S.gexec || key != S.gkey) {
       if (S.gexec) HIP_OK(hipGraphExecDestroy(S.gexec));
       S.gexec = nullptr;
+      if (opt.split_streams > 0) ensure_side(opt.split_streams);  // streams and events exist before the capture
       HIP_OK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
       try {
         record();
