@@ -32,6 +32,31 @@ def test_every_declared_symbol_is_exported():
     assert names == declared
 
 
+def test_default_options_and_struct_layouts():
+    # the ctypes mirrors of ndrho_options and ndrho_stats_t follow the
+    # header field by field; the library's defaults are the documented ones
+    import ctypes
+    with open(os.path.join(ROOT, "include", "ndrho.h")) as f:
+        hdr = f.read()
+    for cname, mirror in (("ndrho_options", nd._binding.Options), ("ndrho_stats_t", nd._binding.Stats)):
+        body = re.search(r"typedef struct \{((?:(?!typedef).)*?)\} %s;" % cname, hdr, re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = []
+        for decl in body.split(";"):
+            m = re.match(r"\s*(int32_t|int64_t|double)\s+(.*)", decl.strip())
+            if m:
+                fields += [(v.strip(), m.group(1)) for v in m.group(2).split(",")]
+        ctype = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
+        assert [(n, ctype[t]) for n, t in fields] == list(mirror._fields_), cname
+    lib = nd.load_library()
+    opt = nd._binding.Options()
+    assert lib.ndrho_default_options(ctypes.byref(opt)) == 0
+    want = {"leaf_rows": 32, "precision": 0, "pole_batch": 0, "mem_fraction": 0.8, "verbose": 0, "fp64_poles": 8,
+            "fp64_pole_im": 0.05, "fp64_far_poles": 8, "use_graph": 1, "gemm_variant": -1, "fp64_small_tiles": -1,
+            "split_streams": 1}
+    assert {k: getattr(opt, k) for k, _ in opt._fields_} == want
+
+
 @pytest.mark.parametrize("n_poles", [1, 2, 5, 60, 80, 100])
 def test_library_poles_match_oracle(n_poles):
     z, r = nd.cf_poles(n_poles)
