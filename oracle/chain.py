@@ -8,6 +8,7 @@ generalized eigenvalues of Eq. (2) are eps_k = (a + 2 b c_k)/(1 + 2 s c_k), the
 S-normalised eigenvectors are phi_k / sqrt(1 + 2 s c_k), and
 
   rho_ij  = 2 sum_k f(beta(eps_k - mu)) phi_k(i) phi_k(j) / (1 + 2 s c_k)   (Eq. (5))
+  e_ij    = 2 sum_k eps_k f(beta(eps_k - mu)) phi_k(i) phi_k(j) / (1 + 2 s c_k)   (Eq. (10))
   G(z)_ij = sum_k phi_k(i) phi_k(j) / ((1 + 2 s c_k)(z - eps_k))           (Eq. (6))
 
 The block form takes 4x4 symmetric matrices E, V, W that commute (built from
@@ -48,6 +49,15 @@ def chain_rho(n, a, b, s, mu, beta):
     ck, phi = chain_modes(n)
     eps = (a + 2.0 * b * ck) / (1.0 + 2.0 * s * ck)
     occ = 2.0 * fermi(beta * (eps - mu)) / (1.0 + 2.0 * s * ck)
+    return (phi * occ[None, :]) @ phi.T
+
+
+def chain_edm(n, a, b, s, mu, beta):
+    """Full n x n energy density matrix of the scalar chain (Eq. (10), first line):
+    e_ij = 2 sum_k eps_k f(beta(eps_k - mu)) phi_k(i) phi_k(j) / (1 + 2 s c_k)."""
+    ck, phi = chain_modes(n)
+    eps = (a + 2.0 * b * ck) / (1.0 + 2.0 * s * ck)
+    occ = 2.0 * eps * fermi(beta * (eps - mu)) / (1.0 + 2.0 * s * ck)
     return (phi * occ[None, :]) @ phi.T
 
 

@@ -9,6 +9,11 @@ Definitions followed (paper Sec. II):
   Eq. (8)   rho = M0 + Im(-(4i/beta) sum_p G(alpha_p) R_p),
             alpha_p = mu + i z_p/beta.  M0 is the zeroth moment of G, whose
             exact value is S^{-1} (the constant 1/2 of Eq. (7) times spin 2).
+  Eq. (10)  e = -(2/pi) Im int E G(E+i0) f((E-mu)/kT) dE, the energy density
+            matrix: with Eq. (9) e = 2 C diag(eps f(beta(eps-mu))) C^T; its pole
+            form is e = M1 + kappa M0 + Im(-(4i/beta) sum_p G(alpha_p) R_p alpha_p)
+            with kappa = (4/beta) sum_p R_p (Eq. (11)) and M1 the first moment of
+            G, exactly S^{-1} H S^{-1} = C diag(eps) C^T (G(Z) = sum_k M_k Z^-(k+1)).
 
 All routines are dense, O(N^3), and meant for N up to a few thousand in
 tests (larger N only in one-off golden-value scripts).
@@ -84,6 +89,27 @@ def rho_cf_pattern(eps, c, mu, beta, n_poles, rows, cols):
     return spectral_on_pattern(c, 2.0 * occ, rows, cols)
 
 
+def edm_exact_pattern(eps, c, mu, beta, rows, cols):
+    """e_ij = 2 sum_nu eps_nu f(beta(eps_nu - mu)) C_i,nu C_j,nu (Eq. (10), first line, with Eq. (9))."""
+    return spectral_on_pattern(c, 2.0 * eps * fermi(beta * (eps - mu)), rows, cols)
+
+
+def edm_cf_pattern(eps, c, mu, beta, n_poles, rows, cols):
+    """``edm_exact_pattern`` with f replaced by its N_p-pole truncation f_M.
+
+    This is what the finite pole sum of Eq. (10) reaches exactly (up to
+    rounding): each eigenvalue weighted by eps f_M(beta(eps - mu)).
+    """
+    z, r = cf_poles(n_poles)
+    occ = fermi_pole_form(beta * (eps - mu), z, r)
+    return spectral_on_pattern(c, 2.0 * eps * occ, rows, cols)
+
+
+def first_moment_pattern(eps, c, rows, cols):
+    """M1 = S^{-1} H S^{-1} = C diag(eps) C^T on the pattern (first moment of G, Eq. (12))."""
+    return spectral_on_pattern(c, np.asarray(eps, dtype=np.float64), rows, cols)
+
+
 def s_inverse_pattern(c, rows, cols):
     """M0 = S^{-1} = C C^T on the pattern (the Z -> infinity limit of Z G(Z))."""
     return spectral_on_pattern(c, np.ones(c.shape[1]), rows, cols)
@@ -110,6 +136,30 @@ def rho_poles_dense(h, s, mu, beta, n_poles, rows, cols):
         g = green_dense(h, s, mu + 1j * zp / beta)
         rho += (-(4.0 / beta) * rp) * g[rows, cols].real
     return rho
+
+
+def edm_poles_dense(h, s, mu, beta, n_poles, rows, cols):
+    """e on the pattern from the pole form of Eq. (10) with dense matrices.
+
+    M0 = S^{-1} and M1 = S^{-1} H S^{-1} by dense products, kappa =
+    (4/beta) sum_p R_p (Eq. (11)), and per pole the term
+    Im(-(4i/beta) G R_p alpha_p) = w_p Re(alpha_p G(alpha_p)) with
+    w_p = -(4/beta) R_p, G from a dense complex inverse.  Independent of
+    ``eigen``.
+    """
+    z, r = cf_poles(n_poles)
+    sd = to_dense(s)
+    hd = to_dense(h)
+    rows = np.asarray(rows)
+    cols = np.asarray(cols)
+    sinv = np.linalg.inv(sd)
+    kappa = (4.0 / beta) * float(np.sum(r))
+    e = (sinv @ hd @ sinv)[rows, cols] + kappa * sinv[rows, cols]
+    for zp, rp in zip(z, r):
+        alpha = mu + 1j * zp / beta
+        g = green_dense(h, s, alpha)
+        e += (-(4.0 / beta) * rp) * (alpha * g[rows, cols]).real
+    return e
 
 
 def trace_rho_s(rho_vals, s_vals):

@@ -174,6 +174,73 @@ def test_trace_rho_s_equals_electron_count():
     assert np.max(np.abs(rho_cf - rho)) < 1e-12
 
 
+# ------------------------------------------- energy density matrix (Eqs. (10)-(12))
+
+@pytest.mark.parametrize("n,a,b,s,mu", [(9, 0.2, -1.0, 0.1, 0.05), (40, -0.3, 0.7, -0.2, 0.4)])
+def test_edm_dense_eigen_matches_closed_form_chain(n, a, b, s, mu):
+    beta = 10.0
+    h, sm = chain.chain_matrices(n, a, b, s)
+    eps, c = dense.eigen(h, sm)
+    rows, cols = np.nonzero(np.ones((n, n)))
+    got = dense.edm_exact_pattern(eps, c, mu, beta, rows, cols)
+    ref = chain.chain_edm(n, a, b, s, mu, beta)[rows, cols]
+    assert np.max(np.abs(got - ref)) < 1e-13
+    # the first moment of G is S^-1 H S^-1 (the Z^-2 term of its expansion)
+    m1 = dense.first_moment_pattern(eps, c, rows, cols)
+    si = np.linalg.inv(sm)
+    assert np.max(np.abs(m1 - (si @ h @ si)[rows, cols])) < 1e-13
+
+
+@pytest.mark.parametrize("n,a,b,s,mu,n_poles", [(12, 0.2, -1.0, 0.1, 0.05, 60), (30, -0.3, 0.7, -0.2, 0.4, 80)])
+def test_edm_pole_sum_by_dense_inverse_matches_closed_form_chain(n, a, b, s, mu, n_poles):
+    # the pole form of Eq. (10) (first moment, kappa of Eq. (11) times M0,
+    # and w_p Re(alpha_p G(alpha_p))) with dense inverses reproduces the
+    # closed-form e; the kappa M0 term cancels most of the far poles' terms
+    # (sum_p |w_p| reaches 2.6e3 at 80 poles), which sets the tolerance
+    beta = 10.0
+    h, sm = chain.chain_matrices(n, a, b, s)
+    rows, cols = np.nonzero(np.abs(h) + np.abs(sm) > 0)
+    got = dense.edm_poles_dense(h, sm, mu, beta, n_poles, rows, cols)
+    ref = chain.chain_edm(n, a, b, s, mu, beta)[rows, cols]
+    assert np.max(np.abs(got - ref)) < 1e-11
+    # and so does the spectral form with the truncated fraction
+    eps, c = dense.eigen(h, sm)
+    cf = dense.edm_cf_pattern(eps, c, mu, beta, n_poles, rows, cols)
+    assert np.max(np.abs(cf - ref)) < 1e-12
+
+
+def test_edm_is_s_inverse_h_rho_and_traces_to_band_energy():
+    # H C = S C eps with C^T S C = I gives e = S^-1 H rho for the full
+    # matrices, and Tr(e S) = 2 sum_nu eps_nu f_nu (needs e only on the
+    # pattern of S)
+    sysd, h, s, rows, cols = _small_lattice((4, 3, 2), "nn2", 12)
+    beta, n = 10.0, sysd["n"]
+    eps, c = dense.eigen(h, s)
+    mu = dense.mu_for_count(eps, beta, float(n))
+    ii, jj = np.nonzero(np.ones((n, n)))
+    rho_full = dense.rho_exact_pattern(eps, c, mu, beta, ii, jj).reshape(n, n)
+    e_full = dense.edm_exact_pattern(eps, c, mu, beta, ii, jj).reshape(n, n)
+    ref = np.linalg.solve(s.toarray(), h.toarray() @ rho_full)
+    assert np.max(np.abs(e_full - ref)) < 1e-11
+    e = dense.edm_exact_pattern(eps, c, mu, beta, rows, cols)
+    band = 2.0 * float(np.sum(eps * poles.fermi(beta * (eps - mu))))
+    assert dense.trace_rho_s(e, sysd["s"]) == pytest.approx(band, abs=1e-10)
+    e_poles = dense.edm_poles_dense(h, s, mu, beta, 80, rows, cols)
+    assert np.max(np.abs(e_poles - e)) < 1e-10
+
+
+def test_edm_with_h_proportional_to_s():
+    # H = c S: every eigenvalue is c, so e = c rho = 2 c f(beta(c - mu)) S^-1
+    sysd, _, s, rows, cols = _small_lattice((3, 3, 2), "nn", 13)
+    beta, mu, cval, n_poles = 10.0, 0.05, 0.37, 60
+    h = cval * s
+    e = dense.edm_poles_dense(h, s, mu, beta, n_poles, rows, cols)
+    rho = dense.rho_poles_dense(h, s, mu, beta, n_poles, rows, cols)
+    assert np.max(np.abs(e - cval * rho)) < 1e-11
+    want = 2.0 * cval * poles.fermi(beta * (cval - mu)) * np.linalg.inv(s.toarray())[rows, cols]
+    assert np.max(np.abs(e - want)) < 1e-11
+
+
 def test_s_inverse_from_eigenvectors():
     sysd, h, s, rows, cols = _small_lattice((3, 3, 2), "nn", 2)
     eps, c = dense.eigen(h, s)
