@@ -95,8 +95,9 @@ def golden_error(name, rho, mu, n_poles):
 
 
 def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_poles, autotune=True, gemm_variant=-1,
-             tune_cache=None, split_streams=1):
-    """Time one precision form on one system (density_matrix) or several
+             tune_cache=None, split_streams=1, energy=False):
+    """Time one precision form on one system (density_matrix, or with
+    energy=True energy_density_matrix: rho and e) or several
     (density_matrix_batch: one schedule); returns (timing dict, rho list)."""
     variant = gemm_variant if precision != "fp64" else -1
     ctx = nd.Context(0, precision=precision, fp64_poles=fp64_poles, fp64_far_poles=fp64_poles, gemm_variant=variant,
@@ -109,15 +110,23 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
         sids.append(sid)
     if precision != "fp64" and autotune and variant < 0:
         ctx.autotune(sids, tune_cache)   # per-launch GEMM variant (untimed set-up, like the plan)
-    setup_s = time.time() - t0
     outs = [ctx.device_buffer(int(sysd["row_ptr"][-1])) for sysd in systems]
     multi = len(systems) > 1
+    e_out = ctx.device_buffer(int(systems[0]["row_ptr"][-1])) if energy else None
 
     def step():
         if multi:
             ctx.density_matrix_batch(sids, outs)
+        elif energy:
+            ctx.energy_density_matrix(sids[0], outs[0], e_out)
         else:
             ctx.density_matrix(sids[0], outs[0])
+
+    if energy:
+        if multi:
+            raise SystemExit("--energy runs on single-structure workloads")
+        step()   # first call: the first moment M1 of the structure (set-up, like M0)
+    setup_s = time.time() - t0
 
     for i in range(warmup):
         step()
@@ -137,8 +146,12 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
     rho = [o.numpy() for o in outs]
     for o in outs:
         o.free()
+    e_vals = None
+    if energy:
+        e_vals = e_out.numpy()
+        e_out.free()
     ctx.close()
-    res = {"precision": precision, "setup_s": setup_s, "ms_per_step": 1e3 * dt / steps,
+    res = {"precision": precision, "setup_s": setup_s, "ms_per_step": 1e3 * dt / steps, "e": e_vals,
            "poles_per_s": n_poles * steps / dt, "stats": st, "prof": prof,
            "ms_by_depth": {k: [round(float(x), 3) for x in v] for k, v in by_depth.items() if v.any()},
            "flops_model_per_step": n_poles * sum(x["flops_per_pole"] for x in st)}
@@ -166,6 +179,8 @@ def main():
     ap.add_argument("--gemm-variant", type=int, default=-1,
                     help="force one GEMM variant on every low-precision front update (see ndrho_options)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--energy", action="store_true",
+                    help="time energy_density_matrix (rho and the energy density matrix e of the same poles)")
     ap.add_argument("--split-streams", type=int, default=1,
                     help="mixed forms: launch chains beside the main one (0 = one chain; see ndrho_options)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -209,24 +224,27 @@ def main():
     # the plain FP64 form is the complex128 reference of the error
     r64 = rho64 = None
     if args.forms != "head" or args.precision == "fp64":
-        r64, rho64 = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, "fp64", 0)
+        r64, rho64 = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, "fp64", 0,
+                              energy=args.energy)
     others = {}
     if args.forms == "all":
         for form in ("mixed_fp32", "mixed_bf16x3"):
             if form != args.precision:
                 r, rr = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, form, args.fp64_poles,
-                                 not args.no_autotune, -1, args.tune_cache, args.split_streams)
+                                 not args.no_autotune, -1, args.tune_cache, args.split_streams, args.energy)
                 others[form] = {
                     "poles_per_s": r["poles_per_s"], "ms_per_step": r["ms_per_step"],
                     "kernel_ms": {k: round(v["ms"], 3) for k, v in r["prof"].items()},
                     "max_abs_err_vs_complex128": max(float(np.max(np.abs(a - b))) for a, b in zip(rr, rho64)),
-                    "max_abs_err_vs_oracle_sample": golden_error(name, rr[0], mu, n_poles) if len(rr) == 1 else None}
+                    "max_abs_err_vs_oracle_sample": golden_error(name, rr[0], mu, n_poles) if len(rr) == 1 else None,
+                    "max_abs_err_e_vs_complex128": (float(np.max(np.abs(r["e"] - r64["e"]))) if args.energy
+                                                    else None)}
     if args.precision == "fp64":
         head, rho = r64, rho64
     else:
         head, rho = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, args.precision,
                              args.fp64_poles, not args.no_autotune, args.gemm_variant, args.tune_cache,
-                             args.split_streams)
+                             args.split_streams, args.energy)
     st, prof = head["stats"][0], head["prof"]
     # dominant kernel: the FP64 front GEMMs in the FP64 form, the FP32-product
     # front GEMMs in the mixed form (peak of their own arithmetic)
@@ -268,6 +286,11 @@ def main():
         "max_abs_err_vs_complex128": (max(float(np.max(np.abs(a - b))) for a, b in zip(rho, rho64))
                                       if rho64 is not None else None),
         "max_abs_err_vs_oracle_sample": golden_error(name, rho[0], mu, n_poles) if len(rho) == 1 else None,
+        "energy_density": None if not args.energy else {
+            "computed": "rho and e (Eq. (10)) from the same poles in every timed step",
+            "max_abs_e": float(np.max(np.abs(head["e"]))),
+            "max_abs_err_e_vs_complex128": (float(np.max(np.abs(head["e"] - r64["e"])))
+                                            if r64 is not None and head is not r64 else None)},
         "fp64_form": None if r64 is None else {
             "poles_per_s": r64["poles_per_s"], "ms_per_step": r64["ms_per_step"],
             "tflops_model": r64["flops_model_per_step"] / (r64["ms_per_step"] * 1e-3) / 1e12,

@@ -148,6 +148,24 @@ int ndrho_set_shifts(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double*
  * Errors: ESTATE (no poles set), ESINGULAR, EDEVICE, ENOMEM. */
 int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int32_t on_device);
 
+/* Energy density matrix e on the pattern (Sec. II A, Eqs. (10)-(11)) together
+ * with rho from the same selected Green functions:
+ *   e = M1 + kappa M0 + sum_p Im(-(4i/beta) G(alpha_p) R_p alpha_p),
+ *   kappa = (4/beta) sum_p R_p,
+ * with M0 = S^-1 and M1 = S^-1 H S^-1 (the zeroth and first moments of G,
+ * Eq. (12)) on the pattern.  M1 is computed on the first call for the
+ * structure (and after ndrho_update_values) from G at two shifts far up the
+ * imaginary axis (FP64, Richardson-extrapolated; relative error about 1e-12
+ * for Hamiltonians of a few eV).  The shifts must be the poles of
+ * ndrho_set_poles.  rho_out and e_out: nnz values each in the caller's CSR
+ * order, host pointers (on_device = 0; the call synchronises) or device
+ * pointers on the context's device (on_device = 1).  In the mixed precision
+ * forms e carries the low-precision error of the mid-range poles weighted by
+ * |alpha_p|, larger than rho's.
+ * Errors: EINVAL (NULL output), ESTATE (no set_poles), ESINGULAR, EDEVICE, ENOMEM. */
+int ndrho_energy_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, double* e_out,
+                                int32_t on_device);
+
 /* rho for k distinct structures in one schedule: their front trees are
  * joined into one forest (planned, uploaded and given its M0 on the first
  * call for this list of ids, then cached), so every launch works on the

@@ -55,6 +55,7 @@ SIGNATURES = [
     ("ndrho_set_poles", C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32]),
     ("ndrho_set_shifts", C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _DP, C.c_int32]),
     ("ndrho_density_matrix", C.c_int, [_P, C.c_int32, _P, C.c_int32]),
+    ("ndrho_energy_density_matrix", C.c_int, [_P, C.c_int32, _P, _P, C.c_int32]),
     ("ndrho_density_matrix_batch", C.c_int, [_P, _I32P, C.c_int32, C.POINTER(_P), C.c_int32]),
     ("ndrho_autotune", C.c_int, [_P, _I32P, C.c_int32, C.c_char_p]),
     ("ndrho_stats", C.c_int, [_P, C.c_int32, C.POINTER(Stats)]),
@@ -302,6 +303,24 @@ class Context:
             raise ValueError("out must be a numpy array or a DeviceBuffer of nnz elements from this context")
         self._check(self._lib.ndrho_density_matrix(self._h, int(sid), C.c_void_p(out.ptr), 1))
         return out
+
+    def energy_density_matrix(self, sid, rho_out=None, e_out=None):
+        """(rho, e) on the pattern in CSR order (see ndrho_energy_density_matrix).
+        Outputs: None (new numpy arrays), float64 numpy arrays, or DeviceBuffers of nnz elements."""
+        nnz = self._nnz[int(sid)]
+        outs = [np.empty(nnz, dtype=np.float64) if o is None else o for o in (rho_out, e_out)]
+        on_dev = [isinstance(o, DeviceBuffer) for o in outs]
+        if on_dev[0] != on_dev[1]:
+            raise ValueError("rho_out and e_out must both be numpy arrays or both DeviceBuffers")
+        for o in outs:
+            if on_dev[0]:
+                if o.ctx is not self or o.n != nnz:
+                    raise ValueError("each DeviceBuffer must hold nnz elements from this context")
+            elif o.dtype != np.float64 or o.size != nnz or not o.flags.c_contiguous:
+                raise ValueError("each output must be a contiguous float64 array of nnz elements")
+        ptrs = [C.c_void_p(o.ptr) if on_dev[0] else o.ctypes.data_as(C.c_void_p) for o in outs]
+        self._check(self._lib.ndrho_energy_density_matrix(self._h, int(sid), ptrs[0], ptrs[1], int(on_dev[0])))
+        return outs[0], outs[1]
 
     def density_matrix_batch(self, sids, outs=None):
         """rho of several structures in one schedule (see ndrho_density_matrix_batch).

@@ -39,6 +39,10 @@ struct DevStruct {
   int32_t split_passes = 0;  // passes of the last recorded evaluation run as several chains
   std::vector<void*> allocs;
   double *h = nullptr, *s = nullptr, *m0 = nullptr;
+  // first moment of G, S^-1 H S^-1 on the pattern (computed on first use)
+  double* m1 = nullptr;
+  bool m1_valid = false;
+  double h_inf = 0.0;  // max_i sum_j |H_ij|
   GemmProb* gemm = nullptr;
   TileRef* gemm_tiles = nullptr;
   InvDesc* inv = nullptr;
@@ -59,8 +63,11 @@ struct DevStruct {
   int n_shifts = 0;
   int n_hi = 0;  // leading shifts evaluated with FP64 front updates
   bool add_m0 = true;
+  bool cf_poles = false;  // shifts are the continued-fraction poles of set_poles
+  double kappa = 0.0;     // (4/beta) sum_p R_p = -sum_p w_p (Eq. (11))
   double2* d_alpha = nullptr;
   double* d_w = nullptr;
+  double2* d_cw = nullptr;  // w_p alpha_p, the weights of the energy density matrix
   std::vector<double> w_host;  // weights as set (batch compatibility checks)
   // GEMM variant per program op (empty: default heuristic not yet applied)
   std::vector<int8_t> variant;
@@ -82,12 +89,25 @@ struct DevStruct {
     allocs.clear();
     if (d_alpha) (void)hipFree(d_alpha);
     if (d_w) (void)hipFree(d_w);
+    if (d_cw) (void)hipFree(d_cw);
     d_alpha = nullptr;
     d_w = nullptr;
+    d_cw = nullptr;
   }
 };
 
 thread_local std::string g_err;  // errors without a context (create, plan utilities)
+
+// max_i sum_j |A_ij| of a matrix on the plan's pattern (values in CSR order)
+double row_sum_norm(const Plan& P, const double* a) {
+  double mx = 0.0;
+  for (int64_t i = 0; i < P.n; ++i) {
+    double r = 0.0;
+    for (int64_t k = P.row_ptr[i]; k < P.row_ptr[i + 1]; ++k) r += std::fabs(a[k]);
+    mx = std::max(mx, r);
+  }
+  return mx;
+}
 
 enum { V_FP64 = 0, V_F32_64 = 1, V_F32_128 = 2, V_BF3_128 = 3, V_BF3_64 = 4, V_BF3S_128 = 5, V_BF3P_128 = 6, V_COUNT = 7 };
 
@@ -166,6 +186,10 @@ struct ndrho_ctx {
   double* acc = nullptr;
   double* outbuf = nullptr;
   int64_t acc_len = 0;
+  // energy density matrix accumulator and output staging (allocated on first use)
+  double* acc_e = nullptr;
+  double* outbuf_e = nullptr;
+  int64_t acc_e_len = 0;
   int* status = nullptr;
   double last_ms = 0;
   int last_batch = 0;
@@ -236,6 +260,8 @@ struct ndrho_ctx {
     if (ws) (void)hipFree(ws);
     if (acc) (void)hipFree(acc);
     if (outbuf) (void)hipFree(outbuf);
+    if (acc_e) (void)hipFree(acc_e);
+    if (outbuf_e) (void)hipFree(outbuf_e);
     if (status) (void)hipFree(status);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     for (int i = 0; i < kMaxChains; ++i) {
@@ -469,14 +495,17 @@ struct ndrho_ctx {
   // Full weighted sum over the structure's shifts into `acc` (sorted order).
   // The first n_hi shifts run with FP64 front updates, the rest in the
   // context's low precision; the sum is taken in shift order either way.
+  // With `edm`, the energy density matrix of the same shifts is summed
+  // beside rho into acc_e: M1 + kappa M0 + sum_p Re(c_p G_p), c_p = S.d_cw.
   void evaluate(DevStruct& S, const double2* alpha, int64_t astride, const double* w, int n, int n_hi, bool add_m0,
-                double hcoef, int spd_check) {
+                double hcoef, int spd_check, bool edm = false) {
     const Plan& P = S.plan;
     const int nb = batch_for(P, n);
     ensure_ws(P, nb);
     last_batch = nb;
     auto record = [&] {
       HIP_OK(launch_init_acc(S.m0, P.nnz, add_m0 ? 1 : 0, acc, status, stream));
+      if (edm) HIP_OK(launch_init_edm(S.m1, S.m0, S.kappa, P.nnz, acc_e, stream));
       S.split_passes = 0;
       for (int p0 = 0; p0 < n; p0 += nb) {
         const int cnt = std::min(nb, n - p0);
@@ -512,6 +541,11 @@ struct ndrho_ctx {
         timed(NDRHO_K_ACCUM, 0.0,
               [&] { ea = launch_accum(S.acc_slot, P.nnz, bufs[BUF_PANEL], P.panel_total, w + p0, cnt, acc, stream); });
         HIP_OK(ea);
+        if (edm)
+          timed(NDRHO_K_ACCUM, 0.0, [&] {
+            ea = launch_accum_edm(S.acc_slot, P.nnz, bufs[BUF_PANEL], P.panel_total, S.d_cw + p0, cnt, acc_e, stream);
+          });
+        HIP_OK(ea);
       }
     };
     if (!opt.use_graph || prof) {
@@ -528,7 +562,16 @@ struct ndrho_ctx {
     key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(n)));
     key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(n_hi)));
     key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>((add_m0 ? 1 : 0) | (spd_check ? 2 : 0) |
-                                                                      (hcoef != 0.0 ? 4 : 0))));
+                                                                      (hcoef != 0.0 ? 4 : 0) | (edm ? 8 : 0))));
+    if (edm) {
+      int64_t kbits;
+      static_assert(sizeof(kbits) == sizeof(S.kappa), "kappa bits");
+      std::memcpy(&kbits, &S.kappa, sizeof(kbits));
+      key.push_back(acc_e);
+      key.push_back(S.d_cw);
+      key.push_back(S.m1);
+      key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(kbits)));
+    }
     if (!S.gexec || key != S.gkey) {
       if (S.gexec) HIP_OK(hipGraphExecDestroy(S.gexec));
       S.gexec = nullptr;
@@ -584,6 +627,59 @@ struct ndrho_ctx {
     }
     (void)hipFree(da);
     (void)hipFree(dw);
+  }
+
+  // M1 = S^{-1} H S^{-1} on the pattern, the first moment of G (G(Z) =
+  // sum_k M_k Z^-(k+1), Eq. (12)).  From two shifts far up the imaginary
+  // axis: Re G(iR) = -M1/R^2 + M3/R^4 - ..., so f(R) = -R^2 Re G(iR) = M1 -
+  // M3/R^2 + ..., and (4 f(2R) - f(R))/3 = M1 + O(M5/R^4) (Richardson).
+  // R = 1e3 max(1e-300, |H|_inf) balances that remainder, O((|S^-1 H|/R)^4),
+  // against the rounding of Re G, O(u R |S^-1|) relative; both about 1e-12
+  // for lattice Hamiltonians of a few eV.  FP64 for both shifts.
+  void compute_m1(DevStruct& S) {
+    const Plan& P = S.plan;
+    if (!S.m1) {
+      if (hipMalloc(&S.m1, P.nnz * sizeof(double)) != hipSuccess) fail(NDRHO_ENOMEM, "M1 allocation failed");
+      S.allocs.push_back(S.m1);
+    }
+    if (S.h_inf == 0.0) {  // H = 0: M1 = 0
+      HIP_OK(hipMemsetAsync(S.m1, 0, P.nnz * sizeof(double), stream));
+      HIP_OK(hipStreamSynchronize(stream));
+      S.m1_valid = true;
+      return;
+    }
+    const double R = 1e3 * S.h_inf;
+    std::vector<double2> a = {make_double2(0.0, R), make_double2(0.0, 2.0 * R)};
+    std::vector<double> w = {R * R / 3.0, -16.0 * R * R / 3.0};
+    double2* da = upload(a, stream);
+    double* dw = upload(w, stream);
+    try {
+      evaluate(S, da, 0, dw, 2, 2, false, 1.0, 0);
+      int st[2];
+      read_status(st);
+      if (st[0]) fail(NDRHO_ESINGULAR, "a tiny pivot occurred in i R S - H (first moment of G)");
+      HIP_OK(hipMemcpyAsync(S.m1, acc, P.nnz * sizeof(double), hipMemcpyDeviceToDevice, stream));
+      HIP_OK(hipStreamSynchronize(stream));
+    } catch (...) {
+      (void)hipFree(da);
+      (void)hipFree(dw);
+      throw;
+    }
+    (void)hipFree(da);
+    (void)hipFree(dw);
+    S.m1_valid = true;
+  }
+
+  // Energy density matrix buffers of nnz entries.
+  void ensure_edm(int64_t nnz) {
+    if (nnz <= acc_e_len) return;
+    if (acc_e) HIP_OK(hipFree(acc_e));
+    if (outbuf_e) HIP_OK(hipFree(outbuf_e));
+    acc_e = outbuf_e = nullptr;
+    acc_e_len = 0;
+    if (hipMalloc(&acc_e, nnz * sizeof(double)) != hipSuccess || hipMalloc(&outbuf_e, nnz * sizeof(double)) != hipSuccess)
+      fail(NDRHO_ENOMEM, "energy density matrix buffers");
+    acc_e_len = nnz;
   }
 
   // Joined plan for a list of structures (built, uploaded and given its own
@@ -664,7 +760,7 @@ struct ndrho_ctx {
   }
 
   void set_shifts(DevStruct& S, const std::vector<double2>& alpha_in, const std::vector<double>& w_in,
-                  bool add_m0) {
+                  bool add_m0, bool cf) {
     // Mixed mode keeps in FP64 the fp64_poles shifts nearest the real axis,
     // the fp64_far_poles farthest from it, and any with |Im alpha| below
     // fp64_pole_im.  Those are moved to the front (stable order otherwise):
@@ -696,15 +792,28 @@ struct ndrho_ctx {
       for (int i = 0; i < n; ++i) hi += keep[i];
     }
     S.n_hi = hi;
+    // weights of the energy density matrix, c_p = w_p alpha_p, and
+    // kappa = (4/beta) sum_p R_p = -sum_p w_p (Eqs. (10), (11))
+    std::vector<double2> cw(alpha.size());
+    double kappa = 0.0;
+    for (size_t p = 0; p < alpha.size(); ++p) {
+      cw[p] = make_double2(w[p] * alpha[p].x, w[p] * alpha[p].y);
+      kappa -= w[p];
+    }
     if (S.d_alpha) HIP_OK(hipFree(S.d_alpha));
     if (S.d_w) HIP_OK(hipFree(S.d_w));
+    if (S.d_cw) HIP_OK(hipFree(S.d_cw));
     S.d_alpha = nullptr;
     S.d_w = nullptr;
+    S.d_cw = nullptr;
     S.d_alpha = upload(alpha, stream);
     S.d_w = upload(w, stream);
+    S.d_cw = upload(cw, stream);
     HIP_OK(hipStreamSynchronize(stream));
     S.n_shifts = static_cast<int>(alpha.size());
     S.add_m0 = add_m0;
+    S.cf_poles = cf;
+    S.kappa = kappa;
     S.w_host = w;
   }
 };
@@ -830,6 +939,7 @@ int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const
       std::vector<double> hv(H, H + P.nnz), sv(S, S + P.nnz);
       ds->h = ds->put(hv, st);
       ds->s = ds->put(sv, st);
+      ds->h_inf = row_sum_norm(P, H);
       upload_plan(*ds, st, ctx->opt.precision);
       HIP_OK(hipStreamSynchronize(st));
       ctx->compute_m0(*ds);
@@ -852,6 +962,8 @@ int ndrho_update_values(ndrho_ctx* ctx, int32_t struct_id, const double* H, cons
     HIP_OK(hipSetDevice(ctx->device));
     HIP_OK(hipMemcpyAsync(ds.h, H, P.nnz * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIP_OK(hipMemcpyAsync(ds.s, S, P.nnz * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    ds.h_inf = row_sum_norm(P, H);
+    ds.m1_valid = false;
     ctx->drop_unions();
     ctx->compute_m0(ds);
   });
@@ -872,7 +984,7 @@ int ndrho_set_poles(ndrho_ctx* ctx, int32_t struct_id, double mu, double beta, i
       w[p] = -(4.0 / beta) * r[p];          // Im(-(4i/beta) G R) = -(4/beta) R Re G
     }
     HIP_OK(hipSetDevice(ctx->device));
-    ctx->set_shifts(ds, a, w, true);
+    ctx->set_shifts(ds, a, w, true, true);
   });
 }
 
@@ -891,7 +1003,7 @@ int ndrho_set_shifts(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double*
       w[k] = weight[k];
     }
     HIP_OK(hipSetDevice(ctx->device));
-    ctx->set_shifts(ds, a, w, add_m0 != 0);
+    ctx->set_shifts(ds, a, w, add_m0 != 0, false);
   });
 }
 
@@ -912,6 +1024,35 @@ int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int
     if (st[0]) fail(NDRHO_ESINGULAR, "a zero, tiny or non-finite pivot occurred in alpha S - H");
     if (!on_device) {
       HIP_OK(hipMemcpyAsync(rho_out, ctx->outbuf, P.nnz * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_OK(hipStreamSynchronize(ctx->stream));
+    }
+    ctx->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  });
+}
+
+int ndrho_energy_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, double* e_out,
+                                int32_t on_device) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    DevStruct& ds = ctx->get(struct_id);
+    if (!rho_out || !e_out) fail(NDRHO_EINVAL, "rho_out and e_out are required");
+    if (ds.n_shifts < 1 || !ds.cf_poles) fail(NDRHO_ESTATE, "set_poles has not been called for this structure");
+    HIP_OK(hipSetDevice(ctx->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    const Plan& P = ds.plan;
+    ctx->ensure_edm(P.nnz);
+    if (!ds.m1_valid) ctx->compute_m1(ds);
+    ctx->evaluate(ds, ds.d_alpha, 0, ds.d_w, ds.n_shifts, ds.n_hi, ds.add_m0, 1.0, 0, true);
+    double* dst = on_device ? rho_out : ctx->outbuf;
+    double* dst_e = on_device ? e_out : ctx->outbuf_e;
+    HIP_OK(launch_scatter(ds.acc_entry, P.nnz, ctx->acc, dst, ctx->stream));
+    HIP_OK(launch_scatter(ds.acc_entry, P.nnz, ctx->acc_e, dst_e, ctx->stream));
+    int st[2];
+    ctx->read_status(st);
+    if (st[0]) fail(NDRHO_ESINGULAR, "a zero, tiny or non-finite pivot occurred in alpha S - H");
+    if (!on_device) {
+      HIP_OK(hipMemcpyAsync(rho_out, ctx->outbuf, P.nnz * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_OK(hipMemcpyAsync(e_out, ctx->outbuf_e, P.nnz * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
       HIP_OK(hipStreamSynchronize(ctx->stream));
     }
     ctx->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -55,5 +55,10 @@ hipError_t launch_accum(const int64_t* slot, int64_t count, const double2* panel
 hipError_t launch_init_acc(const double* m0, int64_t count, int add_m0, double* acc, int* status, hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
 hipError_t launch_scatter(const int32_t* entry, int64_t count, const double* acc, double* out, hipStream_t st);
+// energy density matrix (energy.hip): acc_e = m1 + kappa m0, then acc_e += sum_p Re(cw_p G_p)
+hipError_t launch_init_edm(const double* m1, const double* m0, double kappa, int64_t count, double* acc_e,
+                           hipStream_t st);
+hipError_t launch_accum_edm(const int64_t* slot, int64_t count, const double2* panel, int64_t ps,
+                            const double2* cw, int npoles, double* acc_e, hipStream_t st);
 
 }  // namespace ndrho

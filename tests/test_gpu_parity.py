@@ -114,6 +114,98 @@ def test_chain_closed_form(ctx):
     assert np.max(np.abs(got - ref)) < 1e-10
 
 
+# Tolerance of e in the FP64 form: the pole sum cancels kappa M0 (|kappa| =
+# sum_p |w_p| = 2.6e3 at 80 poles, beta = 10) to O(1), so rounding of order
+# u |kappa| |M0| ~ 1e-12 per entry, plus the first moment's extrapolation
+# (~1e-12 relative); the oracle's own pole form agrees with the closed form
+# to 3e-12.
+EDM_TOL = 5e-11
+
+
+def test_energy_density_matrix_chain_closed_form(ctx):
+    # e of Eq. (10) for the scalar chain against its closed form; the rho
+    # returned with it is the density_matrix result bit for bit
+    n, a, b, sv, mu = 300, 0.1, -1.0, 0.12, 0.05
+    hm, sm = chain.chain_matrices(n, a, b, sv)
+    rows, cols = np.nonzero(np.abs(hm) + np.abs(sm) > 0)
+    row_ptr = np.searchsorted(rows, np.arange(n + 1))
+    coords = np.stack([np.arange(n, dtype=float), np.zeros(n), np.zeros(n)], 1)
+    sid = ctx.set_structure(n, row_ptr, cols, hm[rows, cols], sm[rows, cols], coords)
+    ctx.set_poles(sid, mu, BETA, 60)
+    rho, e = ctx.energy_density_matrix(sid)
+    assert np.array_equal(rho, ctx.density_matrix(sid))
+    ref = chain.chain_edm(n, a, b, sv, mu, BETA)[rows, cols]
+    err = np.max(np.abs(e - ref))
+    print("edm chain err %.3e" % err)
+    assert err < EDM_TOL
+
+
+@pytest.mark.parametrize("dims,nb,n_poles", [((12, 10), "nn2", 80), ((6, 6, 7), "nn", 80), ((256,), "nn", 60)])
+def test_energy_density_matrix_against_dense_eigen_oracle(ctx, dims, nb, n_poles):
+    sysd = lattice(dims, nb, 70)
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    mu = dense.mu_for_count(eps, BETA, float(sysd["n"]))
+    sid = _register(ctx, sysd)
+    ctx.set_poles(sid, mu, BETA, n_poles)
+    rho, e = ctx.energy_density_matrix(sid)
+    ref_e = dense.edm_cf_pattern(eps, c, mu, BETA, n_poles, rows, cols)
+    ref_rho = dense.rho_cf_pattern(eps, c, mu, BETA, n_poles, rows, cols)
+    err = np.max(np.abs(e - ref_e))
+    print("edm %s err %.3e (max |e| %.2f)" % (dims, err, np.abs(ref_e).max()))
+    assert err < EDM_TOL
+    assert np.max(np.abs(rho - ref_rho)) < 1e-10
+
+
+def test_energy_density_matrix_h_proportional_to_s_and_update(ctx):
+    # H = c S gives e = c rho (M1 = c S^-1); after update_values with another
+    # H the first moment is recomputed
+    sysd = lattice((7, 6, 5), "nn", 71)
+    cval, mu = 0.37, 0.05
+    sid = ctx.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], cval * sysd["s"], sysd["s"], sysd["coords"])
+    ctx.set_poles(sid, mu, BETA, 60)
+    rho, e = ctx.energy_density_matrix(sid)
+    assert np.max(np.abs(e - cval * rho)) < 1e-11
+    ctx.update_values(sid, sysd["h"], sysd["s"])
+    rho2, e2 = ctx.energy_density_matrix(sid)
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    assert np.max(np.abs(e2 - dense.edm_cf_pattern(eps, c, mu, BETA, 60, rows, cols))) < EDM_TOL
+
+
+def test_energy_density_matrix_needs_poles(ctx):
+    import paper_1005_0088_amd as nd
+    sysd = lattice((4, 4), "nn", 72)
+    sid = _register(ctx, sysd)
+    with pytest.raises(nd.NdrhoError):
+        ctx.energy_density_matrix(sid)            # no shifts yet
+    ctx.set_shifts(sid, np.array([0.1 + 1.0j]), np.array([1.0]), add_m0=True)
+    with pytest.raises(nd.NdrhoError):
+        ctx.energy_density_matrix(sid)            # shifts not from set_poles
+    ctx.set_poles(sid, 0.0, BETA, 20)
+    rho, e = ctx.energy_density_matrix(sid)
+    assert np.all(np.isfinite(e))
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16x3"])
+def test_energy_density_matrix_mixed_forms(precision):
+    # the mixed forms against the FP64 form on the same input; e carries the
+    # low-precision error of the mid-range poles times |alpha_p|
+    import paper_1005_0088_amd as nd
+    sysd = lattice((14, 13, 12), "nn", 73)
+    out = {}
+    for prec in ("fp64", precision):
+        with nd.Context(0, precision=prec) as c:
+            sid = _register(c, sysd)
+            c.set_poles(sid, 0.0, BETA, 80)
+            out[prec] = c.energy_density_matrix(sid)
+    err_rho = np.max(np.abs(out[precision][0] - out["fp64"][0]))
+    err_e = np.max(np.abs(out[precision][1] - out["fp64"][1]))
+    print("mixed %s: rho err %.3e, e err %.3e" % (precision, err_rho, err_e))
+    assert err_rho < 1e-7
+    assert err_e < 1e-5
+
+
 @pytest.mark.parametrize("dims,nb,n_poles,coords", [((256,), "nn", 60, True), ((12, 10), "nn2", 80, True),
                                                     ((6, 6, 7), "nn", 80, True), ((10, 9), "nn", 40, False)])
 def test_rho_against_dense_eigen_oracle(ctx, dims, nb, n_poles, coords):
