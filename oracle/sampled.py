@@ -5,7 +5,8 @@ obtained by a sparse solve, M0 e_j = S^{-1} e_j likewise, and column j of rho
 follows from Eq. (8): rho e_j = S^{-1} e_j + sum_p w_p Re G(alpha_p) e_j with
 w_p = -(4/beta) R_p.  Restricted to the pattern rows of column j this is the
 exact density matrix up to the solver's rounding (sparse LU), or up to its
-tolerance (GMRES).
+tolerance (GMRES).  The energy density matrix of Eq. (10) follows from the
+same G columns (``rho_edm_columns``).
 """
 import numpy as np
 import scipy.sparse as sp
@@ -63,6 +64,31 @@ def rho_columns(h, s, mu, beta, n_poles, cols, pool=None):
     for wp, g in zip(w, cols_g):
         out += wp * g.real
     return out
+
+
+def rho_edm_columns(h, s, mu, beta, n_poles, cols, pool=None):
+    """Columns `cols` of rho (Eq. (8)) and of the energy density matrix e
+    (Eq. (10)) from the same sparse LU per pole.
+
+    e e_j = M1 e_j + kappa M0 e_j + sum_p w_p Re(alpha_p G(alpha_p) e_j), with
+    M0 = S^{-1}, M1 = S^{-1} H S^{-1} (two solves with S around a product with
+    H) and kappa = (4/beta) sum_p R_p (Eq. (11)).
+    """
+    z, r = cf_poles(n_poles)
+    alphas = mu + 1j * z / beta
+    w = -(4.0 / beta) * r
+    kappa = (4.0 / beta) * float(np.sum(r))
+    lu_s = spl.splu(s.tocsc())
+    m0 = lu_s.solve(unit_columns(s.shape[0], cols, np.float64))
+    m1 = lu_s.solve(np.asarray(h @ m0))
+    rho = m0.copy()
+    e = m1 + kappa * m0
+    args = [(h, s, a, cols) for a in alphas]
+    cols_g = pool.starmap(green_columns_lu, args) if pool is not None else [green_columns_lu(*a) for a in args]
+    for wp, a, g in zip(w, alphas, cols_g):
+        rho += wp * g.real
+        e += wp * (a * g).real
+    return rho, e
 
 
 def _gmres_block(h, s, alpha, cols, rtol):

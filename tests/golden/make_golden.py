@@ -4,6 +4,7 @@ Calls only the oracle (and the seeded input generator).  Usage:
 
     python tests/golden/make_golden.py cubic3d_24x4 [--procs 6]
     python tests/golden/make_golden.py square2d_64x4
+    python tests/golden/make_golden.py square2d_64x4 --edm   # rho and e (Eq. (10))
 
 For each workload: a seeded sample of rows j, and rho_ij on every pattern
 entry of those rows (by symmetry also column j), from Eq. (8) with one sparse
@@ -17,7 +18,12 @@ import os
 import sys
 import time
 
-import numpy as np
+# one BLAS thread per worker process: threaded BLAS state inherited through
+# fork makes the pooled workers spin
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import numpy as np  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
@@ -34,6 +40,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("workload")
     ap.add_argument("--procs", type=int, default=6)
+    ap.add_argument("--edm", action="store_true",
+                    help="also the energy density matrix e of Eq. (10) on the same entries (sparse LU route)")
     a = ap.parse_args()
     name = a.workload
     sysd = config_system(name)
@@ -43,23 +51,31 @@ def main():
     rows = np.sort(rng.choice(n, size=N_ROWS[name], replace=False))
     h, s = sampled.csr_matrices(n, sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"])
     t0 = time.time()
+    e_cols = None
     with mp.get_context("fork").Pool(a.procs) as pool:
-        if name in GMRES:
+        if a.edm:
+            cols, e_cols = sampled.rho_edm_columns(h, s, MU[name], BETA, n_poles, rows, pool=pool)
+        elif name in GMRES:
             cols = sampled.rho_columns_gmres(h, s, MU[name], BETA, n_poles, rows, pool=pool)
         else:
             cols = sampled.rho_columns(h, s, MU[name], BETA, n_poles, rows, pool=pool)
-    entries, values = [], []
+    entries, values, e_values = [], [], []
     for k, j in enumerate(rows):
         for e in range(sysd["row_ptr"][j], sysd["row_ptr"][j + 1]):
             i = int(sysd["col"][e])
             entries.append(int(e))
             values.append(float(cols[i, k]))     # rho_ji = rho_ij
+            if e_cols is not None:
+                e_values.append(float(e_cols[i, k]))
     src = ("oracle.sampled.rho_columns_gmres (GMRES per pole and column, rtol 1e-13, Eq. (8))" if name in GMRES
            else "oracle.sampled.rho_columns (sparse LU per pole, Eq. (8))")
     out = {"workload": name, "source": src,
            "mu": MU[name], "beta": BETA, "n_poles": n_poles, "rows": [int(r) for r in rows],
            "entries": entries, "values": values, "seconds": time.time() - t0}
-    path = os.path.join(HERE, "rho_sampled_%s.json" % name)
+    if a.edm:
+        out["source"] = "oracle.sampled.rho_edm_columns (sparse LU per pole, Eqs. (8) and (10))"
+        out["e_values"] = e_values
+    path = os.path.join(HERE, ("edm_sampled_%s.json" if a.edm else "rho_sampled_%s.json") % name)
     with open(path, "w") as f:
         json.dump(out, f)
     print("wrote", path, len(entries), "entries in %.0f s" % out["seconds"])

@@ -444,6 +444,32 @@ def _golden(name):
         return json.load(f)
 
 
+@pytest.mark.parametrize("name,precision,tol_e", [("square2d_64x4", "fp64", 1e-10), ("cubic3d_24x4", "fp64", 1e-10),
+                                                  ("square2d_64x4", "mixed_bf16x3", 1e-5),
+                                                  ("cubic3d_24x4", "mixed_bf16x3", 1e-5)])
+def test_full_size_energy_density_against_oracle_sample(name, precision, tol_e):
+    # e of Eq. (10) at the benchmark sizes on the stored sampled entries
+    # (sparse LU per pole in the oracle); rho from the same call to its bar
+    import paper_1005_0088_amd as nd
+    from synth import config_system
+    path = os.path.join(GOLDEN, "edm_sampled_%s.json" % name)
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle sample of e for %s" % name)
+    with open(path) as f:
+        g = json.load(f)
+    sysd = config_system(name)
+    with nd.Context(0, precision=precision) as c:
+        sid = _register(c, sysd)
+        c.set_poles(sid, g["mu"], g["beta"], g["n_poles"])
+        rho, e = c.energy_density_matrix(sid)
+    idx = np.asarray(g["entries"])
+    err_e = np.max(np.abs(e[idx] - np.asarray(g["e_values"])))
+    err_rho = np.max(np.abs(rho[idx] - np.asarray(g["values"])))
+    print("%s %s e err %.3e, rho err %.3e on %d sampled entries" % (name, precision, err_e, err_rho, idx.size))
+    assert err_e < tol_e
+    assert err_rho < (1e-10 if precision == "fp64" else 1e-7)
+
+
 @pytest.mark.parametrize("name,precision,tol,variant", [("cubic3d_24x4", "fp64", 1e-10, -1),
                                                         ("cubic3d_24x4", "mixed_fp32", 1e-7, -1),
                                                         ("cubic3d_24x4", "mixed_bf16x3", 1e-7, -1),

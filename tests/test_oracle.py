@@ -229,6 +229,19 @@ def test_edm_is_s_inverse_h_rho_and_traces_to_band_energy():
     assert np.max(np.abs(e_poles - e)) < 1e-10
 
 
+def test_edm_sampled_columns_match_closed_form_chain():
+    # the sampled-column route of Eq. (10) (sparse LU per pole, M1 from two
+    # solves with S) reproduces the closed-form e and rho on the columns
+    import scipy.sparse as sp
+    from oracle import sampled
+    n, a, b, s, mu, beta, n_poles = 50, 0.2, -1.0, 0.1, 0.05, 10.0, 60
+    h, sm = chain.chain_matrices(n, a, b, s)
+    cols = np.array([0, 7, 31, 49])
+    rho, e = sampled.rho_edm_columns(sp.csr_matrix(h), sp.csr_matrix(sm), mu, beta, n_poles, cols)
+    assert np.max(np.abs(rho - chain.chain_rho(n, a, b, s, mu, beta)[:, cols])) < 1e-12
+    assert np.max(np.abs(e - chain.chain_edm(n, a, b, s, mu, beta)[:, cols])) < 1e-11
+
+
 def test_edm_with_h_proportional_to_s():
     # H = c S: every eigenvalue is c, so e = c rho = 2 c f(beta(c - mu)) S^-1
     sysd, _, s, rows, cols = _small_lattice((3, 3, 2), "nn", 13)
