@@ -148,6 +148,28 @@ int ndrho_set_shifts(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double*
  * Errors: ESTATE (no poles set), ESINGULAR, EDEVICE, ENOMEM. */
 int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int32_t on_device);
 
+/* Chemical potential with Tr(rho(mu) S) = n_ideal (Sec. II C, "Finding
+ * chemical potential", Eqs. (40), (44)-(46)): each step sets the structure's
+ * poles at a trial mu (as ndrho_set_poles with beta, n_poles), evaluates rho
+ * and its count deviation dN = Tr(rho S) - n_ideal (Eq. (40)); the trial mu
+ * comes from the quadratic through the three points of smallest |dN|, both
+ * signs of dN among them when available (Muller, Eqs. (45)-(46)), else the
+ * line through the last two (Eq. (44), read with the denominator
+ * dN_i - dN_j), else a first move of 10 kT against the sign of dN; a trial
+ * outside the bracket of points with dN < 0 < dN is replaced by bisection.
+ * Stops when |dN| <= tol or after max_iter evaluations.  The retarded-Green-
+ * function estimate of Eq. (41) and the SCF extrapolation of Eqs. (47)-(48)
+ * are not used.  On return the structure's poles are set at *mu_out.
+ * mu0: first trial; *mu_out: the last trial; delta_n_out (may be NULL): its
+ * dN; iters_out (may be NULL): evaluations made; rho_out (host, nnz values in
+ * CSR order, may be NULL): rho at *mu_out.  Not converging within max_iter
+ * is not an error: check |*delta_n_out|.
+ * Errors: EINVAL (mu_out NULL, n_ideal outside (0, 2n), tol <= 0,
+ * max_iter < 1, bad beta or n_poles), ESINGULAR, EDEVICE, ENOMEM. */
+int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta, int32_t n_poles, double mu0,
+                  double tol, int32_t max_iter, double* mu_out, double* delta_n_out, int32_t* iters_out,
+                  double* rho_out);
+
 /* Energy density matrix e on the pattern (Sec. II A, Eqs. (10)-(11)) together
  * with rho from the same selected Green functions:
  *   e = M1 + kappa M0 + sum_p Im(-(4i/beta) G(alpha_p) R_p alpha_p),

@@ -56,6 +56,8 @@ SIGNATURES = [
     ("ndrho_set_shifts", C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _DP, C.c_int32]),
     ("ndrho_density_matrix", C.c_int, [_P, C.c_int32, _P, C.c_int32]),
     ("ndrho_energy_density_matrix", C.c_int, [_P, C.c_int32, _P, _P, C.c_int32]),
+    ("ndrho_find_mu", C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32), _P]),
     ("ndrho_density_matrix_batch", C.c_int, [_P, _I32P, C.c_int32, C.POINTER(_P), C.c_int32]),
     ("ndrho_autotune", C.c_int, [_P, _I32P, C.c_int32, C.c_char_p]),
     ("ndrho_stats", C.c_int, [_P, C.c_int32, C.POINTER(Stats)]),
@@ -303,6 +305,18 @@ class Context:
             raise ValueError("out must be a numpy array or a DeviceBuffer of nnz elements from this context")
         self._check(self._lib.ndrho_density_matrix(self._h, int(sid), C.c_void_p(out.ptr), 1))
         return out
+
+    def find_mu(self, sid, n_ideal, beta, n_poles, mu0=0.0, tol=1e-8, max_iter=40):
+        """Chemical potential with Tr(rho S) = n_ideal (see ndrho_find_mu).
+        Returns (mu, delta_n, evaluations, rho in CSR order); the structure's
+        poles are left at mu."""
+        nnz = self._nnz[int(sid)]
+        rho = np.empty(nnz, dtype=np.float64)
+        mu, dn, it = C.c_double(), C.c_double(), C.c_int32()
+        self._check(self._lib.ndrho_find_mu(self._h, int(sid), float(n_ideal), float(beta), int(n_poles), float(mu0),
+                                            float(tol), int(max_iter), C.byref(mu), C.byref(dn), C.byref(it),
+                                            rho.ctypes.data_as(C.c_void_p)))
+        return mu.value, dn.value, it.value, rho
 
     def energy_density_matrix(self, sid, rho_out=None, e_out=None):
         """(rho, e) on the pattern in CSR order (see ndrho_energy_density_matrix).

@@ -2,6 +2,7 @@
 // executor that replays a structure's launch program for each pole batch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -69,6 +70,7 @@ struct DevStruct {
   double* d_w = nullptr;
   double2* d_cw = nullptr;  // w_p alpha_p, the weights of the energy density matrix
   std::vector<double> w_host;  // weights as set (batch compatibility checks)
+  std::vector<double> s_host;  // S in CSR order (electron count Tr(rho S))
   // GEMM variant per program op (empty: default heuristic not yet applied)
   std::vector<int8_t> variant;
   int tune_gen = 0;
@@ -670,6 +672,23 @@ struct ndrho_ctx {
     S.m1_valid = true;
   }
 
+  // rho of the structure's current poles (CSR order, host) and the deviation
+  // of its electron count Tr(rho S) = sum_ij rho_ij S_ji (Eq. (40)) from n_ideal.
+  double delta_n(DevStruct& S, double n_ideal, std::vector<double>& rho) {
+    const Plan& P = S.plan;
+    evaluate(S, S.d_alpha, 0, S.d_w, S.n_shifts, S.n_hi, S.add_m0, 1.0, 0);
+    HIP_OK(launch_scatter(S.acc_entry, P.nnz, acc, outbuf, stream));
+    int st[2];
+    read_status(st);
+    if (st[0]) fail(NDRHO_ESINGULAR, "a zero, tiny or non-finite pivot occurred in alpha S - H");
+    rho.resize(P.nnz);
+    HIP_OK(hipMemcpyAsync(rho.data(), outbuf, P.nnz * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    double tr = 0.0;
+    for (int64_t e = 0; e < P.nnz; ++e) tr += rho[e] * S.s_host[e];  // S symmetric: S_ji = S_ij
+    return tr - n_ideal;
+  }
+
   // Energy density matrix buffers of nnz entries.
   void ensure_edm(int64_t nnz) {
     if (nnz <= acc_e_len) return;
@@ -940,6 +959,7 @@ int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const
       ds->h = ds->put(hv, st);
       ds->s = ds->put(sv, st);
       ds->h_inf = row_sum_norm(P, H);
+      ds->s_host = sv;
       upload_plan(*ds, st, ctx->opt.precision);
       HIP_OK(hipStreamSynchronize(st));
       ctx->compute_m0(*ds);
@@ -964,27 +984,138 @@ int ndrho_update_values(ndrho_ctx* ctx, int32_t struct_id, const double* H, cons
     HIP_OK(hipMemcpyAsync(ds.s, S, P.nnz * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     ds.h_inf = row_sum_norm(P, H);
     ds.m1_valid = false;
+    ds.s_host.assign(S, S + P.nnz);
     ctx->drop_unions();
     ctx->compute_m0(ds);
   });
 }
 
+namespace {
+
+// Shifts and weights of Eq. (8) for the continued-fraction poles at mu.
+void set_cf_poles(ndrho_ctx* ctx, DevStruct& ds, double mu, double beta, int32_t n_poles) {
+  if (n_poles < 1 || n_poles > 100000) fail(NDRHO_EINVAL, "n_poles must be in [1, 100000]");
+  if (!(beta > 0.0) || !std::isfinite(beta)) fail(NDRHO_EINVAL, "beta must be positive and finite");
+  if (!std::isfinite(mu)) fail(NDRHO_EINVAL, "mu must be finite");
+  std::vector<double> z(n_poles), r(n_poles), w(n_poles);
+  cf_poles(n_poles, z.data(), r.data());
+  std::vector<double2> a(n_poles);
+  for (int p = 0; p < n_poles; ++p) {
+    a[p] = make_double2(mu, z[p] / beta);  // alpha_p = mu + i z_p / beta
+    w[p] = -(4.0 / beta) * r[p];          // Im(-(4i/beta) G R) = -(4/beta) R Re G
+  }
+  ctx->set_shifts(ds, a, w, true, true);
+}
+
+// Trial mu from three (mu, dN) points by the quadratic through them (Muller,
+// Eqs. (45)-(46)), in coordinates x = mu - mu[0]; the root taken is the one
+// where dN rises through zero (gradient 2 a x + b > 0), in the form without
+// cancellation for either sign of b.  NaN when the quadratic has no such root.
+double muller_step(const double* mu, const double* dn) {
+  const double x1 = mu[1] - mu[0], x2 = mu[2] - mu[0];
+  const double d1 = (dn[1] - dn[0]) / x1, d2 = (dn[2] - dn[0]) / x2;
+  const double a = (d2 - d1) / (x2 - x1);
+  const double b = d1 - a * x1;
+  const double c = dn[0];
+  const double disc = b * b - 4.0 * a * c;
+  if (!(disc >= 0.0)) return std::nan("");
+  const double sq = std::sqrt(disc);
+  double x;
+  if (b >= 0.0) {
+    x = (b + sq) != 0.0 ? -2.0 * c / (b + sq) : std::nan("");
+  } else {
+    x = a != 0.0 ? (-b + sq) / (2.0 * a) : std::nan("");
+  }
+  return mu[0] + x;
+}
+
+}  // namespace
+
 int ndrho_set_poles(ndrho_ctx* ctx, int32_t struct_id, double mu, double beta, int32_t n_poles) {
   if (!ctx) return NDRHO_EINVAL;
   return guarded(ctx, [&] {
     DevStruct& ds = ctx->get(struct_id);
-    if (n_poles < 1 || n_poles > 100000) fail(NDRHO_EINVAL, "n_poles must be in [1, 100000]");
-    if (!(beta > 0.0) || !std::isfinite(beta)) fail(NDRHO_EINVAL, "beta must be positive and finite");
-    if (!std::isfinite(mu)) fail(NDRHO_EINVAL, "mu must be finite");
-    std::vector<double> z(n_poles), r(n_poles), w(n_poles);
-    cf_poles(n_poles, z.data(), r.data());
-    std::vector<double2> a(n_poles);
-    for (int p = 0; p < n_poles; ++p) {
-      a[p] = make_double2(mu, z[p] / beta);  // alpha_p = mu + i z_p / beta
-      w[p] = -(4.0 / beta) * r[p];          // Im(-(4i/beta) G R) = -(4/beta) R Re G
-    }
     HIP_OK(hipSetDevice(ctx->device));
-    ctx->set_shifts(ds, a, w, true, true);
+    set_cf_poles(ctx, ds, mu, beta, n_poles);
+  });
+}
+
+int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta, int32_t n_poles, double mu0,
+                  double tol, int32_t max_iter, double* mu_out, double* delta_n_out, int32_t* iters_out,
+                  double* rho_out) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    DevStruct& ds = ctx->get(struct_id);
+    const Plan& P = ds.plan;
+    if (!mu_out) fail(NDRHO_EINVAL, "mu_out is required");
+    if (!(n_ideal > 0.0 && n_ideal < 2.0 * static_cast<double>(P.n)))
+      fail(NDRHO_EINVAL, "n_ideal must lie strictly between 0 and 2 n");
+    if (!(tol > 0.0) || max_iter < 1) fail(NDRHO_EINVAL, "tol > 0 and max_iter >= 1 are required");
+    HIP_OK(hipSetDevice(ctx->device));
+    std::vector<double> rho;
+    std::vector<double> hm, hd;  // history of (mu, dN)
+    auto eval = [&](double mu) {
+      set_cf_poles(ctx, ds, mu, beta, n_poles);
+      const double d = ctx->delta_n(ds, n_ideal, rho);
+      hm.push_back(mu);
+      hd.push_back(d);
+      return d;
+    };
+    // bracket: dN(lo) < 0 < dN(hi) (the count rises with mu)
+    double lo = -HUGE_VAL, hi = HUGE_VAL, dlo = 0.0, dhi = 0.0;
+    auto bracket = [&](double mu, double d) {
+      if (d < 0.0 && mu > lo) lo = mu, dlo = d;
+      if (d > 0.0 && mu < hi) hi = mu, dhi = d;
+    };
+    double mu = mu0, d = eval(mu0);
+    bracket(mu, d);
+    double step = 10.0 / beta;  // first move: ten kT against the sign of dN
+    while (std::fabs(d) > tol && static_cast<int32_t>(hm.size()) < max_iter) {
+      double t = std::nan("");
+      const size_t k = hm.size();
+      if (k >= 3) {
+        // three points with the smallest |dN|, both signs among them when
+        // the history has both (interpolation rather than extrapolation)
+        std::vector<size_t> idx(k);
+        for (size_t i = 0; i < k; ++i) idx[i] = i;
+        std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return std::fabs(hd[a]) < std::fabs(hd[b]); });
+        std::vector<size_t> pick(idx.begin(), idx.begin() + 3);
+        const bool mixed = (hd[pick[0]] < 0) != (hd[pick[1]] < 0) || (hd[pick[0]] < 0) != (hd[pick[2]] < 0);
+        if (!mixed)
+          for (size_t i = 3; i < k; ++i)
+            if ((hd[idx[i]] < 0) != (hd[pick[0]] < 0)) {
+              pick[2] = idx[i];
+              break;
+            }
+        const double m3[3] = {hm[pick[0]], hm[pick[1]], hm[pick[2]]};
+        const double d3[3] = {hd[pick[0]], hd[pick[1]], hd[pick[2]]};
+        if (m3[0] != m3[1] && m3[0] != m3[2] && m3[1] != m3[2]) t = muller_step(m3, d3);
+      }
+      if (!std::isfinite(t) && k >= 2) {
+        // line through the last two points (Eq. (44), with the denominator
+        // dN_i - dN_j: the printed mu_i - mu_j does not give the zero)
+        const double mi = hm[k - 1], di = hd[k - 1], mj = hm[k - 2], dj = hd[k - 2];
+        if (di != dj) t = (mj * di - mi * dj) / (di - dj);
+      }
+      if (!std::isfinite(t)) t = mu - (d > 0.0 ? step : -step);
+      // safeguards: stay strictly inside a known bracket (else bisect);
+      // with a one-sided bracket move at least as far as the last step
+      if (std::isfinite(lo) && std::isfinite(hi)) {
+        if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
+      } else if (std::isfinite(lo) && !(t > lo)) {
+        t = lo + 2.0 * step;
+      } else if (std::isfinite(hi) && !(t < hi)) {
+        t = hi - 2.0 * step;
+      }
+      step = std::max(std::fabs(t - mu), 1e-3 / beta) * 2.0;
+      mu = t;
+      d = eval(mu);
+      bracket(mu, d);
+    }
+    *mu_out = mu;
+    if (delta_n_out) *delta_n_out = d;
+    if (iters_out) *iters_out = static_cast<int32_t>(hm.size());
+    if (rho_out) std::memcpy(rho_out, rho.data(), P.nnz * sizeof(double));
   });
 }
 

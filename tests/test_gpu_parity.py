@@ -206,6 +206,46 @@ def test_energy_density_matrix_mixed_forms(precision):
     assert err_e < 1e-5
 
 
+@pytest.mark.parametrize("dims,nb,fill,mu0", [((12, 10), "nn2", 1.0, 1.0), ((6, 6, 7), "nn", 0.8, -2.0),
+                                              ((256,), "nn", 1.0, 0.0)])
+def test_find_mu_against_dense_bisection(ctx, dims, nb, fill, mu0):
+    # Tr(rho S) = n_ideal (Eq. (40)) by the library's secant/Muller search
+    # against the oracle's bisection on the exact count from the eigenvalues
+    sysd = lattice(dims, nb, 74)
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    n_ideal = fill * sysd["n"]
+    mu_ref = dense.mu_for_count(eps, BETA, n_ideal)
+    sid = _register(ctx, sysd)
+    mu, dn, it, rho = ctx.find_mu(sid, n_ideal, BETA, 80, mu0=mu0, tol=1e-9, max_iter=40)
+    print("find_mu %s: mu %.12f (oracle %.12f), dN %.2e, %d evaluations" % (dims, mu, mu_ref, dn, it))
+    assert abs(dn) <= 1e-9
+    assert dense.trace_rho_s(rho, sysd["s"]) == pytest.approx(n_ideal, abs=1e-8)
+    # the count is steep at these fillings: mu is fixed to the tolerance over
+    # the density of states
+    dndmu = 2.0 * BETA * float(np.sum(poles_fermi_slope(BETA * (eps - mu_ref))))
+    assert abs(mu - mu_ref) < 1e-8 / dndmu + 1e-9
+    # the structure's poles are left at mu
+    assert np.array_equal(ctx.density_matrix(sid), rho)
+
+
+def poles_fermi_slope(x):
+    from oracle import poles
+    f = poles.fermi(x)
+    return f * (1.0 - f)
+
+
+def test_find_mu_rejects_bad_arguments(ctx):
+    import paper_1005_0088_amd as nd
+    sysd = lattice((4, 4), "nn", 75)
+    sid = _register(ctx, sysd)
+    for n_ideal in (0.0, 2.0 * sysd["n"], -1.0):
+        with pytest.raises(nd.NdrhoError):
+            ctx.find_mu(sid, n_ideal, BETA, 40)
+    with pytest.raises(nd.NdrhoError):
+        ctx.find_mu(sid, sysd["n"], BETA, 40, tol=0.0)
+
+
 @pytest.mark.parametrize("dims,nb,n_poles,coords", [((256,), "nn", 60, True), ((12, 10), "nn2", 80, True),
                                                     ((6, 6, 7), "nn", 80, True), ((10, 9), "nn", 40, False)])
 def test_rho_against_dense_eigen_oracle(ctx, dims, nb, n_poles, coords):
