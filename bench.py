@@ -159,6 +159,27 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
     return res, rho
 
 
+def mu_search(nd, sysd, name, n_poles, args, beta):
+    """One chemical-potential search at half filling (N electrons in N basis
+    functions) from args.find_mu, in the given precision form; prints one JSON line."""
+    fp = args.fp64_poles if args.fp64_poles is not None else FP64_POLES.get(name, 8)
+    with nd.Context(0, precision=args.precision, fp64_poles=fp, fp64_far_poles=fp) as ctx:
+        sid = ctx.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"])
+        ctx.set_poles(sid, args.find_mu, beta, n_poles)
+        if args.precision != "fp64" and not args.no_autotune:
+            ctx.autotune([sid], args.tune_cache)
+        t0 = time.perf_counter()
+        mu, dn, it, rho = ctx.find_mu(sid, float(sysd["n"]), beta, n_poles, mu0=args.find_mu, tol=1e-8)
+        dt = time.perf_counter() - t0
+    print(json.dumps({"metric": "chemical-potential search", "value": dt, "unit": "s", "higher_is_better": False,
+                      "n_gpus": 1, "dtype": {"fp64": "f64", "mixed_fp32": "f64+f32",
+                                             "mixed_bf16x3": "f64+bf16x3"}[args.precision],
+                      "data": "synthetic",
+                      "config": {"workload": name, "n": sysd["n"], "n_poles": n_poles, "n_ideal": sysd["n"],
+                                 "mu0_eV": args.find_mu, "tol_electrons": 1e-8, "precision": args.precision},
+                      "mu_eV": mu, "delta_n": dn, "evaluations": it, "s_per_evaluation": dt / max(1, it)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +200,8 @@ def main():
     ap.add_argument("--gemm-variant", type=int, default=-1,
                     help="force one GEMM variant on every low-precision front update (see ndrho_options)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--find-mu", type=float, default=None, metavar="MU0",
+                    help="time the chemical-potential search (Tr(rho S) = N, half filling) from MU0 instead")
     ap.add_argument("--energy", action="store_true",
                     help="time energy_density_matrix (rho and the energy density matrix e of the same poles)")
     ap.add_argument("--split-streams", type=int, default=1,
@@ -209,6 +232,9 @@ def main():
 
     name = args.workload
     n_poles = CONFIGS[name]["n_poles"]
+    if args.find_mu is not None:
+        mu_search(nd, config_system(name), name, n_poles, args, BETA)
+        return
     if args.fp64_poles is None:
         args.fp64_poles = FP64_POLES.get(name, 8)
     mu = 0.0
