@@ -173,6 +173,25 @@ def test_energy_density_matrix_h_proportional_to_s_and_update(ctx):
     assert np.max(np.abs(e2 - dense.edm_cf_pattern(eps, c, mu, BETA, 60, rows, cols))) < EDM_TOL
 
 
+@pytest.mark.parametrize("n", [1, 37])
+def test_energy_density_matrix_diagonal_closed_form(ctx, n):
+    # uncoupled rows (a forest of one-row fronts): eps_i = h_i / s_i and
+    # e_ii = 2 eps_i f(beta(eps_i - mu)) / s_i; one row with H = 0 has M1 = 0
+    from oracle import poles
+    rng = np.random.default_rng(80 + n)
+    h = rng.normal(0.0, 1.0, n)
+    if n == 1:
+        h[:] = 0.0
+    s = rng.uniform(0.5, 2.0, n)
+    print("case: diagonal e n=%d" % n, flush=True)
+    sid = ctx.set_structure(n, np.arange(n + 1), np.arange(n), h, s, None)
+    ctx.set_poles(sid, 0.1, BETA, 60)
+    rho, e = ctx.energy_density_matrix(sid)
+    eps = h / s
+    want = 2.0 * eps * poles.fermi(BETA * (eps - 0.1)) / s
+    assert np.max(np.abs(e - want)) < EDM_TOL
+
+
 def test_energy_density_matrix_needs_poles(ctx):
     import paper_1005_0088_amd as nd
     sysd = lattice((4, 4), "nn", 72)
