@@ -157,15 +157,29 @@ int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int
  * line through the last two (Eq. (44), read with the denominator
  * dN_i - dN_j), else a first move of 10 kT against the sign of dN; a trial
  * outside the bracket of points with dN < 0 < dN is replaced by bisection.
- * Stops when |dN| <= tol or after max_iter evaluations.  The retarded-Green-
- * function estimate of Eq. (41) and the SCF extrapolation of Eqs. (47)-(48)
- * are not used.  On return the structure's poles are set at *mu_out.
+ * When the first |dN| exceeds one electron, the second trial comes from the
+ * retarded Green function instead (Eqs. (41)-(43)): -(2/pi) Im Tr(G(E + i eta)S)
+ * with eta = 0.01 eV on 2 n_poles points over mu0 +- max(2 eV, 40 kT)
+ * (ndrho_green_traces, FP64), trapezoidal rule, bisection on the trial mu.
+ * Stops when |dN| <= tol or after max_iter density-matrix evaluations.  The
+ * SCF extrapolation of Eqs. (47)-(48) is not used (there is no SCF loop).
+ * On return the structure's poles are set at *mu_out.
  * mu0: first trial; *mu_out: the last trial; delta_n_out (may be NULL): its
  * dN; iters_out (may be NULL): evaluations made; rho_out (host, nnz values in
  * CSR order, may be NULL): rho at *mu_out.  Not converging within max_iter
  * is not an error: check |*delta_n_out|.
  * Errors: EINVAL (mu_out NULL, n_ideal outside (0, 2n), tol <= 0,
  * max_iter < 1, bad beta or n_poles), ESINGULAR, EDEVICE, ENOMEM. */
+/* Tr(G(alpha_k) S) = sum_ij G_ij(alpha_k) S_ji for n shifts alpha_k =
+ * alpha_re[k] + i alpha_im[k] (Im alpha_k > 0, or S - H/alpha_k positive
+ * definite), from the selected inversion on the pattern with FP64 front
+ * updates (Sec. II C, Eq. (42): -(2/pi) Im Tr(G(E + i eta) S) is the density
+ * of states used by the chemical-potential search).  The structure's poles are
+ * not changed.  tr_re, tr_im: n values each (host).
+ * Errors: EINVAL (n < 1, NULL arrays, non-finite shift), ESINGULAR, EDEVICE, ENOMEM. */
+int ndrho_green_traces(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double* alpha_re, const double* alpha_im,
+                       double* tr_re, double* tr_im);
+
 int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta, int32_t n_poles, double mu0,
                   double tol, int32_t max_iter, double* mu_out, double* delta_n_out, int32_t* iters_out,
                   double* rho_out);

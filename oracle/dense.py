@@ -162,6 +162,11 @@ def edm_poles_dense(h, s, mu, beta, n_poles, rows, cols):
     return e
 
 
+def green_trace_s(h, s, alpha):
+    """Tr(G(alpha) S) by a dense complex inverse (Eqs. (6), (42))."""
+    return complex(np.trace(green_dense(h, s, alpha) @ to_dense(s)))
+
+
 def trace_rho_s(rho_vals, s_vals):
     """Tr(rho S) = sum_ij rho_ij S_ji from pattern values (both symmetric, Eq. (40))."""
     return float(np.dot(rho_vals, s_vals))

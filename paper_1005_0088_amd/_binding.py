@@ -56,6 +56,7 @@ SIGNATURES = [
     ("ndrho_set_shifts", C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _DP, C.c_int32]),
     ("ndrho_density_matrix", C.c_int, [_P, C.c_int32, _P, C.c_int32]),
     ("ndrho_energy_density_matrix", C.c_int, [_P, C.c_int32, _P, _P, C.c_int32]),
+    ("ndrho_green_traces", C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P]),
     ("ndrho_find_mu", C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                 C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32), _P]),
     ("ndrho_density_matrix_batch", C.c_int, [_P, _I32P, C.c_int32, C.POINTER(_P), C.c_int32]),
@@ -305,6 +306,16 @@ class Context:
             raise ValueError("out must be a numpy array or a DeviceBuffer of nnz elements from this context")
         self._check(self._lib.ndrho_density_matrix(self._h, int(sid), C.c_void_p(out.ptr), 1))
         return out
+
+    def green_traces(self, sid, alpha):
+        """Tr(G(alpha_k) S) for an array of complex shifts (see ndrho_green_traces)."""
+        a = np.ascontiguousarray(alpha, dtype=np.complex128).ravel()
+        re, im = np.ascontiguousarray(a.real), np.ascontiguousarray(a.imag)
+        tr_re, tr_im = np.empty(a.size), np.empty(a.size)
+        self._check(self._lib.ndrho_green_traces(self._h, int(sid), int(a.size), re.ctypes.data_as(C.c_void_p),
+                                                 im.ctypes.data_as(C.c_void_p), tr_re.ctypes.data_as(C.c_void_p),
+                                                 tr_im.ctypes.data_as(C.c_void_p)))
+        return tr_re + 1j * tr_im
 
     def find_mu(self, sid, n_ideal, beta, n_poles, mu0=0.0, tol=1e-8, max_iter=40):
         """Chemical potential with Tr(rho S) = n_ideal (see ndrho_find_mu).

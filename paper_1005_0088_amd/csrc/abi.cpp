@@ -500,7 +500,7 @@ struct ndrho_ctx {
   // With `edm`, the energy density matrix of the same shifts is summed
   // beside rho into acc_e: M1 + kappa M0 + sum_p Re(c_p G_p), c_p = S.d_cw.
   void evaluate(DevStruct& S, const double2* alpha, int64_t astride, const double* w, int n, int n_hi, bool add_m0,
-                double hcoef, int spd_check, bool edm = false) {
+                double hcoef, int spd_check, bool edm = false, double2* trace_partial = nullptr, int trace_nblk = 0) {
     const Plan& P = S.plan;
     const int nb = batch_for(P, n);
     ensure_ws(P, nb);
@@ -548,6 +548,9 @@ struct ndrho_ctx {
             ea = launch_accum_edm(S.acc_slot, P.nnz, bufs[BUF_PANEL], P.panel_total, S.d_cw + p0, cnt, acc_e, stream);
           });
         HIP_OK(ea);
+        if (trace_partial)
+          HIP_OK(launch_trace_gs(S.acc_slot, S.acc_entry, P.nnz, bufs[BUF_PANEL], P.panel_total, S.s, cnt, trace_nblk,
+                                 trace_partial + int64_t(p0) * trace_nblk, stream));
       }
     };
     if (!opt.use_graph || prof) {
@@ -565,6 +568,10 @@ struct ndrho_ctx {
     key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(n_hi)));
     key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>((add_m0 ? 1 : 0) | (spd_check ? 2 : 0) |
                                                                       (hcoef != 0.0 ? 4 : 0) | (edm ? 8 : 0))));
+    if (trace_partial) {
+      key.push_back(trace_partial);
+      key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(trace_nblk)));
+    }
     if (edm) {
       int64_t kbits;
       static_assert(sizeof(kbits) == sizeof(S.kappa), "kappa bits");
@@ -687,6 +694,46 @@ struct ndrho_ctx {
     double tr = 0.0;
     for (int64_t e = 0; e < P.nnz; ++e) tr += rho[e] * S.s_host[e];  // S symmetric: S_ji = S_ij
     return tr - n_ideal;
+  }
+
+  // Tr(G(alpha_k) S) for n shifts (FP64 front updates for all of them).
+  std::vector<double2> green_traces(DevStruct& S, const std::vector<double2>& alpha) {
+    const Plan& P = S.plan;
+    const int n = static_cast<int>(alpha.size());
+    const int nblk = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(64, (P.nnz + 255) / 256)));
+    std::vector<double> w(n, 0.0);
+    double2* da = upload(alpha, stream);
+    double* dw = upload(w, stream);
+    double2* part = nullptr;
+    std::vector<double2> hp(static_cast<size_t>(n) * nblk);
+    try {
+      if (hipMalloc(&part, hp.size() * sizeof(double2)) != hipSuccess) fail(NDRHO_ENOMEM, "trace buffer");
+      evaluate(S, da, 0, dw, n, n, false, 1.0, 0, false, part, nblk);
+      int st[2];
+      read_status(st);
+      if (st[0]) fail(NDRHO_ESINGULAR, "a zero, tiny or non-finite pivot occurred in alpha S - H");
+      HIP_OK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double2), hipMemcpyDeviceToHost, stream));
+      HIP_OK(hipStreamSynchronize(stream));
+    } catch (...) {
+      (void)hipFree(da);
+      (void)hipFree(dw);
+      if (part) (void)hipFree(part);
+      throw;
+    }
+    (void)hipFree(da);
+    (void)hipFree(dw);
+    (void)hipFree(part);
+    // the graph captured for these buffers must not be replayed after they are freed
+    if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
+    S.gexec = nullptr;
+    S.gkey.clear();
+    std::vector<double2> tr(n, make_double2(0.0, 0.0));
+    for (int k = 0; k < n; ++k)
+      for (int b = 0; b < nblk; ++b) {
+        tr[k].x += hp[static_cast<size_t>(k) * nblk + b].x;
+        tr[k].y += hp[static_cast<size_t>(k) * nblk + b].y;
+      }
+    return tr;
   }
 
   // Energy density matrix buffers of nnz entries.
@@ -1040,6 +1087,62 @@ int ndrho_set_poles(ndrho_ctx* ctx, int32_t struct_id, double mu, double beta, i
   });
 }
 
+int ndrho_green_traces(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double* alpha_re, const double* alpha_im,
+                       double* tr_re, double* tr_im) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    DevStruct& ds = ctx->get(struct_id);
+    if (n < 1 || !alpha_re || !alpha_im || !tr_re || !tr_im) fail(NDRHO_EINVAL, "n >= 1 and all arrays are required");
+    std::vector<double2> a(n);
+    for (int k = 0; k < n; ++k) {
+      if (!std::isfinite(alpha_re[k]) || !std::isfinite(alpha_im[k])) fail(NDRHO_EINVAL, "non-finite shift");
+      a[k] = make_double2(alpha_re[k], alpha_im[k]);
+    }
+    HIP_OK(hipSetDevice(ctx->device));
+    const std::vector<double2> tr = ctx->green_traces(ds, a);
+    for (int k = 0; k < n; ++k) tr_re[k] = tr[k].x, tr_im[k] = tr[k].y;
+  });
+}
+
+namespace {
+
+// Step (2) of the mu search (Eqs. (41)-(43)): the change of the electron
+// count when mu moves from mu_i to mu_t is estimated as
+//   dN(mu_t) = int dE drho(E) [f((E - mu_t)/kT) - f((E - mu_i)/kT)],
+//   drho(E) = -(2/pi) Im Tr(G(E + i eta) S),   eta = 0.01 eV,
+// by the trapezoidal rule on n_grid points over [mu_i - L, mu_i + L], and mu_t
+// solves dN_i + dN(mu_t) = 0 by bisection inside the window (the estimate is
+// monotone in mu_t since drho >= 0).
+double retarded_estimate(ndrho_ctx* ctx, DevStruct& ds, double mu_i, double dn_i, double beta, int n_grid,
+                         double half_width) {
+  const double eta = 0.01;
+  std::vector<double2> a(n_grid);
+  const double h = 2.0 * half_width / (n_grid - 1);
+  for (int k = 0; k < n_grid; ++k) a[k] = make_double2(mu_i - half_width + h * k, eta);
+  const std::vector<double2> tr = ctx->green_traces(ds, a);
+  std::vector<double> drho(n_grid);
+  for (int k = 0; k < n_grid; ++k) drho[k] = -(2.0 / M_PI) * tr[k].y;
+  auto fermi = [&](double x) { return x > 0 ? std::exp(-x) / (1.0 + std::exp(-x)) : 1.0 / (1.0 + std::exp(x)); };
+  auto dn_of = [&](double mu_t) {
+    double acc = 0.0;
+    for (int k = 0; k < n_grid; ++k) {
+      const double e = a[k].x;
+      const double df = fermi(beta * (e - mu_t)) - fermi(beta * (e - mu_i));
+      acc += (k == 0 || k == n_grid - 1 ? 0.5 : 1.0) * h * drho[k] * df;
+    }
+    return acc;
+  };
+  double lo = mu_i - half_width, hi = mu_i + half_width;
+  for (int it = 0; it < 200 && hi - lo > 1e-12 * std::max(1.0, std::fabs(mu_i)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (dn_i + dn_of(mid) < 0.0) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+}  // namespace
+
 int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta, int32_t n_poles, double mu0,
                   double tol, int32_t max_iter, double* mu_out, double* delta_n_out, int32_t* iters_out,
                   double* rho_out) {
@@ -1070,6 +1173,16 @@ int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta
     double mu = mu0, d = eval(mu0);
     bracket(mu, d);
     double step = 10.0 / beta;  // first move: ten kT against the sign of dN
+    if (std::fabs(d) > 1.0 && std::fabs(d) > tol && max_iter > 1) {
+      // far from the count: one estimate from the retarded Green function
+      // (step (2)) on 2 n_poles points over mu0 +- max(2 eV, 40 kT)
+      const double half = std::max(2.0, 40.0 / beta);
+      const double t = retarded_estimate(ctx, ds, mu, d, beta, 2 * n_poles, half);
+      step = std::max(std::fabs(t - mu), 1e-3 / beta) * 2.0;
+      mu = t;
+      d = eval(mu);
+      bracket(mu, d);
+    }
     while (std::fabs(d) > tol && static_cast<int32_t>(hm.size()) < max_iter) {
       double t = std::nan("");
       const size_t k = hm.size();

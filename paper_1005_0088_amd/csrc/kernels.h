@@ -58,6 +58,9 @@ hipError_t launch_scatter(const int32_t* entry, int64_t count, const double* acc
 // energy density matrix (energy.hip): acc_e = m1 + kappa m0, then acc_e += sum_p Re(cw_p G_p)
 hipError_t launch_init_edm(const double* m1, const double* m0, double kappa, int64_t count, double* acc_e,
                            hipStream_t st);
+// Tr(G_p S) per pole (trace.hip): partial[p * nblk + b], b < nblk, summed by the host
+hipError_t launch_trace_gs(const int64_t* slot, const int32_t* entry, int64_t count, const double2* panel, int64_t ps,
+                           const double* s, int npoles, int nblk, double2* partial, hipStream_t st);
 hipError_t launch_accum_edm(const int64_t* slot, int64_t count, const double2* panel, int64_t ps,
                             const double2* cw, int npoles, double* acc_e, hipStream_t st);
 

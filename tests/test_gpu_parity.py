@@ -248,6 +248,38 @@ def test_find_mu_against_dense_bisection(ctx, dims, nb, fill, mu0):
     assert np.array_equal(ctx.density_matrix(sid), rho)
 
 
+def test_green_traces_against_dense(ctx):
+    # Tr(G(alpha) S) on the pattern equals the dense trace, near the real
+    # axis (eta = 0.01 eV, as the retarded estimate of the mu search uses)
+    # and away from it
+    sysd = lattice((9, 8), "nn2", 76)
+    h, s, rows, cols = _dense(sysd)
+    sid = _register(ctx, sysd)
+    alphas = np.array([0.1 + 0.01j, -1.0 + 0.01j, 0.3 + 2.0j, 5.0 + 40.0j, -3.0 + 0.01j])
+    got = ctx.green_traces(sid, alphas)
+    for a, g in zip(alphas, got):
+        ref = dense.green_trace_s(h, s, a)
+        assert abs(g - ref) < 1e-10 * max(1.0, abs(ref)), (a, g, ref)
+
+
+@pytest.mark.parametrize("mu0", [3.0, -4.0])
+def test_find_mu_far_start(ctx, mu0):
+    # a start several eV away (|dN| of hundreds of electrons): the second
+    # trial comes from the retarded-Green-function estimate
+    sysd = lattice((12, 10), "nn2", 77)
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    n_ideal = float(sysd["n"])
+    mu_ref = dense.mu_for_count(eps, BETA, n_ideal)
+    sid = _register(ctx, sysd)
+    mu, dn, it, rho = ctx.find_mu(sid, n_ideal, BETA, 80, mu0=mu0, tol=1e-9, max_iter=40)
+    print("find_mu far start %.1f: mu %.12f (oracle %.12f), dN %.2e, %d evaluations" % (mu0, mu, mu_ref, dn, it))
+    assert abs(dn) <= 1e-9
+    dndmu = 2.0 * BETA * float(np.sum(poles_fermi_slope(BETA * (eps - mu_ref))))
+    assert abs(mu - mu_ref) < 1e-8 / dndmu + 1e-9
+    assert it <= 12
+
+
 def poles_fermi_slope(x):
     from oracle import poles
     f = poles.fermi(x)

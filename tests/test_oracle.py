@@ -254,6 +254,18 @@ def test_edm_with_h_proportional_to_s():
     assert np.max(np.abs(e - want)) < 1e-11
 
 
+def test_green_trace_is_spectral_sum():
+    # C^T S C = I gives Tr(G(alpha) S) = sum_nu 1/(alpha - eps_nu); its
+    # -(2/pi) Im part near the real axis is a sum of Lorentzians (Eq. (42))
+    sysd, h, s, rows, cols = _small_lattice((4, 3, 2), "nn", 14)
+    eps, _ = dense.eigen(h, s)
+    for alpha in (0.1 + 0.01j, -1.0 + 0.01j, 0.3 + 2.0j, 5.0 + 40.0j):
+        got = dense.green_trace_s(h, s, alpha)
+        ref = complex(np.sum(1.0 / (alpha - eps)))
+        assert abs(got - ref) < 1e-10 * max(1.0, abs(ref))
+        assert -(2.0 / np.pi) * got.imag > 0.0
+
+
 def test_s_inverse_from_eigenvectors():
     sysd, h, s, rows, cols = _small_lattice((3, 3, 2), "nn", 2)
     eps, c = dense.eigen(h, s)
