@@ -169,14 +169,16 @@ def mu_search(nd, sysd, name, n_poles, args, beta):
         if args.precision != "fp64" and not args.no_autotune:
             ctx.autotune([sid], args.tune_cache)
         t0 = time.perf_counter()
-        mu, dn, it, rho = ctx.find_mu(sid, float(sysd["n"]), beta, n_poles, mu0=args.find_mu, tol=1e-8)
+        mu, dn, it, rho = ctx.find_mu(sid, float(sysd["n"]), beta, n_poles, mu0=args.find_mu, tol=1e-8,
+                                      retarded_step=args.retarded_step)
         dt = time.perf_counter() - t0
     print(json.dumps({"metric": "chemical-potential search", "value": dt, "unit": "s", "higher_is_better": False,
                       "n_gpus": 1, "dtype": {"fp64": "f64", "mixed_fp32": "f64+f32",
                                              "mixed_bf16x3": "f64+bf16x3"}[args.precision],
                       "data": "synthetic",
                       "config": {"workload": name, "n": sysd["n"], "n_poles": n_poles, "n_ideal": sysd["n"],
-                                 "mu0_eV": args.find_mu, "tol_electrons": 1e-8, "precision": args.precision},
+                                 "mu0_eV": args.find_mu, "tol_electrons": 1e-8, "precision": args.precision,
+                                 "retarded_step": bool(args.retarded_step)},
                       "mu_eV": mu, "delta_n": dn, "evaluations": it, "s_per_evaluation": dt / max(1, it)}))
 
 
@@ -202,6 +204,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--find-mu", type=float, default=None, metavar="MU0",
                     help="time the chemical-potential search (Tr(rho S) = N, half filling) from MU0 instead")
+    ap.add_argument("--retarded-step", action="store_true",
+                    help="with --find-mu: take the second trial from the retarded Green function")
     ap.add_argument("--energy", action="store_true",
                     help="time energy_density_matrix (rho and the energy density matrix e of the same poles)")
     ap.add_argument("--split-streams", type=int, default=1,

@@ -157,10 +157,12 @@ int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int
  * line through the last two (Eq. (44), read with the denominator
  * dN_i - dN_j), else a first move of 10 kT against the sign of dN; a trial
  * outside the bracket of points with dN < 0 < dN is replaced by bisection.
- * When the first |dN| exceeds one electron, the second trial comes from the
- * retarded Green function instead (Eqs. (41)-(43)): -(2/pi) Im Tr(G(E + i eta)S)
- * with eta = 0.01 eV on 2 n_poles points over mu0 +- max(2 eV, 40 kT)
- * (ndrho_green_traces, FP64), trapezoidal rule, bisection on the trial mu.
+ * With retarded_step = 1 and a first |dN| above one electron, the second trial
+ * comes from the retarded Green function instead (Eqs. (41)-(43)):
+ * -(2/pi) Im Tr(G(E + i eta) S) with eta = 0.01 eV on 2 n_poles points over
+ * mu0 +- max(2 eV, 40 kT) (ndrho_green_traces, FP64), trapezoidal rule,
+ * bisection on the trial mu.  It costs about as much as six FP64 density-
+ * matrix evaluations of the structure and saves one or two; 0 skips it.
  * Stops when |dN| <= tol or after max_iter density-matrix evaluations.  The
  * SCF extrapolation of Eqs. (47)-(48) is not used (there is no SCF loop).
  * On return the structure's poles are set at *mu_out.
@@ -181,8 +183,8 @@ int ndrho_green_traces(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const doubl
                        double* tr_re, double* tr_im);
 
 int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta, int32_t n_poles, double mu0,
-                  double tol, int32_t max_iter, double* mu_out, double* delta_n_out, int32_t* iters_out,
-                  double* rho_out);
+                  double tol, int32_t max_iter, int32_t retarded_step, double* mu_out, double* delta_n_out,
+                  int32_t* iters_out, double* rho_out);
 
 /* Energy density matrix e on the pattern (Sec. II A, Eqs. (10)-(11)) together
  * with rho from the same selected Green functions:

@@ -58,7 +58,7 @@ SIGNATURES = [
     ("ndrho_energy_density_matrix", C.c_int, [_P, C.c_int32, _P, _P, C.c_int32]),
     ("ndrho_green_traces", C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P]),
     ("ndrho_find_mu", C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_double, C.c_int32,
-                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32), _P]),
+                                C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32), _P]),
     ("ndrho_density_matrix_batch", C.c_int, [_P, _I32P, C.c_int32, C.POINTER(_P), C.c_int32]),
     ("ndrho_autotune", C.c_int, [_P, _I32P, C.c_int32, C.c_char_p]),
     ("ndrho_stats", C.c_int, [_P, C.c_int32, C.POINTER(Stats)]),
@@ -317,7 +317,7 @@ class Context:
                                                  tr_im.ctypes.data_as(C.c_void_p)))
         return tr_re + 1j * tr_im
 
-    def find_mu(self, sid, n_ideal, beta, n_poles, mu0=0.0, tol=1e-8, max_iter=40):
+    def find_mu(self, sid, n_ideal, beta, n_poles, mu0=0.0, tol=1e-8, max_iter=40, retarded_step=False):
         """Chemical potential with Tr(rho S) = n_ideal (see ndrho_find_mu).
         Returns (mu, delta_n, evaluations, rho in CSR order); the structure's
         poles are left at mu."""
@@ -325,7 +325,8 @@ class Context:
         rho = np.empty(nnz, dtype=np.float64)
         mu, dn, it = C.c_double(), C.c_double(), C.c_int32()
         self._check(self._lib.ndrho_find_mu(self._h, int(sid), float(n_ideal), float(beta), int(n_poles), float(mu0),
-                                            float(tol), int(max_iter), C.byref(mu), C.byref(dn), C.byref(it),
+                                            float(tol), int(max_iter), int(bool(retarded_step)), C.byref(mu),
+                                            C.byref(dn), C.byref(it),
                                             rho.ctypes.data_as(C.c_void_p)))
         return mu.value, dn.value, it.value, rho
 

@@ -1144,8 +1144,8 @@ double retarded_estimate(ndrho_ctx* ctx, DevStruct& ds, double mu_i, double dn_i
 }  // namespace
 
 int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta, int32_t n_poles, double mu0,
-                  double tol, int32_t max_iter, double* mu_out, double* delta_n_out, int32_t* iters_out,
-                  double* rho_out) {
+                  double tol, int32_t max_iter, int32_t retarded_step, double* mu_out, double* delta_n_out,
+                  int32_t* iters_out, double* rho_out) {
   if (!ctx) return NDRHO_EINVAL;
   return guarded(ctx, [&] {
     DevStruct& ds = ctx->get(struct_id);
@@ -1173,7 +1173,7 @@ int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta
     double mu = mu0, d = eval(mu0);
     bracket(mu, d);
     double step = 10.0 / beta;  // first move: ten kT against the sign of dN
-    if (std::fabs(d) > 1.0 && std::fabs(d) > tol && max_iter > 1) {
+    if (retarded_step && std::fabs(d) > 1.0 && std::fabs(d) > tol && max_iter > 1) {
       // far from the count: one estimate from the retarded Green function
       // (step (2)) on 2 n_poles points over mu0 +- max(2 eV, 40 kT)
       const double half = std::max(2.0, 40.0 / beta);

@@ -262,18 +262,19 @@ def test_green_traces_against_dense(ctx):
         assert abs(g - ref) < 1e-10 * max(1.0, abs(ref)), (a, g, ref)
 
 
-@pytest.mark.parametrize("mu0", [3.0, -4.0])
-def test_find_mu_far_start(ctx, mu0):
-    # a start several eV away (|dN| of hundreds of electrons): the second
-    # trial comes from the retarded-Green-function estimate
+@pytest.mark.parametrize("mu0,retarded", [(3.0, True), (-4.0, True), (3.0, False)])
+def test_find_mu_far_start(ctx, mu0, retarded):
+    # a start several eV away (|dN| of hundreds of electrons), with the
+    # second trial from the retarded-Green-function estimate or without it
     sysd = lattice((12, 10), "nn2", 77)
     h, s, rows, cols = _dense(sysd)
     eps, c = dense.eigen(h, s)
     n_ideal = float(sysd["n"])
     mu_ref = dense.mu_for_count(eps, BETA, n_ideal)
     sid = _register(ctx, sysd)
-    mu, dn, it, rho = ctx.find_mu(sid, n_ideal, BETA, 80, mu0=mu0, tol=1e-9, max_iter=40)
-    print("find_mu far start %.1f: mu %.12f (oracle %.12f), dN %.2e, %d evaluations" % (mu0, mu, mu_ref, dn, it))
+    mu, dn, it, rho = ctx.find_mu(sid, n_ideal, BETA, 80, mu0=mu0, tol=1e-9, max_iter=40, retarded_step=retarded)
+    print("find_mu far start %.1f (retarded %s): mu %.12f (oracle %.12f), dN %.2e, %d evaluations"
+          % (mu0, retarded, mu, mu_ref, dn, it))
     assert abs(dn) <= 1e-9
     dndmu = 2.0 * BETA * float(np.sum(poles_fermi_slope(BETA * (eps - mu_ref))))
     assert abs(mu - mu_ref) < 1e-8 / dndmu + 1e-9
