@@ -696,11 +696,14 @@ def test_split_streams_identical(use_graph):
             assert c.stats(sa)["split_passes"] == (1 if split else 0)
             c.density_matrix(sb)   # too little work per pass for a split
             assert c.stats(sb)["split_passes"] == 0
-            out[split] = (reps[0], c.density_matrix_batch([sa, sb]))
+            rho_e, e = c.energy_density_matrix(sa)
+            assert np.array_equal(rho_e, reps[0])
+            out[split] = (reps[0], c.density_matrix_batch([sa, sb]), e)
     for split in (1, 3):
         assert np.array_equal(out[split][0], out[0][0])
         for x, y in zip(out[split][1], out[0][1]):
             assert np.array_equal(x, y)
+        assert np.array_equal(out[split][2], out[0][2])
 
 
 def test_autotune_keeps_accuracy_and_caches(tmp_path):
