@@ -192,6 +192,30 @@ def test_energy_density_matrix_diagonal_closed_form(ctx, n):
     assert np.max(np.abs(e - want)) < EDM_TOL
 
 
+def test_energy_density_matrix_device_outputs_and_mixed_mu_search():
+    # device-resident outputs equal the host ones; the mu search in the
+    # split-BF16 form converges to the FP64 form's mu within its rho error
+    import paper_1005_0088_amd as nd
+    sysd = lattice((10, 9, 8), "nn", 78)
+    with nd.Context(0) as c:
+        sid = _register(c, sysd)
+        c.set_poles(sid, 0.0, BETA, 60)
+        rho_h, e_h = c.energy_density_matrix(sid)
+        nnz = int(sysd["row_ptr"][-1])
+        bo, be = c.device_buffer(nnz), c.device_buffer(nnz)
+        c.energy_density_matrix(sid, bo, be)
+        assert np.array_equal(bo.numpy(), rho_h) and np.array_equal(be.numpy(), e_h)
+        bo.free()
+        be.free()
+        mu64, dn64, _, _ = c.find_mu(sid, float(sysd["n"]), BETA, 80, mu0=0.3, tol=1e-8)
+    with nd.Context(0, precision="mixed_bf16x3") as c:
+        sid = _register(c, sysd)
+        mu, dn, it, _ = c.find_mu(sid, float(sysd["n"]), BETA, 80, mu0=0.3, tol=1e-8)
+    print("mixed mu %.12f fp64 mu %.12f (%d evaluations)" % (mu, mu64, it))
+    assert abs(dn) <= 1e-8 and abs(dn64) <= 1e-8
+    assert abs(mu - mu64) < 1e-6
+
+
 def test_energy_density_matrix_needs_poles(ctx):
     import paper_1005_0088_amd as nd
     sysd = lattice((4, 4), "nn", 72)
