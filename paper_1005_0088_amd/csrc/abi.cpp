@@ -1165,10 +1165,10 @@ int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta
       return d;
     };
     // bracket: dN(lo) < 0 < dN(hi) (the count rises with mu)
-    double lo = -HUGE_VAL, hi = HUGE_VAL, dlo = 0.0, dhi = 0.0;
+    double lo = -HUGE_VAL, hi = HUGE_VAL;
     auto bracket = [&](double mu, double d) {
-      if (d < 0.0 && mu > lo) lo = mu, dlo = d;
-      if (d > 0.0 && mu < hi) hi = mu, dhi = d;
+      if (d < 0.0 && mu > lo) lo = mu;
+      if (d > 0.0 && mu < hi) hi = mu;
     };
     double mu = mu0, d = eval(mu0);
     bracket(mu, d);
