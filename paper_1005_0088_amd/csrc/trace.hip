@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_trace_gs(const int64_t* __restrict__ sl
   red[0][threadIdx.x] = re;
   red[1][threadIdx.x] = im;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
+  for (unsigned h = 128; h > 0; h >>= 1) {
     if (threadIdx.x < h) {
       red[0][threadIdx.x] += red[0][threadIdx.x + h];
       red[1][threadIdx.x] += red[1][threadIdx.x + h];
