@@ -509,10 +509,30 @@ struct ndrho_ctx {
       HIP_OK(launch_init_acc(S.m0, P.nnz, add_m0 ? 1 : 0, acc, status, stream));
       if (edm) HIP_OK(launch_init_edm(S.m1, S.m0, S.kappa, P.nnz, acc_e, stream));
       S.split_passes = 0;
-      for (int p0 = 0; p0 < n; p0 += nb) {
-        const int cnt = std::min(nb, n - p0);
-        const int nhi = std::max(0, std::min(cnt, n_hi - p0));
-        if (opt.split_streams > 0 && !prof && nhi > 0 && nhi < cnt && P.flops_exec * cnt >= kSplitMinFlops) {
+      // With several passes and both kinds of poles, every pass takes its
+      // share of the FP64 poles (sorted first, [0, n_hi)) beside its share
+      // of the low-precision ones, so that each pass can run as two chains;
+      // within a pass, positions [0, nhi) hold the FP64 poles.
+      const int npass = (n + nb - 1) / nb;
+      const bool spread = npass > 1 && n_hi > 0 && n_hi < n;
+      int c0 = 0, h0 = 0;  // poles, and FP64 poles, before this pass
+      for (int b = 0; b < npass; ++b) {
+        const int cnt = std::min(nb, n - c0);
+        int nhi, hfirst, lfirst;  // FP64 count; indices of the first FP64 and first low pole
+        if (spread) {
+          const int h1 = static_cast<int>(int64_t(n_hi) * (c0 + cnt) / n);
+          nhi = h1 - h0;
+          hfirst = h0;
+          lfirst = n_hi + (c0 - h0);
+          h0 = h1;
+        } else {
+          nhi = std::max(0, std::min(cnt, n_hi - c0));
+          hfirst = c0;
+          lfirst = c0 + nhi;
+        }
+        c0 += cnt;
+        const bool both = nhi > 0 && nhi < cnt;
+        if (opt.split_streams > 0 && !prof && both && P.flops_exec * cnt >= kSplitMinFlops) {
           // the FP64 poles and the low-precision poles (in split_streams
           // parts) as independent launch chains: launches that leave compute
           // units idle (small fronts, memory-bound steps) overlap work of the
@@ -522,35 +542,50 @@ struct ndrho_ctx {
           ensure_side(parts);
           HIP_OK(hipEventRecord(ev_fork, stream));
           for (int i = 0; i < parts; ++i) HIP_OK(hipStreamWaitEvent(side[i], ev_fork, 0));
-          run_pass(S, cnt, 0, nhi, alpha + p0, astride, hcoef, spd_check, nhi, side[0]);
+          run_pass(S, cnt, 0, nhi, alpha + hfirst, astride, hcoef, spd_check, nhi, side[0]);
           for (int i = 0; i < parts; ++i) {
             const int q0 = nhi + static_cast<int>(int64_t(cnt - nhi) * i / parts);
             const int q1 = nhi + static_cast<int>(int64_t(cnt - nhi) * (i + 1) / parts);
-            run_pass(S, cnt, q0, q1 - q0, alpha + p0 + q0, astride, hcoef, spd_check, 0, i == 0 ? stream : side[i]);
+            run_pass(S, cnt, q0, q1 - q0, alpha + lfirst + (q0 - nhi), astride, hcoef, spd_check, 0,
+                     i == 0 ? stream : side[i]);
           }
           for (int i = 0; i < parts; ++i) {
             HIP_OK(hipEventRecord(ev_join[i], side[i]));
             HIP_OK(hipStreamWaitEvent(stream, ev_join[i], 0));
           }
+        } else if (both && lfirst != hfirst + nhi) {
+          // the two ranges one after the other on one chain
+          run_pass(S, cnt, 0, nhi, alpha + hfirst, astride, hcoef, spd_check, nhi, stream);
+          run_pass(S, cnt, nhi, cnt - nhi, alpha + lfirst, astride, hcoef, spd_check, 0, stream);
         } else {
-          run_pass(S, cnt, 0, cnt, alpha + p0, astride, hcoef, spd_check, nhi, stream);
+          run_pass(S, cnt, 0, cnt, alpha + (nhi > 0 ? hfirst : lfirst), astride, hcoef, spd_check, nhi, stream);
         }
-        // pole sum over the batch, in shift order
+        // pole sums over the pass: the FP64 positions, then the others
         double2* bufs[BUF_COUNT];
         int64_t strides[BUF_COUNT];
         layout(P, cnt, bufs, strides);
-        hipError_t ea = hipSuccess;
-        timed(NDRHO_K_ACCUM, 0.0,
-              [&] { ea = launch_accum(S.acc_slot, P.nnz, bufs[BUF_PANEL], P.panel_total, w + p0, cnt, acc, stream); });
-        HIP_OK(ea);
-        if (edm)
-          timed(NDRHO_K_ACCUM, 0.0, [&] {
-            ea = launch_accum_edm(S.acc_slot, P.nnz, bufs[BUF_PANEL], P.panel_total, S.d_cw + p0, cnt, acc_e, stream);
-          });
-        HIP_OK(ea);
-        if (trace_partial)
-          HIP_OK(launch_trace_gs(S.acc_slot, S.acc_entry, P.nnz, bufs[BUF_PANEL], P.panel_total, S.s, cnt, trace_nblk,
-                                 trace_partial + int64_t(p0) * trace_nblk, stream));
+        auto sum_range = [&](int q0, int m, int first) {
+          if (m <= 0) return;
+          const double2* panel = bufs[BUF_PANEL] + int64_t(q0) * P.panel_total;
+          hipError_t ea = hipSuccess;
+          timed(NDRHO_K_ACCUM, 0.0,
+                [&] { ea = launch_accum(S.acc_slot, P.nnz, panel, P.panel_total, w + first, m, acc, stream); });
+          HIP_OK(ea);
+          if (edm)
+            timed(NDRHO_K_ACCUM, 0.0, [&] {
+              ea = launch_accum_edm(S.acc_slot, P.nnz, panel, P.panel_total, S.d_cw + first, m, acc_e, stream);
+            });
+          HIP_OK(ea);
+          if (trace_partial)
+            HIP_OK(launch_trace_gs(S.acc_slot, S.acc_entry, P.nnz, panel, P.panel_total, S.s, m, trace_nblk,
+                                   trace_partial + int64_t(first) * trace_nblk, stream));
+        };
+        if (lfirst == hfirst + nhi) {
+          sum_range(0, cnt, nhi > 0 ? hfirst : lfirst);  // contiguous in shift order
+        } else {
+          sum_range(0, nhi, hfirst);
+          sum_range(nhi, cnt - nhi, lfirst);
+        }
       }
     };
     if (!opt.use_graph || prof) {

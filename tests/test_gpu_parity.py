@@ -702,9 +702,9 @@ def test_split_streams_identical(use_graph):
     # or only low ones, on replays of the captured graph, and for a
     # structure batch
     import paper_1005_0088_amd as nd
-    # (40 poles, 16 of them FP64, 12 per pass: FP64 only, 4 + 8, low only,
-    # low only; passes of this lattice are above the library's minimum work
-    # for a split)
+    # (40 poles, 16 of them FP64, 12 per pass: each pass takes its share of
+    # the FP64 poles, 4 + 8, 5 + 7, 5 + 7 and 2 + 2; passes of this lattice
+    # are above the library's minimum work for a split)
     a = lattice((12, 11, 10), "nn", 45)
     b = lattice((12, 11), "nn", 46)
     out = {}
@@ -717,7 +717,7 @@ def test_split_streams_identical(use_graph):
             reps = [c.density_matrix(sa) for _ in range(3)]
             for r in reps[1:]:
                 assert np.array_equal(r, reps[0])
-            assert c.stats(sa)["split_passes"] == (1 if split else 0)
+            assert c.stats(sa)["split_passes"] == (4 if split else 0)
             c.density_matrix(sb)   # too little work per pass for a split
             assert c.stats(sb)["split_passes"] == 0
             rho_e, e = c.energy_density_matrix(sa)
