@@ -10,14 +10,18 @@
  *   nested dissection (Sec. II B 1), factored by block LDL^T (Eqs. (18)-(20))
  *   front by front, and selectively inverted back down the dissection tree
  *   (Eq. (21), Eqs. (38)-(39)).  M0 = S^{-1} on the pattern (the zeroth moment
- *   of G; the constant 1/2 of Eq. (7) times the spin factor 2).
+ *   of G; the constant 1/2 of Eq. (7) times the spin factor 2).  The same
+ *   evaluation also gives the energy density matrix (Eq. (10)), and repeated
+ *   evaluations find the chemical potential (Sec. II C).
  *
  * Conventions for every entry point:
  *   - every call returns an int status (NDRHO_OK or a negative code); no C++
  *     exception crosses this interface;
  *   - after a non-OK status, ndrho_last_error() returns a message;
  *   - a context is not thread safe: the caller serialises calls on it;
- *   - all device work is ordered on the context's HIP stream;
+ *   - all device work is ordered on the context's HIP stream (passes split
+ *     into launch chains fork further streams from it and join them back
+ *     before the pole sum);
  *   - input arrays are copied; the caller keeps ownership of all its buffers.
  *
  * CSR input format (set_structure): 0-based, n rows (1 <= n <= 2^31 - 2), row_ptr[n+1] (int64,
