@@ -97,6 +97,10 @@ typedef struct {
                             before the pole sum, in passes of at least 1e10 modelled flops (smaller ones
                             run one chain); 0 runs one chain.  Results are identical either way.
                             Profiling (ndrho_profile, ndrho_autotune) always runs one chain */
+  double long_tail;      /* screening of long-tail basis functions (Sec. II B 1, step (ii)): 0 (default)
+                            off; L >= 1: in every domain of the dissection, rows whose number of
+                            pattern neighbours inside the domain exceeds L times the domain's median
+                            join the domain's separator before the cut is sought */
 } ndrho_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -302,9 +306,10 @@ int ndrho_device_copy(ndrho_ctx* ctx, void* dst, const void* src, int64_t bytes)
 int ndrho_cf_poles(int32_t n_poles, double* z, double* R);
 
 /* Nested dissection and symbolic analysis only (Sec. II B), for inspection.
- * Same input rules as set_structure (values are not needed). */
+ * Same input rules as set_structure (values are not needed); leaf_rows and
+ * long_tail as in ndrho_options. */
 int ndrho_plan_create(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* coords,
-                      int32_t leaf_rows, ndrho_plan** out);
+                      int32_t leaf_rows, double long_tail, ndrho_plan** out);
 int ndrho_plan_destroy(ndrho_plan* plan);
 const char* ndrho_plan_last_error(void);
 /* Sizes: counts[0] = n_fronts, [1] = n_levels, [2] = sum |U_f|, [3] = nnz,

@@ -26,7 +26,7 @@ class Options(C.Structure):
                 ("mem_fraction", C.c_double), ("verbose", C.c_int32), ("fp64_poles", C.c_int32),
                 ("fp64_pole_im", C.c_double), ("fp64_far_poles", C.c_int32), ("use_graph", C.c_int32),
                 ("gemm_variant", C.c_int32), ("fp64_small_tiles", C.c_int32),
-                ("split_streams", C.c_int32)]
+                ("split_streams", C.c_int32), ("long_tail", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -70,7 +70,7 @@ SIGNATURES = [
     ("ndrho_device_to_host", C.c_int, [_P, _P, _P, C.c_int64]),
     ("ndrho_device_copy", C.c_int, [_P, _P, _P, C.c_int64]),
     ("ndrho_cf_poles", C.c_int, [C.c_int32, _DP, _DP]),
-    ("ndrho_plan_create", C.c_int, [C.c_int64, _I64P, _I32P, _DP, C.c_int32, C.POINTER(_P)]),
+    ("ndrho_plan_create", C.c_int, [C.c_int64, _I64P, _I32P, _DP, C.c_int32, C.c_double, C.POINTER(_P)]),
     ("ndrho_plan_destroy", C.c_int, [_P]),
     ("ndrho_plan_last_error", C.c_char_p, []),
     ("ndrho_plan_counts", C.c_int, [_P, _I64P]),
@@ -127,13 +127,13 @@ def cf_poles(n_poles):
 class Plan:
     """Host-only nested dissection + symbolic analysis (for inspection and tests)."""
 
-    def __init__(self, n, row_ptr, col, coords=None, leaf_rows=32):
+    def __init__(self, n, row_ptr, col, coords=None, leaf_rows=32, long_tail=0.0):
         self._lib = load_library()
         rp, cl = _csr(row_ptr, col)
         xyz = _f64(coords)
         h = C.c_void_p()
         rc = self._lib.ndrho_plan_create(int(n), _ptr(rp, C.c_int64), _ptr(cl, C.c_int32),
-                                         _ptr(xyz, C.c_double), int(leaf_rows), C.byref(h))
+                                         _ptr(xyz, C.c_double), int(leaf_rows), float(long_tail), C.byref(h))
         if rc:
             raise NdrhoError(rc, self._lib.ndrho_plan_last_error().decode())
         self._h = h
@@ -228,7 +228,7 @@ class Context:
 
     def __init__(self, device=0, stream=None, leaf_rows=32, pole_batch=0, mem_fraction=0.8, precision="fp64",
                  fp64_poles=None, fp64_pole_im=None, use_graph=True, gemm_variant=-1, fp64_far_poles=None,
-                 fp64_small_tiles=-1, split_streams=1, verbose=0):
+                 fp64_small_tiles=-1, split_streams=1, long_tail=0.0, verbose=0):
         self._lib = load_library()
         opt = Options()
         self._lib.ndrho_default_options(C.byref(opt))
@@ -246,6 +246,7 @@ class Context:
         opt.gemm_variant = int(gemm_variant)
         opt.fp64_small_tiles = int(fp64_small_tiles)
         opt.split_streams = int(split_streams)
+        opt.long_tail = float(long_tail)
         opt.verbose = int(verbose)
         handle = None
         if stream is not None:

@@ -963,6 +963,7 @@ int ndrho_default_options(ndrho_options* opt) {
   opt->gemm_variant = -1;
   opt->fp64_small_tiles = -1;
   opt->split_streams = 1;
+  opt->long_tail = 0.0;
   return NDRHO_OK;
 }
 
@@ -984,6 +985,7 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
     if (c->opt.fp64_poles < 0 || c->opt.fp64_far_poles < 0 || !(c->opt.fp64_pole_im >= 0.0))
       fail(NDRHO_EINVAL, "invalid FP64 pole rule");
     if (c->opt.fp64_small_tiles < -1 || c->opt.fp64_small_tiles > 1) fail(NDRHO_EINVAL, "invalid fp64_small_tiles");
+    if (!(c->opt.long_tail == 0.0 || c->opt.long_tail >= 1.0)) fail(NDRHO_EINVAL, "long_tail must be 0 or >= 1");
     if (c->opt.split_streams < 0 || c->opt.split_streams > ndrho_ctx::kMaxChains)
       fail(NDRHO_EINVAL, "invalid split_streams");
     if (c->opt.gemm_variant < -1 || c->opt.gemm_variant >= V_COUNT ||
@@ -1034,7 +1036,7 @@ int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const
         if (!std::isfinite(coords[i])) fail(NDRHO_EINVAL, "non-finite coordinate");
     std::unique_ptr<DevStruct> ds(new DevStruct());
     try {
-      build_plan(ds->plan, n, row_ptr, col_idx, coords, ctx->opt.leaf_rows);
+      build_plan(ds->plan, n, row_ptr, col_idx, coords, ctx->opt.leaf_rows, ctx->opt.long_tail);
       Plan& P = ds->plan;
       hipStream_t st = ctx->stream;
       std::vector<double> hv(H, H + P.nnz), sv(S, S + P.nnz);
@@ -1565,13 +1567,13 @@ int ndrho_cf_poles(int32_t n_poles, double* z, double* R) {
 }
 
 int ndrho_plan_create(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* coords,
-                      int32_t leaf_rows, ndrho_plan** out) {
+                      int32_t leaf_rows, double long_tail, ndrho_plan** out) {
   return guarded(nullptr, [&] {
     if (!out) fail(NDRHO_EINVAL, "out is NULL");
     *out = nullptr;
     validate_csr(n, row_ptr, col_idx, nullptr, nullptr);
     std::unique_ptr<ndrho_plan> p(new ndrho_plan());
-    build_plan(p->plan, n, row_ptr, col_idx, coords, leaf_rows);
+    build_plan(p->plan, n, row_ptr, col_idx, coords, leaf_rows, long_tail);
     *out = p.release();
   });
 }

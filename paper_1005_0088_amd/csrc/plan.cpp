@@ -80,8 +80,8 @@ struct NdNode {
 
 class Dissector {
  public:
-  Dissector(int64_t n, const int64_t* rp, const int32_t* col, const double* coords, int leaf)
-      : n_(n), rp_(rp), col_(col), leaf_(leaf), xyz_(3 * n, 0.0), stamp_(n, -1), lab_(n, 0), pos_(n, 0),
+  Dissector(int64_t n, const int64_t* rp, const int32_t* col, const double* coords, int leaf, double tail)
+      : n_(n), rp_(rp), col_(col), leaf_(leaf), tail_(tail), xyz_(3 * n, 0.0), stamp_(n, -1), lab_(n, 0), pos_(n, 0),
         naxes_(coords ? 3 : 1) {
     if (coords) std::copy(coords, coords + 3 * n, xyz_.begin());
   }
@@ -104,6 +104,7 @@ class Dissector {
   const int64_t* rp_;
   const int32_t* col_;
   int leaf_;
+  double tail_;  // long-tail screening: degree above tail_ times the domain's median (0: off)
   std::vector<double> xyz_;
   std::vector<int> stamp_, lab_, pos_;
   int naxes_;
@@ -171,6 +172,50 @@ class Dissector {
     if (nd <= leaf_) return {make_node(lists[0], {})};
     const int st = next_stamp_++;
     for (int v : lists[0]) stamp_[v] = st;
+    // (ii) screening: rows that overlap far more rows of the domain than is
+    // typical (basis functions with a long tail) join the separator before
+    // the dissection, so that they do not hide the sparse structure of the
+    // others; the cut is then sought among the remaining rows
+    std::vector<int> screened;
+    if (tail_ > 0.0) {
+      std::vector<int> deg(nd);
+      for (int q = 0; q < nd; ++q) {
+        const int v = lists[0][q];
+        int d = 0;
+        for (int64_t e = rp_[v]; e < rp_[v + 1]; ++e)
+          if (col_[e] != v && stamp_[col_[e]] == st) ++d;
+        deg[q] = d;
+      }
+      std::vector<int> sorted = deg;
+      std::nth_element(sorted.begin(), sorted.begin() + nd / 2, sorted.end());
+      const double limit = tail_ * std::max(1, sorted[nd / 2]);
+      const int rest_st = next_stamp_++;
+      int kept = 0;
+      for (int q = 0; q < nd; ++q) kept += deg[q] > limit ? 0 : 1;
+      if (kept > 0 && kept < nd) {
+        for (int q = 0; q < nd; ++q) {
+          const int v = lists[0][q];
+          if (deg[q] > limit) screened.push_back(v);
+          else stamp_[v] = rest_st;
+        }
+        for (int a = 0; a < naxes_; ++a) {
+          std::vector<int> keep;
+          keep.reserve(kept);
+          for (int v : lists[a])
+            if (stamp_[v] == rest_st) keep.push_back(v);
+          lists[a].swap(keep);
+        }
+        std::vector<int> r = dissect_rest(lists, rest_st);
+        return {make_node(std::move(screened), std::move(r))};
+      }
+    }
+    return dissect_rest(lists, st);
+  }
+
+  // Steps (iii)-(v) on a domain whose rows carry the stamp `st`.
+  std::vector<int> dissect_rest(std::vector<int> (&lists)[3], int st) {
+    const int nd = static_cast<int>(lists[0].size());
+    if (nd <= leaf_) return {make_node(lists[0], {})};
     if (naxes_ == 1) {
       bfs_coordinate(lists[0], st);
       sort_axis(lists[0], 0);
@@ -434,8 +479,9 @@ struct Builder {
 }  // namespace
 
 void build_plan(Plan& P, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* coords,
-                int leaf_rows) {
+                int leaf_rows, double long_tail) {
   if (leaf_rows < 1) fail(NDRHO_EINVAL, "leaf_rows must be >= 1");
+  if (!(long_tail == 0.0 || long_tail >= 1.0)) fail(NDRHO_EINVAL, "long_tail must be 0 or >= 1");
   P = Plan();
   P.n = n;
   P.nnz = row_ptr[n];
@@ -443,7 +489,7 @@ void build_plan(Plan& P, int64_t n, const int64_t* row_ptr, const int32_t* col, 
   P.col.assign(col, col + P.nnz);
 
   // ---- ordering
-  Dissector nd(n, row_ptr, col, coords, leaf_rows);
+  Dissector nd(n, row_ptr, col, coords, leaf_rows, long_tail);
   std::vector<int> roots = nd.run();
   std::vector<NdNode>& nodes = nd.nodes;
   // postorder: children (in order) before the node

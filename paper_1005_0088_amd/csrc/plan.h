@@ -155,8 +155,10 @@ struct Plan {
 // Validate the CSR pattern (and values if given); throws Error(EINVAL).
 void validate_csr(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* h, const double* s);
 // Ordering + symbolic analysis + program.
+// long_tail: rows whose pattern degree inside a domain exceeds long_tail
+// times the domain's median join that domain's separator first (0: off).
 void build_plan(Plan& plan, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* coords,
-                int leaf_rows);
+                int leaf_rows, double long_tail = 0.0);
 // Layout, tables and program from P's fronts and CSR (called by build_plan).
 void finalize_plan(Plan& P);
 // One plan for several structures: their front trees side by side as a

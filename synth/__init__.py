@@ -5,4 +5,4 @@ This module only draws random matrices and lays them out as CSR; it performs
 none of the density-matrix arithmetic, so neither the GPU library nor the
 oracle depends on the other through it.
 """
-from .lattice import lattice, CONFIGS, BETA, KT_EV, config_system  # noqa: F401
+from .lattice import lattice, with_long_tail, CONFIGS, BETA, KT_EV, config_system  # noqa: F401

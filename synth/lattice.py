@@ -92,6 +92,45 @@ def lattice(dims, neighbours="nn", seed=0, norb=4, onsite_std=1.0, hop_std=0.5, 
             "coords": coords, "dims": dims, "neighbours": neighbours, "seed": seed}
 
 
+def with_long_tail(sysd, m=3, frac=0.3, seed=0, onsite_std=1.0, hop_std=0.1, s_offdiag=0.2):
+    """Append m rows standing for basis functions with a long tail: each
+    overlaps a random fraction `frac` of the existing rows.  Their H couplings
+    are N(0, hop_std); their S couplings share the magnitude s_offdiag / (frac
+    n) with random signs, so each new row's off-diagonal S sum is s_offdiag
+    and S stays positive definite (unit diagonal).  Coordinates: the centre
+    of the existing rows.  Returns a new system dict in the same format."""
+    rng = np.random.default_rng(seed)
+    n0 = sysd["n"]
+    rp0, c0 = sysd["row_ptr"], sysd["col"].astype(np.int64)
+    r0 = np.repeat(np.arange(n0, dtype=np.int64), np.diff(rp0))
+    rows, cols, hv, sv = [r0], [c0], [sysd["h"]], [sysd["s"]]
+    k = max(1, int(frac * n0))
+    smag = s_offdiag / k
+    for t in range(m):
+        i = n0 + t
+        nbr = np.sort(rng.choice(n0, size=k, replace=False)).astype(np.int64)
+        hval = rng.normal(0.0, hop_std, k)
+        sval = smag * rng.choice([-1.0, 1.0], k)
+        rows += [np.full(k, i), nbr, np.array([i])]
+        cols += [nbr, np.full(k, i), np.array([i])]
+        hv += [hval, hval, rng.normal(0.0, onsite_std, 1)]
+        sv += [sval, sval, np.ones(1)]
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    h = np.concatenate(hv)
+    s = np.concatenate(sv)
+    n = n0 + m
+    order = np.lexsort((c, r))
+    r, c, h, s = r[order], c[order], h[order], s[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, r + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    coords = np.vstack([sysd["coords"], np.repeat(sysd["coords"].mean(axis=0)[None, :], m, axis=0)])
+    out = dict(sysd)
+    out.update({"n": n, "row_ptr": row_ptr, "col": c.astype(np.int32), "h": h, "s": s, "coords": coords})
+    return out
+
+
 # The five workloads: 1D chain, 2D lattice, 3D lattice, eight uneven 2D
 # lattices, large 3D lattice.  kT = 0.1 eV everywhere (beta = 10 / eV).
 CONFIGS = {

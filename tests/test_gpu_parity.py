@@ -216,6 +216,32 @@ def test_energy_density_matrix_device_outputs_and_mixed_mu_search():
     assert abs(mu - mu64) < 1e-6
 
 
+def test_long_tail_screening_against_dense_eigen_oracle():
+    # three rows overlapping 30 % of a 3D lattice, centred at its corner:
+    # with the screening of step (ii) they are pivots of the top front; rho
+    # and e match the oracle with and without it
+    import paper_1005_0088_amd as nd
+    from synth import with_long_tail
+    base = lattice((6, 6, 5), "nn", 79)
+    sysd = with_long_tail(base, m=3, frac=0.3, seed=80)
+    sysd["coords"][base["n"]:] = base["coords"][0]
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    mu = dense.mu_for_count(eps, BETA, float(sysd["n"]))
+    ref_rho = dense.rho_cf_pattern(eps, c, mu, BETA, 80, rows, cols)
+    ref_e = dense.edm_cf_pattern(eps, c, mu, BETA, 80, rows, cols)
+    for lt in (0.0, 2.0):
+        with nd.Context(0, long_tail=lt) as cx:
+            sid = _register(cx, sysd)
+            cx.set_poles(sid, mu, BETA, 80)
+            rho, e = cx.energy_density_matrix(sid)
+            flops = cx.stats(sid)["flops_per_pole"]
+        print("long_tail %.1f: rho err %.2e, e err %.2e, flops/pole %.3g"
+              % (lt, np.max(np.abs(rho - ref_rho)), np.max(np.abs(e - ref_e)), flops))
+        assert np.max(np.abs(rho - ref_rho)) < 1e-10
+        assert np.max(np.abs(e - ref_e)) < EDM_TOL
+
+
 def test_energy_density_matrix_needs_poles(ctx):
     import paper_1005_0088_amd as nd
     sysd = lattice((4, 4), "nn", 72)

@@ -53,7 +53,7 @@ def test_default_options_and_struct_layouts():
     assert lib.ndrho_default_options(ctypes.byref(opt)) == 0
     want = {"leaf_rows": 32, "precision": 0, "pole_batch": 0, "mem_fraction": 0.8, "verbose": 0, "fp64_poles": 8,
             "fp64_pole_im": 0.05, "fp64_far_poles": 8, "use_graph": 1, "gemm_variant": -1, "fp64_small_tiles": -1,
-            "split_streams": 1}
+            "split_streams": 1, "long_tail": 0.0}
     assert {k: getattr(opt, k) for k, _ in opt._fields_} == want
 
 
@@ -78,9 +78,9 @@ def _pattern(sysd):
     return rows, sysd["col"].astype(np.int64)
 
 
-def _check_plan(sysd, leaf, coords=True):
+def _check_plan(sysd, leaf, coords=True, long_tail=0.0):
     n = sysd["n"]
-    P = nd.Plan(n, sysd["row_ptr"], sysd["col"], sysd["coords"] if coords else None, leaf)
+    P = nd.Plan(n, sysd["row_ptr"], sysd["col"], sysd["coords"] if coords else None, leaf, long_tail=long_tail)
     ex = P.export()
     perm = ex["perm"]
     assert np.array_equal(np.sort(perm), np.arange(n))
@@ -265,3 +265,49 @@ def test_front_model_through_plan_matches_dense_inverse(dims, nb, leaf, alpha):
         want = x[np.ix_(perm[idx], perm[J])]
         have = asm_flat[poff[f]:poff[f] + want.size].reshape(want.shape, order="F")
         assert np.array_equal(have, want)
+
+
+def _long_tail_system(dims, nb, seed):
+    # a lattice plus three rows overlapping 30 % of all rows, centred at a
+    # corner of the lattice (where they spoil the geometric cuts most)
+    from synth import with_long_tail
+    base = lattice(dims, nb, seed)
+    sysd = with_long_tail(base, m=3, frac=0.3, seed=seed + 1)
+    sysd["coords"][base["n"]:] = base["coords"][0]
+    return base, sysd
+
+
+@pytest.mark.parametrize("dims,nb,leaf", [((5, 4, 4), "nn", 16), ((9, 8), "nn2", 16)])
+def test_long_tail_screening(dims, nb, leaf):
+    # step (ii) of the dissection: the long-tail rows join the top separator
+    # before the cut; the plan stays a valid front tree (closure, tables),
+    # the front model through it reproduces the dense inverse, the work
+    # drops, and a plain lattice is planned as without screening
+    base, sysd = _long_tail_system(dims, nb, 21)
+    n = sysd["n"]
+    P, ex = _check_plan(sysd, leaf, long_tail=2.0)
+    roots = [f for f in range(P.n_fronts) if ex["parent"][f] < 0]
+    root_rows = {int(ex["perm"][j]) for f in roots for j in range(ex["j0"][f], ex["j0"][f] + ex["nj"][f])}
+    assert set(range(base["n"], n)) <= root_rows
+    P0 = nd.Plan(n, sysd["row_ptr"], sysd["col"], sysd["coords"], leaf)
+    assert P.model()[0] < 0.9 * P0.model()[0]
+    rows, cols = _pattern(sysd)
+    h = np.zeros((n, n))
+    s = np.zeros((n, n))
+    h[rows, cols] = sysd["h"]
+    s[rows, cols] = sysd["s"]
+    x = (0.3 + 0.4j) * s - h
+    perm = ex["perm"]
+    flat = _model_selected_inverse(P, ex, x[np.ix_(perm, perm)])
+    out, _, _ = P.slots()
+    g = np.linalg.inv(x)
+    assert np.max(np.abs(flat[out] - g[rows, cols])) < 1e-11 * np.abs(g).max()
+    Pb = nd.Plan(base["n"], base["row_ptr"], base["col"], base["coords"], leaf, long_tail=2.0)
+    Pb0 = nd.Plan(base["n"], base["row_ptr"], base["col"], base["coords"], leaf)
+    assert np.array_equal(Pb.export()["perm"], Pb0.export()["perm"])
+
+
+def test_long_tail_option_validated():
+    sysd = lattice((4, 4), "nn", 3)
+    with pytest.raises(nd.NdrhoError):
+        nd.Plan(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["coords"], 16, long_tail=0.5)
