@@ -311,3 +311,17 @@ def test_long_tail_option_validated():
     sysd = lattice((4, 4), "nn", 3)
     with pytest.raises(nd.NdrhoError):
         nd.Plan(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["coords"], 16, long_tail=0.5)
+
+
+def test_long_tail_generator_keeps_s_positive_definite_and_symmetric():
+    base, sysd = _long_tail_system((5, 4, 4), "nn", 31)
+    n = sysd["n"]
+    rows, cols = _pattern(sysd)
+    s = np.zeros((n, n))
+    h = np.zeros((n, n))
+    s[rows, cols] = sysd["s"]
+    h[rows, cols] = sysd["h"]
+    assert np.array_equal(s, s.T) and np.array_equal(h, h.T)
+    assert np.linalg.eigvalsh(s).min() > 0.0
+    deg = np.diff(sysd["row_ptr"])
+    assert np.all(deg[base["n"]:] >= int(0.3 * base["n"]))
