@@ -212,6 +212,15 @@ int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta
 int ndrho_energy_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, double* e_out,
                                 int32_t on_device);
 
+/* rho and e (as ndrho_energy_density_matrix) for k distinct structures in
+ * one schedule (as ndrho_density_matrix_batch); every member needs poles from
+ * ndrho_set_poles, with the same n_poles and beta (mu may differ).
+ * rho_outs[i], e_outs[i]: nnz values of structure struct_ids[i] each.
+ * Errors: EINVAL (repeated id, mismatched poles, NULL outputs), ESTATE,
+ * ESINGULAR, EDEVICE, ENOMEM. */
+int ndrho_energy_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, double* const* rho_outs,
+                                      double* const* e_outs, int32_t on_device);
+
 /* rho for k distinct structures in one schedule: their front trees are
  * joined into one forest (planned, uploaded and given its M0 on the first
  * call for this list of ids, then cached), so every launch works on the

@@ -56,6 +56,7 @@ SIGNATURES = [
     ("ndrho_set_shifts", C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _DP, C.c_int32]),
     ("ndrho_density_matrix", C.c_int, [_P, C.c_int32, _P, C.c_int32]),
     ("ndrho_energy_density_matrix", C.c_int, [_P, C.c_int32, _P, _P, C.c_int32]),
+    ("ndrho_energy_density_matrix_batch", C.c_int, [_P, _I32P, C.c_int32, C.POINTER(_P), C.POINTER(_P), C.c_int32]),
     ("ndrho_green_traces", C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P]),
     ("ndrho_find_mu", C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                 C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32), _P]),
@@ -348,6 +349,19 @@ class Context:
         ptrs = [C.c_void_p(o.ptr) if on_dev[0] else o.ctypes.data_as(C.c_void_p) for o in outs]
         self._check(self._lib.ndrho_energy_density_matrix(self._h, int(sid), ptrs[0], ptrs[1], int(on_dev[0])))
         return outs[0], outs[1]
+
+    def energy_density_matrix_batch(self, sids):
+        """(rho list, e list) of several structures in one schedule (host arrays;
+        see ndrho_energy_density_matrix_batch)."""
+        sids = [int(s) for s in sids]
+        rhos = [np.empty(self._nnz[s], dtype=np.float64) for s in sids]
+        es = [np.empty(self._nnz[s], dtype=np.float64) for s in sids]
+        ids = np.asarray(sids, dtype=np.int32)
+        pr = (C.c_void_p * len(sids))(*[o.ctypes.data for o in rhos])
+        pe = (C.c_void_p * len(sids))(*[o.ctypes.data for o in es])
+        self._check(self._lib.ndrho_energy_density_matrix_batch(self._h, ids.ctypes.data_as(_I32P), len(sids), pr,
+                                                                pe, 0))
+        return rhos, es
 
     def density_matrix_batch(self, sids, outs=None):
         """rho of several structures in one schedule (see ndrho_density_matrix_batch).

@@ -60,6 +60,7 @@ struct DevStruct {
   int32_t* asm_sid = nullptr;
   int64_t* acc_slot = nullptr;
   int32_t* acc_entry = nullptr;
+  int32_t* acc_sid = nullptr;  // joined plans: structure of each sorted pattern slot
   // shifts and weights
   int n_shifts = 0;
   int n_hi = 0;  // leading shifts evaluated with FP64 front updates
@@ -573,7 +574,8 @@ struct ndrho_ctx {
           HIP_OK(ea);
           if (edm)
             timed(NDRHO_K_ACCUM, 0.0, [&] {
-              ea = launch_accum_edm(S.acc_slot, P.nnz, panel, P.panel_total, S.d_cw + first, m, acc_e, stream);
+              ea = launch_accum_edm(S.acc_slot, P.nnz, panel, P.panel_total, S.d_cw + first, m, S.acc_sid, astride,
+                                    acc_e, stream);
             });
           HIP_OK(ea);
           if (trace_partial)
@@ -805,6 +807,14 @@ struct ndrho_ctx {
         HIP_OK(hipMemcpyAsync(ds->s + P.struct_nnz_off[k], m.s, bytes, hipMemcpyDeviceToDevice, stream));
       }
       upload_plan(*ds, stream, opt.precision);
+      // structure of every sorted slot (energy weights differ per structure)
+      std::vector<int32_t> sid(P.nnz);
+      for (int64_t k = 0; k < P.nnz; ++k)
+        sid[k] = static_cast<int32_t>(std::upper_bound(P.struct_nnz_off.begin(), P.struct_nnz_off.end(),
+                                                       static_cast<int64_t>(P.acc_entry[k])) -
+                                      P.struct_nnz_off.begin()) - 1;
+      ds->acc_sid = ds->put(sid, stream);
+      for (int32_t id : ids) ds->h_inf = std::max(ds->h_inf, get(id).h_inf);
       HIP_OK(hipStreamSynchronize(stream));
       compute_m0(*ds);
     } catch (...) {
@@ -839,19 +849,28 @@ struct ndrho_ctx {
     if (U.n_shifts != n || !U.d_alpha) {
       if (U.d_alpha) HIP_OK(hipFree(U.d_alpha));
       if (U.d_w) HIP_OK(hipFree(U.d_w));
+      if (U.d_cw) HIP_OK(hipFree(U.d_cw));
       U.d_alpha = nullptr;
       U.d_w = nullptr;
+      U.d_cw = nullptr;
       if (hipMalloc(&U.d_alpha, sizeof(double2) * n * k) != hipSuccess ||
-          hipMalloc(&U.d_w, sizeof(double) * n) != hipSuccess)
+          hipMalloc(&U.d_w, sizeof(double) * n) != hipSuccess ||
+          hipMalloc(&U.d_cw, sizeof(double2) * n * k) != hipSuccess)
         fail(NDRHO_ENOMEM, "batch shift allocation failed");
       U.n_shifts = n;
     }
-    for (int32_t i = 0; i < k; ++i)
-      HIP_OK(hipMemcpyAsync(U.d_alpha + int64_t(i) * n, get(ids[i]).d_alpha, sizeof(double2) * n,
-                            hipMemcpyDeviceToDevice, stream));
+    U.cf_poles = true;
+    for (int32_t i = 0; i < k; ++i) {
+      const DevStruct& m = get(ids[i]);
+      HIP_OK(hipMemcpyAsync(U.d_alpha + int64_t(i) * n, m.d_alpha, sizeof(double2) * n, hipMemcpyDeviceToDevice,
+                            stream));
+      HIP_OK(hipMemcpyAsync(U.d_cw + int64_t(i) * n, m.d_cw, sizeof(double2) * n, hipMemcpyDeviceToDevice, stream));
+      U.cf_poles = U.cf_poles && m.cf_poles;
+    }
     HIP_OK(hipMemcpyAsync(U.d_w, first.d_w, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
     U.n_hi = first.n_hi;
     U.add_m0 = first.add_m0;
+    U.kappa = first.kappa;  // the members share their weights
     return U;
   }
 
@@ -1336,6 +1355,40 @@ int ndrho_energy_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_o
       HIP_OK(hipMemcpyAsync(e_out, ctx->outbuf_e, P.nnz * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
       HIP_OK(hipStreamSynchronize(ctx->stream));
     }
+    ctx->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  });
+}
+
+int ndrho_energy_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, double* const* rho_outs,
+                                      double* const* e_outs, int32_t on_device) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    if (k < 1 || !struct_ids || !rho_outs || !e_outs) fail(NDRHO_EINVAL, "invalid batch arguments");
+    for (int32_t i = 0; i < k; ++i)
+      if (!rho_outs[i] || !e_outs[i]) fail(NDRHO_EINVAL, "an output pointer is NULL");
+    std::vector<int32_t> ids(struct_ids, struct_ids + k);
+    HIP_OK(hipSetDevice(ctx->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    DevStruct& U = ctx->prepare_batch(ids);
+    if (!U.cf_poles) fail(NDRHO_ESTATE, "set_poles has not been called for every batch member");
+    const Plan& P = U.plan;
+    const DevStruct& first = ctx->get(ids[0]);
+    const int n = first.n_shifts;
+    ctx->ensure_edm(P.nnz);
+    if (!U.m1_valid) ctx->compute_m1(U);
+    ctx->evaluate(U, U.d_alpha, n, U.d_w, n, first.n_hi, first.add_m0, 1.0, 0, true);
+    HIP_OK(launch_scatter(U.acc_entry, P.nnz, ctx->acc, ctx->outbuf, ctx->stream));
+    HIP_OK(launch_scatter(U.acc_entry, P.nnz, ctx->acc_e, ctx->outbuf_e, ctx->stream));
+    int st[2];
+    ctx->read_status(st);
+    if (st[0]) fail(NDRHO_ESINGULAR, "a zero, tiny or non-finite pivot occurred in alpha S - H");
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    for (int32_t i = 0; i < k; ++i) {
+      const int64_t cnt = ctx->get(ids[i]).plan.nnz;
+      HIP_OK(hipMemcpyAsync(rho_outs[i], ctx->outbuf + P.struct_nnz_off[i], cnt * sizeof(double), kind, ctx->stream));
+      HIP_OK(hipMemcpyAsync(e_outs[i], ctx->outbuf_e + P.struct_nnz_off[i], cnt * sizeof(double), kind, ctx->stream));
+    }
+    HIP_OK(hipStreamSynchronize(ctx->stream));
     ctx->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   });
 }

@@ -20,14 +20,18 @@ __global__ __launch_bounds__(256) void k_init_edm(const double* __restrict__ m1,
   if (k < count) acc_e[k] = m1[k] + kappa * m0[k];
 }
 
-// acc_e += sum_p Re(c_p G_p) at every pattern slot, poles in their order
+// acc_e += sum_p Re(c_p G_p) at every pattern slot, poles in their order;
+// with several structures in one plan, slot k takes the weights of its
+// structure ssid[k], cstride entries apart (ssid NULL: one structure)
 __global__ __launch_bounds__(256) void k_accum_edm(const int64_t* __restrict__ slot, int64_t count,
                                                    const double2* __restrict__ panel, int64_t ps,
                                                    const double2* __restrict__ cw, int npoles,
+                                                   const int32_t* __restrict__ ssid, int64_t cstride,
                                                    double* __restrict__ acc_e) {
   const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (k >= count) return;
   const double2* g = panel + slot[k];
+  if (ssid) cw += int64_t(ssid[k]) * cstride;
   double v = acc_e[k];
   for (int p = 0; p < npoles; ++p) {
     const double2 x = g[int64_t(p) * ps];
@@ -47,10 +51,11 @@ hipError_t launch_init_edm(const double* m1, const double* m0, double kappa, int
 }
 
 hipError_t launch_accum_edm(const int64_t* slot, int64_t count, const double2* panel, int64_t ps,
-                            const double2* cw, int npoles, double* acc_e, hipStream_t st) {
+                            const double2* cw, int npoles, const int32_t* ssid, int64_t cstride, double* acc_e,
+                            hipStream_t st) {
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_accum_edm, dim3(edm_blocks(count)), dim3(256), 0, st, slot, count, panel, ps, cw, npoles,
-                     acc_e);
+                     ssid, cstride, acc_e);
   return hipGetLastError();
 }
 

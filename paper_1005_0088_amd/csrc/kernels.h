@@ -62,6 +62,7 @@ hipError_t launch_init_edm(const double* m1, const double* m0, double kappa, int
 hipError_t launch_trace_gs(const int64_t* slot, const int32_t* entry, int64_t count, const double2* panel, int64_t ps,
                            const double* s, int npoles, int nblk, double2* partial, hipStream_t st);
 hipError_t launch_accum_edm(const int64_t* slot, int64_t count, const double2* panel, int64_t ps,
-                            const double2* cw, int npoles, double* acc_e, hipStream_t st);
+                            const double2* cw, int npoles, const int32_t* ssid, int64_t cstride, double* acc_e,
+                            hipStream_t st);
 
 }  // namespace ndrho

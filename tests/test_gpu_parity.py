@@ -242,6 +242,25 @@ def test_long_tail_screening_against_dense_eigen_oracle():
         assert np.max(np.abs(e - ref_e)) < EDM_TOL
 
 
+def test_energy_density_matrix_batch_matches_single(ctx):
+    # three structures of uneven size and different mu in one schedule: rho
+    # and e of each equal the single-structure results (e to the first
+    # moment's extrapolation error: the joined plan takes R from the largest
+    # |H|_inf of its members, so its M1 rounds differently)
+    systems = [lattice((7, 6, 5), "nn", 81), lattice((15, 13), "nn2", 82), lattice((120,), "nn", 83)]
+    mus = [0.05, -0.2, 0.3]
+    sids = []
+    for sysd, mu in zip(systems, mus):
+        sid = _register(ctx, sysd)
+        ctx.set_poles(sid, mu, BETA, 60)
+        sids.append(sid)
+    rhos, es = ctx.energy_density_matrix_batch(sids)
+    for sid, r, e in zip(sids, rhos, es):
+        r1, e1 = ctx.energy_density_matrix(sid)
+        assert np.max(np.abs(r - r1)) < 1e-12
+        assert np.max(np.abs(e - e1)) < EDM_TOL
+
+
 def test_energy_density_matrix_needs_poles(ctx):
     import paper_1005_0088_amd as nd
     sysd = lattice((4, 4), "nn", 72)
