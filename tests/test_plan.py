@@ -325,3 +325,14 @@ def test_long_tail_generator_keeps_s_positive_definite_and_symmetric():
     assert np.linalg.eigvalsh(s).min() > 0.0
     deg = np.diff(sysd["row_ptr"])
     assert np.all(deg[base["n"]:] >= int(0.3 * base["n"]))
+
+
+def test_bench_refuses_several_gpus():
+    # the benchmark measures one GPU; --gpus N > 1 exits with a message
+    # before touching a device
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
