@@ -5,14 +5,14 @@
  * Method (T. Ozaki, "Numerically exact O(N^{7/3}) method for large-scale
  * electronic structure calculations"):
  *   rho = M0 + Im(-(4i/beta) sum_p G(alpha_p) R_p),   alpha_p = mu + i z_p/beta
- *   (Sec. II A, Eq. (8)), with G(Z) = (Z S - H)^{-1} (Eq. (6)) evaluated only
- *   on the sparsity pattern of H and S (Sec. II B): the matrix is reordered by
- *   nested dissection (Sec. II B 1), factored by block LDL^T (Eqs. (18)-(20))
+ *   (Sec. II B, Eq. (8)), with G(Z) = (Z S - H)^{-1} (Eq. (6)) evaluated only
+ *   on the sparsity pattern of H and S (Sec. II C): the matrix is reordered by
+ *   nested dissection (Sec. II C 1), factored by block LDL^T (Eqs. (18)-(20))
  *   front by front, and selectively inverted back down the dissection tree
  *   (Eq. (21), Eqs. (38)-(39)).  M0 = S^{-1} on the pattern (the zeroth moment
  *   of G; the constant 1/2 of Eq. (7) times the spin factor 2).  The same
  *   evaluation also gives the energy density matrix (Eq. (10)), and repeated
- *   evaluations find the chemical potential (Sec. II C).
+ *   evaluations find the chemical potential (Sec. II C 3).
  *
  * Conventions for every entry point:
  *   - every call returns an int status (NDRHO_OK or a negative code); no C++
@@ -97,7 +97,7 @@ typedef struct {
                             before the pole sum, in passes of at least 1e10 modelled flops (smaller ones
                             run one chain); 0 runs one chain.  Results are identical either way.
                             Profiling (ndrho_profile, ndrho_autotune) always runs one chain */
-  double long_tail;      /* screening of long-tail basis functions (Sec. II B 1, step (ii)): 0 (default)
+  double long_tail;      /* screening of long-tail basis functions (Sec. II C 1, step (ii)): 0 (default)
                             off; L >= 1: in every domain of the dissection, rows whose number of
                             pattern neighbours inside the domain exceeds L times the domain's median
                             join the domain's separator before the cut is sought */
@@ -120,9 +120,9 @@ int ndrho_destroy(ndrho_ctx* ctx);
 const char* ndrho_last_error(const ndrho_ctx* ctx);
 
 /* Register one H, S pair (Sec. II, Eq. (2)): validates the CSR (format above),
- * computes the nested-dissection ordering (Sec. II B 1; geometric, from coords
+ * computes the nested-dissection ordering (Sec. II C 1; geometric, from coords
  * when given as n*3 doubles of basis-function centres, row-major), the
- * front tree and index maps (the "table function" of Sec. II B 2), uploads
+ * front tree and index maps (the "table function" of Sec. II C 2), uploads
  * everything to the device, and computes M0 = S^{-1} on the pattern by one
  * real selected inversion of S, which also checks that S is positive
  * definite.  *struct_id receives the handle for later calls.
@@ -130,6 +130,21 @@ const char* ndrho_last_error(const ndrho_ctx* ctx);
  * ENOTSPD (S not positive definite), ENOMEM, EDEVICE. */
 int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                         const double* H, const double* S, const double* coords, int32_t* struct_id);
+
+/* As ndrho_set_structure, for a periodic system (Sec. II C 1, step (i)):
+ * cell[3] holds the lengths of the periodic cell along x, y and z in the unit
+ * of coords (0 = open boundary along that axis; coords required).  An overlap
+ * whose coordinate difference along a periodic axis exceeds half the cell
+ * length is taken to cross the cell boundary (minimum image), and the
+ * dissection numbers such a neighbour by its periodic image, so that a
+ * periodic lattice is cut by two-plane separators.  H and S hold the
+ * couplings of the cell with its images folded onto the pattern (a Gamma-point
+ * matrix); the result is the same as for any other ordering.
+ * Errors: EINVAL (cell NULL or with a negative or non-finite length, coords
+ * NULL), and those of ndrho_set_structure. */
+int ndrho_set_structure_periodic(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                                 const double* H, const double* S, const double* coords, const double* cell,
+                                 int32_t* struct_id);
 
 /* Replace the values of H and S of a registered structure (same pattern).
  * Recomputes M0.  Errors as set_structure. */
@@ -156,7 +171,17 @@ int ndrho_set_shifts(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double*
  * Errors: ESTATE (no poles set), ESINGULAR, EDEVICE, ENOMEM. */
 int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int32_t on_device);
 
-/* Chemical potential with Tr(rho(mu) S) = n_ideal (Sec. II C, "Finding
+/* Tr(G(alpha_k) S) = sum_ij G_ij(alpha_k) S_ji for n shifts alpha_k =
+ * alpha_re[k] + i alpha_im[k] (Im alpha_k > 0, or S - H/alpha_k positive
+ * definite), from the selected inversion on the pattern with FP64 front
+ * updates (Sec. II C 3, Eq. (42): -(2/pi) Im Tr(G(E + i eta) S) is the density
+ * of states used by the chemical-potential search).  The structure's poles are
+ * not changed.  tr_re, tr_im: n values each (host).
+ * Errors: EINVAL (n < 1, NULL arrays, non-finite shift), ESINGULAR, EDEVICE, ENOMEM. */
+int ndrho_green_traces(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double* alpha_re, const double* alpha_im,
+                       double* tr_re, double* tr_im);
+
+/* Chemical potential with Tr(rho(mu) S) = n_ideal (Sec. II C 3, "Finding
  * chemical potential", Eqs. (40), (44)-(46)): each step sets the structure's
  * poles at a trial mu (as ndrho_set_poles with beta, n_poles), evaluates rho
  * and its count deviation dN = Tr(rho S) - n_ideal (Eq. (40)); the trial mu
@@ -180,21 +205,11 @@ int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int
  * is not an error: check |*delta_n_out|.
  * Errors: EINVAL (mu_out NULL, n_ideal outside (0, 2n), tol <= 0,
  * max_iter < 1, bad beta or n_poles), ESINGULAR, EDEVICE, ENOMEM. */
-/* Tr(G(alpha_k) S) = sum_ij G_ij(alpha_k) S_ji for n shifts alpha_k =
- * alpha_re[k] + i alpha_im[k] (Im alpha_k > 0, or S - H/alpha_k positive
- * definite), from the selected inversion on the pattern with FP64 front
- * updates (Sec. II C, Eq. (42): -(2/pi) Im Tr(G(E + i eta) S) is the density
- * of states used by the chemical-potential search).  The structure's poles are
- * not changed.  tr_re, tr_im: n values each (host).
- * Errors: EINVAL (n < 1, NULL arrays, non-finite shift), ESINGULAR, EDEVICE, ENOMEM. */
-int ndrho_green_traces(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double* alpha_re, const double* alpha_im,
-                       double* tr_re, double* tr_im);
-
 int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta, int32_t n_poles, double mu0,
                   double tol, int32_t max_iter, int32_t retarded_step, double* mu_out, double* delta_n_out,
                   int32_t* iters_out, double* rho_out);
 
-/* Energy density matrix e on the pattern (Sec. II A, Eqs. (10)-(11)) together
+/* Energy density matrix e on the pattern (Sec. II B, Eqs. (10)-(11)) together
  * with rho from the same selected Green functions:
  *   e = M1 + kappa M0 + sum_p Im(-(4i/beta) G(alpha_p) R_p alpha_p),
  *   kappa = (4/beta) sum_p R_p,
@@ -314,11 +329,12 @@ int ndrho_device_copy(ndrho_ctx* ctx, void* dst, const void* src, int64_t bytes)
  * + 1/(x + i z_p)].  Errors: EINVAL. */
 int ndrho_cf_poles(int32_t n_poles, double* z, double* R);
 
-/* Nested dissection and symbolic analysis only (Sec. II B), for inspection.
- * Same input rules as set_structure (values are not needed); leaf_rows and
+/* Nested dissection and symbolic analysis only (Sec. II C), for inspection.
+ * Same input rules as set_structure (values are not needed); cell as in
+ * ndrho_set_structure_periodic (NULL: open boundaries); leaf_rows and
  * long_tail as in ndrho_options. */
 int ndrho_plan_create(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* coords,
-                      int32_t leaf_rows, double long_tail, ndrho_plan** out);
+                      const double* cell, int32_t leaf_rows, double long_tail, ndrho_plan** out);
 int ndrho_plan_destroy(ndrho_plan* plan);
 const char* ndrho_plan_last_error(void);
 /* Sizes: counts[0] = n_fronts, [1] = n_levels, [2] = sum |U_f|, [3] = nnz,

@@ -8,7 +8,7 @@ inputs (from ``synth``) and nothing else.
 
 Modules
   poles   -- continued-fraction poles z_p and residues R_p of the Fermi
-             function (paper Sec. II A, Eq. (7)), plus an independent
+             function (paper Sec. II B, Eq. (7)), plus an independent
              backward-recurrence evaluation of the truncated fraction.
   dense   -- dense generalized eigenproblem H c = eps S c (Eq. (2)), Fermi
              occupations, rho on the pattern (Eq. (5) / Lehmann form Eq. (9)),

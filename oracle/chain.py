@@ -14,7 +14,7 @@ S-normalised eigenvectors are phi_k / sqrt(1 + 2 s c_k), and
 The block form takes 4x4 symmetric matrices E, V, W that commute (built from
 one orthogonal Q): H = I (x) E + T (x) V, S = I (x) I + T (x) W.  Its
 eigenvectors are phi_k (x) q_m with eps = (e_m + 2 c_k v_m)/(1 + 2 c_k w_m).
-Sec. II B's s-valent chain (Fig. 1, Appendix A) is the scalar case.
+Sec. II C 1's s-valent chain (Fig. 1, Appendix A) is the scalar case.
 """
 import numpy as np
 

@@ -1,6 +1,6 @@
 """Continued-fraction (CF) poles and residues of the Fermi-Dirac function.
 
-Paper Sec. II A, Eq. (7): the Fermi function 1/(1+e^x) is written as 1/2 minus
+Paper Sec. II B, Eq. (7): the Fermi function 1/(1+e^x) is written as 1/2 minus
 a continued fraction in (x/2)^2 with partial denominators 1, 3, 5, ...,
 (2M-1), and equivalently as 1/2 + sum_p R_p [1/(x - i z_p) + 1/(x + i z_p)].
 The paper states that z_p, R_p follow from an eigenvalue problem (its ref. on

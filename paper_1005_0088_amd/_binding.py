@@ -51,6 +51,7 @@ SIGNATURES = [
     ("ndrho_destroy", C.c_int, [_P]),
     ("ndrho_last_error", C.c_char_p, [_P]),
     ("ndrho_set_structure", C.c_int, [_P, C.c_int64, _I64P, _I32P, _DP, _DP, _DP, _I32P]),
+    ("ndrho_set_structure_periodic", C.c_int, [_P, C.c_int64, _I64P, _I32P, _DP, _DP, _DP, _DP, _I32P]),
     ("ndrho_update_values", C.c_int, [_P, C.c_int32, _DP, _DP]),
     ("ndrho_set_poles", C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32]),
     ("ndrho_set_shifts", C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _DP, C.c_int32]),
@@ -71,7 +72,7 @@ SIGNATURES = [
     ("ndrho_device_to_host", C.c_int, [_P, _P, _P, C.c_int64]),
     ("ndrho_device_copy", C.c_int, [_P, _P, _P, C.c_int64]),
     ("ndrho_cf_poles", C.c_int, [C.c_int32, _DP, _DP]),
-    ("ndrho_plan_create", C.c_int, [C.c_int64, _I64P, _I32P, _DP, C.c_int32, C.c_double, C.POINTER(_P)]),
+    ("ndrho_plan_create", C.c_int, [C.c_int64, _I64P, _I32P, _DP, _DP, C.c_int32, C.c_double, C.POINTER(_P)]),
     ("ndrho_plan_destroy", C.c_int, [_P]),
     ("ndrho_plan_last_error", C.c_char_p, []),
     ("ndrho_plan_counts", C.c_int, [_P, _I64P]),
@@ -128,13 +129,15 @@ def cf_poles(n_poles):
 class Plan:
     """Host-only nested dissection + symbolic analysis (for inspection and tests)."""
 
-    def __init__(self, n, row_ptr, col, coords=None, leaf_rows=32, long_tail=0.0):
+    def __init__(self, n, row_ptr, col, coords=None, leaf_rows=32, long_tail=0.0, cell=None):
         self._lib = load_library()
         rp, cl = _csr(row_ptr, col)
         xyz = _f64(coords)
+        cl3 = None if cell is None else _f64(np.asarray(cell, dtype=np.float64).reshape(3))
         h = C.c_void_p()
         rc = self._lib.ndrho_plan_create(int(n), _ptr(rp, C.c_int64), _ptr(cl, C.c_int32),
-                                         _ptr(xyz, C.c_double), int(leaf_rows), float(long_tail), C.byref(h))
+                                         _ptr(xyz, C.c_double), _ptr(cl3, C.c_double), int(leaf_rows),
+                                         float(long_tail), C.byref(h))
         if rc:
             raise NdrhoError(rc, self._lib.ndrho_plan_last_error().decode())
         self._h = h
@@ -264,13 +267,21 @@ class Context:
         if rc:
             raise NdrhoError(rc, self._lib.ndrho_last_error(self._h).decode())
 
-    def set_structure(self, n, row_ptr, col, h, s, coords=None):
+    def set_structure(self, n, row_ptr, col, h, s, coords=None, cell=None):
+        """Register H, S (CSR); cell: None (open) or the periodic cell lengths
+        along x, y, z (ndrho_set_structure_periodic)."""
         rp, cl = _csr(row_ptr, col)
         hv, sv, xyz = _f64(h), _f64(s), _f64(coords)
         sid = C.c_int32()
-        self._check(self._lib.ndrho_set_structure(self._h, int(n), _ptr(rp, C.c_int64), _ptr(cl, C.c_int32),
-                                                  _ptr(hv, C.c_double), _ptr(sv, C.c_double),
-                                                  _ptr(xyz, C.c_double), C.byref(sid)))
+        if cell is None:
+            self._check(self._lib.ndrho_set_structure(self._h, int(n), _ptr(rp, C.c_int64), _ptr(cl, C.c_int32),
+                                                      _ptr(hv, C.c_double), _ptr(sv, C.c_double),
+                                                      _ptr(xyz, C.c_double), C.byref(sid)))
+        else:
+            cl3 = _f64(np.asarray(cell, dtype=np.float64).reshape(3))
+            self._check(self._lib.ndrho_set_structure_periodic(
+                self._h, int(n), _ptr(rp, C.c_int64), _ptr(cl, C.c_int32), _ptr(hv, C.c_double),
+                _ptr(sv, C.c_double), _ptr(xyz, C.c_double), _ptr(cl3, C.c_double), C.byref(sid)))
         self._nnz[sid.value] = int(rp[-1])
         return sid.value
 

@@ -72,6 +72,7 @@ struct DevStruct {
   double2* d_cw = nullptr;  // w_p alpha_p, the weights of the energy density matrix
   std::vector<double> w_host;  // weights as set (batch compatibility checks)
   std::vector<double> s_host;  // S in CSR order (electron count Tr(rho S))
+  std::vector<double> h_host;  // H in CSR order
   // GEMM variant per program op (empty: default heuristic not yet applied)
   std::vector<int8_t> variant;
   int tune_gen = 0;
@@ -1043,11 +1044,14 @@ int ndrho_destroy(ndrho_ctx* ctx) {
 
 const char* ndrho_last_error(const ndrho_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
-int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* H,
-                        const double* S, const double* coords, int32_t* struct_id) {
+namespace {
+
+int set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* H,
+                  const double* S, const double* coords, const double* cell, int32_t* struct_id) {
   if (!ctx) return NDRHO_EINVAL;
   return guarded(ctx, [&] {
     if (!H || !S || !struct_id) fail(NDRHO_EINVAL, "H, S and struct_id are required");
+    if (cell && !coords) fail(NDRHO_EINVAL, "a periodic cell needs the coordinates");
     HIP_OK(hipSetDevice(ctx->device));
     validate_csr(n, row_ptr, col_idx, H, S);
     if (coords)
@@ -1055,7 +1059,7 @@ int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const
         if (!std::isfinite(coords[i])) fail(NDRHO_EINVAL, "non-finite coordinate");
     std::unique_ptr<DevStruct> ds(new DevStruct());
     try {
-      build_plan(ds->plan, n, row_ptr, col_idx, coords, ctx->opt.leaf_rows, ctx->opt.long_tail);
+      build_plan(ds->plan, n, row_ptr, col_idx, coords, ctx->opt.leaf_rows, ctx->opt.long_tail, cell);
       Plan& P = ds->plan;
       hipStream_t st = ctx->stream;
       std::vector<double> hv(H, H + P.nnz), sv(S, S + P.nnz);
@@ -1063,6 +1067,7 @@ int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const
       ds->s = ds->put(sv, st);
       ds->h_inf = row_sum_norm(P, H);
       ds->s_host = sv;
+      ds->h_host = hv;
       upload_plan(*ds, st, ctx->opt.precision);
       HIP_OK(hipStreamSynchronize(st));
       ctx->compute_m0(*ds);
@@ -1073,6 +1078,23 @@ int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const
     ctx->structs.push_back(std::move(ds));
     *struct_id = static_cast<int32_t>(ctx->structs.size()) - 1;
   });
+}
+
+}  // namespace
+
+int ndrho_set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* H,
+                        const double* S, const double* coords, int32_t* struct_id) {
+  return set_structure(ctx, n, row_ptr, col_idx, H, S, coords, nullptr, struct_id);
+}
+
+int ndrho_set_structure_periodic(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                                 const double* H, const double* S, const double* coords, const double* cell,
+                                 int32_t* struct_id) {
+  if (!cell) {
+    if (ctx) ctx->err = "cell is required";
+    return NDRHO_EINVAL;
+  }
+  return set_structure(ctx, n, row_ptr, col_idx, H, S, coords, cell, struct_id);
 }
 
 int ndrho_update_values(ndrho_ctx* ctx, int32_t struct_id, const double* H, const double* S) {
@@ -1088,6 +1110,7 @@ int ndrho_update_values(ndrho_ctx* ctx, int32_t struct_id, const double* H, cons
     ds.h_inf = row_sum_norm(P, H);
     ds.m1_valid = false;
     ds.s_host.assign(S, S + P.nnz);
+    ds.h_host.assign(H, H + P.nnz);
     ctx->drop_unions();
     ctx->compute_m0(ds);
   });
@@ -1620,13 +1643,14 @@ int ndrho_cf_poles(int32_t n_poles, double* z, double* R) {
 }
 
 int ndrho_plan_create(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* coords,
-                      int32_t leaf_rows, double long_tail, ndrho_plan** out) {
+                      const double* cell, int32_t leaf_rows, double long_tail, ndrho_plan** out) {
   return guarded(nullptr, [&] {
     if (!out) fail(NDRHO_EINVAL, "out is NULL");
     *out = nullptr;
     validate_csr(n, row_ptr, col_idx, nullptr, nullptr);
+    if (cell && !coords) fail(NDRHO_EINVAL, "a periodic cell needs the coordinates");
     std::unique_ptr<ndrho_plan> p(new ndrho_plan());
-    build_plan(p->plan, n, row_ptr, col_idx, coords, leaf_rows, long_tail);
+    build_plan(p->plan, n, row_ptr, col_idx, coords, leaf_rows, long_tail, cell);
     *out = p.release();
   });
 }

@@ -1,5 +1,5 @@
 // Device kernels of the front-by-front block LDL^T factorization and selected
-// inversion (Sec. II B 2, Eqs. (18)-(21), (38)-(39)) and of the pole sum of
+// inversion (Sec. II C 2, Eqs. (18)-(21), (38)-(39)) and of the pole sum of
 // Eq. (8), for gfx950.  Complex numbers are interleaved (re, im) doubles;
 // every per-pole buffer is laid out as [pole][elements] with a pole stride.
 #include <hip/hip_runtime.h>

@@ -1,5 +1,5 @@
-// Nested dissection (Sec. II B 1), symbolic front tree, the "table function"
-// of pattern positions (Sec. II B 2) and the launch program of the block
+// Nested dissection (Sec. II C 1), symbolic front tree, the "table function"
+// of pattern positions (Sec. II C 2) and the launch program of the block
 // LDL^T factorization and selected inversion (Eqs. (18)-(21), (38)-(39)).
 #include <algorithm>
 #include <cmath>
@@ -59,17 +59,27 @@ void validate_csr(int64_t n, const int64_t* row_ptr, const int32_t* col, const d
 
 // ----------------------------------------------------------- nested dissection
 //
-// Procedures (i), (iii)-(v) of Sec. II B 1.  Each domain is ordered along each
-// axis by the centre coordinate (ties broken by the other two coordinates,
-// then by index).  The nucleus is the function with the fewest overlaps inside
-// the domain; the subdomain grows from the end of the ordering nearest to the
-// nucleus one function at a time, and at each step N0 (subdomain), Ns (rows
-// between the subdomain and the farthest overlapping function) and
+// Procedures (i)-(v) of Sec. II C 1.  Each domain is ordered along each axis
+// by the centre coordinate (ties broken by the other two coordinates, then by
+// index); the position in that order is the ordering number.  The nucleus is
+// the function with the fewest overlaps inside the domain; the subdomain grows
+// from the end of the ordering nearest to the nucleus one function at a time,
+// and at each step N0 (subdomain), Ns (functions between the subdomain and the
+// extreme ordering numbers of the functions overlapping it) and
 // N1 = Nd - N0 - Ns give the measure |N0 - N1| + Ns.  The axis and size with
 // the smallest measure are taken, and both subdomains are dissected again
-// until they hold at most leaf_rows functions.  The screening of long-tail
-// functions, procedure (ii), is not applied (all functions of the lattices
-// have the same range).
+// until they hold at most leaf_rows functions.  Long-tail screening (step
+// (ii)) is optional (see dissect).
+//
+// Periodic cells (step (i)): along an axis with a cell length L > 0, a
+// neighbour reached across the cell boundary (coordinate difference beyond
+// L/2, the minimum image) carries the ordering number of its periodic image,
+// q - Nd or q + Nd for its number q in the domain, so the overlap range of a
+// subdomain can reach below 0 or beyond Nd - 1: the separator then holds the
+// functions after the subdomain and those wrapped round to the other end of
+// the order (two planes for a periodic lattice), and the other subdomain is
+// what lies between.  A cut is kept only if no overlap joins the two
+// subdomains; otherwise the axis is searched again without images.
 
 namespace {
 
@@ -80,10 +90,12 @@ struct NdNode {
 
 class Dissector {
  public:
-  Dissector(int64_t n, const int64_t* rp, const int32_t* col, const double* coords, int leaf, double tail)
+  Dissector(int64_t n, const int64_t* rp, const int32_t* col, const double* coords, const double* cell, int leaf,
+            double tail)
       : n_(n), rp_(rp), col_(col), leaf_(leaf), tail_(tail), xyz_(3 * n, 0.0), stamp_(n, -1), lab_(n, 0), pos_(n, 0),
         naxes_(coords ? 3 : 1) {
     if (coords) std::copy(coords, coords + 3 * n, xyz_.begin());
+    for (int a = 0; a < 3; ++a) cell_[a] = (coords && cell) ? cell[a] : 0.0;
   }
 
   std::vector<int> run() {
@@ -108,6 +120,7 @@ class Dissector {
   std::vector<double> xyz_;
   std::vector<int> stamp_, lab_, pos_;
   int naxes_;
+  double cell_[3] = {0.0, 0.0, 0.0};  // periodic cell length per axis (0: open)
   int next_stamp_ = 0;
 
   // Without coordinates: the breadth-first distance inside the domain from a
@@ -212,6 +225,93 @@ class Dissector {
     return dissect_rest(lists, st);
   }
 
+  // Ordering number of the neighbour u of v along axis a: its position, or
+  // that of its periodic image when the overlap crosses the cell boundary.
+  int image_pos(int v, int u, int a, int nd, bool images) const {
+    const int q = pos_[u];
+    if (!images || cell_[a] <= 0.0) return q;
+    const double d = xyz_[3 * u + a] - xyz_[3 * v + a];
+    if (d > 0.5 * cell_[a]) return q - nd;
+    if (d < -0.5 * cell_[a]) return q + nd;
+    return q;
+  }
+
+  // Steps (iv)-(v): the best cut over all axes, as labels (0 subdomain,
+  // 1 separator, 2 other subdomain) in lab_.  False when no axis has a cut
+  // with a non-empty other subdomain.
+  bool grow(std::vector<int> (&lists)[3], int st, int nucleus, bool images) {
+    const int nd = static_cast<int>(lists[0].size());
+    int64_t best_cost = -1, best_ns = 0;
+    int best_axis = -1, best_cut = 0, best_end = 0, best_hi = 0, best_lo = 0;
+    std::vector<int> hi(nd), lo(nd);
+    for (int a = 0; a < naxes_; ++a) {
+      const std::vector<int>& ord = lists[a];
+      for (int q = 0; q < nd; ++q) pos_[ord[q]] = q;
+      const bool low = pos_[nucleus] < nd - pos_[nucleus];
+      for (int q = 0; q < nd; ++q) {
+        const int v = ord[q];
+        int h = q, l = q;
+        for (int64_t e = rp_[v]; e < rp_[v + 1]; ++e) {
+          const int u = col_[e];
+          if (stamp_[u] != st) continue;
+          const int p = image_pos(v, u, a, nd, images);
+          h = std::max(h, p);
+          l = std::min(l, p);
+        }
+        hi[q] = h;
+        lo[q] = l;
+      }
+      auto consider = [&](int64_t n0, int64_t ns, int64_t n1, int m, int end, int nhi, int nlo) {
+        const int64_t cost = std::llabs(n0 - n1) + ns;
+        if (best_cost < 0 || cost < best_cost || (cost == best_cost && ns <= best_ns && a == best_axis)) {
+          best_cost = cost, best_ns = ns, best_axis = a, best_cut = m, best_end = end, best_hi = nhi, best_lo = nlo;
+        }
+      };
+      if (low) {
+        int nmax = -1, nmin = 0;
+        for (int m = 1; m < nd; ++m) {  // subdomain = ordering numbers [0, m)
+          nmax = std::max(nmax, hi[m - 1]);
+          nmin = std::min(nmin, lo[m - 1]);
+          // separator: (m - 1, nmax] and, wrapped, [nd + nmin, nd)
+          const int64_t n0 = m, ns = int64_t(nmax) - nmin + 1 - m, n1 = nd - n0 - ns;
+          if (n1 < 1) break;
+          consider(n0, ns, n1, m, 0, nmax, nmin);
+        }
+      } else {
+        int nmin = nd, nmax = nd - 1;
+        for (int m = nd - 1; m >= 1; --m) {  // subdomain = ordering numbers [m, nd)
+          nmin = std::min(nmin, lo[m]);
+          nmax = std::max(nmax, hi[m]);
+          // separator: [nmin, m) and, wrapped, [0, nmax - nd]
+          const int64_t n0 = nd - m, ns = int64_t(nmax) - nmin + 1 - n0, n1 = nd - n0 - ns;
+          if (n1 < 1) break;
+          consider(n0, ns, n1, m, 1, nmax, nmin);
+        }
+      }
+    }
+    if (best_axis < 0) return false;
+    const std::vector<int>& ord = lists[best_axis];
+    for (int q = 0; q < nd; ++q) {
+      int l;
+      if (best_end == 0) l = q < best_cut ? 0 : (q <= best_hi || q >= nd + best_lo) ? 1 : 2;
+      else l = q >= best_cut ? 0 : (q >= best_lo || q <= best_hi - nd) ? 1 : 2;
+      lab_[ord[q]] = l;
+    }
+    return true;
+  }
+
+  // No overlap between the two subdomains of the labels in lab_.
+  bool separates(const std::vector<int> (&lists)[3], int st) const {
+    for (int v : lists[0]) {
+      if (lab_[v] == 1) continue;
+      for (int64_t e = rp_[v]; e < rp_[v + 1]; ++e) {
+        const int u = col_[e];
+        if (stamp_[u] == st && lab_[u] != 1 && lab_[u] != lab_[v]) return false;
+      }
+    }
+    return true;
+  }
+
   // Steps (iii)-(v) on a domain whose rows carry the stamp `st`.
   std::vector<int> dissect_rest(std::vector<int> (&lists)[3], int st) {
     const int nd = static_cast<int>(lists[0].size());
@@ -231,58 +331,14 @@ class Dissector {
         nucleus = v;
       }
     }
-    // (iv)-(v) growth along each axis
-    int64_t best_cost = -1, best_ns = 0;
-    int best_axis = -1, best_cut = 0, best_end = 0, best_far = 0;
-    std::vector<int> far(nd);
-    for (int a = 0; a < naxes_; ++a) {
-      const std::vector<int>& ord = lists[a];
-      for (int q = 0; q < nd; ++q) pos_[ord[q]] = q;
-      const bool low = pos_[nucleus] < nd - pos_[nucleus];
-      for (int q = 0; q < nd; ++q) {
-        int v = ord[q];
-        int ext = q;
-        for (int64_t e = rp_[v]; e < rp_[v + 1]; ++e) {
-          int u = col_[e];
-          if (stamp_[u] != st) continue;
-          ext = low ? std::max(ext, pos_[u]) : std::min(ext, pos_[u]);
-        }
-        far[q] = ext;
-      }
-      if (low) {
-        int nmax = -1;
-        for (int m = 1; m < nd; ++m) {  // subdomain = positions [0, m)
-          nmax = std::max(nmax, far[m - 1]);
-          const int64_t n0 = m, ns = nmax + 1 - m, n1 = nd - nmax - 1;
-          if (n1 < 1) break;
-          const int64_t cost = std::llabs(n0 - n1) + ns;
-          if (best_cost < 0 || cost < best_cost || (cost == best_cost && ns <= best_ns && a == best_axis)) {
-            best_cost = cost, best_ns = ns, best_axis = a, best_cut = m, best_end = 0, best_far = nmax;
-          }
-        }
-      } else {
-        int nmin = nd;
-        for (int m = nd - 1; m >= 1; --m) {  // subdomain = positions [m, nd)
-          nmin = std::min(nmin, far[m]);
-          const int64_t n0 = nd - m, ns = m - nmin, n1 = nmin;
-          if (n1 < 1) break;
-          const int64_t cost = std::llabs(n0 - n1) + ns;
-          if (best_cost < 0 || cost < best_cost || (cost == best_cost && ns <= best_ns && a == best_axis)) {
-            best_cost = cost, best_ns = ns, best_axis = a, best_cut = m, best_end = 1, best_far = nmin;
-          }
-        }
-      }
-    }
-    if (best_axis < 0) return {make_node(lists[0], {})};  // no separating cut exists
-    {
-      const std::vector<int>& ord = lists[best_axis];
-      for (int q = 0; q < nd; ++q) {
-        int l;
-        if (best_end == 0) l = q < best_cut ? 0 : (q <= best_far ? 1 : 2);
-        else l = q >= best_cut ? 0 : (q >= best_far ? 1 : 2);
-        lab_[ord[q]] = l;
-      }
-    }
+    // (iv)-(v) growth along each axis, with images across periodic cell
+    // boundaries; the cut separates by construction, which is checked (and
+    // the axes searched again without images should it not)
+    const bool periodic = cell_[0] > 0.0 || cell_[1] > 0.0 || cell_[2] > 0.0;
+    bool found = grow(lists, st, nucleus, periodic);
+    if (found && periodic && !separates(lists, st)) found = grow(lists, st, nucleus, false);
+    if (!found) return {make_node(lists[0], {})};  // no separating cut exists
+    if (!separates(lists, st)) fail(NDRHO_EINVAL, "dissection produced a separator that does not separate");
     std::vector<int> sub[3][3];  // [label][axis]
     for (int a = 0; a < naxes_; ++a)
       for (int v : lists[a]) sub[lab_[v]][a].push_back(v);
@@ -479,7 +535,7 @@ struct Builder {
 }  // namespace
 
 void build_plan(Plan& P, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* coords,
-                int leaf_rows, double long_tail) {
+                int leaf_rows, double long_tail, const double* cell) {
   if (leaf_rows < 1) fail(NDRHO_EINVAL, "leaf_rows must be >= 1");
   if (!(long_tail == 0.0 || long_tail >= 1.0)) fail(NDRHO_EINVAL, "long_tail must be 0 or >= 1");
   P = Plan();
@@ -489,7 +545,10 @@ void build_plan(Plan& P, int64_t n, const int64_t* row_ptr, const int32_t* col, 
   P.col.assign(col, col + P.nnz);
 
   // ---- ordering
-  Dissector nd(n, row_ptr, col, coords, leaf_rows, long_tail);
+  if (cell)
+    for (int a = 0; a < 3; ++a)
+      if (!(cell[a] >= 0.0) || !std::isfinite(cell[a])) fail(NDRHO_EINVAL, "cell lengths must be finite and >= 0");
+  Dissector nd(n, row_ptr, col, coords, cell, leaf_rows, long_tail);
   std::vector<int> roots = nd.run();
   std::vector<NdNode>& nodes = nd.nodes;
   // postorder: children (in order) before the node

@@ -12,7 +12,7 @@ namespace ndrho {
 void cf_poles(int n_poles, double* z, double* r);
 
 // One front of the dissection tree (a domain at the innermost level or a
-// separator, Sec. II B 1).  Its pivot rows J are the contiguous permuted
+// separator, Sec. II C 1).  Its pivot rows J are the contiguous permuted
 // positions [j0, j0 + nj); its update rows U (permuted positions, increasing)
 // are the rows of ancestor separators coupled to its subtree.
 struct Front {
@@ -157,8 +157,10 @@ void validate_csr(int64_t n, const int64_t* row_ptr, const int32_t* col, const d
 // Ordering + symbolic analysis + program.
 // long_tail: rows whose pattern degree inside a domain exceeds long_tail
 // times the domain's median join that domain's separator first (0: off).
+// cell: NULL, or the periodic cell length along x, y, z (0: open boundary)
+// for the coordinates in coords.
 void build_plan(Plan& plan, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* coords,
-                int leaf_rows, double long_tail = 0.0);
+                int leaf_rows, double long_tail = 0.0, const double* cell = nullptr);
 // Layout, tables and program from P's fronts and CSR (called by build_plan).
 void finalize_plan(Plan& P);
 // One plan for several structures: their front trees side by side as a

@@ -1,4 +1,4 @@
-// Continued-fraction poles and residues of the Fermi function (Sec. II A, Eq. (7)).
+// Continued-fraction poles and residues of the Fermi function (Sec. II B, Eq. (7)).
 //
 // With y = x/2 the truncated fraction is f_M(x) = 1/2 - tanh_M(y)/2, and
 // tanh_M(y) = y [(B + i y A)^{-1}]_{11} with B = diag(1, 3, ..., 2M-1) and A

@@ -1,7 +1,7 @@
 // Traces Tr(G(alpha_p) S) = sum_ij G_ij S_ji of the selected Green functions
 // over the pattern (S symmetric: S_ji = S_ij), one per pole of a batch.  They
 // give the density of states of the retarded Green function,
-// -(2/pi) Im Tr(G(E + i eta) S) (Sec. II C, Eq. (42)), used by the
+// -(2/pi) Im Tr(G(E + i eta) S) (Sec. II C 3, Eq. (42)), used by the
 // chemical-potential search.  Partial sums per workgroup; the host adds them
 // (a fixed order, so the result does not depend on scheduling).
 #include <hip/hip_runtime.h>

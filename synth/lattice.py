@@ -6,7 +6,9 @@ geometry with 4 orbitals per site and random blocks:
 
 * site index s = x + Lx (y + Ly z) (x fastest); basis index 4 s + orbital;
   the coordinates of every orbital are its site's lattice coordinates;
-* open boundaries;
+* open boundaries, or periodic ones (``periodic=True``: bonds also join
+  the last and the first site along every axis of length >= 3, the
+  couplings of the cell with its images folded onto one matrix);
 * H onsite block: 4x4 symmetric, upper triangle (with diagonal) iid N(0, 1) eV;
 * H bond block: an independent 4x4 block per bond, iid N(0, 0.5) eV (0.5 is
   the standard deviation), H_ts = H_st^T;
@@ -24,7 +26,7 @@ _NN = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
 _NN2 = [(1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)]
 
 
-def _bonds(dims, offsets):
+def _bonds(dims, offsets, periodic=False):
     lx, ly, lz = dims
     xs, ys, zs = np.meshgrid(np.arange(lx), np.arange(ly), np.arange(lz), indexing="ij")
     # lexicographic site order with x fastest
@@ -34,6 +36,10 @@ def _bonds(dims, offsets):
     src, dst = [], []
     for dx, dy, dz in offsets:
         tx, ty, tz = x + dx, y + dy, z + dz
+        if periodic:   # axes of length >= 3 wrap round
+            tx = np.where(lx >= 3, tx % lx, tx)
+            ty = np.where(ly >= 3, ty % ly, ty)
+            tz = np.where(lz >= 3, tz % lz, tz)
         ok = (tx >= 0) & (tx < lx) & (ty >= 0) & (ty < ly) & (tz >= 0) & (tz < lz)
         s = np.nonzero(ok)[0]
         t = tx[ok] + lx * (ty[ok] + ly * tz[ok])
@@ -44,9 +50,11 @@ def _bonds(dims, offsets):
     return np.zeros(0, np.int64), np.zeros(0, np.int64), np.stack([x, y, z], axis=1)
 
 
-def lattice(dims, neighbours="nn", seed=0, norb=4, onsite_std=1.0, hop_std=0.5, s_scale=0.05):
+def lattice(dims, neighbours="nn", seed=0, norb=4, onsite_std=1.0, hop_std=0.5, s_scale=0.05, periodic=False):
     """Build one system.  Returns a dict with n, row_ptr (int64), col (int32),
-    h, s (float64, CSR order, both triangles), coords (n x 3 float64), dims."""
+    h, s (float64, CSR order, both triangles), coords (n x 3 float64), dims,
+    and cell: None (open), or with periodic=True the cell lengths along x,
+    y, z (0 for an axis shorter than 3, which stays open)."""
     dims = tuple(int(d) for d in dims) + (1,) * (3 - len(dims))
     offsets = list(_NN)
     if neighbours == "nn2":
@@ -54,7 +62,7 @@ def lattice(dims, neighbours="nn", seed=0, norb=4, onsite_std=1.0, hop_std=0.5, 
     elif neighbours != "nn":
         raise ValueError("neighbours must be 'nn' or 'nn2'")
     offsets = [o for o in offsets if all(dims[a] > 1 or o[a] == 0 for a in range(3))]
-    src, dst, site_xyz = _bonds(dims, offsets)
+    src, dst, site_xyz = _bonds(dims, offsets, periodic)
     nsites = site_xyz.shape[0]
     nb = src.shape[0]
     rng = np.random.default_rng(seed)
@@ -88,8 +96,9 @@ def lattice(dims, neighbours="nn", seed=0, norb=4, onsite_std=1.0, hop_std=0.5, 
     np.add.at(row_ptr, r + 1, 1)
     row_ptr = np.cumsum(row_ptr)
     coords = np.repeat(site_xyz.astype(np.float64), norb, axis=0)
+    cell = [float(d) if d >= 3 else 0.0 for d in dims] if periodic else None
     return {"n": n, "row_ptr": row_ptr, "col": c.astype(np.int32), "h": h, "s": s,
-            "coords": coords, "dims": dims, "neighbours": neighbours, "seed": seed}
+            "coords": coords, "dims": dims, "neighbours": neighbours, "seed": seed, "cell": cell}
 
 
 def with_long_tail(sysd, m=3, frac=0.3, seed=0, onsite_std=1.0, hop_std=0.1, s_offdiag=0.2):

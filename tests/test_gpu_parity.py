@@ -383,6 +383,37 @@ def test_rho_against_dense_eigen_oracle(ctx, dims, nb, n_poles, coords):
     assert dense.trace_rho_s(got, sysd["s"]) == pytest.approx(sysd["n"], abs=1e-8)
 
 
+@pytest.mark.parametrize("dims,nb,precision,tol", [((12, 10), "nn2", "fp64", 1e-10), ((6, 6, 5), "nn", "fp64", 1e-10),
+                                                   ((40,), "nn", "fp64", 1e-10),
+                                                   ((12, 10), "nn2", "mixed_bf16x3", 1e-7)])
+def test_periodic_lattice_against_dense_eigen_oracle(dims, nb, precision, tol):
+    # periodic cells (Sec. II C 1): the dissection cuts the periodic lattice
+    # with two-plane separators (ndrho_set_structure_periodic); rho against
+    # the dense eigen oracle at half filling, and the periodic plan is much
+    # smaller than the one the open-boundary ordering finds for the same matrix
+    import paper_1005_0088_amd as nd
+    sysd = lattice(dims, nb, 70, periodic=True)
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    mu = dense.mu_for_count(eps, BETA, float(sysd["n"]))
+    ref = dense.rho_cf_pattern(eps, c, mu, BETA, 80, rows, cols)
+    print("case: periodic dims=%s nb=%s n=%d %s" % (dims, nb, sysd["n"], precision), flush=True)
+    with nd.Context(0, precision=precision, leaf_rows=16) as c:
+        sid = c.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"],
+                              cell=sysd["cell"])
+        c.set_poles(sid, mu, BETA, 80)
+        got = c.density_matrix(sid)
+        st = c.stats(sid)
+        open_sid = c.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"])
+        st_open = c.stats(open_sid)
+    err = np.max(np.abs(got - ref))
+    print("periodic %s: max err %.3e, flops/pole %.3g (open ordering %.3g)"
+          % (precision, err, st["flops_per_pole"], st_open["flops_per_pole"]))
+    assert err < tol
+    assert st["flops_per_pole"] < 0.5 * st_open["flops_per_pole"]
+    assert dense.trace_rho_s(got, sysd["s"]) == pytest.approx(sysd["n"], abs=1e-8 if precision == "fp64" else 1e-5)
+
+
 @pytest.mark.parametrize("n,with_coords", [(1, True), (1, False), (37, True), (37, False)])
 def test_diagonal_systems_closed_form(ctx, n, with_coords):
     # no couplings: every row is its own front (a forest of one-row roots);

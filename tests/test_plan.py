@@ -78,9 +78,10 @@ def _pattern(sysd):
     return rows, sysd["col"].astype(np.int64)
 
 
-def _check_plan(sysd, leaf, coords=True, long_tail=0.0):
+def _check_plan(sysd, leaf, coords=True, long_tail=0.0, cell=None):
     n = sysd["n"]
-    P = nd.Plan(n, sysd["row_ptr"], sysd["col"], sysd["coords"] if coords else None, leaf, long_tail=long_tail)
+    P = nd.Plan(n, sysd["row_ptr"], sysd["col"], sysd["coords"] if coords else None, leaf, long_tail=long_tail,
+                cell=cell)
     ex = P.export()
     perm = ex["perm"]
     assert np.array_equal(np.sort(perm), np.arange(n))
@@ -325,6 +326,76 @@ def test_long_tail_generator_keeps_s_positive_definite_and_symmetric():
     assert np.linalg.eigvalsh(s).min() > 0.0
     deg = np.diff(sysd["row_ptr"])
     assert np.all(deg[base["n"]:] >= int(0.3 * base["n"]))
+
+
+# --------------------------------------------------------- periodic cells
+
+def test_periodic_square_lattice_of_fig2():
+    # Sec. II C 1, Fig. 2: the s-valent nearest-neighbour square lattice of
+    # 1024 atoms in a periodic cell.  The first separator consists of two
+    # lines of atoms, there are six separator levels (0 ... 5), and every
+    # innermost domain holds 9 atoms.
+    sysd = lattice((32, 32), "nn", 0, norb=1, periodic=True)
+    assert sysd["n"] == 1024 and sysd["cell"] == [32.0, 32.0, 0.0]
+    P, ex = _check_plan(sysd, 16, cell=sysd["cell"])
+    nf, parent, nj, depth = P.n_fronts, ex["parent"], ex["nj"], ex["depth"]
+    leaves = [f for f in range(nf) if not np.any(parent == f)]
+    seps = [f for f in range(nf) if np.any(parent == f)]
+    roots = np.nonzero(parent < 0)[0]
+    assert len(roots) == 1
+    root = int(roots[0])
+    top = ex["perm"][ex["j0"][root]:ex["j0"][root] + nj[root]]
+    xy = sysd["coords"][top][:, :2]
+    # two full lines along one axis: 2 x 32 atoms with two distinct coordinates on the other
+    axis = [a for a in (0, 1) if len(np.unique(xy[:, a])) == 2]
+    assert nj[root] == 64 and len(axis) == 1
+    vals = np.unique(xy[:, axis[0]])
+    assert all(np.sum(xy[:, axis[0]] == v) == 32 for v in vals)
+    assert sorted({int(depth[f]) for f in seps}) == [0, 1, 2, 3, 4, 5]
+    assert {int(nj[f]) for f in leaves} == {9}
+    # without the cell the wrapping bonds defeat the cuts: one huge front
+    P0 = nd.Plan(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["coords"], 16)
+    assert P0.max_j > 900
+    assert P.model()[0] < 0.05 * P0.model()[0]
+
+
+@pytest.mark.parametrize("dims,nb,leaf,alpha", [((24,), "nn", 8, 0.2 + 0.5j), ((8, 7), "nn2", 16, -0.3 + 0.314j),
+                                                 ((4, 5, 3), "nn", 16, 1.0 + 2.0j), ((6, 2), "nn", 8, 0.5j)])
+def test_periodic_front_model_matches_dense_inverse(dims, nb, leaf, alpha):
+    # periodic lattices with 4 random orbitals per site (an axis shorter
+    # than 3 stays open): the plan is a valid front tree and the numpy front
+    # model through it gives the dense inverse on the pattern
+    sysd = lattice(dims, nb, 11, periodic=True)
+    n = sysd["n"]
+    rows, cols = _pattern(sysd)
+    h = np.zeros((n, n))
+    s = np.zeros((n, n))
+    h[rows, cols] = sysd["h"]
+    s[rows, cols] = sysd["s"]
+    assert np.array_equal(h, h.T) and np.linalg.eigvalsh(s).min() > 0.0
+    x = alpha * s - h
+    P, ex = _check_plan(sysd, leaf, cell=sysd["cell"])
+    flat = _model_selected_inverse(P, ex, x[np.ix_(ex["perm"], ex["perm"])])
+    out, _, _ = P.slots()
+    g = np.linalg.inv(x)
+    assert np.max(np.abs(flat[out] - g[rows, cols])) < 1e-11 * np.abs(g).max()
+    # the wrapping bonds are present (degree of a corner site equals the bulk's along periodic axes)
+    assert np.diff(sysd["row_ptr"]).min() == np.diff(sysd["row_ptr"]).max() or min(dims + (3,)) < 3
+
+
+def test_periodic_cell_rejected_without_coordinates_or_with_bad_lengths():
+    sysd = lattice((6, 6), "nn", 0, norb=1, periodic=True)
+    with pytest.raises(nd.NdrhoError) as e:
+        nd.Plan(sysd["n"], sysd["row_ptr"], sysd["col"], None, 8, cell=sysd["cell"])
+    assert e.value.name == "EINVAL"
+    with pytest.raises(nd.NdrhoError) as e:
+        nd.Plan(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["coords"], 8, cell=[6.0, -1.0, 0.0])
+    assert e.value.name == "EINVAL"
+    # open lattices are planned as before when a zero cell is given
+    op = lattice((6, 5, 4), "nn", 2)
+    a = nd.Plan(op["n"], op["row_ptr"], op["col"], op["coords"], 16).export()["perm"]
+    b = nd.Plan(op["n"], op["row_ptr"], op["col"], op["coords"], 16, cell=[0.0, 0.0, 0.0]).export()["perm"]
+    assert np.array_equal(a, b)
 
 
 def test_bench_refuses_several_gpus():
