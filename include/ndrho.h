@@ -282,7 +282,23 @@ typedef struct {
                                       launch chains (split_streams) */
 } ndrho_stats_t;
 
-int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out);
+/* Sizes, plan model and last-call figures of one structure.  Errors: EINVAL. */
+int ndrho_structure_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out);
+
+/* Figures of the context's evaluations (any argument may be NULL):
+ *   ms_per_phase[4]: kernel milliseconds, since profiling was last enabled
+ *     (ndrho_profile; zeros without it), of the four phases of the path:
+ *     [0] assembly of alpha S - H (Sec. II C), [1] the upward block LDL^T
+ *     sweep (extend-add, pivot inverses, L and Schur updates; Eqs. (18)-(20)),
+ *     [2] the downward selected inversion (Eqs. (21), (38)-(39)), [3] the pole
+ *     sum of Eq. (8) and its output;
+ *   *flops: algorithmic flops of the last evaluation (the plan's model, 8 real
+ *     flops per complex multiply-add, times the number of shifts);
+ *   *hbm_bytes: algorithmic HBM bytes of the last evaluation (the plan's model
+ *     of front data read and written once per pole, complex128).  Counter
+ *     readings of the device's actual traffic need a profiler.
+ * Errors: EINVAL (ctx NULL). */
+int ndrho_stats(const ndrho_ctx* ctx, double* ms_per_phase, double* flops, double* hbm_bytes);
 
 /* Kernel kinds reported by the profile below. */
 enum { NDRHO_K_EXTADD = 0, NDRHO_K_ASSEMBLE = 1, NDRHO_K_PIVOT_INV = 2, NDRHO_K_GEMM = 3, NDRHO_K_COPY = 4,
@@ -300,6 +316,10 @@ int ndrho_profile(ndrho_ctx* ctx, int32_t enable);
  * flops (complex GEMMs: 8 real flops per complex multiply-add, symmetric
  * outputs counted once), and launch counts; arrays of NDRHO_K_COUNT. */
 int ndrho_profile_read(const ndrho_ctx* ctx, double* ms, double* flops, int64_t* launches);
+/* Algorithmic bytes (operands read and results written once, complex128) of
+ * the profiled front-update GEMM launches per kind, bytes[NDRHO_K_COUNT]
+ * (zero for the other kinds).  EINVAL for NULL arguments. */
+int ndrho_profile_read_bytes(const ndrho_ctx* ctx, double* bytes);
 /* The same milliseconds split by dissection-tree depth of the launch:
  * ms[kind * NDRHO_PROFILE_DEPTHS + depth] (row-major, NDRHO_K_COUNT rows,
  * caller-owned, fully written); depths >= NDRHO_PROFILE_DEPTHS - 2 share the

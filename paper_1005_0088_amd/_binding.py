@@ -63,10 +63,12 @@ SIGNATURES = [
                                 C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32), _P]),
     ("ndrho_density_matrix_batch", C.c_int, [_P, _I32P, C.c_int32, C.POINTER(_P), C.c_int32]),
     ("ndrho_autotune", C.c_int, [_P, _I32P, C.c_int32, C.c_char_p]),
-    ("ndrho_stats", C.c_int, [_P, C.c_int32, C.POINTER(Stats)]),
+    ("ndrho_structure_stats", C.c_int, [_P, C.c_int32, C.POINTER(Stats)]),
+    ("ndrho_stats", C.c_int, [_P, _DP, _DP, _DP]),
     ("ndrho_profile", C.c_int, [_P, C.c_int32]),
     ("ndrho_profile_read", C.c_int, [_P, _DP, _DP, _I64P]),
     ("ndrho_profile_read_depth", C.c_int, [_P, _DP]),
+    ("ndrho_profile_read_bytes", C.c_int, [_P, _DP]),
     ("ndrho_device_alloc", C.c_int, [_P, C.c_int64, C.POINTER(_P)]),
     ("ndrho_device_free", C.c_int, [_P, _P]),
     ("ndrho_device_to_host", C.c_int, [_P, _P, _P, C.c_int64]),
@@ -399,8 +401,19 @@ class Context:
 
     def stats(self, sid):
         st = Stats()
-        self._check(self._lib.ndrho_stats(self._h, int(sid), C.byref(st)))
+        self._check(self._lib.ndrho_structure_stats(self._h, int(sid), C.byref(st)))
         return {k: getattr(st, k) for k, _ in Stats._fields_}
+
+    PHASES = ("assemble", "upward", "downward", "accumulate")
+
+    def phase_stats(self):
+        """ndrho_stats: profiled milliseconds per phase, and the algorithmic
+        flops and bytes of the last evaluation."""
+        ms = np.zeros(4)
+        fl, by = C.c_double(), C.c_double()
+        self._check(self._lib.ndrho_stats(self._h, _ptr(ms, C.c_double), C.byref(fl), C.byref(by)))
+        return {"ms_per_phase": dict(zip(self.PHASES, (float(x) for x in ms))), "flops": fl.value,
+                "hbm_bytes": by.value}
 
     KINDS = ("extadd", "assemble", "pivot_inv", "gemm", "copy", "gather", "accum", "gemm_pivot", "gemm_f32", "gemm_bf16x3")
 
@@ -414,7 +427,9 @@ class Context:
         nl = np.zeros(k, dtype=np.int64)
         self._check(self._lib.ndrho_profile_read(self._h, _ptr(ms, C.c_double), _ptr(fl, C.c_double),
                                                  _ptr(nl, C.c_int64)))
-        return {name: {"ms": float(ms[i]), "flops": float(fl[i]), "launches": int(nl[i])}
+        by = np.zeros(k)
+        self._check(self._lib.ndrho_profile_read_bytes(self._h, _ptr(by, C.c_double)))
+        return {name: {"ms": float(ms[i]), "flops": float(fl[i]), "launches": int(nl[i]), "bytes": float(by[i])}
                 for i, name in enumerate(self.KINDS)}
 
     def profile_read_depth(self):

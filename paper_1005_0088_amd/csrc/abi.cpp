@@ -204,20 +204,28 @@ struct ndrho_ctx {
     int kind;
     size_t ev;
     double flops;
+    double bytes;
     int op;  // program index of the launch (upward ops, then downward), -1 for the pole sum
     int depth;
+    int phase;
   };
   int cur_op = -1;
   int cur_depth = -1;
+  int cur_phase = 3;  // 0 assembly, 1 upward sweep, 2 downward sweep, 3 pole sum and the rest
   std::vector<double>* op_ms = nullptr;  // per-op milliseconds while autotuning
   std::vector<Rec> recs;
   double prof_ms[NDRHO_K_COUNT] = {0};
   double prof_flops[NDRHO_K_COUNT] = {0};
+  double prof_bytes[NDRHO_K_COUNT] = {0};
   int64_t prof_n[NDRHO_K_COUNT] = {0};
   double prof_depth_ms[NDRHO_K_COUNT * NDRHO_PROFILE_DEPTHS] = {0};
+  double prof_phase_ms[4] = {0};
+  // algorithmic flops and bytes (the plan's model) of the last evaluation
+  double last_flops = 0, last_bytes = 0;
   void clear_profile() {
-    for (int k = 0; k < NDRHO_K_COUNT; ++k) prof_ms[k] = prof_flops[k] = 0, prof_n[k] = 0;
+    for (int k = 0; k < NDRHO_K_COUNT; ++k) prof_ms[k] = prof_flops[k] = prof_bytes[k] = 0, prof_n[k] = 0;
     for (double& x : prof_depth_ms) x = 0;
+    for (double& x : prof_phase_ms) x = 0;
   }
 
   hipEvent_t event(size_t i) {
@@ -230,7 +238,7 @@ struct ndrho_ctx {
   }
   // bracket a launch when profiling
   template <class L>
-  void timed(int kind, double flops, L&& launch) {
+  void timed(int kind, double flops, L&& launch, double bytes = 0.0) {
     if (!prof) {
       launch();
       return;
@@ -239,7 +247,7 @@ struct ndrho_ctx {
     HIP_OK(hipEventRecord(event(i), stream));
     launch();
     HIP_OK(hipEventRecord(event(i + 1), stream));
-    recs.push_back(Rec{kind, i, flops, cur_op, cur_depth});
+    recs.push_back(Rec{kind, i, flops, bytes, cur_op, cur_depth, kind == NDRHO_K_ASSEMBLE ? 0 : cur_phase});
   }
   // fold recorded events into the totals (stream must be complete)
   void fold_profile() {
@@ -248,7 +256,9 @@ struct ndrho_ctx {
       HIP_OK(hipEventElapsedTime(&ms, events[r.ev], events[r.ev + 1]));
       prof_ms[r.kind] += ms;
       prof_flops[r.kind] += r.flops;
+      prof_bytes[r.kind] += r.bytes;
       prof_n[r.kind] += 1;
+      prof_phase_ms[r.phase] += ms;
       const int d = r.depth < 0 ? NDRHO_PROFILE_DEPTHS - 1 : std::min(r.depth, NDRHO_PROFILE_DEPTHS - 2);
       prof_depth_ms[r.kind * NDRHO_PROFILE_DEPTHS + d] += ms;
       if (op_ms && r.op >= 0 && r.op < static_cast<int>(op_ms->size())) (*op_ms)[r.op] += ms;
@@ -423,13 +433,13 @@ struct ndrho_ctx {
           };
           if (!split) {
             const DevOp h = fp64_launch(d);
-            timed(k64, op.flops * nb, [&] { e = launch_gemm(h, st); });
+            timed(k64, op.flops * nb, [&] { e = launch_gemm(h, st); }, op.bytes * nb);
             break;
           }
           if (nhi > 0) {  // FP64 for the poles nearest the real axis
             DevOp h = fp64_launch(d);
             h.npoles = nhi;
-            timed(k64, op.flops * nhi, [&] { e = launch_gemm(h, st); });
+            timed(k64, op.flops * nhi, [&] { e = launch_gemm(h, st); }, op.bytes * nhi);
             if (e != hipSuccess) break;
           }
           DevOp l = d;  // low-precision products for the others
@@ -445,7 +455,7 @@ struct ndrho_ctx {
           l.a += nhi * l.sa, l.b += nhi * l.sb, l.c += nhi * l.sc;
           if (op.flags & (G_BETA | G_EXTC0)) l.c0 += nhi * l.sc0;
           timed(l.bf3 ? NDRHO_K_GEMM_BF16X3 : NDRHO_K_GEMM_F32, op.flops * (nb - nhi),
-                [&] { e = launch_gemm(l, st); });
+                [&] { e = launch_gemm(l, st); }, op.bytes * (nb - nhi));
           break;
         }
         case OP_COPY:
@@ -466,11 +476,13 @@ struct ndrho_ctx {
       if (e != hipSuccess) fail(NDRHO_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     };
     cur_op = 0;
+    cur_phase = 1;
     for (const Op& op : P.upward) {
       cur_depth = op.depth;
       run(op);
       ++cur_op;
     }
+    cur_phase = 2;
     for (const Op& op : P.downward) {
       cur_depth = op.depth;
       run(op);
@@ -478,6 +490,7 @@ struct ndrho_ctx {
     }
     cur_op = -1;
     cur_depth = -1;
+    cur_phase = 3;
   }
 
   // Passes of less work than this run as one chain: there the fork and join
@@ -507,6 +520,8 @@ struct ndrho_ctx {
     const int nb = batch_for(P, n);
     ensure_ws(P, nb);
     last_batch = nb;
+    last_flops = P.flops_model * n;
+    last_bytes = P.bytes_model * n;
     auto record = [&] {
       HIP_OK(launch_init_acc(S.m0, P.nnz, add_m0 ? 1 : 0, acc, status, stream));
       if (edm) HIP_OK(launch_init_edm(S.m1, S.m0, S.kappa, P.nnz, acc_e, stream));
@@ -1535,7 +1550,7 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
   });
 }
 
-int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out) {
+int ndrho_structure_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out) {
   if (!ctx || !out) return NDRHO_EINVAL;
   ndrho_ctx* c = const_cast<ndrho_ctx*>(ctx);
   return guarded(c, [&] {
@@ -1566,6 +1581,15 @@ int ndrho_stats(const ndrho_ctx* ctx, int32_t struct_id, ndrho_stats_t* out) {
   });
 }
 
+int ndrho_stats(const ndrho_ctx* ctx, double* ms_per_phase, double* flops, double* hbm_bytes) {
+  if (!ctx) return NDRHO_EINVAL;
+  if (ms_per_phase)
+    for (int k = 0; k < 4; ++k) ms_per_phase[k] = ctx->prof_phase_ms[k];
+  if (flops) *flops = ctx->last_flops;
+  if (hbm_bytes) *hbm_bytes = ctx->last_bytes;
+  return NDRHO_OK;
+}
+
 int ndrho_profile(ndrho_ctx* ctx, int32_t enable) {
   if (!ctx) return NDRHO_EINVAL;
   return guarded(ctx, [&] {
@@ -1583,6 +1607,12 @@ int ndrho_profile_read(const ndrho_ctx* ctx, double* ms, double* flops, int64_t*
     if (flops) flops[k] = ctx->prof_flops[k];
     if (launches) launches[k] = ctx->prof_n[k];
   }
+  return NDRHO_OK;
+}
+
+int ndrho_profile_read_bytes(const ndrho_ctx* ctx, double* bytes) {
+  if (!ctx || !bytes) return NDRHO_EINVAL;
+  for (int k = 0; k < NDRHO_K_COUNT; ++k) bytes[k] = ctx->prof_bytes[k];
   return NDRHO_OK;
 }
 

@@ -381,10 +381,18 @@ struct Builder {
     op.count = static_cast<int64_t>(probs.size());
     op.tile_begin = static_cast<int64_t>(P.gemm_tiles.size());
     op.depth = depth;
-    double fl = 0;
+    double fl = 0, by = 0;
     for (size_t i = 0; i < probs.size(); ++i) {
       const GemmProb& g = probs[i];
       P.gemm.push_back(g);
+      // algorithmic bytes: A (lower triangle if stored so), B, C written (lower
+      // triangle unless mirrored), C0 read with G_BETA, the children's
+      // entries of a G_EXTC0 sum taken as one read per result element
+      const double ea = (flags & G_SYMA) ? double(g.k) * (g.k + 1) / 2 : double(g.m) * g.k;
+      const double ec = (flags & G_SYM) ? ((flags & G_NOMIRROR) ? double(g.n) * (g.n + 1) / 2 : double(g.m) * g.n)
+                                        : double(g.m) * g.n;
+      const double ec0 = (flags & G_SYM) ? double(g.n) * (g.n + 1) / 2 : double(g.m) * g.n;
+      by += 16.0 * (ea + double(g.k) * g.n + ec + ((flags & (G_BETA | G_EXTC0)) ? ec0 : 0.0));
       const int tm = (g.m + 63) / 64, tn = (g.n + 63) / 64;
       for (int a = 0; a < tm; ++a)
         for (int b = 0; b < tn; ++b) {
@@ -428,6 +436,7 @@ struct Builder {
       if (std::max(ea, eb) >= 2147483632.0) op.off32 = false;
     }
     op.flops = fl;
+    op.bytes = by;
     P.flops_exec += fl;
     prog.push_back(op);
   }
@@ -667,6 +676,14 @@ void finalize_plan(Plan& P) {
   std::vector<std::vector<int>> by_depth(P.n_levels);
   for (int f = 0; f < nf; ++f) by_depth[P.fronts[f].depth].push_back(f);
   int64_t po = 0;
+  for (int f = 0; f < nf; ++f) {
+    const Front& F = P.fronts[f];
+    // the extend-add and gather kernels index a front's panel and update
+    // block with 32-bit element numbers
+    if (int64_t(F.nj + F.nu) * F.nj >= (int64_t(1) << 32) || int64_t(F.nu) * F.nu >= (int64_t(1) << 32))
+      fail(NDRHO_EINVAL, "a front of " + std::to_string(F.nj) + " pivot and " + std::to_string(F.nu) +
+                             " update rows exceeds 2^32 elements per block");
+  }
   for (int f = 0; f < nf; ++f) {
     Front& F = P.fronts[f];
     F.panel_off = po;

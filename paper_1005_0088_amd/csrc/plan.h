@@ -106,6 +106,7 @@ struct Op {
   int64_t inv16 = 0, inv32 = 0;  // SMALLINV: leading descriptors with n <= 16, then n <= 32
   int depth = 0;
   double flops = 0;          // useful flops per pole (GEMM)
+  double bytes = 0;          // algorithmic bytes per pole: operands read and results written once, complex128
 };
 
 struct Plan {

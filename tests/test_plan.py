@@ -176,6 +176,22 @@ def test_plan_empty_and_disconnected():
     assert sorted(int(x) for x in ex["perm"]) == [0, 1, 2]
 
 
+def test_plan_rejects_front_beyond_32_bit_element_indexing():
+    # a chain of 65536 rows kept as one leaf front: its 65536 x 65536 panel has
+    # 2^32 elements, beyond the 32-bit element numbering of the extend-add
+    # and gather kernels, so the plan is refused before anything is sized
+    n = 1 << 16
+    i = np.arange(n)
+    rows = np.concatenate([i, i[:-1], i[1:]])
+    cols = np.concatenate([i, i[1:], i[:-1]])
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    row_ptr = np.searchsorted(rows, np.arange(n + 1))
+    with pytest.raises(nd.NdrhoError) as e:
+        nd.Plan(n, row_ptr, cols, None, 1 << 30)
+    assert e.value.name == "EINVAL" and "2^32" in str(e.value)
+
+
 def test_plan_rejects_bad_csr():
     sysd = lattice((4, 3), "nn", 0)
     col = sysd["col"].copy()
