@@ -162,6 +162,15 @@ def edm_poles_dense(h, s, mu, beta, n_poles, rows, cols):
     return e
 
 
+def eigenstates_near(h, s, xi, k):
+    """The k eigenpairs of Eq. (2) whose eigenvalues lie nearest the energy xi
+    (Appendix B, Eq. (B1): the states a block shift-invert iteration around
+    xi converges to).  Returns (eps ascending, C with C^T S C = I)."""
+    eps, c = eigen(h, s)
+    idx = np.sort(np.argsort(np.abs(eps - xi), kind="stable")[:k])
+    return eps[idx], c[:, idx]
+
+
 def green_trace_s(h, s, alpha):
     """Tr(G(alpha) S) by a dense complex inverse (Eqs. (6), (42))."""
     return complex(np.trace(green_dense(h, s, alpha) @ to_dense(s)))

@@ -337,3 +337,40 @@ def test_appendix_a_intermediates():
     assert np.allclose(l10, it["L10T"]) and np.allclose(l11, it["L11T"])
     s10 = x[6, 6] - b10 @ l10 - b11 @ l11
     assert s10 == pytest.approx(it["S10"])
+
+
+# ------------------------------------------------------------- selected eigenstates (Appendix B)
+
+@pytest.mark.parametrize("n,a,b,s,xi,k", [(60, 0.1, -1.0, 0.12, 0.3, 5), (41, -0.2, 0.8, -0.2, -0.5, 8)])
+def test_eigenstates_near_match_closed_form_chain(n, a, b, s, xi, k):
+    # the k eigenvalues nearest xi of the open chain, from the closed form
+    # eps_j = (a + 2 b c_j)/(1 + 2 s c_j) with eigenvectors phi_j / sqrt(1 + 2 s c_j)
+    hm, sm = chain.chain_matrices(n, a, b, s)
+    eps, c = dense.eigenstates_near(hm, sm, xi, k)
+    ck, phi = chain.chain_modes(n)
+    ref = (a + 2.0 * b * ck) / (1.0 + 2.0 * s * ck)
+    pick = np.sort(np.argsort(np.abs(ref - xi))[:k])
+    order = np.argsort(ref[pick])
+    assert np.allclose(eps, ref[pick][order], rtol=0, atol=1e-12)
+    for col, j in zip(c.T, pick[order]):
+        v = phi[:, j] / np.sqrt(1.0 + 2.0 * s * ck[j])     # S-normalised closed-form vector
+        assert abs(abs(v @ sm @ col) - 1.0) < 1e-10
+    assert np.allclose(c.T @ sm @ c, np.eye(k), atol=1e-12)
+
+
+def test_eigenstates_near_satisfy_shift_invert_relation():
+    # Eq. (B1): (H - xi S)^{-1} S c = c / (eps - xi) for each returned pair
+    from synth import lattice
+    sysd = lattice((5, 4), "nn2", 3)
+    n = sysd["n"]
+    rows = np.repeat(np.arange(n), np.diff(sysd["row_ptr"]))
+    h = np.zeros((n, n))
+    s = np.zeros((n, n))
+    h[rows, sysd["col"]] = sysd["h"]
+    s[rows, sysd["col"]] = sysd["s"]
+    xi = 0.17
+    eps, c = dense.eigenstates_near(h, s, xi, 6)
+    lhs = np.linalg.solve(h - xi * s, s @ c)
+    assert np.allclose(lhs, c / (eps - xi)[None, :], rtol=1e-9, atol=1e-9)
+    allev = np.linalg.eigvalsh(np.linalg.solve(np.linalg.cholesky(s), np.linalg.solve(np.linalg.cholesky(s), h).T))
+    assert np.max(np.abs(eps - xi)) <= np.sort(np.abs(allev - xi))[5] + 1e-12
