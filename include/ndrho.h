@@ -209,6 +209,29 @@ int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta
                   double tol, int32_t max_iter, int32_t retarded_step, double* mu_out, double* delta_n_out,
                   int32_t* iters_out, double* rho_out);
 
+/* The k eigenpairs (H c = eps S c, Eq. (2)) nearest the energy xi, by the
+ * block shift-invert iteration of Appendix B: B_l = X^{-1} S C_l (Eq. (B2))
+ * through the factor X = L D L^T of X = alpha S - H, alpha = xi + i eta,
+ * stored by one upward sweep (Eq. (B5)) and applied in the three tree passes
+ * of Eqs. (B8)-(B14); then the projected problem <b|H|b> c = <b|S|b> c eps
+ * (Eq. (B3)) on the real basis [Re B_l, Im B_l], with the null directions of
+ * its S-metric removed, gives the next block of 16 Ritz vectors (the 16 Ritz
+ * values nearest xi; the first k are the wanted ones, the rest speed the
+ * iteration).  eta > 0 keeps every pivot of the unpivoted factorization
+ * nonsingular (the Hermitian part of -i X is then positive definite) without
+ * changing the eigenpairs, which the projection recovers from the real and
+ * imaginary parts; eta = 0 factors the real X, where a tiny pivot returns
+ * ESINGULAR.  The iteration stops when every wanted Ritz pair has
+ * ||H c - eps S c||_2 <= tol (c S-normalised, tol in the unit of H), or
+ * after max_iter iterations (not an error: check resid_out).
+ * k in [1, min(16, n)].  Outputs (host): eps_out[k] ascending; c_out (may be
+ * NULL) n*k, column i the eigenvector of eps_out[i] in the caller's row order,
+ * c^T S c = 1 (sign arbitrary); iters_out, resid_out[k] (may be NULL).
+ * Errors: EINVAL (bad k, xi, eta, tol, max_iter; eps_out NULL), ESINGULAR,
+ * EDEVICE, ENOMEM. */
+int ndrho_eigenstates(ndrho_ctx* ctx, int32_t struct_id, double xi, double eta, int32_t k, int32_t max_iter,
+                      double tol, double* eps_out, double* c_out, int32_t* iters_out, double* resid_out);
+
 /* Energy density matrix e on the pattern (Sec. II B, Eqs. (10)-(11)) together
  * with rho from the same selected Green functions:
  *   e = M1 + kappa M0 + sum_p Im(-(4i/beta) G(alpha_p) R_p alpha_p),

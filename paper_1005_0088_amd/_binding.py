@@ -58,6 +58,8 @@ SIGNATURES = [
     ("ndrho_density_matrix", C.c_int, [_P, C.c_int32, _P, C.c_int32]),
     ("ndrho_energy_density_matrix", C.c_int, [_P, C.c_int32, _P, _P, C.c_int32]),
     ("ndrho_energy_density_matrix_batch", C.c_int, [_P, _I32P, C.c_int32, C.POINTER(_P), C.POINTER(_P), C.c_int32]),
+    ("ndrho_eigenstates", C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_double, _DP, _DP,
+                                    _I32P, _DP]),
     ("ndrho_green_traces", C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P]),
     ("ndrho_find_mu", C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                 C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32), _P]),
@@ -264,6 +266,7 @@ class Context:
             raise NdrhoError(rc, self._lib.ndrho_last_error(None).decode())
         self._h = h
         self._nnz = {}
+        self._n = {}
 
     def _check(self, rc):
         if rc:
@@ -285,6 +288,7 @@ class Context:
                 self._h, int(n), _ptr(rp, C.c_int64), _ptr(cl, C.c_int32), _ptr(hv, C.c_double),
                 _ptr(sv, C.c_double), _ptr(xyz, C.c_double), _ptr(cl3, C.c_double), C.byref(sid)))
         self._nnz[sid.value] = int(rp[-1])
+        self._n[sid.value] = int(n)
         return sid.value
 
     def update_values(self, sid, h, s):
@@ -321,6 +325,20 @@ class Context:
             raise ValueError("out must be a numpy array or a DeviceBuffer of nnz elements from this context")
         self._check(self._lib.ndrho_density_matrix(self._h, int(sid), C.c_void_p(out.ptr), 1))
         return out
+
+    def eigenstates(self, sid, xi, k, eta=1e-3, max_iter=200, tol=1e-9, vectors=True):
+        """The k eigenpairs nearest xi (ndrho_eigenstates).  Returns (eps,
+        C (n x k, or None), iterations, residual norms)."""
+        n = self._n[int(sid)]
+        eps = np.empty(int(k))
+        res = np.empty(int(k))
+        c = np.empty((int(k), n)) if vectors else None
+        it = C.c_int32()
+        self._check(self._lib.ndrho_eigenstates(self._h, int(sid), float(xi), float(eta), int(k), int(max_iter),
+                                                float(tol), _ptr(eps, C.c_double),
+                                                _ptr(c, C.c_double) if vectors else None, C.byref(it),
+                                                _ptr(res, C.c_double)))
+        return eps, (c.T.copy() if vectors else None), it.value, res
 
     def green_traces(self, sid, alpha):
         """Tr(G(alpha_k) S) for an array of complex shifts (see ndrho_green_traces)."""

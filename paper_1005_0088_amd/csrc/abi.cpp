@@ -79,6 +79,21 @@ struct DevStruct {
   // captured launch sequence of a full evaluation, valid for `gkey`
   hipGraphExec_t gexec = nullptr;
   std::vector<const void*> gkey;
+  // solves through the stored factor (selected eigenstates), built on first use
+  struct EigenPlan {
+    bool built = false;
+    SolveFront* fronts = nullptr;
+    SolveChild* kids = nullptr;
+    int32_t *inv = nullptr, *urows = nullptr, *perm = nullptr, *iperm = nullptr, *col = nullptr;
+    int64_t* rp = nullptr;
+    SolveTile* gtiles = nullptr;
+    TsProb* probs = nullptr;
+    TsTile* ttiles = nullptr;
+    int64_t w_rows = 0;
+    // per depth: forward-gather tiles, forward / backward product tiles; one range for the diagonal
+    std::vector<int64_t> g_begin, f_begin, b_begin;
+    int64_t d_begin = 0, d_count = 0;
+  } eig;
 
   template <class T>
   T* put(const std::vector<T>& v, hipStream_t st) {
@@ -86,9 +101,13 @@ struct DevStruct {
     if (p) allocs.push_back(p);
     return p;
   }
-  void release() {
+  void drop_graph() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     gexec = nullptr;
+    gkey.clear();
+  }
+  void release() {
+    drop_graph();
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
     if (d_alpha) (void)hipFree(d_alpha);
@@ -101,6 +120,7 @@ struct DevStruct {
 };
 
 thread_local std::string g_err;  // errors without a context (create, plan utilities)
+
 
 // max_i sum_j |A_ij| of a matrix on the plan's pattern (values in CSR order)
 double row_sum_norm(const Plan& P, const double* a) {
@@ -267,21 +287,32 @@ struct ndrho_ctx {
   }
 
   ~ndrho_ctx() {
+    // Teardown order: the streams' work completes, the captured graphs go,
+    // the device drains, the further streams and events go, and only then is
+    // memory freed (memory that a graph with forked streams ran on was
+    // otherwise kept by the runtime after hipFree).
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (int i = 0; i < kMaxChains; ++i)
+      if (side[i]) (void)hipStreamSynchronize(side[i]);
+    for (auto& s : structs)
+      if (s) s->drop_graph();
+    for (auto& u : unions) u.second->drop_graph();
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    for (int i = 0; i < kMaxChains; ++i) {
+      if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
+      if (side[i]) (void)hipStreamDestroy(side[i]);
+    }
     for (auto& s : structs)
       if (s) s->release();
     for (auto& u : unions) u.second->release();
-    for (hipEvent_t e : events) (void)hipEventDestroy(e);
     if (ws) (void)hipFree(ws);
     if (acc) (void)hipFree(acc);
     if (outbuf) (void)hipFree(outbuf);
     if (acc_e) (void)hipFree(acc_e);
     if (outbuf_e) (void)hipFree(outbuf_e);
     if (status) (void)hipFree(status);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    for (int i = 0; i < kMaxChains; ++i) {
-      if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
-      if (side[i]) (void)hipStreamDestroy(side[i]);
-    }
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
@@ -300,7 +331,18 @@ struct ndrho_ctx {
   void ensure_ws(const Plan& P, int nb) {
     const size_t need = static_cast<size_t>(per_pole_elems(P)) * nb * sizeof(double2);
     if (need > ws_bytes) {
-      if (ws) HIP_OK(hipFree(ws));
+      if (ws) {
+        // graphs captured on the old workspace go first (their keys hold its
+        // address, so they would be captured again anyway)
+        HIP_OK(hipStreamSynchronize(stream));
+        for (int i = 0; i < kMaxChains; ++i)
+          if (side[i]) HIP_OK(hipStreamSynchronize(side[i]));
+        for (auto& s : structs)
+          if (s) s->drop_graph();
+        for (auto& u : unions) u.second->drop_graph();
+        HIP_OK(hipDeviceSynchronize());
+        HIP_OK(hipFree(ws));
+      }
       ws = nullptr;
       ws_bytes = 0;
       if (hipMalloc(&ws, need) != hipSuccess) {
@@ -356,7 +398,7 @@ struct ndrho_ctx {
   // disjoint position ranges share no memory but the pivot status counters,
   // which are updated atomically.
   void run_pass(DevStruct& S, int nlay, int q0, int nb, const double2* alpha, int64_t astride, double hcoef,
-                int spd_check, int nhi, hipStream_t st) {
+                int spd_check, int nhi, hipStream_t st, bool up_only = false) {
     const Plan& P = S.plan;
     double2* bufs[BUF_COUNT];
     int64_t strides[BUF_COUNT];
@@ -484,6 +526,7 @@ struct ndrho_ctx {
     }
     cur_phase = 2;
     for (const Op& op : P.downward) {
+      if (up_only) break;
       cur_depth = op.depth;
       run(op);
       ++cur_op;
@@ -606,7 +649,32 @@ struct ndrho_ctx {
         }
       }
     };
-    if (!opt.use_graph || prof) {
+    // Does any pass run as several launch chains?  (the same test as in record)
+    bool any_split = false;
+    if (opt.split_streams > 0 && !prof && n_hi > 0 && n_hi < n) {
+      const int npass = (n + nb - 1) / nb;
+      const bool spread = npass > 1;
+      int c0 = 0, h0 = 0;
+      for (int b = 0; b < npass; ++b) {
+        const int cnt = std::min(nb, n - c0);
+        int nhi;
+        if (spread) {
+          const int h1 = static_cast<int>(int64_t(n_hi) * (c0 + cnt) / n);
+          nhi = h1 - h0;
+          h0 = h1;
+        } else {
+          nhi = std::max(0, std::min(cnt, n_hi - c0));
+        }
+        c0 += cnt;
+        any_split = any_split || (nhi > 0 && nhi < cnt && P.flops_exec * cnt >= kSplitMinFlops);
+      }
+    }
+    // Evaluations with several launch chains are not captured: device memory
+    // that a graph with forked streams had run on stayed allocated after
+    // hipFree on this runtime (measured: the whole workspace of every such
+    // context), and their launches are long enough that graph replay gains
+    // little there.
+    if (!opt.use_graph || prof || any_split) {
       record();
       return;
     }
@@ -895,6 +963,136 @@ struct ndrho_ctx {
     unions.clear();
   }
 
+  // Tables of the solve X^{-1} y through the stored factor (Appendix B):
+  // fronts by depth, the children's inverse maps, update-row lists, and the
+  // tiles of the forward gather and of the grouped products of each step.
+  void build_eigen_plan(DevStruct& S) {
+    DevStruct::EigenPlan& E = S.eig;
+    if (E.built) return;
+    const Plan& P = S.plan;
+    const int nf = static_cast<int>(P.fronts.size());
+    std::vector<int> order(nf), pos(nf);
+    for (int f = 0; f < nf; ++f) order[f] = f;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P.fronts[a].depth < P.fronts[b].depth; });
+    for (int i = 0; i < nf; ++i) pos[order[i]] = i;
+    std::vector<int64_t> wrow(nf, 0), urow(nf, 0);
+    int64_t wr = 0, ur = 0;
+    std::vector<int32_t> urows;
+    for (int f = 0; f < nf; ++f) {
+      wrow[f] = wr;
+      wr += P.fronts[f].nu;
+      urow[f] = ur;
+      ur += P.fronts[f].nu;
+      urows.insert(urows.end(), P.fronts[f].u.begin(), P.fronts[f].u.end());
+    }
+    E.w_rows = std::max<int64_t>(wr, 1);
+    if (urows.empty()) urows.push_back(0);
+    std::vector<SolveFront> fr(nf);
+    std::vector<SolveChild> kids;
+    std::vector<int32_t> inv;
+    for (int i = 0; i < nf; ++i) {
+      const Front& F = P.fronts[order[i]];
+      SolveFront d{F.j0, wrow[order[i]] * EIG_NR, F.nj, F.nu, static_cast<int32_t>(kids.size()),
+                   static_cast<int32_t>(F.children.size())};
+      for (int c : F.children) {
+        const Front& C = P.fronts[c];
+        kids.push_back(SolveChild{wrow[c] * EIG_NR, static_cast<int64_t>(inv.size()), C.nu, 0});
+        std::vector<int32_t> m(F.nj + F.nu, -1);
+        for (int k = 0; k < C.nu; ++k) m[C.rel[k]] = k;
+        inv.insert(inv.end(), m.begin(), m.end());
+      }
+      fr[i] = d;
+    }
+    if (kids.empty()) kids.push_back(SolveChild{0, 0, 0, 0});
+    if (inv.empty()) inv.push_back(-1);
+    const int nd = P.n_levels;
+    std::vector<SolveTile> gt;
+    std::vector<TsProb> probs;
+    std::vector<TsTile> tt;
+    auto add_prob = [&](const TsProb& p) {
+      const int32_t id = static_cast<int32_t>(probs.size());
+      probs.push_back(p);
+      for (int m0 = 0; m0 < p.m; m0 += 64) tt.push_back(TsTile{id, m0});
+    };
+    E.g_begin.assign(nd + 1, 0);
+    E.f_begin.assign(nd + 1, 0);
+    E.b_begin.assign(nd + 1, 0);
+    auto range_of = [&](int d, int& lo, int& hi) {
+      lo = static_cast<int>(std::lower_bound(order.begin(), order.end(), d,
+                                             [&](int f, int v) { return P.fronts[f].depth < v; }) - order.begin());
+      hi = static_cast<int>(std::upper_bound(order.begin(), order.end(), d,
+                                             [&](int v, int f) { return v < P.fronts[f].depth; }) - order.begin());
+    };
+    for (int d = 0; d < nd; ++d) {  // forward gather tiles and forward products, per depth
+      int lo, hi;
+      range_of(d, lo, hi);
+      E.g_begin[d] = static_cast<int64_t>(gt.size());
+      for (int i = lo; i < hi; ++i)
+        for (int r0 = 0; r0 < fr[i].nj + fr[i].nu; r0 += EIG_GROWS) gt.push_back(SolveTile{i, r0});
+      E.f_begin[d] = static_cast<int64_t>(tt.size());
+      for (int i = lo; i < hi; ++i) {
+        const Front& F = P.fronts[order[i]];
+        if (F.nu == 0) continue;
+        add_prob(TsProb{F.l_off, F.j0, wrow[order[i]], wrow[order[i]], F.nu, F.nu, F.nj, 0});
+      }
+    }
+    E.g_begin[nd] = static_cast<int64_t>(gt.size());
+    E.f_begin[nd] = static_cast<int64_t>(tt.size());
+    E.d_begin = static_cast<int64_t>(tt.size());
+    for (int i = 0; i < nf; ++i) {  // diagonal: every front at once
+      const Front& F = P.fronts[order[i]];
+      add_prob(TsProb{F.panel_off, F.j0, F.j0, 0, F.nj + F.nu, F.nj, F.nj, 0});
+    }
+    E.d_count = static_cast<int64_t>(tt.size()) - E.d_begin;
+    for (int d = 0; d < nd; ++d) {  // backward products, per depth
+      int lo, hi;
+      range_of(d, lo, hi);
+      E.b_begin[d] = static_cast<int64_t>(tt.size());
+      for (int i = lo; i < hi; ++i) {
+        const Front& F = P.fronts[order[i]];
+        add_prob(TsProb{F.l_off, urow[order[i]], F.j0, F.j0, std::max(F.nu, 1), F.nj, F.nu, 0});
+      }
+    }
+    E.b_begin[nd] = static_cast<int64_t>(tt.size());
+    E.fronts = S.put(fr, stream);
+    E.kids = S.put(kids, stream);
+    E.inv = S.put(inv, stream);
+    E.urows = S.put(urows, stream);
+    E.gtiles = S.put(gt, stream);
+    E.probs = S.put(probs, stream);
+    E.ttiles = S.put(tt, stream);
+    E.perm = S.put(P.perm, stream);
+    E.iperm = S.put(P.iperm, stream);
+    E.rp = S.put(P.row_ptr, stream);
+    E.col = S.put(P.col, stream);
+    HIP_OK(hipStreamSynchronize(stream));
+    E.built = true;
+  }
+
+  // x = X^{-1} y through the factor held in the workspace (pole 0): the
+  // three steps of Eqs. (B8)-(B14); y, z, z2, x: n x EIG_NR complex in the
+  // permuted order; w: the update blocks.
+  void solve_factor(DevStruct& S, const double2* y, double2* z, double2* z2, double2* x, double2* w) {
+    const Plan& P = S.plan;
+    const DevStruct::EigenPlan& E = S.eig;
+    double2* bufs[BUF_COUNT];
+    int64_t strides[BUF_COUNT];
+    layout(P, 1, bufs, strides);
+    const double2* L = bufs[BUF_L];
+    const double2* panel = bufs[BUF_PANEL];
+    for (int d = P.n_levels - 1; d >= 0; --d) {
+      HIP_OK(launch_solve_gather(E.fronts, E.kids, E.inv, E.gtiles + E.g_begin[d], E.g_begin[d + 1] - E.g_begin[d],
+                                 y, z, w, stream));
+      HIP_OK(launch_tsgemm(TS_FORWARD, E.probs, E.ttiles + E.f_begin[d], E.f_begin[d + 1] - E.f_begin[d], L, z,
+                           nullptr, w, w, stream));
+    }
+    HIP_OK(launch_tsgemm(TS_DIAGONAL, E.probs, E.ttiles + E.d_begin, E.d_count, panel, z, nullptr, nullptr, z2,
+                         stream));
+    for (int d = 0; d < P.n_levels; ++d)
+      HIP_OK(launch_tsgemm(TS_BACKWARD, E.probs, E.ttiles + E.b_begin[d], E.b_begin[d + 1] - E.b_begin[d], L, x,
+                           E.urows, z2, x, stream));
+  }
+
   void set_shifts(DevStruct& S, const std::vector<double2>& alpha_in, const std::vector<double>& w_in,
                   bool add_m0, bool cf) {
     // Mixed mode keeps in FP64 the fp64_poles shifts nearest the real axis,
@@ -1170,6 +1368,65 @@ double muller_step(const double* mu, const double* dn) {
   return mu[0] + x;
 }
 
+// Eigenpairs of a real symmetric n x n matrix a (row-major) by cyclic Jacobi
+// rotations: eigenvalues w ascending, eigenvectors as the columns of v
+// (row-major n x n).
+void sym_eig(int n, std::vector<double> a, std::vector<double>& w, std::vector<double>& v) {
+  v.assign(static_cast<size_t>(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) v[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += a[i * n + j] * a[i * n + j];
+        if (i != j) off += a[i * n + j] * a[i * n + j];
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[p * n + q];
+        if (apq == 0.0) continue;
+        const double th = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = a[k * n + p], akq = a[k * n + q];
+          a[k * n + p] = c * akp - sn * akq;
+          a[k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = a[p * n + k], aqk = a[q * n + k];
+          a[p * n + k] = c * apk - sn * aqk;
+          a[q * n + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = v[k * n + p], vkq = v[k * n + q];
+          v[k * n + p] = c * vkp - sn * vkq;
+          v[k * n + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return a[x * n + x] < a[y * n + y]; });
+  std::vector<double> vs(static_cast<size_t>(n) * n);
+  w.resize(n);
+  for (int j = 0; j < n; ++j) {
+    w[j] = a[idx[j] * n + idx[j]];
+    for (int k = 0; k < n; ++k) vs[k * n + j] = v[k * n + idx[j]];
+  }
+  v.swap(vs);
+}
+
+// Counter-based uniform numbers in [-1, 1) (SplitMix64 of the counter).
+double splitmix_uniform(uint64_t i) {
+  uint64_t z = i + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return static_cast<double>(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
 }  // namespace
 
 int ndrho_set_poles(ndrho_ctx* ctx, int32_t struct_id, double mu, double beta, int32_t n_poles) {
@@ -1323,6 +1580,181 @@ int ndrho_find_mu(ndrho_ctx* ctx, int32_t struct_id, double n_ideal, double beta
     if (delta_n_out) *delta_n_out = d;
     if (iters_out) *iters_out = static_cast<int32_t>(hm.size());
     if (rho_out) std::memcpy(rho_out, rho.data(), P.nnz * sizeof(double));
+  });
+}
+
+int ndrho_eigenstates(ndrho_ctx* ctx, int32_t struct_id, double xi, double eta, int32_t k, int32_t max_iter,
+                      double tol, double* eps_out, double* c_out, int32_t* iters_out, double* resid_out) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    DevStruct& ds = ctx->get(struct_id);
+    const Plan& P = ds.plan;
+    const int64_t n = P.n;
+    if (k < 1 || k > EIG_NR || k > n) fail(NDRHO_EINVAL, "k must be in [1, min(16, n)]");
+    if (!std::isfinite(xi) || !(eta >= 0.0) || !std::isfinite(eta)) fail(NDRHO_EINVAL, "xi finite and eta >= 0 required");
+    if (max_iter < 1 || !(tol > 0.0)) fail(NDRHO_EINVAL, "max_iter >= 1 and tol > 0 required");
+    if (!eps_out) fail(NDRHO_EINVAL, "eps_out is required");
+    HIP_OK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    ctx->build_eigen_plan(ds);
+    const DevStruct::EigenPlan& E = ds.eig;
+    // device buffers of this call
+    std::vector<void*> mem;
+    auto dalloc = [&](size_t bytes) {
+      void* p = nullptr;
+      if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(NDRHO_ENOMEM, "eigenstate buffers");
+      }
+      mem.push_back(p);
+      return p;
+    };
+    struct Free {
+      std::vector<void*>& m;
+      ~Free() {
+        for (void* p : m) (void)hipFree(p);
+      }
+    } free_guard{mem};
+    constexpr int NB = 2 * EIG_NR;
+    const size_t cvec = static_cast<size_t>(n) * EIG_NR * sizeof(double2);
+    double2* y = static_cast<double2*>(dalloc(cvec));
+    double2* z = static_cast<double2*>(dalloc(cvec));
+    double2* z2 = static_cast<double2*>(dalloc(cvec));
+    double2* x = static_cast<double2*>(dalloc(cvec));
+    double2* w = static_cast<double2*>(dalloc(static_cast<size_t>(E.w_rows) * EIG_NR * sizeof(double2)));
+    double* V = static_cast<double*>(dalloc(static_cast<size_t>(n) * NB * sizeof(double)));
+    double* HV = static_cast<double*>(dalloc(static_cast<size_t>(n) * NB * sizeof(double)));
+    double* SV = static_cast<double*>(dalloc(static_cast<size_t>(n) * NB * sizeof(double)));
+    double* C = static_cast<double*>(dalloc(static_cast<size_t>(n) * EIG_NR * sizeof(double)));
+    double* HC = static_cast<double*>(dalloc(static_cast<size_t>(n) * EIG_NR * sizeof(double)));
+    double* SC = static_cast<double*>(dalloc(static_cast<size_t>(n) * EIG_NR * sizeof(double)));
+    double* Yc = static_cast<double*>(dalloc(NB * EIG_NR * sizeof(double)));
+    double* th = static_cast<double*>(dalloc(EIG_NR * sizeof(double)));
+    const int nblk = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(256, (n + 255) / 256)));
+    const int64_t chunk = (n + nblk - 1) / nblk;
+    double* part = static_cast<double*>(dalloc(static_cast<size_t>(nblk) * NB * NB * sizeof(double)));
+    double2* d_alpha = static_cast<double2*>(dalloc(sizeof(double2)));
+
+    // factor X = alpha S - H, alpha = xi + i eta (upward sweep of one pole, FP64)
+    const double2 alpha = make_double2(xi, eta);
+    HIP_OK(hipMemcpyAsync(d_alpha, &alpha, sizeof(double2), hipMemcpyHostToDevice, st));
+    ctx->ensure_ws(P, 1);
+    HIP_OK(launch_init_acc(ds.m0, 0, 0, ctx->acc, ctx->status, st));
+    ctx->run_pass(ds, 1, 0, 1, d_alpha, 0, 1.0, 0, 1, st, true);
+    int stat[2];
+    HIP_OK(hipMemcpyAsync(stat, ctx->status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (stat[0]) fail(NDRHO_ESINGULAR, "a zero, tiny or non-finite pivot occurred in alpha S - H (use eta > 0)");
+
+    // starting block: counter-based uniform numbers
+    std::vector<double> h0(static_cast<size_t>(n) * EIG_NR);
+    for (size_t i = 0; i < h0.size(); ++i) h0[i] = splitmix_uniform(i);
+    HIP_OK(hipMemcpyAsync(C, h0.data(), h0.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    std::vector<double> hp(static_cast<size_t>(nblk) * NB * NB), hs(NB * NB), hh(NB * NB);
+    std::vector<double> theta(EIG_NR, 0.0), res(EIG_NR, 0.0), ycoef(NB * EIG_NR, 0.0);
+    auto gram = [&](const double* W, std::vector<double>& out) {
+      HIP_OK(launch_gram(V, W, n, chunk, nblk, part, st));
+      HIP_OK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      for (int e = 0; e < NB * NB; ++e) {
+        double acc = 0.0;
+        for (int b = 0; b < nblk; ++b) acc += hp[static_cast<size_t>(b) * NB * NB + e];
+        out[e] = acc;
+      }
+      for (int i = 0; i < NB; ++i)  // symmetrize the rounding
+        for (int j = 0; j < i; ++j) out[i * NB + j] = out[j * NB + i] = 0.5 * (out[i * NB + j] + out[j * NB + i]);
+    };
+    int it = 0;
+    bool done = false;
+    std::vector<int> wanted;
+    while (it < max_iter && !done) {
+      ++it;
+      // Eq. (B2): B = X^{-1} S C; the real basis V = [Re B, Im B]
+      HIP_OK(launch_spmm_perm(E.rp, E.col, ds.s, E.perm, n, C, y, st));
+      ctx->solve_factor(ds, y, z, z2, x, w);
+      HIP_OK(launch_unperm_split(x, E.iperm, n, V, st));
+      HIP_OK(launch_spmm2(E.rp, E.col, ds.h, n, V, HV, st));
+      HIP_OK(launch_spmm2(E.rp, E.col, ds.s, n, V, SV, st));
+      // Eq. (B3): <V|H|V> y = <V|S|V> y eps, with the S-metric's null
+      // directions removed (canonical orthogonalization)
+      gram(HV, hh);
+      gram(SV, hs);
+      std::vector<double> ls, us;
+      sym_eig(NB, hs, ls, us);
+      const double lmax = std::max(ls[NB - 1], 0.0);
+      std::vector<int> keep;
+      for (int i = 0; i < NB; ++i)
+        if (ls[i] > 1e-13 * lmax) keep.push_back(i);
+      const int r = static_cast<int>(keep.size());
+      if (r == 0) fail(NDRHO_ESINGULAR, "the shift-invert block vanished");
+      std::vector<double> W(static_cast<size_t>(NB) * r);  // NB x r, W = U_keep diag(l^-1/2)
+      for (int i = 0; i < NB; ++i)
+        for (int j = 0; j < r; ++j) W[i * r + j] = us[i * NB + keep[j]] / std::sqrt(ls[keep[j]]);
+      std::vector<double> ht(static_cast<size_t>(r) * r, 0.0);  // W^T Hs W
+      for (int a = 0; a < r; ++a)
+        for (int b = 0; b < r; ++b) {
+          double acc = 0.0;
+          for (int i = 0; i < NB; ++i) {
+            double t = 0.0;
+            for (int j = 0; j < NB; ++j) t += hh[i * NB + j] * W[j * r + b];
+            acc += W[i * r + a] * t;
+          }
+          ht[a * r + b] = acc;
+        }
+      for (int a = 0; a < r; ++a)
+        for (int b = 0; b < a; ++b) ht[a * r + b] = ht[b * r + a] = 0.5 * (ht[a * r + b] + ht[b * r + a]);
+      std::vector<double> lt, zt;
+      sym_eig(r, ht, lt, zt);
+      // the Ritz pairs nearest xi fill the next block (nearest first)
+      std::vector<int> ord(r);
+      for (int i = 0; i < r; ++i) ord[i] = i;
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(lt[a] - xi) < std::fabs(lt[b] - xi); });
+      const int m = std::min(r, EIG_NR);
+      std::fill(ycoef.begin(), ycoef.end(), 0.0);
+      std::fill(theta.begin(), theta.end(), 0.0);
+      for (int c = 0; c < m; ++c) {
+        theta[c] = lt[ord[c]];
+        for (int i = 0; i < NB; ++i) {
+          double acc = 0.0;
+          for (int j = 0; j < r; ++j) acc += W[i * r + j] * zt[j * r + ord[c]];
+          ycoef[i * EIG_NR + c] = acc;
+        }
+      }
+      HIP_OK(hipMemcpyAsync(Yc, ycoef.data(), ycoef.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      HIP_OK(hipMemcpyAsync(th, theta.data(), theta.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      HIP_OK(launch_combine(V, Yc, n, C, st));
+      HIP_OK(launch_combine(HV, Yc, n, HC, st));
+      HIP_OK(launch_combine(SV, Yc, n, SC, st));
+      HIP_OK(launch_resid(HC, SC, th, n, chunk, nblk, part, st));
+      std::vector<double> rp(static_cast<size_t>(nblk) * EIG_NR);
+      HIP_OK(hipMemcpyAsync(rp.data(), part, rp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      for (int c = 0; c < EIG_NR; ++c) {
+        double acc = 0.0;
+        for (int b = 0; b < nblk; ++b) acc += rp[static_cast<size_t>(b) * EIG_NR + c];
+        res[c] = std::sqrt(acc);
+      }
+      if (m < k) continue;  // not enough independent directions yet
+      done = true;
+      for (int c = 0; c < k; ++c) done = done && res[c] <= tol;
+    }
+    // the k Ritz pairs nearest xi, ascending in energy
+    std::vector<int> pick(k);
+    for (int c = 0; c < k; ++c) pick[c] = c;
+    std::sort(pick.begin(), pick.end(), [&](int a, int b) { return theta[a] < theta[b]; });
+    for (int c = 0; c < k; ++c) {
+      eps_out[c] = theta[pick[c]];
+      if (resid_out) resid_out[c] = res[pick[c]];
+    }
+    if (iters_out) *iters_out = it;
+    if (c_out) {
+      std::vector<double> hc(static_cast<size_t>(n) * EIG_NR);
+      HIP_OK(hipMemcpyAsync(hc.data(), C, hc.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      for (int c = 0; c < k; ++c)
+        for (int64_t i = 0; i < n; ++i) c_out[int64_t(c) * n + i] = hc[static_cast<size_t>(i) * EIG_NR + pick[c]];
+    }
+    HIP_OK(hipStreamSynchronize(st));
   });
 }
 

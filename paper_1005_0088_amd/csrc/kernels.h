@@ -43,6 +43,49 @@ struct DevOp {
   int64_t sa = 0, sb = 0, sc0 = 0, sc = 0;
 };
 
+// ---- selected eigenstates (eigen.hip): block vectors of EIG_NR columns
+constexpr int EIG_NR = 16;     // columns of a block vector
+constexpr int EIG_GROWS = 16;  // rows of a forward-gather tile (EIG_GROWS x EIG_NR threads)
+// One front of the solve through the stored factor, fronts ordered by depth.
+struct SolveFront {
+  int64_t j0;     // first pivot row (permuted position)
+  int64_t w_off;  // its update rows' block in the update buffer (complex elements, EIG_NR per row)
+  int32_t nj, nu, child_begin, child_count;
+};
+struct SolveChild {
+  int64_t w_off;    // the child's update block (complex elements)
+  int64_t inv_off;  // its inverse map over the parent's local rows (J then U): child update row or -1
+  int32_t nu, pad;
+};
+struct SolveTile {  // EIG_GROWS local rows of one front
+  int32_t front, r0;
+};
+// C rows (c_off + r) = [C0 rows (c0_off + r)] +/- op(A) B, A at a_off (column-major, lda), B rows b_off + k
+// (or idx[b_off + k]); row offsets count rows of EIG_NR complex values.
+struct TsProb {
+  int64_t a_off, b_off, c_off, c0_off;
+  int32_t lda, m, k, pad;
+};
+struct TsTile {  // 64 rows of one problem
+  int32_t prob, m0;
+};
+enum { TS_FORWARD = 0, TS_DIAGONAL = 1, TS_BACKWARD = 2 };
+hipError_t launch_spmm_perm(const int64_t* rp, const int32_t* col, const double* a, const int32_t* perm, int64_t n,
+                            const double* x, double2* y, hipStream_t st);
+hipError_t launch_spmm2(const int64_t* rp, const int32_t* col, const double* a, int64_t n, const double* x, double* w,
+                        hipStream_t st);
+hipError_t launch_solve_gather(const SolveFront* fronts, const SolveChild* kids, const int32_t* inv,
+                               const SolveTile* tiles, int64_t ntiles, const double2* y, double2* z, double2* w,
+                               hipStream_t st);
+hipError_t launch_tsgemm(int mode, const TsProb* probs, const TsTile* tiles, int64_t ntiles, const double2* A,
+                         const double2* B, const int32_t* idx, const double2* C0, double2* C, hipStream_t st);
+hipError_t launch_unperm_split(const double2* x, const int32_t* iperm, int64_t n, double* v, hipStream_t st);
+hipError_t launch_gram(const double* V, const double* W, int64_t n, int64_t chunk, int nblk, double* part,
+                       hipStream_t st);
+hipError_t launch_combine(const double* V, const double* Y, int64_t n, double* out, hipStream_t st);
+hipError_t launch_resid(const double* hc, const double* sc, const double* theta, int64_t n, int64_t chunk, int nblk,
+                        double* part, hipStream_t st);
+
 hipError_t launch_extadd(const DevOp& o, hipStream_t st);
 hipError_t launch_assemble(const DevOp& o, const double* hv, const double* sv, const double2* alpha,
                            int64_t astride, double hcoef, hipStream_t st);
