@@ -22,8 +22,8 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
-# split-BF16 front updates: 4 real products x 6 slice products of 2 flops per
-# complex multiply-add (8 useful flops)
+# split-BF16 front updates execute 4 real products x 6 slice products of 2
+# flops per complex multiply-add, for 8 useful flops
 BF16X3_EXEC_PER_USEFUL = 48.0 / 8.0
 HBM_PEAK_GBS = 8000.0
 
@@ -42,28 +42,78 @@ WORKLOADS = {
 FP64_POLES = {"cubic3d_40x4": 12}
 
 
-def cpu_baseline(sysd, mu, beta, n_poles, budget_s=15.0):
-    """The oracle's sampled-column route timed on the host: GMRES solves of
-    (alpha_1 S - H) x = e_j for the pole nearest the real axis, columns drawn
-    until the budget is used; scaled to poles/s as 1 / (N * seconds per column)
-    since the full selected rho of one pole needs every column by this route."""
-    from oracle import poles, sampled
-    h, s = sampled.csr_matrices(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"])
+def cpu_baseline(sysd, mu, beta, n_poles, budget_s=20.0):
+    """The oracle timed on the host's cores (BLAS threads = all cores): its
+    per-pole dense route (one complex128 inverse of alpha_p S - H per pole,
+    oracle.dense.green_dense) and its eigen route (generalized eigensolve,
+    oracle.dense.eigen, at the sizes half the budget allows) are timed on
+    lattices of the same kind at n = 1024, 2048, 4096 (one pole each, while
+    the budget lasts), fitted as c n^3 and extrapolated to the
+    workload's n (the dense matrix of the workload itself does not fit the
+    host at the 3D sizes).  poles/s = 1 / (extrapolated seconds per pole)."""
+    import platform
+    import subprocess
+    from oracle import dense, poles
+    from synth import lattice
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
+        blas = ", ".join(sorted({"%s %s" % (i.get("internal_api"), i.get("version")) for i in info
+                                 if i.get("user_api") == "blas"}))
+    except Exception:
+        threads, blas = os.cpu_count() or 1, "unknown"
+    try:
+        model = [l.split(":", 1)[1].strip() for l in subprocess.run(["lscpu"], capture_output=True, text=True,
+                                                                   timeout=10).stdout.splitlines()
+                 if l.startswith("Model name")][0]
+    except Exception:
+        model = platform.processor() or "unknown"
+    dims = sysd["dims"]
+    ndim = sum(1 for d in dims if d > 1)
+    shapes = {1: [(256,), (512,), (1024,)], 2: [(16, 16), (32, 16), (32, 32)], 3: [(8, 8, 4), (8, 8, 8), (16, 8, 8)]}
     z, _ = poles.cf_poles(n_poles)
     alpha = mu + 1j * z[0] / beta
-    rng = np.random.default_rng(7)
+    t_pole, t_eig, ns, ns_eig = [], [], [], []
     t0 = time.time()
-    cols = 0
-    while True:
-        j = int(rng.integers(sysd["n"]))
-        sampled.green_column_gmres(h, s, alpha, j)
-        cols += 1
+    for shp in shapes[ndim]:
+        small = lattice(shp, sysd.get("neighbours", "nn"), 7)
+        h, s = _dense_pair(small)
+        a = time.perf_counter()
+        dense.green_dense(h, s, alpha)
+        ns.append(small["n"])
+        t_pole.append(time.perf_counter() - a)
+        if time.time() - t0 < 0.5 * budget_s:   # the eigen route at the sizes the budget allows
+            a = time.perf_counter()
+            dense.eigen(h, s)
+            ns_eig.append(small["n"])
+            t_eig.append(time.perf_counter() - a)
         if time.time() - t0 > budget_s:
             break
-    dt = (time.time() - t0) / cols
-    return {"value": 1.0 / (sysd["n"] * dt), "unit": "poles/s", "cores": 1, "kind": "oracle",
-            "sample": "GMRES(200), rtol 1e-13, for %d columns of G(alpha_1) (lowest pole) of the same system; "
-                      "%.3f s per column; scaled by N=%d columns per pole" % (cols, dt, sysd["n"])}
+    ns, ns_eig = np.asarray(ns, dtype=float), np.asarray(ns_eig, dtype=float)
+    # least squares fit of t = k n^3 on the measured sizes (the largest weigh most)
+    k_pole = float(np.sum(np.asarray(t_pole) * ns ** 3) / np.sum(ns ** 6))
+    k_eig = float(np.sum(np.asarray(t_eig) * ns_eig ** 3) / np.sum(ns_eig ** 6))
+    n_big = float(sysd["n"])
+    sec_pole = k_pole * n_big ** 3
+    return {"value": 1.0 / sec_pole, "unit": "poles/s", "cores": int(threads), "kind": "oracle",
+            "sample": "oracle per-pole dense route (complex128 inverse of alpha S - H, one pole) timed at n = %s "
+                      "(%s s) on %d BLAS threads, fitted as k n^3 and extrapolated to n = %d: %.3g s per pole; "
+                      "eigen route (generalized eigensolve) %s s at n = %s, extrapolated %.3g s"
+                      % ([int(x) for x in ns], [round(x, 3) for x in t_pole], threads, int(n_big), sec_pole,
+                         [round(x, 3) for x in t_eig], [int(x) for x in ns_eig], k_eig * n_big ** 3),
+            "extrapolated": True, "nproc": os.cpu_count(), "lscpu_model": model, "blas": blas,
+            "eigen_route_s_extrapolated": k_eig * n_big ** 3}
+
+
+def _dense_pair(sysd):
+    n = sysd["n"]
+    rows = np.repeat(np.arange(n), np.diff(sysd["row_ptr"]))
+    h = np.zeros((n, n))
+    s = np.zeros((n, n))
+    h[rows, sysd["col"]] = sysd["h"]
+    s[rows, sysd["col"]] = sysd["s"]
+    return h, s
 
 
 def measured_traffic(name, precision):
@@ -142,6 +192,7 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
     step()
     prof = ctx.profile_read()
     by_depth = ctx.profile_read_depth()
+    phases = ctx.phase_stats()
     ctx.profile(False)
     rho = [o.numpy() for o in outs]
     for o in outs:
@@ -152,6 +203,7 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
         e_out.free()
     ctx.close()
     res = {"precision": precision, "setup_s": setup_s, "ms_per_step": 1e3 * dt / steps, "e": e_vals,
+           "phases": phases,
            "poles_per_s": n_poles * steps / dt, "stats": st, "prof": prof,
            "ms_by_depth": {k: [round(float(x), 3) for x in v] for k, v in by_depth.items() if v.any()},
            "flops_model_per_step": n_poles * sum(x["flops_per_pole"] for x in st)}
@@ -289,9 +341,10 @@ def main():
     else:
         g, peak, kname = prof["gemm_f32"], FP32_MFMA_PEAK_TFLOPS, "k_cgemm32 (complex front-update GEMMs, FP32 products)"
     useful = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
-    achieved = useful * exec_per_useful
     gemm_tf = {k: (v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0)
                for k, v in prof.items() if k.startswith("gemm")}
+    alg_bytes_per_launch = g["bytes"] / max(1, g["launches"])
+    traffic = measured_traffic(name, head["precision"])
 
     line = {
         "metric": "poles/sec (selected inversion) on 3D 24^3x4 at 1e-7 rho error; MFMA TFLOP/s",
@@ -307,7 +360,10 @@ def main():
         "dtype": {"fp64": "f64", "mixed_fp32": "f64+f32", "mixed_bf16x3": "f64+bf16x3"}[head["precision"]],
         "data": "synthetic",
         "config": {"workload": name, "description": WORKLOADS[name], "structures": len(systems), "n": n,
-                   "nnz": nnz, "n_poles": n_poles, "kT_eV": 1.0 / BETA, "mu_eV": mu, "precision": head["precision"],
+                   "nnz": nnz, "n_poles": n_poles, "kT_eV": 1.0 / BETA, "mu_eV": mu,
+                   "mu_rule": "fixed at 0 eV for every workload (H is drawn symmetric about 0; on the 24^3 x 4 "
+                              "lattice the half-filling mu from ndrho_find_mu is -0.0037 eV)",
+                   "precision": head["precision"],
                    "fp64_poles": st["n_fp64_poles"], "fronts": sum(x["n_fronts"] for x in head["stats"]),
                    "levels": max(x["n_levels"] for x in head["stats"]), "root_j": st["root_j"],
                    "pole_batch": st["pole_batch"]},
@@ -332,12 +388,19 @@ def main():
         "kernel_ms_by_depth": head["ms_by_depth"],
         "gemm_tflops": gemm_tf,
         "roofline": {"kernel": kname, "bound": "mfma",
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "useful_complex_tflops": useful,
-                     "traffic": measured_traffic(name, head["precision"]),
-                     "traffic_unit": "bytes per launch (calibrated HBM read + write)",
+                     "achieved": useful, "peak": peak, "unit": "TFLOP/s",
+                     "frac": useful / peak,
+                     "achieved_counts": "useful complex flops (8 per complex multiply-add) per launch / average "
+                                        "launch duration (HIP events on the launching stream)",
+                     "executed_tflops": useful * exec_per_useful, "executed_frac": useful * exec_per_useful / peak,
+                     "traffic": traffic,
+                     "traffic_unit": "bytes per launch (calibrated HBM read + write, timed launch mix)",
+                     "algorithmic_bytes_per_launch": alg_bytes_per_launch,
+                     "traffic_over_algorithmic": (traffic / alg_bytes_per_launch
+                                                  if traffic and alg_bytes_per_launch > 0 else None),
                      "launches": g["launches"], "avg_launch_ms": g["ms"] / max(1, g["launches"]),
                      "flops_per_step": g["flops"]},
+        "ms_per_phase": head["phases"]["ms_per_phase"],
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(systems[-1], mu, BETA, n_poles, args.cpu_seconds)
