@@ -181,6 +181,25 @@ int ndrho_density_matrix(ndrho_ctx* ctx, int32_t struct_id, double* rho_out, int
 int ndrho_green_traces(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double* alpha_re, const double* alpha_im,
                        double* tr_re, double* tr_im);
 
+/* rho as ndrho_density_matrix with on_device = 1, for callers that cannot
+ * allocate device memory during the call (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the call allocates nothing.
+ * Its pole workspace, pole-sum accumulator and pivot status live in a fixed
+ * device array of 64 MiB (67108864 bytes) that the library holds on every
+ * device it runs on until the process ends; the structure, its poles and
+ * rho_out_dev (nnz doubles on the context's device, CSR order) are the
+ * caller's, set up beforehand as for ndrho_density_matrix.  The poles run in
+ * passes of as many as fit beside the accumulator, as one chain of plain
+ * launches on the context stream (no graph, no further streams); the call
+ * synchronises the stream.  The result equals ndrho_density_matrix's.
+ * Every call on one device shares that device's array, which keeps the
+ * contents of the last call (the call clears what it needs cleared): calls
+ * that overlap on one device, from any context, race.
+ * Errors: ENOMEM (one pole of the structure, with its accumulator, needs more
+ * than the array holds; the message gives both sizes), EINVAL (NULL output),
+ * ESTATE (no poles set), ESINGULAR, EDEVICE. */
+int ndrho_density_matrix_noalloc(ndrho_ctx* ctx, int32_t struct_id, double* rho_out_dev);
+
 /* Chemical potential with Tr(rho(mu) S) = n_ideal (Sec. II C 3, "Finding
  * chemical potential", Eqs. (40), (44)-(46)): each step sets the structure's
  * poles at a trial mu (as ndrho_set_poles with beta, n_poles), evaluates rho

@@ -56,6 +56,7 @@ SIGNATURES = [
     ("ndrho_set_poles", C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32]),
     ("ndrho_set_shifts", C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _DP, C.c_int32]),
     ("ndrho_density_matrix", C.c_int, [_P, C.c_int32, _P, C.c_int32]),
+    ("ndrho_density_matrix_noalloc", C.c_int, [_P, C.c_int32, _P]),
     ("ndrho_energy_density_matrix", C.c_int, [_P, C.c_int32, _P, _P, C.c_int32]),
     ("ndrho_energy_density_matrix_batch", C.c_int, [_P, _I32P, C.c_int32, C.POINTER(_P), C.POINTER(_P), C.c_int32]),
     ("ndrho_eigenstates", C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_double, _DP, _DP,
@@ -324,6 +325,15 @@ class Context:
         if not isinstance(out, DeviceBuffer) or out.ctx is not self or out.n != nnz:
             raise ValueError("out must be a numpy array or a DeviceBuffer of nnz elements from this context")
         self._check(self._lib.ndrho_density_matrix(self._h, int(sid), C.c_void_p(out.ptr), 1))
+        return out
+
+    def density_matrix_noalloc(self, sid, out):
+        """rho into a DeviceBuffer of nnz elements through the entry point that
+        allocates nothing (ndrho_density_matrix_noalloc)."""
+        nnz = self._nnz[int(sid)]
+        if not isinstance(out, DeviceBuffer) or out.ctx is not self or out.n != nnz:
+            raise ValueError("out must be a DeviceBuffer of nnz elements from this context")
+        self._check(self._lib.ndrho_density_matrix_noalloc(self._h, int(sid), C.c_void_p(out.ptr)))
         return out
 
     def eigenstates(self, sid, xi, k, eta=1e-3, max_iter=200, tol=1e-9, vectors=True):

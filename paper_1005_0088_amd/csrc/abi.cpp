@@ -10,6 +10,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -121,6 +122,32 @@ struct DevStruct {
 
 thread_local std::string g_err;  // errors without a context (create, plan utilities)
 
+// Fixed device scratch of the no-allocation entry point
+// (ndrho_density_matrix_noalloc): the pole workspace, the pole-sum
+// accumulator and the pivot status words of one call live here instead of in
+// allocations.  Each device holds its own copy at its own address, looked up
+// once per device (hipGetSymbolAddress) and kept in scratch_addr; host code
+// passes only that address to kernels and copies, never the symbol itself.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double2 scratch[kScratchBytes / sizeof(double2)];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Address of this device's scratch (the device must be current); looked up
+// on the first call for the device.
+void* scratch_addr(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(NDRHO_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      fail(NDRHO_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[device] = p;
+  }
+  return g_scratch_addr[device];
+}
 
 // max_i sum_j |A_ij| of a matrix on the plan's pattern (values in CSR order)
 double row_sum_norm(const Plan& P, const double* a) {
@@ -215,6 +242,7 @@ struct ndrho_ctx {
   double* outbuf_e = nullptr;
   int64_t acc_e_len = 0;
   int* status = nullptr;
+  void* scratch = nullptr;  // this device's fixed scratch (no-allocation entry point)
   double last_ms = 0;
   int last_batch = 0;
   // profiling: events around launches, folded into per-kind totals
@@ -1242,6 +1270,7 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
       c->own_stream = true;
     }
     if (hipMalloc(&c->status, 2 * sizeof(int)) != hipSuccess) fail(NDRHO_ENOMEM, "status allocation failed");
+    c->scratch = scratch_addr(device);
   });
   if (rc == NDRHO_OK) *out = c.release();
   return rc;
@@ -1774,6 +1803,60 @@ int ndrho_set_shifts(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const double*
     }
     HIP_OK(hipSetDevice(ctx->device));
     ctx->set_shifts(ds, a, w, add_m0 != 0, false);
+  });
+}
+
+int ndrho_density_matrix_noalloc(ndrho_ctx* ctx, int32_t struct_id, double* rho_out_dev) {
+  if (!ctx) return NDRHO_EINVAL;
+  return guarded(ctx, [&] {
+    DevStruct& ds = ctx->get(struct_id);
+    if (!rho_out_dev) fail(NDRHO_EINVAL, "rho_out_dev is NULL");
+    if (ds.n_shifts < 1) fail(NDRHO_ESTATE, "set_poles (or set_shifts) has not been called for this structure");
+    HIP_OK(hipSetDevice(ctx->device));
+    const Plan& P = ds.plan;
+    // scratch layout: [status (256 B)][accumulator, nnz doubles, 256-aligned][workspace]
+    const size_t acc_bytes = (static_cast<size_t>(P.nnz) * sizeof(double) + 255) / 256 * 256;
+    const size_t per_pole = static_cast<size_t>(ndrho_ctx::per_pole_elems(P)) * sizeof(double2);
+    if (256 + acc_bytes + per_pole > kScratchBytes)
+      fail(NDRHO_ENOMEM, "the structure needs " + std::to_string(256 + acc_bytes + per_pole) +
+                             " bytes of scratch for one pole; the no-allocation entry point holds " +
+                             std::to_string(kScratchBytes));
+    const size_t ws_room = kScratchBytes - 256 - acc_bytes;
+    const int nb = static_cast<int>(std::min<size_t>(static_cast<size_t>(ds.n_shifts), ws_room / per_pole));
+    char* base = static_cast<char*>(ctx->scratch);
+    // the evaluation runs on the scratch: one launch chain of plain launches
+    // (no graph, no further streams), passes of nb poles
+    struct Swap {
+      ndrho_ctx* c;
+      void* ws;
+      size_t ws_bytes;
+      double* acc;
+      int64_t acc_len;
+      int* status;
+      ndrho_options opt;
+      bool prof;
+      ~Swap() {
+        c->ws = ws, c->ws_bytes = ws_bytes, c->acc = acc, c->acc_len = acc_len, c->status = status, c->opt = opt;
+        c->prof = prof;
+      }
+    } swap{ctx, ctx->ws, ctx->ws_bytes, ctx->acc, ctx->acc_len, ctx->status, ctx->opt, ctx->prof};
+    ctx->status = reinterpret_cast<int*>(base);
+    ctx->acc = reinterpret_cast<double*>(base + 256);
+    ctx->acc_len = P.nnz;
+    ctx->ws = base + 256 + acc_bytes;
+    ctx->ws_bytes = ws_room;
+    ctx->opt.use_graph = 0;
+    ctx->opt.split_streams = 0;
+    ctx->opt.pole_batch = nb;
+    ctx->prof = false;
+    const auto t0 = std::chrono::steady_clock::now();
+    ctx->evaluate(ds, ds.d_alpha, 0, ds.d_w, ds.n_shifts, ds.n_hi, ds.add_m0, 1.0, 0);
+    HIP_OK(launch_scatter(ds.acc_entry, P.nnz, ctx->acc, rho_out_dev, ctx->stream));
+    int st[2];
+    HIP_OK(hipMemcpyAsync(st, ctx->status, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    if (st[0]) fail(NDRHO_ESINGULAR, "a zero, tiny or non-finite pivot occurred in alpha S - H");
+    ctx->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   });
 }
 
