@@ -36,10 +36,11 @@ WORKLOADS = {
 }
 
 # Shifts kept in FP64 at each end of the pole list (nearest and farthest from
-# the real axis) in the mixed forms.  The 40^3 x 4 system needs 12 + 12 to stay
-# within 1e-7 of the complex128 result (8 + 8 leaves 1.03e-7 there, 12 + 12
+# the real axis) in the mixed forms, as measured against the complex128 result
+# of the same input (bar 1e-7): 24^3 x 4 keeps 4 + 4 (6.6e-8; 2 + 2 leaves
+# 8.8e-8, 8 + 8 3.1e-8); 40^3 x 4 needs 12 + 12 (8 + 8 leaves 1.03e-7, 12 + 12
 # 8.4e-8); the others meet it with the library default of 8 + 8.
-FP64_POLES = {"cubic3d_40x4": 12}
+FP64_POLES = {"cubic3d_24x4": 4, "cubic3d_40x4": 12}
 
 
 def cpu_baseline(sysd, mu, beta, n_poles, budget_s=20.0):
