@@ -261,8 +261,10 @@ def main():
                     help="with --find-mu: take the second trial from the retarded Green function")
     ap.add_argument("--energy", action="store_true",
                     help="time energy_density_matrix (rho and the energy density matrix e of the same poles)")
-    ap.add_argument("--split-streams", type=int, default=1,
-                    help="mixed forms: launch chains beside the main one (0 = one chain; see ndrho_options)")
+    ap.add_argument("--split-streams", type=int, default=0,
+                    help="mixed forms: launch chains beside the main one (default 0: one captured chain, so that "
+                         "the kernels' durations in the timed steps are those of the instrumented step and of "
+                         "the profiler's trace; 1 runs the FP64 poles beside, about 1 %% faster on 24^3 x 4)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
