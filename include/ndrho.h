@@ -101,6 +101,11 @@ typedef struct {
                             off; L >= 1: in every domain of the dissection, rows whose number of
                             pattern neighbours inside the domain exceeds L times the domain's median
                             join the domain's separator before the cut is sought */
+  int32_t small_fronts;  /* must be 0 (the default): every front runs level by level.  Reserved for
+                            a persistent schedule of the small fronts (one launch per pass and
+                            direction taking (front, pole) tasks in tree order); that schedule is
+                            disabled, since its launches stalled on gfx950 with the cause not
+                            found, and any other value fails with NDRHO_EINVAL */
 } ndrho_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -345,10 +350,11 @@ int ndrho_stats(const ndrho_ctx* ctx, double* ms_per_phase, double* flops, doubl
 /* Kernel kinds reported by the profile below. */
 enum { NDRHO_K_EXTADD = 0, NDRHO_K_ASSEMBLE = 1, NDRHO_K_PIVOT_INV = 2, NDRHO_K_GEMM = 3, NDRHO_K_COPY = 4,
        NDRHO_K_GATHER = 5, NDRHO_K_ACCUM = 6, NDRHO_K_GEMM_PIVOT = 7, NDRHO_K_GEMM_F32 = 8,
-       NDRHO_K_GEMM_BF16X3 = 9, NDRHO_K_COUNT = 10 };
+       NDRHO_K_GEMM_BF16X3 = 9, NDRHO_K_SMALL = 10, NDRHO_K_COUNT = 11 };
 /* NDRHO_K_GEMM: FP64 front-update GEMMs; NDRHO_K_GEMM_PIVOT: FP64 GEMMs of the
  * recursive pivot-block inverse; NDRHO_K_GEMM_F32: FP32-product front updates;
- * NDRHO_K_GEMM_BF16X3: split-BF16 front updates. */
+ * NDRHO_K_GEMM_BF16X3: split-BF16 front updates; NDRHO_K_SMALL: launches of
+ * the persistent small-front schedule (disabled: always zero). */
 
 /* enable != 0: from now on every launch is bracketed by HIP events on the
  * context stream and its duration is added to a per-kind total (clears the

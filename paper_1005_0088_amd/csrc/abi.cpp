@@ -62,6 +62,9 @@ struct DevStruct {
   int64_t* acc_slot = nullptr;
   int32_t* acc_entry = nullptr;
   int32_t* acc_sid = nullptr;  // joined plans: structure of each sorted pattern slot
+  SmallFront *small_up = nullptr, *small_down = nullptr;  // persistent schedule of the small fronts
+  SmallChild* small_kids = nullptr;
+  int32_t* small_inv = nullptr;
   // shifts and weights
   int n_shifts = 0;
   int n_hi = 0;  // leading shifts evaluated with FP64 front updates
@@ -212,6 +215,10 @@ void upload_plan(DevStruct& ds, hipStream_t st, int precision) {
   ds.asm_sid = ds.put(P.asm_sid_sorted, st);
   ds.acc_slot = ds.put(P.acc_slot, st);
   ds.acc_entry = ds.put(P.acc_entry, st);
+  ds.small_up = ds.put(P.small_up, st);
+  ds.small_down = ds.put(P.small_down, st);
+  ds.small_kids = ds.put(P.small_kids, st);
+  ds.small_inv = ds.put(P.small_inv, st);
   ds.variant = default_variants(P, precision);
 }
 
@@ -241,8 +248,12 @@ struct ndrho_ctx {
   double* acc_e = nullptr;
   double* outbuf_e = nullptr;
   int64_t acc_e_len = 0;
-  int* status = nullptr;
+  int* status = nullptr;  // [0] singular pivots, [1] non-positive pivots of S, [2] schedule wait bound hit, [3] spare
+  // dependency flags, task counters and abort words of the small-front schedule
+  void* sched = nullptr;
+  size_t sched_bytes = 0;
   void* scratch = nullptr;  // this device's fixed scratch (no-allocation entry point)
+  long long wait_ticks = 0;  // 2 s of the device's constant-rate clock (bound of a schedule wait)
   double last_ms = 0;
   int last_batch = 0;
   // profiling: events around launches, folded into per-kind totals
@@ -341,6 +352,7 @@ struct ndrho_ctx {
     if (acc_e) (void)hipFree(acc_e);
     if (outbuf_e) (void)hipFree(outbuf_e);
     if (status) (void)hipFree(status);
+    if (sched) (void)hipFree(sched);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
@@ -379,6 +391,20 @@ struct ndrho_ctx {
       }
       ws_bytes = need;
     }
+    const size_t sneed = sched_need(P, nb);
+    if (sneed > sched_bytes) {
+      if (sched) {
+        HIP_OK(hipStreamSynchronize(stream));
+        HIP_OK(hipFree(sched));
+      }
+      sched = nullptr;
+      sched_bytes = 0;
+      if (hipMalloc(&sched, sneed) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(NDRHO_ENOMEM, "schedule flags allocation failed");
+      }
+      sched_bytes = sneed;
+    }
     if (P.nnz > acc_len) {
       if (acc) HIP_OK(hipFree(acc));
       if (outbuf) HIP_OK(hipFree(outbuf));
@@ -388,6 +414,25 @@ struct ndrho_ctx {
         fail(NDRHO_ENOMEM, "accumulator allocation failed");
       acc_len = P.nnz;
     }
+  }
+
+  // Bytes of the small-front schedule's words for `nb` poles: completion
+  // flags per (front, pole position), then per pole position two task
+  // counters (upward, downward) and two abort words.
+  static size_t sched_need(const Plan& P, int nb) {
+    const size_t nf = std::max(P.small_up.size(), size_t(1));
+    return (nf * nb * sizeof(int) + 255) / 256 * 256 + 2 * size_t(nb) * sizeof(unsigned long long) +
+           2 * size_t(nb) * sizeof(int);
+  }
+  void sched_words(int nlay, int q0, bool up, int** flags, unsigned long long** head, int** abort_flag,
+                   const Plan& P) const {
+    char* b = static_cast<char*>(sched);
+    const size_t nf = std::max(P.small_up.size(), size_t(1));
+    const size_t fbytes = (nf * nlay * sizeof(int) + 255) / 256 * 256;
+    *flags = reinterpret_cast<int*>(b) + q0;
+    *head = reinterpret_cast<unsigned long long*>(b + fbytes) + 2 * q0 + (up ? 0 : 1);
+    *abort_flag = reinterpret_cast<int*>(b + fbytes + 2 * size_t(nlay) * sizeof(unsigned long long)) + 2 * q0 +
+                  (up ? 0 : 1);
   }
 
   // Poles per device pass for plan P.
@@ -533,12 +578,35 @@ struct ndrho_ctx {
           d.copy_tiles = S.copy_tiles + op.tile_begin;
           timed(NDRHO_K_COPY, 0.0, [&] { e = launch_copy(d, st); });
           break;
+        case OP_SMALL: {
+          SmallLaunch sl;
+          sl.up = op.flags == 0;
+          sl.fronts = sl.up ? S.small_up : S.small_down;
+          sl.kids = S.small_kids;
+          sl.inv = S.small_inv;
+          sl.rel = S.rel;
+          sl.nfronts = op.count;
+          sl.npoles = nb;
+          sl.panel = bufs[BUF_PANEL], sl.ps = strides[BUF_PANEL];
+          sl.lbuf = bufs[BUF_L], sl.ls = strides[BUF_L];
+          sl.upd0 = bufs[BUF_UPD0], sl.upd1 = bufs[BUF_UPD1], sl.us = strides[BUF_UPD0];
+          sl.asm_slot = S.asm_slot, sl.asm_entry = S.asm_entry, sl.asm_sid = S.asm_sid;
+          sl.hv = S.h, sl.sv = S.s;
+          sl.alpha = alpha, sl.astride = astride, sl.hcoef = hcoef, sl.spd_check = spd_check;
+          sl.status = status;
+          sched_words(nlay, q0, sl.up, &sl.flags, &sl.head, &sl.abort_flag, P);
+          sl.fstride = nlay;
+          sl.wait_ticks = wait_ticks;
+          const double fl = sl.up ? P.small_flops_up : P.small_flops_down;
+          timed(NDRHO_K_SMALL, fl * nb, [&] { e = launch_small(sl, st); });
+          break;
+        }
         case OP_GATHER:
           d.gat = S.gat + op.begin;
           d.rel = S.rel;
           d.elem_tiles = S.gat_tiles + op.tile_begin;
           d.nhi = nhi;
-          d.gat_out32 = guu32[op.depth];
+          d.gat_out32 = op.keep64 ? 0 : guu32[op.depth];
           d.gat_in32 = op.depth > 0 ? guu32[op.depth - 1] : 0;
           timed(NDRHO_K_GATHER, 0.0, [&] { e = launch_gather(d, st); });
           break;
@@ -754,9 +822,13 @@ struct ndrho_ctx {
   }
 
   void read_status(int* st) {
-    HIP_OK(hipMemcpyAsync(st, status, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    int w[4];
+    HIP_OK(hipMemcpyAsync(w, status, 4 * sizeof(int), hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     if (!recs.empty()) fold_profile();
+    if (w[2]) fail(NDRHO_EDEVICE, "a wait of the small-front schedule exceeded its bound");
+    st[0] = w[0];
+    st[1] = w[1];
   }
 
   // M0 = S^{-1} on the pattern: the real selected inversion of S (alpha = 1,
@@ -1225,6 +1297,7 @@ int ndrho_default_options(ndrho_options* opt) {
   opt->fp64_small_tiles = -1;
   opt->split_streams = 1;
   opt->long_tail = 0.0;
+  opt->small_fronts = 0;
   return NDRHO_OK;
 }
 
@@ -1247,6 +1320,10 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
       fail(NDRHO_EINVAL, "invalid FP64 pole rule");
     if (c->opt.fp64_small_tiles < -1 || c->opt.fp64_small_tiles > 1) fail(NDRHO_EINVAL, "invalid fp64_small_tiles");
     if (!(c->opt.long_tail == 0.0 || c->opt.long_tail >= 1.0)) fail(NDRHO_EINVAL, "long_tail must be 0 or >= 1");
+    if (c->opt.small_fronts != 0)
+      fail(NDRHO_EINVAL,
+           "small_fronts must be 0: the persistent small-front schedule is disabled (its launches stalled on "
+           "gfx950, cause not found)");
     if (c->opt.split_streams < 0 || c->opt.split_streams > ndrho_ctx::kMaxChains)
       fail(NDRHO_EINVAL, "invalid split_streams");
     if (c->opt.gemm_variant < -1 || c->opt.gemm_variant >= V_COUNT ||
@@ -1269,8 +1346,11 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
       HIP_OK(hipStreamCreate(&c->stream));
       c->own_stream = true;
     }
-    if (hipMalloc(&c->status, 2 * sizeof(int)) != hipSuccess) fail(NDRHO_ENOMEM, "status allocation failed");
+    if (hipMalloc(&c->status, 4 * sizeof(int)) != hipSuccess) fail(NDRHO_ENOMEM, "status allocation failed");
     c->scratch = scratch_addr(device);
+    int khz = 0;
+    HIP_OK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
+    c->wait_ticks = 2000LL * (khz > 0 ? khz : 100000);
   });
   if (rc == NDRHO_OK) *out = c.release();
   return rc;
@@ -1301,7 +1381,8 @@ int set_structure(ndrho_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32
         if (!std::isfinite(coords[i])) fail(NDRHO_EINVAL, "non-finite coordinate");
     std::unique_ptr<DevStruct> ds(new DevStruct());
     try {
-      build_plan(ds->plan, n, row_ptr, col_idx, coords, ctx->opt.leaf_rows, ctx->opt.long_tail, cell);
+      build_plan(ds->plan, n, row_ptr, col_idx, coords, ctx->opt.leaf_rows, ctx->opt.long_tail, cell,
+                 ctx->opt.small_fronts != 0);
       Plan& P = ds->plan;
       hipStream_t st = ctx->stream;
       std::vector<double> hv(H, H + P.nnz), sv(S, S + P.nnz);
@@ -1671,8 +1752,7 @@ int ndrho_eigenstates(ndrho_ctx* ctx, int32_t struct_id, double xi, double eta, 
     HIP_OK(launch_init_acc(ds.m0, 0, 0, ctx->acc, ctx->status, st));
     ctx->run_pass(ds, 1, 0, 1, d_alpha, 0, 1.0, 0, 1, st, true);
     int stat[2];
-    HIP_OK(hipMemcpyAsync(stat, ctx->status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    ctx->read_status(stat);
     if (stat[0]) fail(NDRHO_ESINGULAR, "a zero, tiny or non-finite pivot occurred in alpha S - H (use eta > 0)");
 
     // starting block: counter-based uniform numbers
@@ -1814,16 +1894,21 @@ int ndrho_density_matrix_noalloc(ndrho_ctx* ctx, int32_t struct_id, double* rho_
     if (ds.n_shifts < 1) fail(NDRHO_ESTATE, "set_poles (or set_shifts) has not been called for this structure");
     HIP_OK(hipSetDevice(ctx->device));
     const Plan& P = ds.plan;
-    // scratch layout: [status (256 B)][accumulator, nnz doubles, 256-aligned][workspace]
+    // scratch layout: [status (256 B)][accumulator, nnz doubles, 256-aligned]
+    // [small-front schedule words for nb poles][workspace of nb poles]
     const size_t acc_bytes = (static_cast<size_t>(P.nnz) * sizeof(double) + 255) / 256 * 256;
     const size_t per_pole = static_cast<size_t>(ndrho_ctx::per_pole_elems(P)) * sizeof(double2);
-    if (256 + acc_bytes + per_pole > kScratchBytes)
-      fail(NDRHO_ENOMEM, "the structure needs " + std::to_string(256 + acc_bytes + per_pole) +
+    auto need = [&](int nb) {
+      return 256 + acc_bytes + (ndrho_ctx::sched_need(P, nb) + 255) / 256 * 256 + per_pole * size_t(nb);
+    };
+    if (need(1) > kScratchBytes)
+      fail(NDRHO_ENOMEM, "the structure needs " + std::to_string(need(1)) +
                              " bytes of scratch for one pole; the no-allocation entry point holds " +
                              std::to_string(kScratchBytes));
-    const size_t ws_room = kScratchBytes - 256 - acc_bytes;
-    const int nb = static_cast<int>(std::min<size_t>(static_cast<size_t>(ds.n_shifts), ws_room / per_pole));
+    int nb = 1;
+    while (nb < ds.n_shifts && need(nb + 1) <= kScratchBytes) ++nb;
     char* base = static_cast<char*>(ctx->scratch);
+    const size_t sched_bytes = (ndrho_ctx::sched_need(P, nb) + 255) / 256 * 256;
     // the evaluation runs on the scratch: one launch chain of plain launches
     // (no graph, no further streams), passes of nb poles
     struct Swap {
@@ -1833,18 +1918,24 @@ int ndrho_density_matrix_noalloc(ndrho_ctx* ctx, int32_t struct_id, double* rho_
       double* acc;
       int64_t acc_len;
       int* status;
+      void* sched;
+      size_t sched_bytes;
       ndrho_options opt;
       bool prof;
       ~Swap() {
         c->ws = ws, c->ws_bytes = ws_bytes, c->acc = acc, c->acc_len = acc_len, c->status = status, c->opt = opt;
+        c->sched = sched, c->sched_bytes = sched_bytes;
         c->prof = prof;
       }
-    } swap{ctx, ctx->ws, ctx->ws_bytes, ctx->acc, ctx->acc_len, ctx->status, ctx->opt, ctx->prof};
+    } swap{ctx, ctx->ws, ctx->ws_bytes, ctx->acc, ctx->acc_len, ctx->status, ctx->sched, ctx->sched_bytes, ctx->opt,
+           ctx->prof};
     ctx->status = reinterpret_cast<int*>(base);
     ctx->acc = reinterpret_cast<double*>(base + 256);
     ctx->acc_len = P.nnz;
-    ctx->ws = base + 256 + acc_bytes;
-    ctx->ws_bytes = ws_room;
+    ctx->sched = base + 256 + acc_bytes;
+    ctx->sched_bytes = sched_bytes;
+    ctx->ws = base + 256 + acc_bytes + sched_bytes;
+    ctx->ws_bytes = per_pole * size_t(nb);
     ctx->opt.use_graph = 0;
     ctx->opt.split_streams = 0;
     ctx->opt.pole_batch = nb;
@@ -1853,8 +1944,7 @@ int ndrho_density_matrix_noalloc(ndrho_ctx* ctx, int32_t struct_id, double* rho_
     ctx->evaluate(ds, ds.d_alpha, 0, ds.d_w, ds.n_shifts, ds.n_hi, ds.add_m0, 1.0, 0);
     HIP_OK(launch_scatter(ds.acc_entry, P.nnz, ctx->acc, rho_out_dev, ctx->stream));
     int st[2];
-    HIP_OK(hipMemcpyAsync(st, ctx->status, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_OK(hipStreamSynchronize(ctx->stream));
+    ctx->read_status(st);
     if (st[0]) fail(NDRHO_ESINGULAR, "a zero, tiny or non-finite pivot occurred in alpha S - H");
     ctx->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   });
@@ -2265,8 +2355,8 @@ int ndrho_plan_program(const ndrho_plan* plan, int64_t* count, int32_t* kind, in
   const Plan& P = plan->plan;
   int64_t i = 0;
   auto put = [&](const Op& op) {
-    static const int kmap[] = {NDRHO_K_EXTADD, NDRHO_K_ASSEMBLE, NDRHO_K_PIVOT_INV,
-                               NDRHO_K_GEMM,   NDRHO_K_COPY,     NDRHO_K_GATHER};
+    static const int kmap[] = {NDRHO_K_EXTADD, NDRHO_K_ASSEMBLE, NDRHO_K_PIVOT_INV, NDRHO_K_GEMM,
+                               NDRHO_K_COPY,   NDRHO_K_GATHER,   NDRHO_K_SMALL};
     if (kind) kind[i] = kmap[op.kind];
     if (depth) depth[i] = op.depth;
     if (flops) flops[i] = op.flops;

@@ -86,6 +86,35 @@ hipError_t launch_combine(const double* V, const double* Y, int64_t n, double* o
 hipError_t launch_resid(const double* hc, const double* sc, const double* theta, int64_t n, int64_t chunk, int nblk,
                         double* part, hipStream_t st);
 
+// ---- persistent schedule of the small fronts (persist.hip)
+struct SmallLaunch {
+  bool up = true;
+  const SmallFront* fronts = nullptr;
+  const SmallChild* kids = nullptr;
+  const int32_t* inv = nullptr;
+  const int32_t* rel = nullptr;
+  int64_t nfronts = 0;
+  int npoles = 0;
+  double2 *panel = nullptr, *lbuf = nullptr, *upd0 = nullptr, *upd1 = nullptr;
+  int64_t ps = 0, ls = 0, us = 0;
+  const int64_t* asm_slot = nullptr;
+  const int32_t* asm_entry = nullptr;
+  const int32_t* asm_sid = nullptr;
+  const double *hv = nullptr, *sv = nullptr;
+  const double2* alpha = nullptr;
+  int64_t astride = 0;
+  double hcoef = 1.0;
+  int spd_check = 0;
+  int* status = nullptr;           // [0] singular pivots, [1] non-positive pivots of S, [2] schedule wait bound hit
+  int* flags = nullptr;            // task completion, [front * fstride + pole]
+  int64_t fstride = 0;
+  unsigned long long* head = nullptr;  // the launch's task counter
+  int* abort_flag = nullptr;
+  int64_t max_groups = 512;  // workgroups of a launch (two per compute unit are resident)
+  long long wait_ticks = 0;  // bound of one dependency wait, in ticks of the device's constant-rate clock
+};
+hipError_t launch_small(const SmallLaunch& s, hipStream_t st);
+
 hipError_t launch_extadd(const DevOp& o, hipStream_t st);
 hipError_t launch_assemble(const DevOp& o, const double* hv, const double* sv, const double2* alpha,
                            int64_t astride, double hcoef, hipStream_t st);

@@ -1417,7 +1417,7 @@ __global__ __launch_bounds__(256) void k_accum(const int64_t* __restrict__ slot,
 __global__ __launch_bounds__(256) void k_init_acc(const double* __restrict__ m0, int64_t count, int add_m0,
                                                   double* __restrict__ acc, int* __restrict__ status) {
   const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (k < 2) status[k] = 0;
+  if (k < 4) status[k] = 0;
   if (k < count) acc[k] = add_m0 ? m0[k] : 0.0;
 }
 
@@ -1587,7 +1587,7 @@ hipError_t launch_accum(const int64_t* slot, int64_t count, const double2* panel
 }
 
 hipError_t launch_init_acc(const double* m0, int64_t count, int add_m0, double* acc, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_acc, dim3(blocks_for(count > 2 ? count : 2, 256)), dim3(256), 0, st, m0, count, add_m0, acc,
+  hipLaunchKernelGGL(k_init_acc, dim3(blocks_for(count > 4 ? count : 4, 256)), dim3(256), 0, st, m0, count, add_m0, acc,
                      status);
   return hipGetLastError();
 }

@@ -544,10 +544,12 @@ struct Builder {
 }  // namespace
 
 void build_plan(Plan& P, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* coords,
-                int leaf_rows, double long_tail, const double* cell) {
+                int leaf_rows, double long_tail, const double* cell, bool small_fronts) {
+  // (small_fronts: the persistent schedule takes the small fronts)
   if (leaf_rows < 1) fail(NDRHO_EINVAL, "leaf_rows must be >= 1");
   if (!(long_tail == 0.0 || long_tail >= 1.0)) fail(NDRHO_EINVAL, "long_tail must be 0 or >= 1");
   P = Plan();
+  P.small_enabled = small_fronts;
   P.n = n;
   P.nnz = row_ptr[n];
   P.row_ptr.assign(row_ptr, row_ptr + n + 1);
@@ -701,10 +703,26 @@ void finalize_plan(Plan& P) {
     lo += int64_t(F.nu) * F.nj;
   }
   P.l_total = std::max<int64_t>(lo, 1);
+  // small fronts (the persistent schedule's): at most 64 pivot rows, at most
+  // kSmallFrontRows pivot plus update rows, every descendant small too
+  // (postorder: children come first)
+  std::vector<char> small(nf, 0);
+  if (P.small_enabled)
+    for (int f = 0; f < nf; ++f) {
+      const Front& F = P.fronts[f];
+      bool sm = F.nj <= 64 && F.nj + F.nu <= kSmallFrontRows;
+      for (int c : F.children) sm = sm && small[c];
+      small[f] = sm;
+    }
+  // update / G_UU blocks: the large fronts of a depth side by side in their
+  // depth's buffer (reused by the depths of the same parity), every small
+  // front a block of its own after them (the persistent schedule runs fronts
+  // of several depths at once)
   for (int d = 0; d < P.n_levels; ++d) {
     int64_t uo = 0, to = 0;
     for (int f : by_depth[d]) {
       Front& F = P.fronts[f];
+      if (small[f]) continue;
       F.upd_off = uo;
       uo += int64_t(F.nu) * F.nu;
       F.temp_off = to;
@@ -713,13 +731,24 @@ void finalize_plan(Plan& P) {
     P.upd_total = std::max(P.upd_total, uo);
     P.temp_total = std::max(P.temp_total, to);
   }
+  {
+    int64_t so[2] = {P.upd_total, P.upd_total};
+    for (int f = 0; f < nf; ++f) {
+      Front& F = P.fronts[f];
+      if (!small[f]) continue;
+      F.upd_off = so[F.depth & 1];
+      so[F.depth & 1] += int64_t(F.nu) * F.nu;
+      F.temp_off = 0;
+    }
+    P.upd_total = std::max(P.upd_total, std::max(so[0], so[1]));
+  }
   P.upd_total = std::max<int64_t>(P.upd_total, 1);
   P.temp_total = std::max<int64_t>(P.temp_total, 1);
 
   // ---- table of pattern positions (assembly and output slots)
   P.out_slot.resize(P.nnz);
   P.asm_slot.resize(P.nnz);
-  std::vector<std::vector<std::pair<int64_t, int32_t>>> asm_by_depth(P.n_levels);
+  std::vector<std::vector<std::pair<int64_t, int32_t>>> asm_by_depth(P.n_levels), asm_small(nf);
   for (int64_t i = 0; i < P.n; ++i) {
     for (int64_t e = P.row_ptr[i]; e < P.row_ptr[i + 1]; ++e) {
       const int pi = P.iperm[i], pj = P.iperm[P.col[e]];
@@ -738,7 +767,10 @@ void finalize_plan(Plan& P) {
         P.out_slot[e] = slot;
         P.asm_slot[e] = (pi == b) ? slot : -1;
       }
-      if (P.asm_slot[e] >= 0) asm_by_depth[F.depth].push_back({P.asm_slot[e], static_cast<int32_t>(e)});
+      if (P.asm_slot[e] >= 0) {
+        if (small[owner[a]]) asm_small[owner[a]].push_back({P.asm_slot[e], static_cast<int32_t>(e)});
+        else asm_by_depth[F.depth].push_back({P.asm_slot[e], static_cast<int32_t>(e)});
+      }
     }
   }
   P.asm_depth_begin.assign(P.n_levels + 1, 0);
@@ -752,6 +784,19 @@ void finalize_plan(Plan& P) {
     }
   }
   P.asm_depth_begin[P.n_levels] = static_cast<int64_t>(P.asm_slot_sorted.size());
+  // the small fronts' entries follow, front by front (sorted by slot)
+  std::vector<int64_t> asm_small_begin(nf, 0), asm_small_end(nf, 0);
+  for (int f = 0; f < nf; ++f) {
+    if (!small[f]) continue;
+    auto& v = asm_small[f];
+    std::sort(v.begin(), v.end());
+    asm_small_begin[f] = static_cast<int64_t>(P.asm_slot_sorted.size());
+    for (auto& pr : v) {
+      P.asm_slot_sorted.push_back(pr.first);
+      P.asm_entry_sorted.push_back(pr.second);
+    }
+    asm_small_end[f] = static_cast<int64_t>(P.asm_slot_sorted.size());
+  }
   P.asm_sid_sorted.assign(P.asm_entry_sorted.size(), 0);
   if (!P.struct_nnz_off.empty())
     for (size_t k = 0; k < P.asm_entry_sorted.size(); ++k)
@@ -777,11 +822,88 @@ void finalize_plan(Plan& P) {
     P.rel_all.insert(P.rel_all.end(), P.fronts[f].rel.begin(), P.fronts[f].rel.end());
   }
 
+  // ---- persistent schedule of the small fronts: the upward list children
+  // first (deepest depth first), the downward list parents first
+  P.small_up.clear();
+  P.small_down.clear();
+  P.small_flops_up = P.small_flops_down = 0;
+  P.small_kids.clear();
+  P.small_inv.clear();
+  {
+    std::vector<int> up, down;
+    for (int d = P.n_levels - 1; d >= 0; --d)
+      for (int f : by_depth[d])
+        if (small[f]) up.push_back(f);
+    for (int d = 0; d < P.n_levels; ++d)
+      for (int f : by_depth[d])
+        if (small[f]) down.push_back(f);
+    std::vector<int32_t> up_pos(nf, -1), down_pos(nf, -1);
+    for (size_t i = 0; i < up.size(); ++i) up_pos[up[i]] = static_cast<int32_t>(i);
+    for (size_t i = 0; i < down.size(); ++i) down_pos[down[i]] = static_cast<int32_t>(i);
+    auto base = [&](int f) {
+      const Front& F = P.fronts[f];
+      SmallFront s{};
+      s.panel_off = F.panel_off;
+      s.l_off = F.l_off;
+      s.upd_off = F.upd_off;
+      s.asm_begin = asm_small_begin[f];
+      s.asm_end = asm_small_end[f];
+      s.rel_off = rel_off[f];
+      s.nj = F.nj;
+      s.nu = F.nu;
+      s.depth = F.depth;
+      s.parent_task = -1;
+      if (F.parent >= 0) {
+        const Front& Pa = P.fronts[F.parent];
+        s.ppanel_off = Pa.panel_off;
+        s.pguu_off = Pa.upd_off;
+        s.pnj = Pa.nj;
+        s.pnu = Pa.nu;
+      }
+      return s;
+    };
+    for (int f : up) {
+      const Front& F = P.fronts[f];
+      SmallFront s = base(f);
+      s.child_begin = static_cast<int32_t>(P.small_kids.size());
+      s.child_count = static_cast<int32_t>(F.children.size());
+      for (int c : F.children) {
+        const Front& C = P.fronts[c];
+        std::vector<int32_t> inv(F.nj + F.nu, -1);
+        for (int k = 0; k < C.nu; ++k) inv[C.rel[k]] = k;
+        P.small_kids.push_back(SmallChild{C.upd_off, static_cast<int64_t>(P.small_inv.size()), C.nu, up_pos[c]});
+        P.small_inv.insert(P.small_inv.end(), inv.begin(), inv.end());
+      }
+      P.small_up.push_back(s);
+      const double fu = 8.0 * (double(F.nj) * F.nj * F.nj + double(F.nu) * F.nj * F.nj + double(F.nu) * F.nu * F.nj / 2);
+      const double fd = 8.0 * (double(F.nu) * F.nu * F.nj + double(F.nu) * F.nj * F.nj / 2);
+      P.small_flops_up += fu;
+      P.small_flops_down += fd;
+      P.flops_exec += fu + fd;
+    }
+    for (int f : down) {
+      const Front& F = P.fronts[f];
+      SmallFront s = base(f);
+      if (F.parent >= 0 && small[F.parent]) s.parent_task = down_pos[F.parent];
+      P.small_down.push_back(s);
+    }
+  }
+
   // ---- program
   Builder B(P);
   const int64_t kTile = 1024;
+  if (!P.small_up.empty()) {
+    Op op;
+    op.kind = OP_SMALL;
+    op.flags = 0;
+    op.count = static_cast<int64_t>(P.small_up.size());
+    op.depth = P.n_levels - 1;
+    P.upward.push_back(op);
+  }
   for (int d = P.n_levels - 1; d >= 0; --d) {
-    const std::vector<int>& fr = by_depth[d];
+    std::vector<int> fr;
+    for (int f : by_depth[d])
+      if (!small[f]) fr.push_back(f);
     const int ubuf = (d % 2 == 0) ? BUF_UPD0 : BUF_UPD1;
     const int cbuf = (d % 2 == 0) ? BUF_UPD1 : BUF_UPD0;
     // extend-add into the panels (every element the pivot inverse and the
@@ -868,17 +990,26 @@ void finalize_plan(Plan& P) {
     }
   }
   for (int d = 1; d < P.n_levels; ++d) {
-    const std::vector<int>& fr = by_depth[d];
+    std::vector<int> fr, top;  // large fronts; small fronts with a large parent
+    for (int f : by_depth[d]) {
+      if (!small[f]) fr.push_back(f);
+      else if (!small[P.fronts[f].parent]) top.push_back(f);
+    }
     const int ubuf = (d % 2 == 0) ? BUF_UPD0 : BUF_UPD1;
     const int pbuf = (d % 2 == 0) ? BUF_UPD1 : BUF_UPD0;
-    {
+    // G_UU of the small fronts whose parent is large, gathered here (right
+    // after the parent's level) into their own blocks, kept FP64 for the
+    // persistent schedule that continues from them
+    for (int pass = 0; pass < 2; ++pass) {
+      const std::vector<int>& list = pass == 0 ? fr : top;
       Op op;
       op.kind = OP_GATHER;
+      op.keep64 = pass == 1;
       op.buf_a = pbuf, op.buf_b = BUF_PANEL, op.buf_c = ubuf;
       op.begin = static_cast<int64_t>(P.gat.size());
       op.tile_begin = static_cast<int64_t>(P.gat_tiles.size());
       op.depth = d;
-      for (int f : fr) {
+      for (int f : list) {
         const Front& F = P.fronts[f];
         if (F.nu == 0) continue;
         const Front& Pa = P.fronts[F.parent];
@@ -909,6 +1040,14 @@ void finalize_plan(Plan& P) {
     }
     B.gemm(P.downward, G_NEG | G_SYMA, ubuf, BUF_L, 0, BUF_PANEL, g3, d);
     B.gemm(P.downward, G_TA | G_SYM | G_BETA | G_NEG, BUF_L, BUF_PANEL, BUF_PANEL, BUF_PANEL, g4, d);
+  }
+  if (!P.small_down.empty()) {
+    Op op;
+    op.kind = OP_SMALL;
+    op.flags = 1;
+    op.count = static_cast<int64_t>(P.small_down.size());
+    op.depth = P.n_levels - 1;
+    P.downward.push_back(op);
   }
 }
 
@@ -942,6 +1081,7 @@ void join_plans(Plan& U, const std::vector<const Plan*>& parts) {
   U.n = rows;
   U.nnz = nnz;
   U.n_levels = levels;
+  U.small_enabled = parts.empty() ? true : parts[0]->small_enabled;
   finalize_plan(U);
 }
 

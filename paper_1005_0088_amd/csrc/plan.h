@@ -75,9 +75,28 @@ struct GatherDesc {
   int32_t nu, pnj, pnu, pad;
 };
 
+// One front of the persistent schedule of the small fronts (lists ordered
+// children first for the upward launch, parents first for the downward one).
+struct SmallFront {
+  int64_t panel_off, l_off, upd_off;  // upd_off: its own update / G_UU block in its depth's buffer
+  int64_t asm_begin, asm_end;         // its assembly entries (sorted tables)
+  int64_t rel_off;                    // its relative map into the parent's local rows
+  int64_t ppanel_off, pguu_off;       // the parent's panel and G_UU block
+  int32_t nj, nu, depth;
+  int32_t child_begin, child_count;   // its children (all small) in the child table
+  int32_t parent_task;                // downward list: the parent's position, -1 for a large parent
+  int32_t pnj, pnu;
+};
+struct SmallChild {
+  int64_t upd_off;  // the child's update block (in the child's depth buffer)
+  int64_t inv_off;  // its inverse map over the parent's local rows (child update row or -1)
+  int32_t nu;
+  int32_t task;     // the child's position in the upward list
+};
+
 enum BufId { BUF_PANEL = 0, BUF_UPD0 = 1, BUF_UPD1 = 2, BUF_TEMP = 3, BUF_L = 4, BUF_COUNT = 5 };
 
-enum OpKind { OP_EXTADD, OP_ASSEMBLE, OP_SMALLINV, OP_GEMM, OP_COPY, OP_GATHER };
+enum OpKind { OP_EXTADD, OP_ASSEMBLE, OP_SMALLINV, OP_GEMM, OP_COPY, OP_GATHER, OP_SMALL };
 
 // G_SYMA: A is symmetric and only its lower triangle is stored (entry (m, k)
 // is read from (max, min)); G_NOMIRROR: with G_SYM, write the lower triangle
@@ -104,6 +123,7 @@ struct Op {
   bool off32 = true;         // GEMM: every operand element of every problem lies within 2^31 - 16
                              // bytes of the problem's operand origin (32-bit offsets suffice)
   int64_t inv16 = 0, inv32 = 0;  // SMALLINV: leading descriptors with n <= 16, then n <= 32
+  bool keep64 = false;       // GATHER: the G_UU it writes stays FP64 (its consumer is the small-front schedule)
   int depth = 0;
   double flops = 0;          // useful flops per pole (GEMM)
   double bytes = 0;          // algorithmic bytes per pole: operands read and results written once, complex128
@@ -146,6 +166,13 @@ struct Plan {
   double flops_model = 0, bytes_model = 0;    // per pole
   double flops_exec = 0;                      // flops of the program per pole
 
+  // persistent schedule of the small fronts (OP_SMALL; flags 0 upward, 1 downward)
+  bool small_enabled = true;
+  double small_flops_up = 0, small_flops_down = 0;  // useful flops per pole of the two launches
+  std::vector<SmallFront> small_up, small_down;
+  std::vector<SmallChild> small_kids;
+  std::vector<int32_t> small_inv;
+
   // several structures joined into one forest (empty for one structure):
   // first row / first CSR entry of each structure, and the structure of
   // every assembly entry (for per-structure shifts)
@@ -161,7 +188,9 @@ void validate_csr(int64_t n, const int64_t* row_ptr, const int32_t* col, const d
 // cell: NULL, or the periodic cell length along x, y, z (0: open boundary)
 // for the coordinates in coords.
 void build_plan(Plan& plan, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* coords,
-                int leaf_rows, double long_tail = 0.0, const double* cell = nullptr);
+                int leaf_rows, double long_tail = 0.0, const double* cell = nullptr, bool small_fronts = false);
+// Small fronts: at most 64 pivot rows and at most this many pivot plus update rows
+constexpr int kSmallFrontRows = 320;
 // Layout, tables and program from P's fronts and CSR (called by build_plan).
 void finalize_plan(Plan& P);
 // One plan for several structures: their front trees side by side as a

@@ -623,6 +623,9 @@ def test_errors(ctx):
     with pytest.raises(nd.NdrhoError) as e:
         ctx.set_poles(sid, 0.0, BETA, 0)
     assert e.value.name == "EINVAL"
+    with pytest.raises(nd.NdrhoError) as e:     # the persistent small-front schedule is disabled
+        nd.Context(0, small_fronts=1)
+    assert e.value.name == "EINVAL"
     bad = dict(sysd)
     bad["s"] = sysd["s"].copy()
     diag = np.nonzero(np.repeat(np.arange(sysd["n"]), np.diff(sysd["row_ptr"])) == sysd["col"])[0]
@@ -831,6 +834,68 @@ def test_eight_lattice_batch_against_oracle_sample(precision, tol, tmp_path):
         err = np.max(np.abs(rho[np.asarray(m["entries"])] - np.asarray(m["values"])))
         print("multi2d member %s %s: max err %.3e on %d entries" % (m["dims"], precision, err, len(m["entries"])))
         assert err < tol
+
+
+# ------------------------------------------------------------- persistent small-front schedule
+
+@pytest.mark.skip(reason="the persistent small-front schedule is disabled: its launches stalled on gfx950 "
+                         "(inside the first FP64 evaluation of the 256-site chain, also with one workgroup, "
+                         "where no dependency wait can block); a CPU emulation of both kernels reproduces "
+                         "G on that chain, the device-side cause is not found; the context rejects "
+                         "small_fronts != 0")
+@pytest.mark.parametrize("precision", ["fp64", "mixed_bf16x3"])
+def test_small_front_schedule_matches_level_schedule(precision):
+    # the persistent launches over the small fronts (one upward, one downward
+    # per pass, tasks taken in tree order with dependency flags) against the
+    # level-by-level launches of the same fronts: the 1D chain (every front
+    # small), a 2D and a 3D lattice (small subtrees under large separators),
+    # a periodic lattice, several passes over pole batches, a structure batch.
+    # Mode 2 runs the same launches with one workgroup (tasks strictly in
+    # list order), mode 1 with the full grid.
+    import paper_1005_0088_amd as nd
+    systems = [lattice((256,), "nn", 0), lattice((24, 22), "nn2", 81), lattice((10, 9, 8), "nn", 82),
+               lattice((12, 12), "nn", 83, periodic=True)]
+    out = {}
+    for small in (0, 2, 1):
+        with nd.Context(0, precision=precision, small_fronts=small, pole_batch=16) as c:
+            sids = []
+            for k, sysd in enumerate(systems):
+                sid = c.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"],
+                                      cell=sysd["cell"])
+                c.set_poles(sid, 0.1 * k, BETA, 40)
+                sids.append(sid)
+            singles = []
+            for k, s in enumerate(sids):
+                print("small_fronts=%d %s: system %d" % (small, precision, k), flush=True)
+                singles.append(c.density_matrix(s))
+            again = [c.density_matrix(s) for s in sids]
+            print("small_fronts=%d %s: batch" % (small, precision), flush=True)
+            batch = c.density_matrix_batch(sids)
+            rho_e, e = c.energy_density_matrix(sids[2])
+            c.profile(True)
+            c.density_matrix(sids[1])
+            prof = c.profile_read()
+            c.profile(False)
+            out[small] = (singles, batch, e)
+        for a, b in zip(singles, again):
+            assert np.array_equal(a, b)                  # repeatable bit for bit
+        launches = prof["small_fronts"]["launches"]
+        print("small_fronts=%d %s: %d persistent launches, %.3f ms" % (small, precision, launches,
+                                                                      prof["small_fronts"]["ms"]), flush=True)
+        assert (launches > 0) == (small != 0)
+    tol = 1e-12 if precision == "fp64" else 2e-7
+    for mode in (2, 1):
+        for a, b in zip(out[0][0], out[mode][0]):
+            assert np.max(np.abs(a - b)) < tol
+        for a, b in zip(out[0][1], out[mode][1]):
+            assert np.max(np.abs(a - b)) < tol
+        assert np.max(np.abs(out[0][2] - out[mode][2])) < (1e-10 if precision == "fp64" else 1e-5)
+    if precision == "fp64":   # and against the dense oracle
+        for k, (sysd, got) in enumerate(zip(systems, out[1][0])):
+            h, s, rows, cols = _dense(sysd)
+            eps, cc = dense.eigen(h, s)
+            ref = dense.rho_cf_pattern(eps, cc, 0.1 * k, BETA, 40, rows, cols)
+            assert np.max(np.abs(got - ref)) < 1e-10
 
 
 # ------------------------------------------------------------- several structures, one schedule

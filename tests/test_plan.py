@@ -53,7 +53,7 @@ def test_default_options_and_struct_layouts():
     assert lib.ndrho_default_options(ctypes.byref(opt)) == 0
     want = {"leaf_rows": 32, "precision": 0, "pole_batch": 0, "mem_fraction": 0.8, "verbose": 0, "fp64_poles": 8,
             "fp64_pole_im": 0.05, "fp64_far_poles": 8, "use_graph": 1, "gemm_variant": -1, "fp64_small_tiles": -1,
-            "split_streams": 1, "long_tail": 0.0}
+            "split_streams": 1, "long_tail": 0.0, "small_fronts": 0}
     assert {k: getattr(opt, k) for k, _ in opt._fields_} == want
 
 
@@ -328,6 +328,13 @@ def test_long_tail_option_validated():
     sysd = lattice((4, 4), "nn", 3)
     with pytest.raises(nd.NdrhoError):
         nd.Plan(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["coords"], 16, long_tail=0.5)
+
+
+def test_disabled_small_front_schedule_is_rejected():
+    # the option is checked before any device call, so this runs on the host
+    with pytest.raises(nd.NdrhoError) as e:
+        nd.Context(0, small_fronts=1)
+    assert e.value.name == "EINVAL" and "disabled" in str(e.value)
 
 
 def test_long_tail_generator_keeps_s_positive_definite_and_symmetric():
