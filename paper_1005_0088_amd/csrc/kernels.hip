@@ -1380,19 +1380,34 @@ __global__ __launch_bounds__(256) void k_gather(const GatherDesc* __restrict__ d
   const double2* pg = pguu + pole * gs + d.pguu_off;
   double2* out = guu + pole * us + d.dst_off;
   const int64_t pld = d.pnj + d.pnu;
+  // four elements per thread: the map reads of all four, then their value
+  // reads, are in flight together
+  uint32_t e[4];
+  bool live[4];
+  int r[4], s[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const uint32_t e = uint32_t(t.e0) + threadIdx.x + 256 * i;
-    if (e >= total) break;
-    const uint32_t b = e / uint32_t(d.nu), a = e - b * uint32_t(d.nu);
-    if (a < b) continue;  // G_UU is kept as its lower triangle
-    const int r = rl[a], s = rl[b];  // r >= s (increasing map)
-    const int64_t gi = (r - d.pnj) + int64_t(s - d.pnj) * d.pnu;
-    const double2 v = s < d.pnj ? pan[r + int64_t(s) * pld] : rd32 ? a_elem<true>(pg, gi) : pg[gi];
+    e[i] = uint32_t(t.e0) + threadIdx.x + 256 * i;
+    const uint32_t b = e[i] / uint32_t(d.nu), a = e[i] - b * uint32_t(d.nu);
+    live[i] = e[i] < total && a >= b;  // G_UU is kept as its lower triangle
+    r[i] = live[i] ? rl[a] : 0;
+    s[i] = live[i] ? rl[b] : 0;  // r >= s (increasing map)
+  }
+  double2 v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t gi = (r[i] - d.pnj) + int64_t(s[i] - d.pnj) * d.pnu;
+    v[i] = !live[i] ? make_double2(0.0, 0.0)
+           : s[i] < d.pnj ? pan[r[i] + int64_t(s[i]) * pld]
+           : rd32 ? a_elem<true>(pg, gi) : pg[gi];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (!live[i]) continue;
     if (wr32)
-      reinterpret_cast<float2*>(out)[e] = make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+      reinterpret_cast<float2*>(out)[e[i]] = make_float2(static_cast<float>(v[i].x), static_cast<float>(v[i].y));
     else
-      out[e] = v;
+      out[e[i]] = v[i];
   }
 }
 
