@@ -339,7 +339,7 @@ def main():
     elif head["precision"] == "mixed_bf16x3":
         g, peak, kname = (prof["gemm_bf16x3"], BF16_MFMA_PEAK_TFLOPS,
                           "k_cgemm_bf3, k_cgemm_bf3s, k_cgemm_bf3p (complex front-update GEMMs, split-BF16 "
-                          "products; executed BF16 flops)")
+                          "products; achieved on useful flops, executed BF16 flops beside)")
         exec_per_useful = BF16X3_EXEC_PER_USEFUL
     else:
         g, peak, kname = prof["gemm_f32"], FP32_MFMA_PEAK_TFLOPS, "k_cgemm32 (complex front-update GEMMs, FP32 products)"
