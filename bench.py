@@ -156,7 +156,8 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
     t0 = time.time()
     sids = []
     for sysd in systems:
-        sid = ctx.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"])
+        sid = ctx.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"],
+                                cell=sysd.get("cell"))
         ctx.set_poles(sid, mu, beta, n_poles)
         sids.append(sid)
     if precision != "fp64" and autotune and variant < 0:
@@ -235,6 +236,41 @@ def mu_search(nd, sysd, name, n_poles, args, beta):
                       "mu_eV": mu, "delta_n": dn, "evaluations": it, "s_per_evaluation": dt / max(1, it)}))
 
 
+def eigen_run(nd, sysd, name, args):
+    """The k eigenpairs nearest args.eigenstates by block shift-invert
+    (ndrho_eigenstates, Appendix B), timed once after one untimed call (the
+    plan and the kernels warm); prints one JSON line.  At full size no dense
+    eigensolve is in reach, so the pairs are checked on the host by properties
+    that hold at any size: ||H c - eps S c|| recomputed from the CSR matrices
+    and the S-orthonormality of the vectors."""
+    k, eta, tol = args.eig_k, 1e-3, 1e-8
+    with nd.Context(0, precision="fp64") as ctx:
+        sid = ctx.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"])
+        ctx.eigenstates(sid, args.eigenstates, k, eta=eta, max_iter=args.eig_iter, tol=tol, vectors=False)
+        t0 = time.perf_counter()
+        eps, c, it, res = ctx.eigenstates(sid, args.eigenstates, k, eta=eta, max_iter=args.eig_iter, tol=tol)
+        dt = time.perf_counter() - t0
+    n = sysd["n"]
+    rows = np.repeat(np.arange(n), np.diff(sysd["row_ptr"]))
+
+    def csr_mul(vals, x):   # y = A x for the CSR values of H or S
+        y = np.zeros_like(x)
+        np.add.at(y, rows, vals[:, None] * x[sysd["col"]])
+        return y
+
+    hc, sc = csr_mul(sysd["h"], c), csr_mul(sysd["s"], c)
+    host_res = np.linalg.norm(hc - sc * eps[None, :], axis=0)
+    ortho = float(np.max(np.abs(c.T @ sc - np.eye(k))))
+    print(json.dumps({"metric": "selected eigenstates (block shift-invert)", "value": dt, "unit": "s",
+                      "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": name, "n": n, "xi_eV": args.eigenstates, "eta_eV": eta, "k": k,
+                                 "tol": tol, "max_iter": args.eig_iter},
+                      "iterations": it, "s_per_iteration": dt / max(1, it),
+                      "eigenvalues_eV": [float(x) for x in eps],
+                      "max_residual_library": float(np.max(res)), "max_residual_host": float(np.max(host_res)),
+                      "max_abs_CtSC_minus_I": ortho}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +302,13 @@ def main():
                          "the kernels' durations in the timed steps are those of the instrumented step and of "
                          "the profiler's trace; 1 runs the FP64 poles beside, about 1 %% faster on 24^3 x 4)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--periodic", action="store_true",
+                    help="close the workload's lattice into a periodic cell (Sec. II C 1, step (i)); the stored "
+                         "oracle samples are of the open lattices, so the line then carries no oracle error")
+    ap.add_argument("--eigenstates", type=float, default=None, metavar="XI",
+                    help="time the eigenpairs nearest XI eV by block shift-invert (Appendix B) instead")
+    ap.add_argument("--eig-k", type=int, default=8, help="with --eigenstates: number of eigenpairs (1..16)")
+    ap.add_argument("--eig-iter", type=int, default=300, help="with --eigenstates: iteration limit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole hot path on a single MI355X "
@@ -294,13 +337,19 @@ def main():
     if args.find_mu is not None:
         mu_search(nd, config_system(name), name, n_poles, args, BETA)
         return
+    if args.eigenstates is not None:
+        if name == "multi2d_8x4":
+            raise SystemExit("--eigenstates runs on single-structure workloads")
+        eigen_run(nd, config_system(name), name, args)
+        return
     if args.fp64_poles is None:
         args.fp64_poles = FP64_POLES.get(name, 8)
     mu = 0.0
     if name == "multi2d_8x4":
-        systems = [config_system(name, i) for i in range(len(CONFIGS[name]["dims"]))]
+        systems = [config_system(name, i, args.periodic) for i in range(len(CONFIGS[name]["dims"]))]
     else:
-        systems = [config_system(name)]
+        systems = [config_system(name, periodic=args.periodic)]
+    gname = name + "_periodic" if args.periodic else name   # no stored sample or counters for periodic cells
     n = sum(x["n"] for x in systems)
     nnz = sum(int(x["row_ptr"][-1]) for x in systems)
     print("bench: %s structures=%d n=%d nnz=%d poles=%d" % (name, len(systems), n, nnz, n_poles), file=sys.stderr,
@@ -321,7 +370,7 @@ def main():
                     "poles_per_s": r["poles_per_s"], "ms_per_step": r["ms_per_step"],
                     "kernel_ms": {k: round(v["ms"], 3) for k, v in r["prof"].items()},
                     "max_abs_err_vs_complex128": max(float(np.max(np.abs(a - b))) for a, b in zip(rr, rho64)),
-                    "max_abs_err_vs_oracle_sample": golden_error(name, rr[0], mu, n_poles) if len(rr) == 1 else None,
+                    "max_abs_err_vs_oracle_sample": golden_error(gname, rr[0], mu, n_poles) if len(rr) == 1 else None,
                     "max_abs_err_e_vs_complex128": (float(np.max(np.abs(r["e"] - r64["e"]))) if args.energy
                                                     else None)}
     if args.precision == "fp64":
@@ -347,7 +396,7 @@ def main():
     gemm_tf = {k: (v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0)
                for k, v in prof.items() if k.startswith("gemm")}
     alg_bytes_per_launch = g["bytes"] / max(1, g["launches"])
-    traffic = measured_traffic(name, head["precision"])
+    traffic = measured_traffic(gname, head["precision"])
 
     line = {
         "metric": "poles/sec (selected inversion) on 3D 24^3x4 at 1e-7 rho error; MFMA TFLOP/s",
@@ -362,7 +411,8 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "mixed_fp32": "f64+f32", "mixed_bf16x3": "f64+bf16x3"}[head["precision"]],
         "data": "synthetic",
-        "config": {"workload": name, "description": WORKLOADS[name], "structures": len(systems), "n": n,
+        "config": {"workload": gname, "description": WORKLOADS[name] + (", periodic cell" if args.periodic else ""),
+                   "structures": len(systems), "n": n,
                    "nnz": nnz, "n_poles": n_poles, "kT_eV": 1.0 / BETA, "mu_eV": mu,
                    "mu_rule": "fixed at 0 eV for every workload (H is drawn symmetric about 0; on the 24^3 x 4 "
                               "lattice the half-filling mu from ndrho_find_mu is -0.0037 eV)",
@@ -374,7 +424,7 @@ def main():
         "tflops_model": head["flops_model_per_step"] / (head["ms_per_step"] * 1e-3) / 1e12,
         "max_abs_err_vs_complex128": (max(float(np.max(np.abs(a - b))) for a, b in zip(rho, rho64))
                                       if rho64 is not None else None),
-        "max_abs_err_vs_oracle_sample": golden_error(name, rho[0], mu, n_poles) if len(rho) == 1 else None,
+        "max_abs_err_vs_oracle_sample": golden_error(gname, rho[0], mu, n_poles) if len(rho) == 1 else None,
         "energy_density": None if not args.energy else {
             "computed": "rho and e (Eq. (10)) from the same poles in every timed step",
             "max_abs_e": float(np.max(np.abs(head["e"]))),
@@ -385,7 +435,7 @@ def main():
             "tflops_model": r64["flops_model_per_step"] / (r64["ms_per_step"] * 1e-3) / 1e12,
             "gemm_tflops": r64["prof"]["gemm"]["flops"] / (r64["prof"]["gemm"]["ms"] * 1e-3) / 1e12,
             "kernel_ms": {k: round(v["ms"], 3) for k, v in r64["prof"].items()},
-            "max_abs_err_vs_oracle_sample": golden_error(name, rho64[0], mu, n_poles) if len(rho64) == 1 else None},
+            "max_abs_err_vs_oracle_sample": golden_error(gname, rho64[0], mu, n_poles) if len(rho64) == 1 else None},
         "other_forms": others,
         "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
         "kernel_ms_by_depth": head["ms_by_depth"],

@@ -154,9 +154,11 @@ KT_EV = 0.1
 BETA = 1.0 / KT_EV
 
 
-def config_system(name, index=0):
-    """The system of a named workload (``index`` picks a lattice of multi2d)."""
+def config_system(name, index=0, periodic=False):
+    """The system of a named workload (``index`` picks a lattice of multi2d;
+    ``periodic`` closes the lattice into a periodic cell along every axis of
+    length 3 or more)."""
     cfg = CONFIGS[name]
     if name == "multi2d_8x4":
-        return lattice(cfg["dims"][index], cfg["neighbours"], cfg["seed"] + index)
-    return lattice(cfg["dims"], cfg["neighbours"], cfg["seed"])
+        return lattice(cfg["dims"][index], cfg["neighbours"], cfg["seed"] + index, periodic=periodic)
+    return lattice(cfg["dims"], cfg["neighbours"], cfg["seed"], periodic=periodic)
