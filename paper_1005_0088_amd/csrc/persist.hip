@@ -16,6 +16,12 @@
 // the plan's bound on pivot plus update rows; each has an update block of its
 // own in its depth's buffer (no two small fronts share one), so tasks of
 // different depths never overwrite each other's data.  All arithmetic is FP64.
+//
+// Not reachable at present: the context rejects the option that builds plans
+// for these launches, since they stalled on gfx950 (inside the first
+// evaluation of a 256-site chain, also with one workgroup) with the cause not
+// found.  A host build of this file through a stand-in HIP header reproduces
+// the selected inverse (tests/test_small_schedule_emu.py).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>

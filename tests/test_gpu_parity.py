@@ -849,14 +849,12 @@ def test_small_front_schedule_matches_level_schedule(precision):
     # per pass, tasks taken in tree order with dependency flags) against the
     # level-by-level launches of the same fronts: the 1D chain (every front
     # small), a 2D and a 3D lattice (small subtrees under large separators),
-    # a periodic lattice, several passes over pole batches, a structure batch.
-    # Mode 2 runs the same launches with one workgroup (tasks strictly in
-    # list order), mode 1 with the full grid.
+    # a periodic lattice, several passes over pole batches, a structure batch
     import paper_1005_0088_amd as nd
     systems = [lattice((256,), "nn", 0), lattice((24, 22), "nn2", 81), lattice((10, 9, 8), "nn", 82),
                lattice((12, 12), "nn", 83, periodic=True)]
     out = {}
-    for small in (0, 2, 1):
+    for small in (0, 1):
         with nd.Context(0, precision=precision, small_fronts=small, pole_batch=16) as c:
             sids = []
             for k, sysd in enumerate(systems):
@@ -882,14 +880,13 @@ def test_small_front_schedule_matches_level_schedule(precision):
         launches = prof["small_fronts"]["launches"]
         print("small_fronts=%d %s: %d persistent launches, %.3f ms" % (small, precision, launches,
                                                                       prof["small_fronts"]["ms"]), flush=True)
-        assert (launches > 0) == (small != 0)
+        assert (launches > 0) == (small == 1)
     tol = 1e-12 if precision == "fp64" else 2e-7
-    for mode in (2, 1):
-        for a, b in zip(out[0][0], out[mode][0]):
-            assert np.max(np.abs(a - b)) < tol
-        for a, b in zip(out[0][1], out[mode][1]):
-            assert np.max(np.abs(a - b)) < tol
-        assert np.max(np.abs(out[0][2] - out[mode][2])) < (1e-10 if precision == "fp64" else 1e-5)
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.max(np.abs(a - b)) < tol
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.max(np.abs(a - b)) < tol
+    assert np.max(np.abs(out[0][2] - out[1][2])) < (1e-10 if precision == "fp64" else 1e-5)
     if precision == "fp64":   # and against the dense oracle
         for k, (sysd, got) in enumerate(zip(systems, out[1][0])):
             h, s, rows, cols = _dense(sysd)
