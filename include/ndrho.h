@@ -397,7 +397,7 @@ int ndrho_device_copy(ndrho_ctx* ctx, void* dst, const void* src, int64_t bytes)
  * + 1/(x + i z_p)].  Errors: EINVAL. */
 int ndrho_cf_poles(int32_t n_poles, double* z, double* R);
 
-/* Nested dissection and symbolic analysis only (Sec. II C), for inspection.
+/* Nested dissection and symbolic analysis only (Secs. II C 1 and II C 2), for inspection.
  * Same input rules as set_structure (values are not needed); cell as in
  * ndrho_set_structure_periodic (NULL: open boundaries); leaf_rows and
  * long_tail as in ndrho_options. */
