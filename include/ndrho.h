@@ -75,10 +75,12 @@ typedef struct {
   int32_t pole_batch;   /* poles per device pass; 0 = largest that fits the memory budget */
   double mem_fraction;  /* fraction of free device memory the workspace may use (default 0.8) */
   int32_t verbose;      /* 0 = quiet; 1: ndrho_autotune reports each timed variant on stderr */
-  int32_t fp64_poles;   /* mixed mode: the fp64_poles shifts nearest the real axis stay FP64 (default 8) */
+  int32_t fp64_poles;   /* mixed mode: the fp64_poles shifts nearest the real axis stay FP64 (default 12:
+                           with 12 + 12, a 40^3-site lattice with 4 orbitals and 100 poles is within
+                           1e-7 of the FP64 result; smaller fronts need fewer) */
   double fp64_pole_im;  /* mixed mode: shifts with Im alpha < fp64_pole_im also stay FP64 (default 0.05) */
   int32_t fp64_far_poles; /* mixed mode: the fp64_far_poles shifts farthest from the axis stay FP64 too
-                             (default 8): their residues are as large as those of the nearest ones */
+                             (default 12): their residues are as large as those of the nearest ones */
   int32_t use_graph;    /* 1 (default): capture the launch sequence of an evaluation in a hipGraph and replay it */
   int32_t gemm_variant; /* mixed mode, front-update GEMMs of the low poles: -1 (default) per-launch choice
                            (heuristic, refined by ndrho_autotune); 0 FP64; 1 FP32 products on 64x64 tiles;

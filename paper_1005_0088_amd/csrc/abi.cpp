@@ -1289,9 +1289,9 @@ int ndrho_default_options(ndrho_options* opt) {
   opt->pole_batch = 0;
   opt->mem_fraction = 0.8;
   opt->verbose = 0;
-  opt->fp64_poles = 8;
+  opt->fp64_poles = 12;
   opt->fp64_pole_im = 0.05;
-  opt->fp64_far_poles = 8;
+  opt->fp64_far_poles = 12;
   opt->use_graph = 1;
   opt->gemm_variant = -1;
   opt->fp64_small_tiles = -1;

@@ -7,6 +7,7 @@ Calls only the oracle (and the seeded input generator).  Usage:
     python tests/golden/make_golden.py square2d_64x4 --edm   # rho and e (Eq. (10))
 
     python tests/golden/make_golden.py multi2d_8x4         # the eight lattices, one file
+    python tests/golden/make_golden.py cubic3d_24x4 --periodic   # the lattice closed into a periodic cell
 
 For each workload: rows j at chosen lattice sites, and rho_ij on every pattern
 entry of those rows (by symmetry also column j), from Eq. (8) with one sparse
@@ -16,7 +17,11 @@ middle of the first axis (one of the two lies in the top separator, which
 cuts the lattice there), a pair across the middle of the second axis in one
 half (a first-level separator), and the two far corners (innermost
 domains).  mu is fixed (stated in the file), since the half-filling mu of
-these sizes is not available from dense algebra.
+these sizes is not available from dense algebra.  With --periodic the lattice
+is closed into a periodic cell along every axis (couplings across the cell
+boundary folded onto the pattern) and the same sites are sampled; the 3D cell
+takes the GMRES route (its separators are two planes, so sparse LU fills in
+far more).
 """
 import argparse
 import json
@@ -75,14 +80,14 @@ def sample_rows(dims, count):
     return sorted(rows)
 
 
-def one_system(name, sysd, n_poles, count, edm, pool):
+def one_system(name, sysd, n_poles, count, edm, pool, gmres=False):
     rows = np.asarray(sample_rows(sysd["dims"], count))
     n = sysd["n"]
     h, s = sampled.csr_matrices(n, sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"])
     e_cols = None
     if edm:
         cols, e_cols = sampled.rho_edm_columns(h, s, MU[name], BETA, n_poles, rows, pool=pool)
-    elif name in GMRES:
+    elif name in GMRES or gmres:
         cols = sampled.rho_columns_gmres(h, s, MU[name], BETA, n_poles, rows, pool=pool)
     else:
         cols = sampled.rho_columns(h, s, MU[name], BETA, n_poles, rows, pool=pool)
@@ -103,11 +108,13 @@ def main():
     ap.add_argument("--procs", type=int, default=6)
     ap.add_argument("--edm", action="store_true",
                     help="also the energy density matrix e of Eq. (10) on the same entries (sparse LU route)")
+    ap.add_argument("--periodic", action="store_true", help="the workload's lattice in a periodic cell")
     a = ap.parse_args()
     name = a.workload
     n_poles = CONFIGS[name]["n_poles"]
     t0 = time.time()
-    src = ("oracle.sampled.rho_columns_gmres (GMRES per pole and column, rtol 1e-13, Eq. (8))" if name in GMRES
+    gmres = a.periodic and len([d for d in CONFIGS[name]["dims"] if d > 1]) == 3
+    src = ("oracle.sampled.rho_columns_gmres (GMRES per pole and column, rtol 1e-13, Eq. (8))" if name in GMRES or gmres
            else "oracle.sampled.rho_columns (sparse LU per pole, Eq. (8))")
     if a.edm:
         src = "oracle.sampled.rho_edm_columns (sparse LU per pole, Eqs. (8) and (10))"
@@ -123,14 +130,15 @@ def main():
             out = {"workload": name, "source": src, "mu": MU[name], "beta": BETA, "n_poles": n_poles,
                    "members": members, "seconds": time.time() - t0}
         else:
-            sysd = config_system(name)
-            rows, entries, values, e_values = one_system(name, sysd, n_poles, N_ROWS[name], a.edm, pool)
-            out = {"workload": name, "source": src,
+            sysd = config_system(name, periodic=a.periodic)
+            rows, entries, values, e_values = one_system(name, sysd, n_poles, N_ROWS[name], a.edm, pool, gmres)
+            out = {"workload": name + ("_periodic" if a.periodic else ""), "source": src, "cell": sysd["cell"],
                    "mu": MU[name], "beta": BETA, "n_poles": n_poles, "rows": [int(r) for r in rows],
                    "entries": entries, "values": values, "seconds": time.time() - t0}
             if a.edm:
                 out["e_values"] = e_values
-    path = os.path.join(HERE, ("edm_sampled_%s.json" if a.edm else "rho_sampled_%s.json") % name)
+    tag = name + ("_periodic" if a.periodic else "")
+    path = os.path.join(HERE, ("edm_sampled_%s.json" if a.edm else "rho_sampled_%s.json") % tag)
     with open(path, "w") as f:
         json.dump(out, f)
     print("wrote", path, "in %.0f s" % out["seconds"])

@@ -16,7 +16,7 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _levels_of_rows(sysd, rows):
-    P = nd.Plan(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["coords"], 32)
+    P = nd.Plan(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["coords"], 32, cell=sysd["cell"])
     ex = P.export()
     pos = np.empty(sysd["n"], np.int64)
     pos[ex["perm"]] = np.arange(sysd["n"])
@@ -58,3 +58,13 @@ def test_eight_lattice_sample_spans_the_levels_of_every_member():
     assert g["n_poles"] == 100
     for i, m in enumerate(g["members"]):
         _check_strata(config_system("multi2d_8x4", i), m["rows"])
+
+
+@pytest.mark.parametrize("name", ["square2d_64x4", "cubic3d_24x4"])
+def test_periodic_sample_rows_span_the_dissection_levels(name):
+    g = _load(name + "_periodic")
+    sysd = config_system(name, periodic=True)
+    assert g["cell"] == sysd["cell"]
+    _check_strata(sysd, g["rows"])
+    rows_of = np.repeat(np.arange(sysd["n"]), np.diff(sysd["row_ptr"]))
+    assert set(rows_of[np.asarray(g["entries"])].tolist()) == set(g["rows"])

@@ -1055,25 +1055,53 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
     assert len(lines) == 2 and lines[0] == bad and set(lines[1].split()[-1]) <= set("012")
 
 
-@pytest.mark.parametrize("precision,fp64_poles,tol", [("fp64", 0, 1e-10), ("mixed_bf16x3", 12, 1e-7)])
-def test_large_3d_against_oracle_sample(precision, fp64_poles, tol):
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed_bf16x3", 1e-7)])
+def test_large_3d_against_oracle_sample(precision, tol):
     # 40^3 sites x 4 (N = 256 000), 100 poles, 10 poles per device pass.  The
     # stored values come from GMRES solves (rtol 1e-13) per pole and column:
     # their error, rtol times the conditioning of each shifted matrix (tens
     # for the low poles) weighted by sum_p 4|R_p|/z_p ~ 7, stays below 1e-11,
     # under the FP64 bar of 1e-10.  The rows span the top separator, a
-    # mid-level separator and an innermost domain.  The mixed form keeps
-    # 12 + 12 poles in FP64 (the setting that holds 1e-7 at this size) on the
-    # default launch variants.
+    # mid-level separator and an innermost domain.  The mixed form runs with
+    # the library's default FP64 poles (12 + 12, the setting that holds 1e-7
+    # at this size) on the default launch variants.
     import paper_1005_0088_amd as nd
     from synth import config_system
     g = _golden("cubic3d_40x4")
     sysd = config_system("cubic3d_40x4")
-    with nd.Context(0, precision=precision, fp64_poles=fp64_poles, fp64_far_poles=fp64_poles) as c:
+    with nd.Context(0, precision=precision) as c:
         sid = _register(c, sysd)
         c.set_poles(sid, g["mu"], g["beta"], g["n_poles"])
         rho = c.density_matrix(sid)
         assert c.stats(sid)["pole_batch"] < g["n_poles"]     # several passes over pole batches
+        assert c.stats(sid)["n_fp64_poles"] == (24 if precision != "fp64" else 100)
     err = np.max(np.abs(rho[np.asarray(g["entries"])] - np.asarray(g["values"])))
     print("cubic3d_40x4 %s max err on %d sampled entries: %.3e" % (precision, len(g["entries"]), err))
+    assert err < tol
+
+
+@pytest.mark.parametrize("name,precision,fp64_poles,tol", [("square2d_64x4", "fp64", 0, 1e-10),
+                                                           ("square2d_64x4", "mixed_bf16x3", 8, 1e-7),
+                                                           ("cubic3d_24x4", "fp64", 0, 1e-10),
+                                                           ("cubic3d_24x4", "mixed_bf16x3", 4, 1e-7)])
+def test_periodic_full_size_against_oracle_sample(name, precision, fp64_poles, tol):
+    # the workload's lattice closed into a periodic cell (Sec. II C 1, step
+    # (i)): two-plane separators, J = 4 608 at the top of the 3D cell, whose
+    # poles take two device passes.  Stored rows span the top separator, lower
+    # separators and innermost domains (sparse LU per pole for the 2D cell,
+    # GMRES per pole and column, rtol 1e-13, for the 3D one).  The mixed form
+    # keeps the FP64 poles the benchmark keeps for the open lattice.
+    import paper_1005_0088_amd as nd
+    from synth import config_system
+    g = _golden(name + "_periodic")
+    sysd = config_system(name, periodic=True)
+    assert g["cell"] == sysd["cell"]
+    with nd.Context(0, precision=precision, fp64_poles=fp64_poles, fp64_far_poles=fp64_poles) as c:
+        print("case: %s periodic %s" % (name, precision), flush=True)
+        sid = c.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"],
+                              cell=sysd["cell"])
+        c.set_poles(sid, g["mu"], g["beta"], g["n_poles"])
+        rho = c.density_matrix(sid)
+    err = np.max(np.abs(rho[np.asarray(g["entries"])] - np.asarray(g["values"])))
+    print("%s periodic %s max err on %d sampled entries: %.3e" % (name, precision, len(g["entries"]), err))
     assert err < tol
