@@ -95,8 +95,7 @@ def load_library():
     global _lib
     if _lib is None:
         if not os.path.exists(lib_path):
-            raise ImportError("libndrho.so is not built: run `python -m paper_1005_0088_amd.build` "
-                              "(or __graft_entry__.build())")
+            raise ImportError("libndrho.so is not built: run `python -m paper_1005_0088_amd.build`")
         lib = C.CDLL(lib_path)
         for name, res, args in SIGNATURES:
             f = getattr(lib, name)
