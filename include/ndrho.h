@@ -129,7 +129,8 @@ const char* ndrho_last_error(const ndrho_ctx* ctx);
 /* Register one H, S pair (Sec. II, Eq. (2)): validates the CSR (format above),
  * computes the nested-dissection ordering (Sec. II C 1; geometric, from coords
  * when given as n*3 doubles of basis-function centres, row-major), the
- * front tree and index maps (the "table function" of Sec. II C 2), uploads
+ * front tree and index maps (the table from pattern entries to front positions,
+ * Sec. II C 2), uploads
  * everything to the device, and computes M0 = S^{-1} on the pattern by one
  * real selected inversion of S, which also checks that S is positive
  * definite.  *struct_id receives the handle for later calls.
@@ -207,8 +208,8 @@ int ndrho_green_traces(ndrho_ctx* ctx, int32_t struct_id, int32_t n, const doubl
  * ESTATE (no poles set), ESINGULAR, EDEVICE. */
 int ndrho_density_matrix_noalloc(ndrho_ctx* ctx, int32_t struct_id, double* rho_out_dev);
 
-/* Chemical potential with Tr(rho(mu) S) = n_ideal (Sec. II C 3, "Finding
- * chemical potential", Eqs. (40), (44)-(46)): each step sets the structure's
+/* Chemical potential with Tr(rho(mu) S) = n_ideal (the search of Sec. II C 3,
+ * Eqs. (40), (44)-(46)): each step sets the structure's
  * poles at a trial mu (as ndrho_set_poles with beta, n_poles), evaluates rho
  * and its count deviation dN = Tr(rho S) - n_ideal (Eq. (40)); the trial mu
  * comes from the quadratic through the three points of smallest |dN|, both

@@ -1,5 +1,5 @@
-// Nested dissection (Sec. II C 1), symbolic front tree, the "table function"
-// of pattern positions (Sec. II C 2) and the launch program of the block
+// Nested dissection (Sec. II C 1), symbolic front tree, the table from pattern
+// entries to front positions (Sec. II C 2) and the launch program of the block
 // LDL^T factorization and selected inversion (Eqs. (18)-(21), (38)-(39)).
 #include <algorithm>
 #include <cmath>

@@ -50,7 +50,7 @@ def test_pole_form_equals_backward_recurrence(n_poles):
 
 @pytest.mark.parametrize("n_poles", [60, 80, 100])
 def test_cf_reproduces_fermi_in_double_precision(n_poles):
-    # "100 poles at 600 K are exact within double precision" (Sec. II B).
+    # The paper states that 100 poles at 600 K reach double precision (Sec. II B).
     # With N_p poles the truncated fraction matches 1/(1+e^x) to a few ulp for
     # |x| up to about N_p^2/4.
     z, r = poles.cf_poles(n_poles)
