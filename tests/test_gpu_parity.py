@@ -383,6 +383,51 @@ def test_rho_against_dense_eigen_oracle(ctx, dims, nb, n_poles, coords):
     assert dense.trace_rho_s(got, sysd["s"]) == pytest.approx(sysd["n"], abs=1e-8)
 
 
+def _sweep_cases():
+    # seeded draw of small systems: 1D, 2D and 3D lattices of random extent,
+    # nearest or also second neighbours, open or periodic cells, dissection
+    # leaf sizes and pole counts
+    rng = np.random.default_rng(20261203)
+    cases = []
+    for i in range(12):
+        kind = i % 3
+        if kind == 0:
+            dims = (int(rng.integers(20, 150)),)
+        elif kind == 1:
+            dims = (int(rng.integers(3, 15)), int(rng.integers(3, 15)))
+        else:
+            dims = tuple(int(x) for x in rng.integers(2, 7, size=3))
+        nb = "nn2" if kind > 0 and rng.random() < 0.5 else "nn"
+        periodic = bool(rng.random() < 0.4)
+        leaf = int(rng.choice([8, 16, 32]))
+        n_poles = int(rng.choice([20, 40, 60]))
+        cases.append((dims, nb, periodic, leaf, n_poles, 100 + i))
+    return cases
+
+
+_SWEEP = _sweep_cases()
+
+
+@pytest.mark.parametrize("case", range(len(_SWEEP)))
+def test_seeded_sweep_of_small_lattices_against_dense_eigen_oracle(case):
+    import paper_1005_0088_amd as nd
+    dims, nb, periodic, leaf, n_poles, seed = _SWEEP[case]
+    sysd = lattice(dims, nb, seed, periodic=periodic)
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    mu = dense.mu_for_count(eps, BETA, float(sysd["n"]))
+    with nd.Context(0, leaf_rows=leaf) as cx:
+        print("case: sweep %d dims=%s nb=%s periodic=%s leaf=%d poles=%d n=%d" % (case, dims, nb, periodic, leaf,
+                                                                                n_poles, sysd["n"]), flush=True)
+        sid = cx.set_structure(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["h"], sysd["s"], sysd["coords"],
+                               cell=sysd["cell"])
+        cx.set_poles(sid, mu, BETA, n_poles)
+        got = cx.density_matrix(sid)
+    ref = dense.rho_cf_pattern(eps, c, mu, BETA, n_poles, rows, cols)
+    assert np.max(np.abs(got - ref)) < 1e-10
+    assert dense.trace_rho_s(got, sysd["s"]) == pytest.approx(sysd["n"], abs=1e-8)
+
+
 @pytest.mark.parametrize("dims,nb,precision,tol", [((12, 10), "nn2", "fp64", 1e-10), ((6, 6, 5), "nn", "fp64", 1e-10),
                                                    ((40,), "nn", "fp64", 1e-10),
                                                    ((12, 10), "nn2", "mixed_bf16x3", 1e-7)])
