@@ -421,12 +421,16 @@ def main():
                    "precision": head["precision"],
                    "fp64_poles": st["n_fp64_poles"], "fronts": sum(x["n_fronts"] for x in head["stats"]),
                    "levels": max(x["n_levels"] for x in head["stats"]), "root_j": st["root_j"],
-                   "pole_batch": st["pole_batch"]},
+                   "pole_batch": st["pole_batch"], "seeds": [int(x["seed"]) for x in systems],
+                   "neighbours": systems[0]["neighbours"]},
         "pole_structures_per_s": head["poles_per_s"] * len(systems),
         "tflops_model": head["flops_model_per_step"] / (head["ms_per_step"] * 1e-3) / 1e12,
         "max_abs_err_vs_complex128": (max(float(np.max(np.abs(a - b))) for a, b in zip(rho, rho64))
                                       if rho64 is not None else None),
         "max_abs_err_vs_oracle_sample": golden_error(gname, rho[0], mu, n_poles) if len(rho) == 1 else None,
+        # electron count Tr(rho S) (Eq. (40)) from the pattern values, against N (half filling); mu is fixed,
+        # so the difference is the distance of that mu from half filling, not an error
+        "trace_rho_s_minus_n": [float(np.dot(r, x["s"]) - x["n"]) for r, x in zip(rho, systems)],
         "energy_density": None if not args.energy else {
             "computed": "rho and e (Eq. (10)) from the same poles in every timed step",
             "max_abs_e": float(np.max(np.abs(head["e"]))),
