@@ -161,6 +161,7 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
                                 cell=sysd.get("cell"))
         ctx.set_poles(sid, mu, beta, n_poles)
         sids.append(sid)
+    register_s = time.time() - t0   # dissection, symbolic analysis, upload and M0 of every structure
     if precision != "fp64" and autotune and variant < 0:
         ctx.autotune(sids, tune_cache)   # per-launch GEMM variant (untimed set-up, like the plan)
     outs = [ctx.device_buffer(int(sysd["row_ptr"][-1])) for sysd in systems]
@@ -205,7 +206,8 @@ def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_pole
         e_vals = e_out.numpy()
         e_out.free()
     ctx.close()
-    res = {"precision": precision, "setup_s": setup_s, "ms_per_step": 1e3 * dt / steps, "e": e_vals,
+    res = {"precision": precision, "setup_s": setup_s, "register_s": register_s, "ms_per_step": 1e3 * dt / steps,
+           "e": e_vals,
            "phases": phases,
            "poles_per_s": n_poles * steps / dt, "stats": st, "prof": prof,
            "ms_by_depth": {k: [round(float(x), 3) for x in v] for k, v in by_depth.items() if v.any()},
@@ -460,6 +462,9 @@ def main():
                      "launches": g["launches"], "avg_launch_ms": g["ms"] / max(1, g["launches"]),
                      "flops_per_step": g["flops"]},
         "ms_per_phase": head["phases"]["ms_per_phase"],
+        # set-up outside the timed steps: registration (dissection, symbolic analysis, upload, M0) and the
+        # whole set-up including the autotuner (and, with --energy, the first moment M1)
+        "setup_s": {"register": head["register_s"], "total": head["setup_s"]},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(systems[-1], mu, BETA, n_poles, args.cpu_seconds)
