@@ -93,12 +93,15 @@ typedef struct {
   int32_t fp64_small_tiles; /* FP64 GEMM launches: -1 (default) one wave per 32x32 output tile where the
                                launch's problems would fill less than half of the 64x64 tiles; 0 never;
                                1 always */
-  int32_t split_streams; /* mixed mode, 0-4: k >= 1 (default 1) runs the FP64 poles of a pass and its
-                            low-precision poles, divided into k parts, as k + 1 independent launch chains
-                            on further streams that the context creates (default priority), joined back
-                            before the pole sum, in passes of at least 1e10 modelled flops (smaller ones
-                            run one chain); 0 runs one chain.  Results are identical either way.
-                            Profiling (ndrho_profile, ndrho_autotune) always runs one chain */
+  int32_t split_streams; /* mixed mode, 0-4: 0 (default) runs every pass as one launch chain, captured in
+                            a hipGraph; k >= 1 runs the FP64 poles of a pass and its low-precision poles,
+                            divided into k parts, as k + 1 independent launch chains on further streams
+                            that the context creates (default priority), joined back before the pole sum,
+                            in passes of at least 1e10 modelled flops (smaller ones run one chain); such
+                            forked passes are launched directly, not captured.  The chains share the
+                            compute units: on one GPU they measured no faster than one chain.  Results
+                            are identical either way.  Profiling (ndrho_profile, ndrho_autotune) always
+                            runs one chain */
   double long_tail;      /* screening of long-tail basis functions (Sec. II C 1, step (ii)): 0 (default)
                             off; L >= 1: in every domain of the dissection, rows whose number of
                             pattern neighbours inside the domain exceeds L times the domain's median

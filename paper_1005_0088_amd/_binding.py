@@ -236,7 +236,7 @@ class Context:
 
     def __init__(self, device=0, stream=None, leaf_rows=32, pole_batch=0, mem_fraction=0.8, precision="fp64",
                  fp64_poles=None, fp64_pole_im=None, use_graph=True, gemm_variant=-1, fp64_far_poles=None,
-                 fp64_small_tiles=-1, split_streams=1, long_tail=0.0, verbose=0, small_fronts=0):
+                 fp64_small_tiles=-1, split_streams=0, long_tail=0.0, verbose=0, small_fronts=0):
         self._lib = load_library()
         opt = Options()
         self._lib.ndrho_default_options(C.byref(opt))

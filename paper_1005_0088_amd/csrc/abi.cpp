@@ -1295,7 +1295,7 @@ int ndrho_default_options(ndrho_options* opt) {
   opt->use_graph = 1;
   opt->gemm_variant = -1;
   opt->fp64_small_tiles = -1;
-  opt->split_streams = 1;
+  opt->split_streams = 0;
   opt->long_tail = 0.0;
   opt->small_fronts = 0;
   return NDRHO_OK;

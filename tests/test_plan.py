@@ -53,7 +53,7 @@ def test_default_options_and_struct_layouts():
     assert lib.ndrho_default_options(ctypes.byref(opt)) == 0
     want = {"leaf_rows": 32, "precision": 0, "pole_batch": 0, "mem_fraction": 0.8, "verbose": 0, "fp64_poles": 12,
             "fp64_pole_im": 0.05, "fp64_far_poles": 12, "use_graph": 1, "gemm_variant": -1, "fp64_small_tiles": -1,
-            "split_streams": 1, "long_tail": 0.0, "small_fronts": 0}
+            "split_streams": 0, "long_tail": 0.0, "small_fronts": 0}
     assert {k: getattr(opt, k) for k, _ in opt._fields_} == want
 
 
