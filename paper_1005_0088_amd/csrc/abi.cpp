@@ -778,7 +778,7 @@ struct ndrho_ctx {
     // hipGraph and replayed; anything that changes a launch argument (the
     // workspace, the shift arrays, the batch size, the precision split)
     // changes the key and triggers a new capture.
-    std::vector<const void*> key = {ws, acc, status, alpha, w, S.m0, reinterpret_cast<const void*>(astride),
+    std::vector<const void*> key = {ws, acc, status, sched, alpha, w, S.m0, reinterpret_cast<const void*>(astride),
                                     reinterpret_cast<const void*>(static_cast<intptr_t>(S.tune_gen))};
     key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(nb)));
     key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(n)));
