@@ -52,6 +52,41 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t total) {
   return x * q + (x < r ? x : r) + local;
 }
 
+// Relative maps of a G_EXTC0 tile staged in LDS: for each child c of the
+// front (at most XM_MAX), the child-local update index (or -1) of the tile's
+// rows m0 .. m0 + tile - 1 at [c][0 .. tile) and of its columns n0 ..
+// n0 + tile - 1 at [c][tile .. 2 tile).  p == nullptr: not staged (a front
+// with more children, or a kernel without LDS); the epilogue then reads the
+// maps from global memory.
+constexpr int XM_MAX = 4;
+struct XMap {
+  const int32_t* p;
+  int m0, n0, tile;
+};
+
+// Copies the maps of the tile's children into LDS (`mem`, at least
+// 2 * XM_MAX * tile int32) once the main loop has finished with it: every
+// kernel's K loop ends on a barrier after its last read of the staging
+// memory, so the copy may start at once; a barrier follows it.  Called by the
+// whole workgroup (the child count is uniform).
+template <int NT>
+__device__ __forceinline__ XMap stage_ext_maps(void* mem, int tile, const GemmProb& pr, const ExtAddDesc& xd,
+                                               const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi,
+                                               int m0, int n0) {
+  if (xd.child_count > XM_MAX) return XMap{nullptr, m0, n0, tile};
+  int32_t* xm = static_cast<int32_t*>(mem);
+  const int per = 2 * tile;
+  for (int e = threadIdx.x; e < xd.child_count * per; e += NT) {
+    const int c = e / per, w = e % per;
+    const bool col = w >= tile;
+    const int pos = (col ? n0 : m0) + (col ? w - tile : w);
+    const ExtAddChild k = xk[xd.child_begin + c];
+    xm[e] = pos < (col ? pr.n : pr.m) ? xi[k.inv_off + xd.nj + pos] : -1;
+  }
+  __syncthreads();
+  return XMap{xm, m0, n0, tile};
+}
+
 // Epilogue of a chunk of NE result elements held by one thread,
 // C = [C0 +] (+/-) product: negate, add C0 (read from memory with G_BETA,
 // formed from the children with G_EXTC0), store, and with a mirrored
@@ -59,14 +94,15 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t total) {
 // above the diagonal of a symmetric output, are skipped.  With G_EXTC0 the C0
 // of an element of a front's U x U update is the sum, in child order, of the
 // children's lower-stored update entries that map onto it (the same sum the
-// extend-add forms for the panel); the map reads of the whole chunk are issued
-// before any of its value reads, so that a thread waits twice per child and
-// not twice per element and child.
+// extend-add forms for the panel).  With the maps staged in LDS (xm.p), the
+// entry reads of two children are issued together, so that a thread waits
+// once per pair of children; otherwise the map reads of the whole chunk are
+// issued before any of its value reads (two waits per child).
 template <int FLAGS, int NE>
 __device__ __forceinline__ void store_chunk(double2 (&v)[NE], const int (&m)[NE], const int (&n)[NE],
                                             const GemmProb& pr, const double2* C0p, double2* Cp,
                                             const ExtAddDesc& xd, const ExtAddChild* __restrict__ xk,
-                                            const int32_t* __restrict__ xi) {
+                                            const int32_t* __restrict__ xi, const XMap& xm) {
   constexpr bool BETA = (FLAGS & G_BETA) != 0, NEG = (FLAGS & G_NEG) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
   constexpr bool SYM = (FLAGS & G_SYM) != 0, MIRROR = SYM && !(FLAGS & G_NOMIRROR);
   bool live[NE];
@@ -76,22 +112,56 @@ __device__ __forceinline__ void store_chunk(double2 (&v)[NE], const int (&m)[NE]
   if (EXTC0) {
 #pragma unroll
     for (int q = 0; q < NE; ++q) c0[q] = make_double2(0.0, 0.0);
-    for (int c = 0; c < xd.child_count; ++c) {
-      const ExtAddChild k = xk[xd.child_begin + c];
-      const int32_t* im = xi + k.inv_off + xd.nj;
-      int32_t a[NE], b[NE];
+    if (xm.p) {
+      for (int c = 0; c < xd.child_count; c += 2) {
+        const bool two = c + 1 < xd.child_count;
+        const ExtAddChild k0 = xk[xd.child_begin + c];
+        const ExtAddChild k1 = xk[xd.child_begin + (two ? c + 1 : c)];
+        const int32_t* r0 = xm.p + c * 2 * xm.tile;
+        const int32_t* r1 = r0 + 2 * xm.tile;
+        double2 x0[NE], x1[NE];
+        bool ok0[NE], ok1[NE];
 #pragma unroll
-      for (int q = 0; q < NE; ++q) {
-        a[q] = live[q] ? im[m[q]] : -1;
-        b[q] = live[q] ? im[n[q]] : -1;
-      }
-#pragma unroll
-      for (int q = 0; q < NE; ++q)
-        if (a[q] >= 0 && b[q] >= 0) {  // the children store the lower triangle of their update
-          const double2 x = C0p[k.upd_off + max(a[q], b[q]) + int64_t(min(a[q], b[q])) * k.nu];
-          c0[q].x += x.x;
-          c0[q].y += x.y;
+        for (int q = 0; q < NE; ++q) {
+          const int a0 = live[q] ? r0[m[q] - xm.m0] : -1, b0 = live[q] ? r0[xm.tile + n[q] - xm.n0] : -1;
+          const int a1 = live[q] && two ? r1[m[q] - xm.m0] : -1;
+          const int b1 = live[q] && two ? r1[xm.tile + n[q] - xm.n0] : -1;
+          ok0[q] = a0 >= 0 && b0 >= 0;
+          ok1[q] = a1 >= 0 && b1 >= 0;
+          // the children store the lower triangle of their update
+          x0[q] = ok0[q] ? C0p[k0.upd_off + max(a0, b0) + int64_t(min(a0, b0)) * k0.nu] : make_double2(0.0, 0.0);
+          x1[q] = ok1[q] ? C0p[k1.upd_off + max(a1, b1) + int64_t(min(a1, b1)) * k1.nu] : make_double2(0.0, 0.0);
         }
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          if (ok0[q]) {
+            c0[q].x += x0[q].x;
+            c0[q].y += x0[q].y;
+          }
+          if (ok1[q]) {
+            c0[q].x += x1[q].x;
+            c0[q].y += x1[q].y;
+          }
+        }
+      }
+    } else {
+      for (int c = 0; c < xd.child_count; ++c) {
+        const ExtAddChild k = xk[xd.child_begin + c];
+        const int32_t* im = xi + k.inv_off + xd.nj;
+        int32_t a[NE], b[NE];
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          a[q] = live[q] ? im[m[q]] : -1;
+          b[q] = live[q] ? im[n[q]] : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+          if (a[q] >= 0 && b[q] >= 0) {  // the children store the lower triangle of their update
+            const double2 x = C0p[k.upd_off + max(a[q], b[q]) + int64_t(min(a[q], b[q])) * k.nu];
+            c0[q].x += x.x;
+            c0[q].y += x.y;
+          }
+      }
     }
   }
 #pragma unroll
@@ -441,6 +511,7 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
 
   const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
+  const XMap xm = EXTC0 ? stage_ext_maps<256>(&As[0][0][0], BM, pr, xd, xk, xi, m0, n0) : XMap{nullptr, 0, 0, 0};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
@@ -454,7 +525,7 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
         nn[4 * j + r] = n0 + wn * 32 + j * 16 + F64_DROW(r, lane);
         v[4 * j + r] = make_double2(p1[i][j][r] - p2[i][j][r], p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
       }
-    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
+    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
   }
 }
 
@@ -541,6 +612,7 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__
 
   const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
+  const XMap xm{nullptr, 0, 0, 0};  // no LDS in this kernel: maps read from global memory
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
@@ -554,7 +626,7 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__
         nn[4 * j + q] = n0 + j * 16 + F64_DROW(q, lane);
         v[4 * j + q] = make_double2(p1[i][j][q] - p2[i][j][q], p3[i][j][q] - p1[i][j][q] - p2[i][j][q]);
       }
-    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
+    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
   }
 }
 
@@ -683,6 +755,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
 
   const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
+  const XMap xm = EXTC0 ? stage_ext_maps<256>(&As[0][0][0], TM, pr, xd, xk, xi, m0, n0) : XMap{nullptr, 0, 0, 0};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < WT; ++i)
@@ -698,7 +771,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const GemmProb* __restrict__
           nn[4 * (j - j0) + r] = n0 + wn * 16 * WT + j * 16 + F32_DROW(r, lane);
           v[4 * (j - j0) + r] = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
         }
-      store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
+      store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
     }
 }
 
@@ -921,6 +994,7 @@ __global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restric
 
   const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
+  const XMap xm = EXTC0 ? stage_ext_maps<NT>(&lds[0][0], B3_TM, pr, xd, xk, xi, m0, n0) : XMap{nullptr, 0, 0, 0};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < IB; ++i) {
@@ -934,7 +1008,7 @@ __global__ __launch_bounds__(NW * 64) void k_cgemm_bf3(const GemmProb* __restric
         nn[4 * j + r] = n0 + wn * WCOL + j * 16 + F32_DROW(r, lane);
         v[4 * j + r] = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
       }
-    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
+    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
   }
 }
 
@@ -1104,6 +1178,7 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__
 
   const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
+  const XMap xm = EXTC0 ? stage_ext_maps<512>(lds, B3S_TM, pr, xd, xk, xi, m0, n0) : XMap{nullptr, 0, 0, 0};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -1117,7 +1192,7 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3s(const GemmProb* __restrict__
         nn[4 * j + r] = n0 + wn * 32 + j * 16 + F32_DROW(r, lane);
         v[4 * j + r] = make_double2(static_cast<double>(cre[i][j][r]), static_cast<double>(cim[i][j][r]));
       }
-    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
+    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
   }
 }
 
@@ -1299,6 +1374,7 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3p(const GemmProb* __restrict__
   // row = column n of the tile (B block first), column = row m
   const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
+  const XMap xm = EXTC0 ? stage_ext_maps<512>(lds, B3P_TM, pr, xd, xk, xi, m0, n0) : XMap{nullptr, 0, 0, 0};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -1313,7 +1389,7 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3p(const GemmProb* __restrict__
         nn[t] = n0 + wn * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         v[t] = make_double2(static_cast<double>(cre[i][r]), static_cast<double>(cim[i][r]));
       }
-      store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi);
+      store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
     }
 }
 
