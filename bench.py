@@ -147,13 +147,13 @@ def golden_error(name, rho, mu, n_poles):
 
 
 def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_poles, autotune=True, gemm_variant=-1,
-             tune_cache=None, split_streams=1, energy=False):
+             tune_cache=None, split_streams=1, energy=False, small_fronts=0):
     """Time one precision form on one system (density_matrix, or with
     energy=True energy_density_matrix: rho and e) or several
     (density_matrix_batch: one schedule); returns (timing dict, rho list)."""
     variant = gemm_variant if precision != "fp64" else -1
     ctx = nd.Context(0, precision=precision, fp64_poles=fp64_poles, fp64_far_poles=fp64_poles, gemm_variant=variant,
-                     split_streams=split_streams, verbose=1)
+                     split_streams=split_streams, verbose=1, small_fronts=small_fronts)
     t0 = time.time()
     sids = []
     for sysd in systems:
@@ -305,6 +305,9 @@ def main():
                          "the kernels' durations in the timed steps are those of the instrumented step and of "
                          "the profiler's trace; 1 runs the FP64 poles beside, about 1 %% faster on 24^3 x 4)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--small-fronts", type=int, default=0, choices=[0, 1],
+                    help="1: the small fronts of the deep levels run in fused launches (one per depth and "
+                         "direction, one workgroup per front and pole)")
     ap.add_argument("--periodic", action="store_true",
                     help="close the workload's lattice into a periodic cell (Sec. II C 1, step (i)); the stored "
                          "oracle samples are of the open lattices, so the line then carries no oracle error")
@@ -362,13 +365,14 @@ def main():
     r64 = rho64 = None
     if args.forms != "head" or args.precision == "fp64":
         r64, rho64 = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, "fp64", 0,
-                              energy=args.energy)
+                              energy=args.energy, small_fronts=args.small_fronts)
     others = {}
     if args.forms == "all":
         for form in ("mixed_fp32", "mixed_bf16x3"):
             if form != args.precision:
                 r, rr = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, form, args.fp64_poles,
-                                 not args.no_autotune, -1, args.tune_cache, args.split_streams, args.energy)
+                                 not args.no_autotune, -1, args.tune_cache, args.split_streams, args.energy,
+                                 args.small_fronts)
                 others[form] = {
                     "poles_per_s": r["poles_per_s"], "ms_per_step": r["ms_per_step"],
                     "kernel_ms": {k: round(v["ms"], 3) for k, v in r["prof"].items()},
@@ -381,7 +385,7 @@ def main():
     else:
         head, rho = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, args.precision,
                              args.fp64_poles, not args.no_autotune, args.gemm_variant, args.tune_cache,
-                             args.split_streams, args.energy)
+                             args.split_streams, args.energy, args.small_fronts)
     st, prof = head["stats"][0], head["prof"]
     # dominant kernel: the FP64 front GEMMs in the FP64 form, the FP32-product
     # front GEMMs in the mixed form (peak of their own arithmetic)
@@ -424,6 +428,7 @@ def main():
                    "fp64_poles": st["n_fp64_poles"], "fronts": sum(x["n_fronts"] for x in head["stats"]),
                    "levels": max(x["n_levels"] for x in head["stats"]), "root_j": st["root_j"],
                    "pole_batch": st["pole_batch"], "seeds": [int(x["seed"]) for x in systems],
+                   "small_fronts": args.small_fronts,
                    "neighbours": systems[0]["neighbours"]},
         "pole_structures_per_s": head["poles_per_s"] * len(systems),
         "tflops_model": head["flops_model_per_step"] / (head["ms_per_step"] * 1e-3) / 1e12,

@@ -106,11 +106,13 @@ typedef struct {
                             off; L >= 1: in every domain of the dissection, rows whose number of
                             pattern neighbours inside the domain exceeds L times the domain's median
                             join the domain's separator before the cut is sought */
-  int32_t small_fronts;  /* must be 0 (the default): every front runs level by level.  Reserved for
-                            a persistent schedule of the small fronts (one launch per pass and
-                            direction taking (front, pole) tasks in tree order); that schedule is
-                            disabled, since its launches stalled on gfx950 with the cause not
-                            found, and any other value fails with NDRHO_EINVAL */
+  int32_t small_fronts;  /* 0 (default): every front runs in the level launches of its depth (extend-add,
+                            pivot inverse and update GEMMs as separate grouped launches).  1: the small
+                            fronts (at most 64 pivot rows and 320 pivot plus update rows, with every
+                            descendant small) run in fused launches instead, one per depth and direction
+                            with one workgroup per (front, pole) doing the front's whole step in FP64
+                            (extend-add, assembly, pivot inverse, L and the Schur update upward; the
+                            G_UU gather, G_UJ and G_JJ downward).  Other values: NDRHO_EINVAL */
 } ndrho_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -359,8 +361,8 @@ enum { NDRHO_K_EXTADD = 0, NDRHO_K_ASSEMBLE = 1, NDRHO_K_PIVOT_INV = 2, NDRHO_K_
        NDRHO_K_GEMM_BF16X3 = 9, NDRHO_K_SMALL = 10, NDRHO_K_COUNT = 11 };
 /* NDRHO_K_GEMM: FP64 front-update GEMMs; NDRHO_K_GEMM_PIVOT: FP64 GEMMs of the
  * recursive pivot-block inverse; NDRHO_K_GEMM_F32: FP32-product front updates;
- * NDRHO_K_GEMM_BF16X3: split-BF16 front updates; NDRHO_K_SMALL: launches of
- * the persistent small-front schedule (disabled: always zero). */
+ * NDRHO_K_GEMM_BF16X3: split-BF16 front updates; NDRHO_K_SMALL: the fused
+ * small-front launches (small_fronts = 1). */
 
 /* enable != 0: from now on every launch is bracketed by HIP events on the
  * context stream and its duration is added to a per-kind total (clears the

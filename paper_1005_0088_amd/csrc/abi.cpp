@@ -62,7 +62,7 @@ struct DevStruct {
   int64_t* acc_slot = nullptr;
   int32_t* acc_entry = nullptr;
   int32_t* acc_sid = nullptr;  // joined plans: structure of each sorted pattern slot
-  SmallFront *small_up = nullptr, *small_down = nullptr;  // persistent schedule of the small fronts
+  SmallFront *small_up = nullptr, *small_down = nullptr;  // the fused small-front launches' fronts
   SmallChild* small_kids = nullptr;
   int32_t* small_inv = nullptr;
   // shifts and weights
@@ -248,12 +248,8 @@ struct ndrho_ctx {
   double* acc_e = nullptr;
   double* outbuf_e = nullptr;
   int64_t acc_e_len = 0;
-  int* status = nullptr;  // [0] singular pivots, [1] non-positive pivots of S, [2] schedule wait bound hit, [3] spare
-  // dependency flags, task counters and abort words of the small-front schedule
-  void* sched = nullptr;
-  size_t sched_bytes = 0;
+  int* status = nullptr;  // [0] singular pivots, [1] non-positive pivots of S, [2], [3] spare
   void* scratch = nullptr;  // this device's fixed scratch (no-allocation entry point)
-  long long wait_ticks = 0;  // 2 s of the device's constant-rate clock (bound of a schedule wait)
   double last_ms = 0;
   int last_batch = 0;
   // profiling: events around launches, folded into per-kind totals
@@ -352,7 +348,6 @@ struct ndrho_ctx {
     if (acc_e) (void)hipFree(acc_e);
     if (outbuf_e) (void)hipFree(outbuf_e);
     if (status) (void)hipFree(status);
-    if (sched) (void)hipFree(sched);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
@@ -391,20 +386,6 @@ struct ndrho_ctx {
       }
       ws_bytes = need;
     }
-    const size_t sneed = sched_need(P, nb);
-    if (sneed > sched_bytes) {
-      if (sched) {
-        HIP_OK(hipStreamSynchronize(stream));
-        HIP_OK(hipFree(sched));
-      }
-      sched = nullptr;
-      sched_bytes = 0;
-      if (hipMalloc(&sched, sneed) != hipSuccess) {
-        (void)hipGetLastError();
-        fail(NDRHO_ENOMEM, "schedule flags allocation failed");
-      }
-      sched_bytes = sneed;
-    }
     if (P.nnz > acc_len) {
       if (acc) HIP_OK(hipFree(acc));
       if (outbuf) HIP_OK(hipFree(outbuf));
@@ -414,25 +395,6 @@ struct ndrho_ctx {
         fail(NDRHO_ENOMEM, "accumulator allocation failed");
       acc_len = P.nnz;
     }
-  }
-
-  // Bytes of the small-front schedule's words for `nb` poles: completion
-  // flags per (front, pole position), then per pole position two task
-  // counters (upward, downward) and two abort words.
-  static size_t sched_need(const Plan& P, int nb) {
-    const size_t nf = std::max(P.small_up.size(), size_t(1));
-    return (nf * nb * sizeof(int) + 255) / 256 * 256 + 2 * size_t(nb) * sizeof(unsigned long long) +
-           2 * size_t(nb) * sizeof(int);
-  }
-  void sched_words(int nlay, int q0, bool up, int** flags, unsigned long long** head, int** abort_flag,
-                   const Plan& P) const {
-    char* b = static_cast<char*>(sched);
-    const size_t nf = std::max(P.small_up.size(), size_t(1));
-    const size_t fbytes = (nf * nlay * sizeof(int) + 255) / 256 * 256;
-    *flags = reinterpret_cast<int*>(b) + q0;
-    *head = reinterpret_cast<unsigned long long*>(b + fbytes) + 2 * q0 + (up ? 0 : 1);
-    *abort_flag = reinterpret_cast<int*>(b + fbytes + 2 * size_t(nlay) * sizeof(unsigned long long)) + 2 * q0 +
-                  (up ? 0 : 1);
   }
 
   // Poles per device pass for plan P.
@@ -581,7 +543,7 @@ struct ndrho_ctx {
         case OP_SMALL: {
           SmallLaunch sl;
           sl.up = op.flags == 0;
-          sl.fronts = sl.up ? S.small_up : S.small_down;
+          sl.fronts = (sl.up ? S.small_up : S.small_down) + op.begin;
           sl.kids = S.small_kids;
           sl.inv = S.small_inv;
           sl.rel = S.rel;
@@ -594,11 +556,7 @@ struct ndrho_ctx {
           sl.hv = S.h, sl.sv = S.s;
           sl.alpha = alpha, sl.astride = astride, sl.hcoef = hcoef, sl.spd_check = spd_check;
           sl.status = status;
-          sched_words(nlay, q0, sl.up, &sl.flags, &sl.head, &sl.abort_flag, P);
-          sl.fstride = nlay;
-          sl.wait_ticks = wait_ticks;
-          const double fl = sl.up ? P.small_flops_up : P.small_flops_down;
-          timed(NDRHO_K_SMALL, fl * nb, [&] { e = launch_small(sl, st); });
+          timed(NDRHO_K_SMALL, op.flops * nb, [&] { e = launch_small(sl, st); });
           break;
         }
         case OP_GATHER:
@@ -778,7 +736,7 @@ struct ndrho_ctx {
     // hipGraph and replayed; anything that changes a launch argument (the
     // workspace, the shift arrays, the batch size, the precision split)
     // changes the key and triggers a new capture.
-    std::vector<const void*> key = {ws, acc, status, sched, alpha, w, S.m0, reinterpret_cast<const void*>(astride),
+    std::vector<const void*> key = {ws, acc, status, alpha, w, S.m0, reinterpret_cast<const void*>(astride),
                                     reinterpret_cast<const void*>(static_cast<intptr_t>(S.tune_gen))};
     key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(nb)));
     key.push_back(reinterpret_cast<const void*>(static_cast<intptr_t>(n)));
@@ -826,7 +784,6 @@ struct ndrho_ctx {
     HIP_OK(hipMemcpyAsync(w, status, 4 * sizeof(int), hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     if (!recs.empty()) fold_profile();
-    if (w[2]) fail(NDRHO_EDEVICE, "a wait of the small-front schedule exceeded its bound");
     st[0] = w[0];
     st[1] = w[1];
   }
@@ -1320,10 +1277,7 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
       fail(NDRHO_EINVAL, "invalid FP64 pole rule");
     if (c->opt.fp64_small_tiles < -1 || c->opt.fp64_small_tiles > 1) fail(NDRHO_EINVAL, "invalid fp64_small_tiles");
     if (!(c->opt.long_tail == 0.0 || c->opt.long_tail >= 1.0)) fail(NDRHO_EINVAL, "long_tail must be 0 or >= 1");
-    if (c->opt.small_fronts != 0)
-      fail(NDRHO_EINVAL,
-           "small_fronts must be 0: the persistent small-front schedule is disabled (its launches stalled on "
-           "gfx950, cause not found)");
+    if (c->opt.small_fronts != 0 && c->opt.small_fronts != 1) fail(NDRHO_EINVAL, "small_fronts must be 0 or 1");
     if (c->opt.split_streams < 0 || c->opt.split_streams > ndrho_ctx::kMaxChains)
       fail(NDRHO_EINVAL, "invalid split_streams");
     if (c->opt.gemm_variant < -1 || c->opt.gemm_variant >= V_COUNT ||
@@ -1348,9 +1302,6 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
     }
     if (hipMalloc(&c->status, 4 * sizeof(int)) != hipSuccess) fail(NDRHO_ENOMEM, "status allocation failed");
     c->scratch = scratch_addr(device);
-    int khz = 0;
-    HIP_OK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
-    c->wait_ticks = 2000LL * (khz > 0 ? khz : 100000);
   });
   if (rc == NDRHO_OK) *out = c.release();
   return rc;
@@ -1895,11 +1846,11 @@ int ndrho_density_matrix_noalloc(ndrho_ctx* ctx, int32_t struct_id, double* rho_
     HIP_OK(hipSetDevice(ctx->device));
     const Plan& P = ds.plan;
     // scratch layout: [status (256 B)][accumulator, nnz doubles, 256-aligned]
-    // [small-front schedule words for nb poles][workspace of nb poles]
+    // [workspace of nb poles]
     const size_t acc_bytes = (static_cast<size_t>(P.nnz) * sizeof(double) + 255) / 256 * 256;
     const size_t per_pole = static_cast<size_t>(ndrho_ctx::per_pole_elems(P)) * sizeof(double2);
     auto need = [&](int nb) {
-      return 256 + acc_bytes + (ndrho_ctx::sched_need(P, nb) + 255) / 256 * 256 + per_pole * size_t(nb);
+      return 256 + acc_bytes + per_pole * size_t(nb);
     };
     if (need(1) > kScratchBytes)
       fail(NDRHO_ENOMEM, "the structure needs " + std::to_string(need(1)) +
@@ -1908,7 +1859,6 @@ int ndrho_density_matrix_noalloc(ndrho_ctx* ctx, int32_t struct_id, double* rho_
     int nb = 1;
     while (nb < ds.n_shifts && need(nb + 1) <= kScratchBytes) ++nb;
     char* base = static_cast<char*>(ctx->scratch);
-    const size_t sched_bytes = (ndrho_ctx::sched_need(P, nb) + 255) / 256 * 256;
     // the evaluation runs on the scratch: one launch chain of plain launches
     // (no graph, no further streams), passes of nb poles
     struct Swap {
@@ -1918,23 +1868,17 @@ int ndrho_density_matrix_noalloc(ndrho_ctx* ctx, int32_t struct_id, double* rho_
       double* acc;
       int64_t acc_len;
       int* status;
-      void* sched;
-      size_t sched_bytes;
       ndrho_options opt;
       bool prof;
       ~Swap() {
         c->ws = ws, c->ws_bytes = ws_bytes, c->acc = acc, c->acc_len = acc_len, c->status = status, c->opt = opt;
-        c->sched = sched, c->sched_bytes = sched_bytes;
         c->prof = prof;
       }
-    } swap{ctx, ctx->ws, ctx->ws_bytes, ctx->acc, ctx->acc_len, ctx->status, ctx->sched, ctx->sched_bytes, ctx->opt,
-           ctx->prof};
+    } swap{ctx, ctx->ws, ctx->ws_bytes, ctx->acc, ctx->acc_len, ctx->status, ctx->opt, ctx->prof};
     ctx->status = reinterpret_cast<int*>(base);
     ctx->acc = reinterpret_cast<double*>(base + 256);
     ctx->acc_len = P.nnz;
-    ctx->sched = base + 256 + acc_bytes;
-    ctx->sched_bytes = sched_bytes;
-    ctx->ws = base + 256 + acc_bytes + sched_bytes;
+    ctx->ws = base + 256 + acc_bytes;
     ctx->ws_bytes = per_pole * size_t(nb);
     ctx->opt.use_graph = 0;
     ctx->opt.split_streams = 0;

@@ -86,10 +86,11 @@ hipError_t launch_combine(const double* V, const double* Y, int64_t n, double* o
 hipError_t launch_resid(const double* hc, const double* sc, const double* theta, int64_t n, int64_t chunk, int nblk,
                         double* part, hipStream_t st);
 
-// ---- persistent schedule of the small fronts (persist.hip)
+// ---- fused kernels of the small fronts (smallfront.hip): one launch per depth
+// and direction, one workgroup per (front, pole)
 struct SmallLaunch {
   bool up = true;
-  const SmallFront* fronts = nullptr;
+  const SmallFront* fronts = nullptr;  // the fronts of one depth
   const SmallChild* kids = nullptr;
   const int32_t* inv = nullptr;
   const int32_t* rel = nullptr;
@@ -105,13 +106,7 @@ struct SmallLaunch {
   int64_t astride = 0;
   double hcoef = 1.0;
   int spd_check = 0;
-  int* status = nullptr;           // [0] singular pivots, [1] non-positive pivots of S, [2] schedule wait bound hit
-  int* flags = nullptr;            // task completion, [front * fstride + pole]
-  int64_t fstride = 0;
-  unsigned long long* head = nullptr;  // the launch's task counter
-  int* abort_flag = nullptr;
-  int64_t max_groups = 512;  // workgroups of a launch (two per compute unit are resident)
-  long long wait_ticks = 0;  // bound of one dependency wait, in ticks of the device's constant-rate clock
+  int* status = nullptr;           // [0] singular pivots, [1] non-positive pivots of S
 };
 hipError_t launch_small(const SmallLaunch& s, hipStream_t st);
 

@@ -545,7 +545,7 @@ struct Builder {
 
 void build_plan(Plan& P, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* coords,
                 int leaf_rows, double long_tail, const double* cell, bool small_fronts) {
-  // (small_fronts: the persistent schedule takes the small fronts)
+  // (small_fronts: the small fronts run in the fused small-front launches)
   if (leaf_rows < 1) fail(NDRHO_EINVAL, "leaf_rows must be >= 1");
   if (!(long_tail == 0.0 || long_tail >= 1.0)) fail(NDRHO_EINVAL, "long_tail must be 0 or >= 1");
   P = Plan();
@@ -703,8 +703,9 @@ void finalize_plan(Plan& P) {
     lo += int64_t(F.nu) * F.nj;
   }
   P.l_total = std::max<int64_t>(lo, 1);
-  // small fronts (the persistent schedule's): at most 64 pivot rows, at most
-  // kSmallFrontRows pivot plus update rows, every descendant small too
+  // small fronts (those of the fused small-front launches): at most 64 pivot
+  // rows, at most kSmallFrontRows pivot plus update rows, every descendant
+  // small too
   // (postorder: children come first)
   std::vector<char> small(nf, 0);
   if (P.small_enabled)
@@ -716,8 +717,7 @@ void finalize_plan(Plan& P) {
     }
   // update / G_UU blocks: the large fronts of a depth side by side in their
   // depth's buffer (reused by the depths of the same parity), every small
-  // front a block of its own after them (the persistent schedule runs fronts
-  // of several depths at once)
+  // front a block of its own after them
   for (int d = 0; d < P.n_levels; ++d) {
     int64_t uo = 0, to = 0;
     for (int f : by_depth[d]) {
@@ -822,24 +822,15 @@ void finalize_plan(Plan& P) {
     P.rel_all.insert(P.rel_all.end(), P.fronts[f].rel.begin(), P.fronts[f].rel.end());
   }
 
-  // ---- persistent schedule of the small fronts: the upward list children
-  // first (deepest depth first), the downward list parents first
+  // ---- fused small-front launches: the small fronts by depth, deepest
+  // first upward and top first downward; one launch per depth and direction
   P.small_up.clear();
   P.small_down.clear();
-  P.small_flops_up = P.small_flops_down = 0;
   P.small_kids.clear();
   P.small_inv.clear();
+  std::vector<int64_t> small_up_begin(P.n_levels + 1, 0), small_down_begin(P.n_levels + 1, 0);
+  std::vector<double> small_fl_up(P.n_levels, 0.0), small_fl_down(P.n_levels, 0.0);
   {
-    std::vector<int> up, down;
-    for (int d = P.n_levels - 1; d >= 0; --d)
-      for (int f : by_depth[d])
-        if (small[f]) up.push_back(f);
-    for (int d = 0; d < P.n_levels; ++d)
-      for (int f : by_depth[d])
-        if (small[f]) down.push_back(f);
-    std::vector<int32_t> up_pos(nf, -1), down_pos(nf, -1);
-    for (size_t i = 0; i < up.size(); ++i) up_pos[up[i]] = static_cast<int32_t>(i);
-    for (size_t i = 0; i < down.size(); ++i) down_pos[down[i]] = static_cast<int32_t>(i);
     auto base = [&](int f) {
       const Front& F = P.fronts[f];
       SmallFront s{};
@@ -852,55 +843,77 @@ void finalize_plan(Plan& P) {
       s.nj = F.nj;
       s.nu = F.nu;
       s.depth = F.depth;
-      s.parent_task = -1;
+      s.parent_small = 0;
       if (F.parent >= 0) {
         const Front& Pa = P.fronts[F.parent];
         s.ppanel_off = Pa.panel_off;
         s.pguu_off = Pa.upd_off;
         s.pnj = Pa.nj;
         s.pnu = Pa.nu;
+        s.parent_small = small[F.parent] ? 1 : 0;
       }
       return s;
     };
-    for (int f : up) {
-      const Front& F = P.fronts[f];
-      SmallFront s = base(f);
-      s.child_begin = static_cast<int32_t>(P.small_kids.size());
-      s.child_count = static_cast<int32_t>(F.children.size());
-      for (int c : F.children) {
-        const Front& C = P.fronts[c];
-        std::vector<int32_t> inv(F.nj + F.nu, -1);
-        for (int k = 0; k < C.nu; ++k) inv[C.rel[k]] = k;
-        P.small_kids.push_back(SmallChild{C.upd_off, static_cast<int64_t>(P.small_inv.size()), C.nu, up_pos[c]});
-        P.small_inv.insert(P.small_inv.end(), inv.begin(), inv.end());
+    // upward lists: small_up_begin[d] .. small_up_begin[d + 1] for depth d,
+    // stored deepest first (the range of depth d starts after those deeper)
+    for (int d = P.n_levels - 1; d >= 0; --d) {
+      small_up_begin[d] = static_cast<int64_t>(P.small_up.size());
+      for (int f : by_depth[d]) {
+        if (!small[f]) continue;
+        const Front& F = P.fronts[f];
+        SmallFront s = base(f);
+        s.child_begin = static_cast<int32_t>(P.small_kids.size());
+        s.child_count = static_cast<int32_t>(F.children.size());
+        for (int c : F.children) {
+          const Front& C = P.fronts[c];
+          std::vector<int32_t> inv(F.nj + F.nu, -1);
+          for (int k = 0; k < C.nu; ++k) inv[C.rel[k]] = k;
+          P.small_kids.push_back(SmallChild{C.upd_off, static_cast<int64_t>(P.small_inv.size()), C.nu, 0});
+          P.small_inv.insert(P.small_inv.end(), inv.begin(), inv.end());
+        }
+        P.small_up.push_back(s);
+        const double fu = 8.0 * (double(F.nj) * F.nj * F.nj + double(F.nu) * F.nj * F.nj + double(F.nu) * F.nu * F.nj / 2);
+        const double fd = 8.0 * (double(F.nu) * F.nu * F.nj + double(F.nu) * F.nj * F.nj / 2);
+        small_fl_up[d] += fu;
+        small_fl_down[d] += fd;
+        P.flops_exec += fu + fd;
       }
-      P.small_up.push_back(s);
-      const double fu = 8.0 * (double(F.nj) * F.nj * F.nj + double(F.nu) * F.nj * F.nj + double(F.nu) * F.nu * F.nj / 2);
-      const double fd = 8.0 * (double(F.nu) * F.nu * F.nj + double(F.nu) * F.nj * F.nj / 2);
-      P.small_flops_up += fu;
-      P.small_flops_down += fd;
-      P.flops_exec += fu + fd;
     }
-    for (int f : down) {
-      const Front& F = P.fronts[f];
-      SmallFront s = base(f);
-      if (F.parent >= 0 && small[F.parent]) s.parent_task = down_pos[F.parent];
-      P.small_down.push_back(s);
+    small_up_begin[P.n_levels] = static_cast<int64_t>(P.small_up.size());
+    for (int d = 0; d < P.n_levels; ++d) {
+      small_down_begin[d] = static_cast<int64_t>(P.small_down.size());
+      for (int f : by_depth[d])
+        if (small[f]) P.small_down.push_back(base(f));
     }
+    small_down_begin[P.n_levels] = static_cast<int64_t>(P.small_down.size());
   }
+  // the upward launch of the small fronts of depth d, then their downward one
+  auto small_op = [&](int d, bool up) {
+    Op op;
+    op.kind = OP_SMALL;
+    op.flags = up ? 0 : 1;
+    if (up) {
+      op.begin = small_up_begin[d];
+      // the range of depth d ends where the next shallower depth's starts
+      op.count = (d > 0 ? small_up_begin[d - 1] : small_up_begin[P.n_levels]) - op.begin;
+      op.flops = small_fl_up[d];
+    } else {
+      op.begin = small_down_begin[d];
+      op.count = small_down_begin[d + 1] - op.begin;
+      op.flops = small_fl_down[d];
+    }
+    op.depth = d;
+    return op;
+  };
 
   // ---- program
   Builder B(P);
   const int64_t kTile = 1024;
-  if (!P.small_up.empty()) {
-    Op op;
-    op.kind = OP_SMALL;
-    op.flags = 0;
-    op.count = static_cast<int64_t>(P.small_up.size());
-    op.depth = P.n_levels - 1;
-    P.upward.push_back(op);
-  }
   for (int d = P.n_levels - 1; d >= 0; --d) {
+    {
+      const Op op = small_op(d, true);
+      if (op.count) P.upward.push_back(op);
+    }
     std::vector<int> fr;
     for (int f : by_depth[d])
       if (!small[f]) fr.push_back(f);
@@ -999,7 +1012,7 @@ void finalize_plan(Plan& P) {
     const int pbuf = (d % 2 == 0) ? BUF_UPD1 : BUF_UPD0;
     // G_UU of the small fronts whose parent is large, gathered here (right
     // after the parent's level) into their own blocks, kept FP64 for the
-    // persistent schedule that continues from them
+    // small-front launch of this depth that continues from them
     for (int pass = 0; pass < 2; ++pass) {
       const std::vector<int>& list = pass == 0 ? fr : top;
       Op op;
@@ -1040,14 +1053,10 @@ void finalize_plan(Plan& P) {
     }
     B.gemm(P.downward, G_NEG | G_SYMA, ubuf, BUF_L, 0, BUF_PANEL, g3, d);
     B.gemm(P.downward, G_TA | G_SYM | G_BETA | G_NEG, BUF_L, BUF_PANEL, BUF_PANEL, BUF_PANEL, g4, d);
-  }
-  if (!P.small_down.empty()) {
-    Op op;
-    op.kind = OP_SMALL;
-    op.flags = 1;
-    op.count = static_cast<int64_t>(P.small_down.size());
-    op.depth = P.n_levels - 1;
-    P.downward.push_back(op);
+    {
+      const Op op = small_op(d, false);
+      if (op.count) P.downward.push_back(op);
+    }
   }
 }
 

@@ -75,8 +75,8 @@ struct GatherDesc {
   int32_t nu, pnj, pnu, pad;
 };
 
-// One front of the persistent schedule of the small fronts (lists ordered
-// children first for the upward launch, parents first for the downward one).
+// One small front of a fused small-front launch (lists ordered by depth,
+// deepest first for the upward launches, top first for the downward ones).
 struct SmallFront {
   int64_t panel_off, l_off, upd_off;  // upd_off: its own update / G_UU block in its depth's buffer
   int64_t asm_begin, asm_end;         // its assembly entries (sorted tables)
@@ -84,14 +84,13 @@ struct SmallFront {
   int64_t ppanel_off, pguu_off;       // the parent's panel and G_UU block
   int32_t nj, nu, depth;
   int32_t child_begin, child_count;   // its children (all small) in the child table
-  int32_t parent_task;                // downward list: the parent's position, -1 for a large parent
+  int32_t parent_small;               // 1: the parent is small (the downward step gathers G_UU itself)
   int32_t pnj, pnu;
 };
 struct SmallChild {
   int64_t upd_off;  // the child's update block (in the child's depth buffer)
   int64_t inv_off;  // its inverse map over the parent's local rows (child update row or -1)
-  int32_t nu;
-  int32_t task;     // the child's position in the upward list
+  int32_t nu, pad;
 };
 
 enum BufId { BUF_PANEL = 0, BUF_UPD0 = 1, BUF_UPD1 = 2, BUF_TEMP = 3, BUF_L = 4, BUF_COUNT = 5 };
@@ -123,9 +122,9 @@ struct Op {
   bool off32 = true;         // GEMM: every operand element of every problem lies within 2^31 - 16
                              // bytes of the problem's operand origin (32-bit offsets suffice)
   int64_t inv16 = 0, inv32 = 0;  // SMALLINV: leading descriptors with n <= 16, then n <= 32
-  bool keep64 = false;       // GATHER: the G_UU it writes stays FP64 (its consumer is the small-front schedule)
+  bool keep64 = false;       // GATHER: the G_UU it writes stays FP64 (its consumer is a small-front launch)
   int depth = 0;
-  double flops = 0;          // useful flops per pole (GEMM)
+  double flops = 0;          // useful flops per pole (GEMM, SMALL)
   double bytes = 0;          // algorithmic bytes per pole: operands read and results written once, complex128
 };
 
@@ -166,9 +165,10 @@ struct Plan {
   double flops_model = 0, bytes_model = 0;    // per pole
   double flops_exec = 0;                      // flops of the program per pole
 
-  // persistent schedule of the small fronts (OP_SMALL; flags 0 upward, 1 downward)
+  // fused small-front launches (OP_SMALL, one per depth and direction: flags 0
+  // upward, 1 downward; begin/count index small_up or small_down, which hold
+  // the small fronts by depth, deepest first upward, top first downward)
   bool small_enabled = true;
-  double small_flops_up = 0, small_flops_down = 0;  // useful flops per pole of the two launches
   std::vector<SmallFront> small_up, small_down;
   std::vector<SmallChild> small_kids;
   std::vector<int32_t> small_inv;

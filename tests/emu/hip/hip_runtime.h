@@ -1,15 +1,12 @@
 // Host stand-in for the HIP runtime header, used only by the host emulation
-// test of the persistent small-front kernels: a kernel launch runs its
-// workgroups one after another, each as one std::thread per device thread,
-// with __syncthreads() as a std::barrier, __shared__ variables as statics
-// (one workgroup runs at a time) and the device atomics as host atomics.
+// test of the fused small-front kernels: a kernel launch runs its workgroups
+// one after another, each as one std::thread per device thread, with
+// __syncthreads() as a std::barrier, __shared__ variables as statics (one
+// workgroup runs at a time) and the device atomics as host atomics.
 #pragma once
-#include <sched.h>
-
 #include <algorithm>
 #include <atomic>
 #include <barrier>
-#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <thread>
@@ -27,6 +24,7 @@ inline float2 make_float2(float a, float b) { return float2{a, b}; }
 typedef int hipError_t;
 typedef void* hipStream_t;
 constexpr int hipSuccess = 0;
+constexpr int hipErrorInvalidValue = 1;
 inline hipError_t hipGetLastError() { return hipSuccess; }
 
 struct dim3 {
@@ -56,31 +54,8 @@ inline void __syncthreads() { emu_barrier()->arrive_and_wait(); }
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
-#define __HIP_MEMORY_SCOPE_AGENT 0
 
-// constant-rate clock in ticks of 10 ns (the device's is 100 MHz)
-inline long long wall_clock64() {
-  return std::chrono::duration_cast<std::chrono::nanoseconds>(
-             std::chrono::steady_clock::now().time_since_epoch())
-             .count() /
-         10;
-}
-#define __builtin_amdgcn_s_sleep(n) sched_yield()
-#define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
-inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
-template <class T>
-T __hip_atomic_load(const T* p, int, int) {
-  return __atomic_load_n(p, __ATOMIC_SEQ_CST);
-}
-template <class T>
-void __hip_atomic_store(T* p, T v, int, int) {
-  __atomic_store_n(p, v, __ATOMIC_SEQ_CST);
-}
-inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v) {
-  return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
-}
 inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
-inline int atomicOr(int* p, int v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
 using std::fabs;
 using std::fma;
 using std::fmax;

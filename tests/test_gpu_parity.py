@@ -668,8 +668,8 @@ def test_errors(ctx):
     with pytest.raises(nd.NdrhoError) as e:
         ctx.set_poles(sid, 0.0, BETA, 0)
     assert e.value.name == "EINVAL"
-    with pytest.raises(nd.NdrhoError) as e:     # the persistent small-front schedule is disabled
-        nd.Context(0, small_fronts=1)
+    with pytest.raises(nd.NdrhoError) as e:     # small_fronts is 0 or 1
+        nd.Context(0, small_fronts=2)
     assert e.value.name == "EINVAL"
     bad = dict(sysd)
     bad["s"] = sysd["s"].copy()
@@ -881,20 +881,15 @@ def test_eight_lattice_batch_against_oracle_sample(precision, tol, tmp_path):
         assert err < tol
 
 
-# ------------------------------------------------------------- persistent small-front schedule
+# ------------------------------------------------------------- fused small-front launches
 
-@pytest.mark.skip(reason="the persistent small-front schedule is disabled: its launches stalled on gfx950 "
-                         "(inside the first FP64 evaluation of the 256-site chain, also with one workgroup, "
-                         "where no dependency wait can block); a CPU emulation of both kernels reproduces "
-                         "G on that chain, the device-side cause is not found; the context rejects "
-                         "small_fronts != 0")
 @pytest.mark.parametrize("precision", ["fp64", "mixed_bf16x3"])
 def test_small_front_schedule_matches_level_schedule(precision):
-    # the persistent launches over the small fronts (one upward, one downward
-    # per pass, tasks taken in tree order with dependency flags) against the
-    # level-by-level launches of the same fronts: the 1D chain (every front
-    # small), a 2D and a 3D lattice (small subtrees under large separators),
-    # a periodic lattice, several passes over pole batches, a structure batch
+    # the fused launches of the small fronts (one per depth and direction,
+    # one workgroup per front and pole) against the level launches of the
+    # same fronts: the 1D chain (every front small), a 2D and a 3D lattice
+    # (small subtrees under large separators), a periodic lattice, several
+    # passes over pole batches, a structure batch
     import paper_1005_0088_amd as nd
     systems = [lattice((256,), "nn", 0), lattice((24, 22), "nn2", 81), lattice((10, 9, 8), "nn", 82),
                lattice((12, 12), "nn", 83, periodic=True)]
@@ -923,7 +918,7 @@ def test_small_front_schedule_matches_level_schedule(precision):
         for a, b in zip(singles, again):
             assert np.array_equal(a, b)                  # repeatable bit for bit
         launches = prof["small_fronts"]["launches"]
-        print("small_fronts=%d %s: %d persistent launches, %.3f ms" % (small, precision, launches,
+        print("small_fronts=%d %s: %d fused small-front launches, %.3f ms" % (small, precision, launches,
                                                                       prof["small_fronts"]["ms"]), flush=True)
         assert (launches > 0) == (small == 1)
     tol = 1e-12 if precision == "fp64" else 2e-7

@@ -330,11 +330,11 @@ def test_long_tail_option_validated():
         nd.Plan(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["coords"], 16, long_tail=0.5)
 
 
-def test_disabled_small_front_schedule_is_rejected():
+def test_small_front_option_validated():
     # the option is checked before any device call, so this runs on the host
     with pytest.raises(nd.NdrhoError) as e:
-        nd.Context(0, small_fronts=1)
-    assert e.value.name == "EINVAL" and "disabled" in str(e.value)
+        nd.Context(0, small_fronts=2)
+    assert e.value.name == "EINVAL" and "small_fronts" in str(e.value)
 
 
 def test_long_tail_generator_keeps_s_positive_definite_and_symmetric():

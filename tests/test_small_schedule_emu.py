@@ -1,10 +1,9 @@
-"""Host emulation of the persistent small-front schedule (disabled on the
-device): the two kernels of csrc/persist.hip, compiled for the host through a
-stand-in HIP header (tests/emu), run the upward and downward passes of lattices
-whose fronts are all small, and the selected G they leave on the pattern must
-equal the oracle's dense inverse of X = alpha S - H (Sec. II C 2, Eqs.
-(18)-(21), (38)-(39)).  One workgroup takes the tasks in list order, so every
-dependency wait is already satisfied when it is made."""
+"""Host emulation of the fused small-front launches: the two kernels of
+csrc/smallfront.hip, compiled for the host through a stand-in HIP header
+(tests/emu), run the upward and downward launches (one per depth and
+direction) of lattices whose fronts are all small, and the selected G they
+leave on the pattern must equal the oracle's dense inverse of X = alpha S - H
+(Sec. II C 2, Eqs. (18)-(21), (38)-(39))."""
 import os
 import shutil
 import subprocess
@@ -27,7 +26,7 @@ def emulator(tmp_path_factory):
     exe = str(tmp_path_factory.mktemp("emu") / "small_schedule_emu")
     cmd = [gxx, "-std=c++20", "-O1", "-pthread", "-I", os.path.join(ROOT, "tests", "emu"), "-I", CSRC,
            "-I", os.path.join(ROOT, "include"), "-x", "c++", os.path.join(ROOT, "tests", "emu", "small_schedule_emu.cpp"),
-           os.path.join(CSRC, "persist.hip"), "-x", "none", os.path.join(CSRC, "plan.cpp"),
+           os.path.join(CSRC, "smallfront.hip"), "-x", "none", os.path.join(CSRC, "plan.cpp"),
            os.path.join(CSRC, "poles.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-4000:]
@@ -47,7 +46,6 @@ def _run(exe, sysd, alpha, hcoef, tmp_path):
         sysd["h"].astype(np.float64).tofile(f)
         sysd["s"].astype(np.float64).tofile(f)
         np.array([alpha.real, alpha.imag, hcoef], np.float64).tofile(f)
-        np.array([1], np.int64).tofile(f)
     r = subprocess.run([exe, inp, out], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, "emulator exit %d %s" % (r.returncode, r.stderr[-2000:])
     raw = np.fromfile(out, np.uint8)
@@ -73,6 +71,6 @@ def test_small_front_kernels_give_selected_inverse(emulator, dims, nb, seed, per
     h[rows, sysd["col"]] = sysd["h"]
     s[rows, sysd["col"]] = sysd["s"]
     got, status = _run(emulator, sysd, alpha, hcoef, tmp_path)
-    assert list(status) == [0, 0, 0]            # no bad pivot, no wait beyond its bound
+    assert list(status) == [0, 0]               # no bad pivot
     ref = dense.green_dense(hcoef * h, s, alpha)[rows, sysd["col"]]
     assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.abs(ref).max())
