@@ -147,13 +147,14 @@ def golden_error(name, rho, mu, n_poles):
 
 
 def run_form(nd, systems, mu, beta, n_poles, steps, warmup, precision, fp64_poles, autotune=True, gemm_variant=-1,
-             tune_cache=None, split_streams=1, energy=False, small_fronts=0):
+             tune_cache=None, split_streams=1, energy=False, small_fronts=0, pivot_variant=0):
     """Time one precision form on one system (density_matrix, or with
     energy=True energy_density_matrix: rho and e) or several
     (density_matrix_batch: one schedule); returns (timing dict, rho list)."""
     variant = gemm_variant if precision != "fp64" else -1
     ctx = nd.Context(0, precision=precision, fp64_poles=fp64_poles, fp64_far_poles=fp64_poles, gemm_variant=variant,
-                     split_streams=split_streams, verbose=1, small_fronts=small_fronts)
+                     split_streams=split_streams, verbose=1, small_fronts=small_fronts,
+                     pivot_variant=pivot_variant if precision != "fp64" else -1)
     t0 = time.time()
     sids = []
     for sysd in systems:
@@ -305,6 +306,9 @@ def main():
                          "the kernels' durations in the timed steps are those of the instrumented step and of "
                          "the profiler's trace; 1 runs the FP64 poles beside, about 1 %% faster on 24^3 x 4)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--pivot-variant", type=int, default=0,
+                    help="mixed forms: GEMM variant of the low poles' pivot-inverse products (0: FP64, the "
+                         "default; -1: per-launch choice; see ndrho_options.pivot_variant)")
     ap.add_argument("--small-fronts", type=int, default=0, choices=[0, 1],
                     help="1: the small fronts of the deep levels run in fused launches (one per depth and "
                          "direction, one workgroup per front and pole)")
@@ -372,7 +376,7 @@ def main():
             if form != args.precision:
                 r, rr = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, form, args.fp64_poles,
                                  not args.no_autotune, -1, args.tune_cache, args.split_streams, args.energy,
-                                 args.small_fronts)
+                                 args.small_fronts, args.pivot_variant)
                 others[form] = {
                     "poles_per_s": r["poles_per_s"], "ms_per_step": r["ms_per_step"],
                     "kernel_ms": {k: round(v["ms"], 3) for k, v in r["prof"].items()},
@@ -385,7 +389,7 @@ def main():
     else:
         head, rho = run_form(nd, systems, mu, BETA, n_poles, args.steps, args.warmup, args.precision,
                              args.fp64_poles, not args.no_autotune, args.gemm_variant, args.tune_cache,
-                             args.split_streams, args.energy, args.small_fronts)
+                             args.split_streams, args.energy, args.small_fronts, args.pivot_variant)
     st, prof = head["stats"][0], head["prof"]
     # dominant kernel: the FP64 front GEMMs in the FP64 form, the FP32-product
     # front GEMMs in the mixed form (peak of their own arithmetic)
@@ -428,7 +432,7 @@ def main():
                    "fp64_poles": st["n_fp64_poles"], "fronts": sum(x["n_fronts"] for x in head["stats"]),
                    "levels": max(x["n_levels"] for x in head["stats"]), "root_j": st["root_j"],
                    "pole_batch": st["pole_batch"], "seeds": [int(x["seed"]) for x in systems],
-                   "small_fronts": args.small_fronts,
+                   "small_fronts": args.small_fronts, "pivot_variant": args.pivot_variant,
                    "neighbours": systems[0]["neighbours"]},
         "pole_structures_per_s": head["poles_per_s"] * len(systems),
         "tflops_model": head["flops_model_per_step"] / (head["ms_per_step"] * 1e-3) / 1e12,

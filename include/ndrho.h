@@ -113,6 +113,13 @@ typedef struct {
                             with one workgroup per (front, pole) doing the front's whole step in FP64
                             (extend-add, assembly, pivot inverse, L and the Schur update upward; the
                             G_UU gather, G_UJ and G_JJ downward).  Other values: NDRHO_EINVAL */
+  int32_t pivot_variant; /* mixed mode, GEMMs of the recursive pivot-block inverse (blocks of more than 64
+                            rows) for the low poles: 0 (default) FP64, as for the FP64 poles, so that the
+                            pivot-block factorizations are FP64 throughout; -1 per-launch choice
+                            (split-BF16 or FP32 products on 64x64 tiles where a launch's largest problem has
+                            256 rows or more, else FP64; refined by ndrho_autotune); 1-6 one of the
+                            gemm_variant values the precision mode accepts.  The inverses of the 64-row
+                            blocks at the bottom of the recursion and the FP64 poles stay FP64 */
 } ndrho_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -302,7 +309,8 @@ int ndrho_energy_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids,
 int ndrho_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, double* const* rho_outs,
                                int32_t on_device);
 
-/* Autotuner of the front-update GEMM launches of one structure (k = 1) or of
+/* Autotuner of the front-update GEMM launches (and, with pivot_variant = -1,
+ * of the pivot-block inverse's GEMM launches) of one structure (k = 1) or of
  * a batch of k structures (as run by ndrho_density_matrix_batch): for every
  * launch it times, on one full evaluation of the current shifts per variant,
  * each gemm_variant the precision mode accepts (FP64 for all poles; FP32
@@ -312,7 +320,7 @@ int ndrho_density_matrix_batch(ndrho_ctx* ctx, const int32_t* struct_ids, int32_
  * double-buffered bf16 planes; the low-precision variants apply only to the
  * poles the mode puts in low precision) and keeps the fastest.  With
  * cache_path non-NULL the choice is looked up in, or appended to, that text
- * file under a key of the plan's shape, pole count, batch size and precision
+ * file under a key of the plan's shape, pole count, batch size, precision and pivot_variant
  * (a line whose choice names a variant the mode does not accept is ignored).
  * FP64 mode: nothing to tune.  With opt.verbose each timed variant and the
  * choice (one digit per launch of the program) are reported on stderr.  Errors: EINVAL, ESTATE (no shifts set), EDEVICE. */

@@ -26,7 +26,8 @@ class Options(C.Structure):
                 ("mem_fraction", C.c_double), ("verbose", C.c_int32), ("fp64_poles", C.c_int32),
                 ("fp64_pole_im", C.c_double), ("fp64_far_poles", C.c_int32), ("use_graph", C.c_int32),
                 ("gemm_variant", C.c_int32), ("fp64_small_tiles", C.c_int32),
-                ("split_streams", C.c_int32), ("long_tail", C.c_double), ("small_fronts", C.c_int32)]
+                ("split_streams", C.c_int32), ("long_tail", C.c_double), ("small_fronts", C.c_int32),
+                ("pivot_variant", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -236,7 +237,8 @@ class Context:
 
     def __init__(self, device=0, stream=None, leaf_rows=32, pole_batch=0, mem_fraction=0.8, precision="fp64",
                  fp64_poles=None, fp64_pole_im=None, use_graph=True, gemm_variant=-1, fp64_far_poles=None,
-                 fp64_small_tiles=-1, split_streams=0, long_tail=0.0, verbose=0, small_fronts=0):
+                 fp64_small_tiles=-1, split_streams=0, long_tail=0.0, verbose=0, small_fronts=0,
+                 pivot_variant=0):
         self._lib = load_library()
         opt = Options()
         self._lib.ndrho_default_options(C.byref(opt))
@@ -256,6 +258,7 @@ class Context:
         opt.split_streams = int(split_streams)
         opt.long_tail = float(long_tail)
         opt.small_fronts = int(small_fronts)
+        opt.pivot_variant = int(pivot_variant)
         opt.verbose = int(verbose)
         handle = None
         if stream is not None:

@@ -176,19 +176,22 @@ static bool variant_allowed(int precision, int v) {
 }
 
 // Default GEMM variant per op before any tuning: low-precision products on
-// 128x128 tiles where the op's largest problem fills several such tiles,
-// plain FP64 for the small fronts of the deep levels (where they do not pay).
+// 128x128 tiles (front updates) or 64x64 tiles (the pivot-block inverse's
+// products) where the op's largest problem fills several such tiles, plain
+// FP64 for the small fronts of the deep levels (where they do not pay).
 std::vector<int8_t> default_variants(const Plan& P, int precision) {
   const int8_t low = precision == NDRHO_MIXED_BF16X3 ? int8_t(V_BF3_128) : int8_t(V_F32_128);
+  const int8_t low_piv = precision == NDRHO_MIXED_BF16X3 ? int8_t(V_BF3_64) : int8_t(V_F32_64);
   std::vector<int8_t> v;
   auto pick = [&](const Op& op) {
-    if (op.kind != OP_GEMM || (op.flags & OP_PIVOT)) return int8_t(V_FP64);
+    if (op.kind != OP_GEMM) return int8_t(V_FP64);
     int mx = 0;
     for (int64_t i = 0; i < op.count; ++i) {
       const GemmProb& g = P.gemm[op.begin + i];
       mx = std::max(mx, std::min(g.m, g.n));
     }
-    return mx >= 256 ? low : int8_t(V_FP64);
+    if (mx < 256) return int8_t(V_FP64);
+    return (op.flags & OP_PIVOT) ? low_piv : low;
   };
   for (const Op& op : P.upward) v.push_back(pick(op));
   for (const Op& op : P.downward) v.push_back(pick(op));
@@ -494,9 +497,12 @@ struct ndrho_ctx {
           // autotuner, or forced by gemm_variant): V_FP64 keeps every pole in
           // FP64; the others give the low poles FP32 products (V_F32_64,
           // V_F32_128) or split-BF16 products (V_BF3_128, V_BF3_64, V_BF3S_128, V_BF3P_128)
-          int var = opt.gemm_variant >= 0 ? opt.gemm_variant : S.variant[cur_op];
+          // (pivot-inverse GEMMs: pivot_variant if set, else the per-launch choice)
+          const bool pivot = (op.flags & OP_PIVOT) != 0;
+          const int forced = pivot ? opt.pivot_variant : opt.gemm_variant;
+          int var = forced >= 0 ? forced : S.variant[cur_op];
           if (var == V_BF3P_128 && !op.off32) var = V_BF3_128;  // 32-bit operand offsets only
-          const bool split = !(op.flags & OP_PIVOT) && nhi < nb && var != V_FP64;
+          const bool split = nhi < nb && var != V_FP64;
           const int k64 = (op.flags & OP_PIVOT) ? NDRHO_K_GEMM_PIVOT : NDRHO_K_GEMM;
           // FP64 launches of small problems: one wave per 32x32 tile
           const bool small = opt.fp64_small_tiles < 0 ? op.small : opt.fp64_small_tiles != 0;
@@ -531,7 +537,7 @@ struct ndrho_ctx {
           l.a32 = op.flags == (G_NEG | G_SYMA) && guu32[op.depth];
           l.a += nhi * l.sa, l.b += nhi * l.sb, l.c += nhi * l.sc;
           if (op.flags & (G_BETA | G_EXTC0)) l.c0 += nhi * l.sc0;
-          timed(l.bf3 ? NDRHO_K_GEMM_BF16X3 : NDRHO_K_GEMM_F32, op.flops * (nb - nhi),
+          timed(pivot ? NDRHO_K_GEMM_PIVOT : l.bf3 ? NDRHO_K_GEMM_BF16X3 : NDRHO_K_GEMM_F32, op.flops * (nb - nhi),
                 [&] { e = launch_gemm(l, st); }, op.bytes * (nb - nhi));
           break;
         }
@@ -1255,6 +1261,7 @@ int ndrho_default_options(ndrho_options* opt) {
   opt->split_streams = 0;
   opt->long_tail = 0.0;
   opt->small_fronts = 0;
+  opt->pivot_variant = 0;
   return NDRHO_OK;
 }
 
@@ -1280,6 +1287,9 @@ int ndrho_create(ndrho_ctx** out, int device, void* hip_stream, const ndrho_opti
     if (c->opt.small_fronts != 0 && c->opt.small_fronts != 1) fail(NDRHO_EINVAL, "small_fronts must be 0 or 1");
     if (c->opt.split_streams < 0 || c->opt.split_streams > ndrho_ctx::kMaxChains)
       fail(NDRHO_EINVAL, "invalid split_streams");
+    if (c->opt.pivot_variant < -1 || c->opt.pivot_variant >= V_COUNT ||
+        (c->opt.pivot_variant >= 0 && !variant_allowed(c->opt.precision, c->opt.pivot_variant)))
+      fail(NDRHO_EINVAL, "invalid pivot_variant for this precision");
     if (c->opt.gemm_variant < -1 || c->opt.gemm_variant >= V_COUNT ||
         (c->opt.gemm_variant >= 0 && !variant_allowed(c->opt.precision, c->opt.gemm_variant)))
       fail(NDRHO_EINVAL, "invalid gemm_variant for this precision");
@@ -2022,11 +2032,19 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
     const int nb = ctx->batch_for(P, T.n_shifts);
     char keybuf[256];
     std::snprintf(keybuf, sizeof(keybuf),
-                  "ndrho-tune-v4 n=%lld nnz=%lld fronts=%zu shifts=%d fp64=%d batch=%d prec=%d ops=%d",
+                  "ndrho-tune-v5 n=%lld nnz=%lld fronts=%zu shifts=%d fp64=%d batch=%d prec=%d piv=%d ops=%d",
                   static_cast<long long>(P.n), static_cast<long long>(P.nnz), P.fronts.size(), T.n_shifts, T.n_hi,
-                  nb, ctx->opt.precision, nops);
+                  nb, ctx->opt.precision, ctx->opt.pivot_variant, nops);
     const std::string key(keybuf);
-    if (T.n_hi >= T.n_shifts || ctx->opt.gemm_variant >= 0) return;  // nothing to choose
+    // the launches whose variant is chosen here: front updates unless
+    // gemm_variant forces one, pivot-inverse products unless pivot_variant does
+    auto tunable = [&](const Op& op) {
+      return op.kind == OP_GEMM && ((op.flags & OP_PIVOT) ? ctx->opt.pivot_variant < 0 : ctx->opt.gemm_variant < 0);
+    };
+    bool any = false;
+    for (const Op& op : P.upward) any = any || tunable(op);
+    for (const Op& op : P.downward) any = any || tunable(op);
+    if (T.n_hi >= T.n_shifts || !any) return;  // nothing to choose
     if (cache_path) {
       std::ifstream in(cache_path);
       std::string line;
@@ -2048,7 +2066,7 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
         return;
       }
     }
-    // time every variant of every front-update GEMM on one full evaluation each
+    // time every variant of every tunable GEMM launch on one full evaluation each
     std::vector<std::vector<double>> ms(V_COUNT, std::vector<double>(nops, 0.0));
     const bool was_prof = ctx->prof;
     const std::vector<int8_t> saved = T.variant;
@@ -2058,7 +2076,7 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
         if (!variant_allowed(ctx->opt.precision, v)) continue;
         for (int i = 0; i < nops; ++i) {
           const Op& op = i < static_cast<int>(P.upward.size()) ? P.upward[i] : P.downward[i - P.upward.size()];
-          T.variant[i] = (op.kind == OP_GEMM && !(op.flags & OP_PIVOT)) ? static_cast<int8_t>(v) : int8_t(V_FP64);
+          T.variant[i] = tunable(op) ? static_cast<int8_t>(v) : int8_t(V_FP64);
         }
         ctx->prof = true;
         ctx->op_ms = &ms[v];
@@ -2083,8 +2101,8 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
     std::string choice;
     for (int i = 0; i < nops; ++i) {
       const Op& op = i < static_cast<int>(P.upward.size()) ? P.upward[i] : P.downward[i - P.upward.size()];
-      int best = V_FP64;  // only front-update GEMMs have variants
-      if (op.kind == OP_GEMM && !(op.flags & OP_PIVOT))
+      int best = V_FP64;  // only the tunable GEMM launches have variants
+      if (tunable(op))
         for (int v = 1; v < V_COUNT; ++v)
           if (variant_allowed(ctx->opt.precision, v) && ms[v][i] < ms[best][i]) best = v;
       T.variant[i] = static_cast<int8_t>(best);

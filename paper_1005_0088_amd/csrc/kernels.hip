@@ -1615,8 +1615,10 @@ hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
   if (o.tile_count == 0) return hipSuccess;
   if (o.a32 && (o.flags != (G_NEG | G_SYMA) || !(o.bf3 || o.fp32))) return hipErrorInvalidValue;
   if (o.bf3) {
-    switch (o.flags) {  // front updates only
+    switch (o.flags) {  // front updates and pivot-inverse products
       case 0: gemm_bf3_inst<0>(o, st); break;
+      case G_NEG: gemm_bf3_inst<G_NEG>(o, st); break;
+      case G_TB | G_SYM | G_BETA | G_NEG: gemm_bf3_inst<G_TB | G_SYM | G_BETA | G_NEG>(o, st); break;
       case G_NEG | G_SYMA:
         if (o.a32) gemm_bf3_inst<G_NEG | G_SYMA | G_A32>(o, st);
         else gemm_bf3_inst<G_NEG | G_SYMA>(o, st);
@@ -1628,8 +1630,10 @@ hipError_t launch_gemm(const DevOp& o, hipStream_t st) {
     return hipGetLastError();
   }
   if (o.fp32) {
-    switch (o.flags) {  // front updates only (pivot GEMMs are always FP64)
+    switch (o.flags) {  // front updates and pivot-inverse products
       case 0: gemm32_inst<0>(o, st); break;
+      case G_NEG: gemm32_inst<G_NEG>(o, st); break;
+      case G_TB | G_SYM | G_BETA | G_NEG: gemm32_inst<G_TB | G_SYM | G_BETA | G_NEG>(o, st); break;
       case G_NEG | G_SYMA:
         if (o.a32) gemm32_inst<G_NEG | G_SYMA | G_A32>(o, st);
         else gemm32_inst<G_NEG | G_SYMA>(o, st);

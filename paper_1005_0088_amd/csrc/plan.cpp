@@ -404,16 +404,14 @@ struct Builder {
     }
     op.tile_count = static_cast<int64_t>(P.gemm_tiles.size()) - op.tile_begin;
     op.tile128_begin = static_cast<int64_t>(P.gemm_tiles.size());
-    if (!(flags & OP_PIVOT)) {  // front updates may run as low-precision GEMMs on 128x128 tiles
-      for (size_t i = 0; i < probs.size(); ++i) {
-        const GemmProb& g = probs[i];
-        const int tm = (g.m + 127) / 128, tn = (g.n + 127) / 128;
-        for (int a = 0; a < tm; ++a)
-          for (int b = 0; b < tn; ++b) {
-            if ((flags & G_SYM) && b > a) continue;
-            P.gemm_tiles.push_back(TileRef{static_cast<int32_t>(i), a, b, 0});
-          }
-      }
+    for (size_t i = 0; i < probs.size(); ++i) {  // for low-precision GEMMs on 128x128 tiles
+      const GemmProb& g = probs[i];
+      const int tm = (g.m + 127) / 128, tn = (g.n + 127) / 128;
+      for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tn; ++b) {
+          if ((flags & G_SYM) && b > a) continue;
+          P.gemm_tiles.push_back(TileRef{static_cast<int32_t>(i), a, b, 0});
+        }
     }
     op.tile128_count = static_cast<int64_t>(P.gemm_tiles.size()) - op.tile128_begin;
     op.tile32_begin = static_cast<int64_t>(P.gemm_tiles.size());

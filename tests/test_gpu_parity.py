@@ -747,6 +747,36 @@ def test_mixed_rho_against_oracle(dims, nb, fp64_poles, tol, precision, variant)
     assert err < tol
 
 
+@pytest.mark.parametrize("precision,pivot_variant", [("mixed_bf16x3", 4), ("mixed_bf16x3", 6), ("mixed_fp32", 1),
+                                                     ("mixed_bf16x3", -1)])
+def test_low_precision_pivot_products_against_oracle(precision, pivot_variant, tmp_path):
+    # the option that gives the low poles' recursive pivot-inverse products
+    # (blocks of more than 64 rows: the 324-row root of this lattice) the
+    # mode's low-precision GEMMs, forced or chosen per launch by the
+    # autotuner: rho within the mixed form's bar of the dense oracle, and
+    # different from the all-FP64-pivot run (the option really acts)
+    import paper_1005_0088_amd as nd
+    sysd = lattice((9, 9, 9), "nn", 15)
+    h, s, rows, cols = _dense(sysd)
+    eps, c = dense.eigen(h, s)
+    mu = dense.mu_for_count(eps, BETA, float(sysd["n"]))
+    ref = dense.rho_cf_pattern(eps, c, mu, BETA, 80, rows, cols)
+    out = {}
+    for pv in (0, pivot_variant):
+        with nd.Context(0, precision=precision, fp64_poles=8, fp64_far_poles=8, pivot_variant=pv) as cx:
+            sid = _register(cx, sysd)
+            cx.set_poles(sid, mu, BETA, 80)
+            if pv < 0:
+                cx.autotune([sid], str(tmp_path / "tune.txt"))
+            out[pv] = cx.density_matrix(sid)
+    err = np.max(np.abs(out[pivot_variant] - ref))
+    print("%s pivot_variant=%d err=%.3e (FP64 pivots %.3e)" % (precision, pivot_variant, err,
+                                                             np.max(np.abs(out[0] - ref))))
+    assert err < 1e-7
+    if pivot_variant > 0:
+        assert not np.array_equal(out[0], out[pivot_variant])
+
+
 # ------------------------------------------------------------- full-size sampled parity
 
 def _golden(name):
@@ -1063,7 +1093,7 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
     assert np.array_equal(got, again)
     with open(cache) as f:
         lines = f.read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("ndrho-tune-v4 ")
+    assert len(lines) == 1 and lines[0].startswith("ndrho-tune-v5 ") and " piv=0 " in lines[0]
     choice = lines[0].split()[-1]
     assert set(choice) <= set("012")
     with nd.Context(0, precision="mixed_fp32") as c:   # cached choice is reused, not re-tuned

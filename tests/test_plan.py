@@ -53,7 +53,8 @@ def test_default_options_and_struct_layouts():
     assert lib.ndrho_default_options(ctypes.byref(opt)) == 0
     want = {"leaf_rows": 32, "precision": 0, "pole_batch": 0, "mem_fraction": 0.8, "verbose": 0, "fp64_poles": 12,
             "fp64_pole_im": 0.05, "fp64_far_poles": 12, "use_graph": 1, "gemm_variant": -1, "fp64_small_tiles": -1,
-            "split_streams": 0, "long_tail": 0.0, "small_fronts": 0}
+            "split_streams": 0, "long_tail": 0.0, "small_fronts": 0,
+            "pivot_variant": 0}
     assert {k: getattr(opt, k) for k, _ in opt._fields_} == want
 
 
@@ -328,6 +329,14 @@ def test_long_tail_option_validated():
     sysd = lattice((4, 4), "nn", 3)
     with pytest.raises(nd.NdrhoError):
         nd.Plan(sysd["n"], sysd["row_ptr"], sysd["col"], sysd["coords"], 16, long_tail=0.5)
+
+
+def test_pivot_variant_option_validated():
+    # checked before any device call: FP32 mode accepts variants 0-2, split-BF16 mode 0-6, and -1
+    for precision, pv in (("mixed_fp32", 6), ("mixed_bf16x3", 7), ("mixed_bf16x3", -2)):
+        with pytest.raises(nd.NdrhoError) as e:
+            nd.Context(0, precision=precision, pivot_variant=pv)
+        assert e.value.name == "EINVAL" and "pivot_variant" in str(e.value)
 
 
 def test_small_front_option_validated():
