@@ -8,7 +8,7 @@
 // int32 col[nnz]; double coords[3n]; double cell[3] if has_cell; double
 // h[nnz], s[nnz]; double alpha_re, alpha_im, hcoef.
 // Output file: double (re, im) per pattern entry, then int32 status[2].
-// Exit code 2: the plan has fronts outside the small-front schedule.
+// Exit code 2: the plan has fronts outside the fused small-front launches.
 #include <cstdio>
 #include <fstream>
 #include <vector>
