@@ -226,6 +226,7 @@ def mu_search(nd, sysd, name, n_poles, args, beta):
         ctx.set_poles(sid, args.find_mu, beta, n_poles)
         if args.precision != "fp64" and not args.no_autotune:
             ctx.autotune([sid], args.tune_cache)
+        ctx.density_matrix(sid)   # untimed: workspace allocation and graph capture, as for the other timings
         t0 = time.perf_counter()
         mu, dn, it, rho = ctx.find_mu(sid, float(sysd["n"]), beta, n_poles, mu0=args.find_mu, tol=1e-8,
                                       retarded_step=args.retarded_step)
