@@ -399,7 +399,7 @@ def main():
         g, peak, kname = prof["gemm"], FP64_MFMA_PEAK_TFLOPS, "k_zgemm (complex FP64 front-update GEMMs)"
     elif head["precision"] == "mixed_bf16x3":
         g, peak, kname = (prof["gemm_bf16x3"], BF16_MFMA_PEAK_TFLOPS,
-                          "k_cgemm_bf3, k_cgemm_bf3s, k_cgemm_bf3p (complex front-update GEMMs, split-BF16 "
+                          "k_cgemm_bf3, k_cgemm_bf3s, k_cgemm_bf3p, k_cgemm_bf3w (complex front-update GEMMs, split-BF16 "
                           "products; achieved on useful flops, executed BF16 flops beside)")
         exec_per_useful = BF16X3_EXEC_PER_USEFUL
     else:

@@ -88,8 +88,9 @@ typedef struct {
                            4 split-BF16 products on 64x64 tiles; 5 split-BF16 products on 128x128 tiles,
                            each element split once per stage; 6 split-BF16 products on 128x128 tiles, K by
                            16 through double-buffered bf16 planes on the 32x32x16 matrix-core shape (a
-                           launch whose operands span 2^31 bytes or more runs variant 3 instead).  FP32
-                           mode accepts 0-2, split-BF16 mode 0-6 */
+                           launch whose operands span 2^31 bytes or more runs variant 3 instead); 7 as 6
+                           on sixteen waves of one 32x32 block each (same results bit for bit; the same
+                           fallback).  FP32 mode accepts 0-2, split-BF16 mode 0-7 */
   int32_t fp64_small_tiles; /* FP64 GEMM launches: -1 (default) one wave per 32x32 output tile where the
                                launch's problems would fill less than half of the 64x64 tiles; 0 never;
                                1 always */
@@ -117,7 +118,7 @@ typedef struct {
                             rows) for the low poles: 0 (default) FP64, as for the FP64 poles, so that the
                             pivot-block factorizations are FP64 throughout; -1 per-launch choice
                             (split-BF16 or FP32 products on 64x64 tiles where a launch's largest problem has
-                            256 rows or more, else FP64; refined by ndrho_autotune); 1-6 one of the
+                            256 rows or more, else FP64; refined by ndrho_autotune); 1-7 one of the
                             gemm_variant values the precision mode accepts.  The inverses of the 64-row
                             blocks at the bottom of the recursion and the FP64 poles stay FP64 */
 } ndrho_options;

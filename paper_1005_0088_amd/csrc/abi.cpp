@@ -163,7 +163,8 @@ double row_sum_norm(const Plan& P, const double* a) {
   return mx;
 }
 
-enum { V_FP64 = 0, V_F32_64 = 1, V_F32_128 = 2, V_BF3_128 = 3, V_BF3_64 = 4, V_BF3S_128 = 5, V_BF3P_128 = 6, V_COUNT = 7 };
+enum { V_FP64 = 0, V_F32_64 = 1, V_F32_128 = 2, V_BF3_128 = 3, V_BF3_64 = 4, V_BF3S_128 = 5, V_BF3P_128 = 6, V_BF3W_128 = 7,
+       V_COUNT = 8 };
 
 // Variants a precision mode may choose from: FP32 mode its FP32 products;
 // split-BF16 mode its split-BF16 products and, where a launch runs faster
@@ -496,12 +497,13 @@ struct ndrho_ctx {
           // variant of a front-update GEMM (chosen by heuristic or by the
           // autotuner, or forced by gemm_variant): V_FP64 keeps every pole in
           // FP64; the others give the low poles FP32 products (V_F32_64,
-          // V_F32_128) or split-BF16 products (V_BF3_128, V_BF3_64, V_BF3S_128, V_BF3P_128)
+          // V_F32_128) or split-BF16 products (V_BF3_128, V_BF3_64, V_BF3S_128, V_BF3P_128,
+          // V_BF3W_128)
           // (pivot-inverse GEMMs: pivot_variant if set, else the per-launch choice)
           const bool pivot = (op.flags & OP_PIVOT) != 0;
           const int forced = pivot ? opt.pivot_variant : opt.gemm_variant;
           int var = forced >= 0 ? forced : S.variant[cur_op];
-          if (var == V_BF3P_128 && !op.off32) var = V_BF3_128;  // 32-bit operand offsets only
+          if ((var == V_BF3P_128 || var == V_BF3W_128) && !op.off32) var = V_BF3_128;  // 32-bit operand offsets only
           const bool split = nhi < nb && var != V_FP64;
           const int k64 = (op.flags & OP_PIVOT) ? NDRHO_K_GEMM_PIVOT : NDRHO_K_GEMM;
           // FP64 launches of small problems: one wave per 32x32 tile
@@ -527,8 +529,9 @@ struct ndrho_ctx {
           }
           DevOp l = d;  // low-precision products for the others
           l.fp32 = var == V_F32_64 || var == V_F32_128;
-          l.bf3 = var == V_BF3_128 ? 1 : var == V_BF3_64 ? 2 : var == V_BF3S_128 ? 3 : var == V_BF3P_128 ? 4 : 0;
-          if (var == V_F32_128 || var == V_BF3_128 || var == V_BF3S_128 || var == V_BF3P_128) {
+          l.bf3 = var == V_BF3_128 ? 1 : var == V_BF3_64 ? 2 : var == V_BF3S_128 ? 3 : var == V_BF3P_128 ? 4
+                 : var == V_BF3W_128 ? 5 : 0;
+          if (var == V_F32_128 || var == V_BF3_128 || var == V_BF3S_128 || var == V_BF3P_128 || var == V_BF3W_128) {
             l.tile128 = true;
             l.gemm_tiles = S.gemm_tiles + op.tile128_begin;
             l.tile_count = op.tile128_count;
@@ -2032,7 +2035,7 @@ int ndrho_autotune(ndrho_ctx* ctx, const int32_t* struct_ids, int32_t k, const c
     const int nb = ctx->batch_for(P, T.n_shifts);
     char keybuf[256];
     std::snprintf(keybuf, sizeof(keybuf),
-                  "ndrho-tune-v5 n=%lld nnz=%lld fronts=%zu shifts=%d fp64=%d batch=%d prec=%d piv=%d ops=%d",
+                  "ndrho-tune-v6 n=%lld nnz=%lld fronts=%zu shifts=%d fp64=%d batch=%d prec=%d piv=%d ops=%d",
                   static_cast<long long>(P.n), static_cast<long long>(P.nnz), P.fronts.size(), T.n_shifts, T.n_hi,
                   nb, ctx->opt.precision, ctx->opt.pivot_variant, nops);
     const std::string key(keybuf);

@@ -22,7 +22,8 @@ struct DevOp {
   bool small = false;    // FP64 GEMM with one wave per 32x32 tile
   int bf3 = 0;           // split-BF16 products: 0 no; 1 128x128 tiles on 8 waves; 2 64x64 tiles on 4;
                          // 3 128x128 tiles, one split per element and stage; 4 128x128 tiles, K by
-                         // 16 in double-buffered bf16 planes (needs Op::off32)
+                         // 16 in double-buffered bf16 planes (needs Op::off32); 5 the same on sixteen
+                         // waves of 32 x 32
   int64_t count = 0, tile_count = 0;
   int64_t count16 = 0, count32 = 0;  // pivot inverse: blocks of the n <= 16 and n <= 32 classes
   const GemmProb* gemm = nullptr;

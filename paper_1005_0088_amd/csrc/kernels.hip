@@ -1393,6 +1393,160 @@ __global__ __launch_bounds__(512) void k_cgemm_bf3p(const GemmProb* __restrict__
     }
 }
 
+// Sixteen-wave form of the pre-split contraction: the same 128 x 128 tile,
+// the same twelve bf16 planes per 16-k stage in LDS (double-buffered) and the
+// same slice products in the same order per accumulator (so the results are
+// those of k_cgemm_bf3p bit for bit), but each wave computes one 32 x 32
+// block, four waves per SIMD.  Each thread stages two consecutive k of one
+// row per operand and stage.
+template <int FLAGS>
+__global__ __launch_bounds__(1024) void k_cgemm_bf3w(const GemmProb* __restrict__ probs,
+                                                    const TileRef* __restrict__ tiles, int64_t ntiles,
+                                                    int64_t npoles, const double2* __restrict__ A, int64_t sA,
+                                                    const double2* __restrict__ B, int64_t sB, const double2* C0,
+                                                    int64_t sC0, double2* C, int64_t sC,
+    const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
+  constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0, A32 = (FLAGS & G_A32) != 0;
+  static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
+  __shared__ __attribute__((aligned(16))) unsigned short lds[2 * B3P_STAGE];
+
+  const int64_t total = ntiles * npoles;
+  const int64_t logical = xcd_remap(blockIdx.x, total);
+  const int64_t pole = logical / ntiles;
+  const TileRef tr = tiles[logical % ntiles];
+  const GemmProb pr = probs[tr.prob];
+  const double2* Ap = A + pole * sA + pr.a_off;
+  const double2* Bp = B + pole * sB + pr.b_off;
+  const int M = pr.m, N = pr.n, K = pr.k;
+  const int m0 = tr.tm * B3P_TM, n0 = tr.tn * B3P_TM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 3, wn = wave >> 2;   // wave block: rows 32 wm.., columns 32 wn..
+
+  f16v cre, cim;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    cre[r] = 0.f;
+    cim[r] = 0.f;
+  }
+
+  // staging position: each wave covers 16 rows x 4 pairs of k, so that its
+  // store of one plane (rows 12 banks apart) hits 64 distinct LDS banks
+  const int srow = 16 * (wave & 7) + (lane & 15), sk = 2 * ((lane >> 4) + 4 * (wave >> 3));
+  const int arow = srow, ak = sk, brow = srow, bk = sk;
+  double2 ra0[2], rb0[2], ra1[2], rb1[2];   // two stages in flight
+  const __amdgpu_buffer_rsrc_t arsrc =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double2*>(Ap), static_cast<short>(0), B3P_OOB, 0x00020000);
+  const __amdgpu_buffer_rsrc_t brsrc =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double2*>(Bp), static_cast<short>(0), B3P_OOB, 0x00020000);
+  const uint32_t ulda = static_cast<uint32_t>(pr.lda), uldb = static_cast<uint32_t>(pr.ldb);
+  const uint32_t gm = static_cast<uint32_t>(m0 + arow), gn = static_cast<uint32_t>(n0 + brow);
+  const uint32_t uM = static_cast<uint32_t>(M), uN = static_cast<uint32_t>(N), uK = static_cast<uint32_t>(K);
+#define W3_LOAD(k0, ra, rb)                                                                             \
+  {                                                                                                     \
+    _Pragma("unroll") for (int q = 0; q < 2; ++q) {                                                     \
+      const uint32_t gk = static_cast<uint32_t>((k0) + ak + q);                                         \
+      const uint32_t o = (TA || (SYMA && gm < gk)) ? gk + gm * ulda : gm + gk * ulda;                   \
+      if (A32) {                                                                                        \
+        const float2 x_ = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(               \
+                                              arsrc, (gm < uM && gk < uK) ? o * 8u : B3P_OOB, 0, 0));   \
+        ra[q] = make_double2(static_cast<double>(x_.x), static_cast<double>(x_.y));                     \
+      } else {                                                                                          \
+        ra[q] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(                      \
+                                                arsrc, (gm < uM && gk < uK) ? o * 16u : B3P_OOB, 0, 0)); \
+      }                                                                                                 \
+    }                                                                                                   \
+    _Pragma("unroll") for (int q = 0; q < 2; ++q) {                                                     \
+      const uint32_t gk = static_cast<uint32_t>((k0) + bk + q);                                         \
+      const uint32_t o = TB ? gn + gk * uldb : gk + gn * uldb;                                          \
+      rb[q] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(                        \
+                                              brsrc, (gn < uN && gk < uK) ? o * 16u : B3P_OOB, 0, 0));  \
+    }                                                                                                   \
+  }
+#define W3_PUT(base, row, kk, v)                                                                        \
+  do {                                                                                                  \
+    unsigned h_, m_, l_;                                                                                \
+    unsigned short* d_ = lds + (base) + (row) * B3P_LD + (kk);                                          \
+    split2(f2{static_cast<float>((v)[0].x), static_cast<float>((v)[1].x)}, h_, m_, l_);                 \
+    *reinterpret_cast<unsigned*>(d_) = h_;                                                              \
+    *reinterpret_cast<unsigned*>(d_ + 2 * B3P_PLANE) = m_;                                              \
+    *reinterpret_cast<unsigned*>(d_ + 4 * B3P_PLANE) = l_;                                              \
+    split2(f2{static_cast<float>((v)[0].y), static_cast<float>((v)[1].y)}, h_, m_, l_);                 \
+    *reinterpret_cast<unsigned*>(d_ + B3P_PLANE) = h_;                                                  \
+    *reinterpret_cast<unsigned*>(d_ + 3 * B3P_PLANE) = m_;                                              \
+    *reinterpret_cast<unsigned*>(d_ + 5 * B3P_PLANE) = l_;                                              \
+  } while (0)
+#define W3_STORE(stage, ra, rb)                                                                         \
+  {                                                                                                     \
+    _Pragma("unroll") for (int q = 0; q < 2; ++q) {                                                     \
+      asm volatile("" : "+v"(ra[q].x), "+v"(ra[q].y), "+v"(rb[q].x), "+v"(rb[q].y));                   \
+    }                                                                                                   \
+    W3_PUT((stage) * B3P_STAGE, arow, ak, ra);                                                          \
+    W3_PUT((stage) * B3P_STAGE + 6 * B3P_PLANE, brow, bk, rb);                                          \
+  }
+
+  const int nk = (K + B3P_BK - 1) / B3P_BK, nk2 = nk + (nk & 1);
+  W3_LOAD(0, ra0, rb0)
+  W3_STORE(0, ra0, rb0)
+  W3_LOAD(B3P_BK, ra1, rb1)
+  __syncthreads();
+  const int orow = lane & 31, ok = 8 * (lane >> 5);
+#define W3_STEP(kt, rnow, bnow, rnext, bnext)                                                           \
+  {                                                                                                     \
+    W3_LOAD(((kt) + 2) * B3P_BK, rnow, bnow)                                                            \
+    asm volatile("" ::: "memory");                                                                      \
+    W3_MMA((kt) & 1)                                                                                    \
+    W3_STORE(((kt) & 1) ^ 1, rnext, bnext)                                                              \
+    __syncthreads();                                                                                    \
+  }
+#define W3_MMA(cur)                                                                                     \
+  {                                                                                                     \
+    const unsigned short* L = lds + (cur) * B3P_STAGE;                                                  \
+    bf8 a[6], b[6], na[3];                                                                              \
+    _Pragma("unroll") for (int pl = 0; pl < 6; ++pl)                                                    \
+      b[pl] = *reinterpret_cast<const bf8*>(L + (6 + pl) * B3P_PLANE + (wn * 32 + orow) * B3P_LD + ok); \
+    _Pragma("unroll") for (int pl = 0; pl < 6; ++pl)                                                    \
+      a[pl] = *reinterpret_cast<const bf8*>(L + pl * B3P_PLANE + (wm * 32 + orow) * B3P_LD + ok);       \
+    _Pragma("unroll") for (int sl = 0; sl < 3; ++sl)                                                    \
+      na[sl] = __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, a[2 * sl + 1]) ^ 0x80008000u);           \
+    _Pragma("unroll") for (int sa = 0; sa < 3; ++sa)                                                    \
+      _Pragma("unroll") for (int sb = 0; sb + sa < 3; ++sb) {                                           \
+        cre = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2 * sb], a[2 * sa], cre, 0, 0, 0);              \
+        cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2 * sb], a[2 * sa + 1], cim, 0, 0, 0);          \
+        cre = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2 * sb + 1], na[sa], cre, 0, 0, 0);             \
+        cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2 * sb + 1], a[2 * sa], cim, 0, 0, 0);          \
+      }                                                                                                 \
+  }
+  for (int kt = 0; kt < nk2; kt += 2) {
+    W3_STEP(kt, ra0, rb0, ra1, rb1)
+    W3_STEP(kt + 1, ra1, rb1, ra0, rb0)
+  }
+#undef W3_STEP
+#undef W3_MMA
+#undef W3_LOAD
+#undef W3_PUT
+#undef W3_STORE
+
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
+  const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
+  const XMap xm = EXTC0 ? stage_ext_maps<1024>(lds, B3P_TM, pr, xd, xk, xi, m0, n0) : XMap{nullptr, 0, 0, 0};
+  double2* Cp = C + pole * sC + pr.c_off;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {  // chunks of eight registers
+    double2 v[8];
+    int mm[8], nn[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = 8 * h + t;
+      mm[t] = m0 + wm * 32 + (lane & 31);
+      nn[t] = n0 + wn * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      v[t] = make_double2(static_cast<double>(cre[r]), static_cast<double>(cim[r]));
+    }
+    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
+  }
+}
+
 // ----------------------------------------------------------------- copy
 //
 // dst (rows x cols) <- src, or <- src^T through an LDS tile so that both the
@@ -1605,6 +1759,9 @@ static void gemm_bf3_inst(const DevOp& o, hipStream_t st) {
                        o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
   else if (o.bf3 == 3)
     hipLaunchKernelGGL(k_cgemm_bf3s<F>, dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm, o.gemm_tiles,
+                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
+  else if (o.bf3 == 5)
+    hipLaunchKernelGGL(k_cgemm_bf3w<F>, dim3(static_cast<unsigned>(total)), dim3(1024), 0, st, o.gemm, o.gemm_tiles,
                        o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
   else
     hipLaunchKernelGGL(k_cgemm_bf3p<F>, dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm, o.gemm_tiles,

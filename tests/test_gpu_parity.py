@@ -700,7 +700,8 @@ def test_errors(ctx):
 # ------------------------------------------------------------- precision form
 
 @pytest.mark.parametrize("precision,variant", [("mixed_fp32", 1), ("mixed_fp32", 2), ("mixed_bf16x3", 3),
-                                               ("mixed_bf16x3", 4), ("mixed_bf16x3", 5), ("mixed_bf16x3", 6)])
+                                               ("mixed_bf16x3", 4), ("mixed_bf16x3", 5), ("mixed_bf16x3", 6),
+                                               ("mixed_bf16x3", 7)])
 def test_mixed_single_shift_close_to_dense(precision, variant):
     # FP32 products with FP32 accumulation (64x64 or 128x128 tiles), or
     # split-BF16 products with FP32 accumulation: relative error of G well
@@ -727,7 +728,8 @@ def test_mixed_single_shift_close_to_dense(precision, variant):
                           ((9, 9, 9), "nn", 8, 1e-7, "mixed_bf16x3", 4), ((20, 18), "nn2", 8, 1e-7, "mixed_bf16x3", 4),
                           ((9, 9, 9), "nn", 8, 1e-7, "mixed_bf16x3", 5), ((20, 18), "nn2", 8, 1e-7, "mixed_bf16x3", 5),
                           ((9, 9, 9), "nn", 8, 1e-7, "mixed_bf16x3", 6), ((20, 18), "nn2", 8, 1e-7, "mixed_bf16x3", 6),
-                          ((9, 9, 9), "nn", 0, 1e-6, "mixed_bf16x3", 6)])
+                          ((9, 9, 9), "nn", 0, 1e-6, "mixed_bf16x3", 6), ((9, 9, 9), "nn", 8, 1e-7, "mixed_bf16x3", 7),
+                          ((20, 18), "nn2", 8, 1e-7, "mixed_bf16x3", 7)])
 def test_mixed_rho_against_oracle(dims, nb, fp64_poles, tol, precision, variant):
     # fp64_poles shifts nearest and as many farthest from the real axis in FP64
     import paper_1005_0088_amd as nd
@@ -745,6 +747,28 @@ def test_mixed_rho_against_oracle(dims, nb, fp64_poles, tol, precision, variant)
     err = np.max(np.abs(got - ref))
     print("%s fp64_poles=%d err=%.3e" % (precision, fp64_poles, err))
     assert err < tol
+
+
+@pytest.mark.parametrize("dims,nb", [((9, 9, 9), "nn"), ((20, 18), "nn2"), ((5, 4, 3), "nn")])
+def test_sixteen_wave_split_bf16_kernel_matches_eight_wave_bitwise(dims, nb):
+    # variant 7 (sixteen waves of 32 x 32) runs the same slice products in the
+    # same order per accumulator as variant 6 (eight waves of 64 x 32): rho
+    # and the energy density matrix agree bit for bit, every front update of
+    # every low pole on the one kernel (all four product shapes, the
+    # epilogue's extend-add, the FP32-stored G_UU operand, ragged tiles)
+    import paper_1005_0088_amd as nd
+    sysd = lattice(dims, nb, 21)
+    out = {}
+    for v in (6, 7):
+        with nd.Context(0, precision="mixed_bf16x3", fp64_poles=2, fp64_far_poles=2, fp64_pole_im=0.0,
+                        gemm_variant=v) as c:
+            sid = _register(c, sysd)
+            c.set_poles(sid, 0.0, BETA, 60)
+            rho = c.density_matrix(sid)
+            _, e = c.energy_density_matrix(sid)
+            out[v] = (rho, e)
+    assert np.array_equal(out[6][0], out[7][0]) and np.array_equal(out[6][1], out[7][1])
+    assert np.all(np.isfinite(out[7][0])) and np.max(np.abs(out[7][0])) > 0
 
 
 @pytest.mark.parametrize("precision,pivot_variant", [("mixed_bf16x3", 4), ("mixed_bf16x3", 6), ("mixed_fp32", 1),
@@ -1093,7 +1117,7 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
     assert np.array_equal(got, again)
     with open(cache) as f:
         lines = f.read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("ndrho-tune-v5 ") and " piv=0 " in lines[0]
+    assert len(lines) == 1 and lines[0].startswith("ndrho-tune-v6 ") and " piv=0 " in lines[0]
     choice = lines[0].split()[-1]
     assert set(choice) <= set("012")
     with nd.Context(0, precision="mixed_fp32") as c:   # cached choice is reused, not re-tuned
@@ -1110,7 +1134,7 @@ def test_autotune_keeps_accuracy_and_caches(tmp_path):
         assert np.max(np.abs(c.density_matrix(s3) - ref)) < 1e-7
     with open(cache) as f:
         lines = f.read().splitlines()
-    assert len(lines) == 2 and set(lines[1].split()[-1]) <= set("0123456")
+    assert len(lines) == 2 and set(lines[1].split()[-1]) <= set("01234567")
     # a cached choice naming variants the mode does not accept is ignored and tuned again
     bad = lines[0].rsplit(" ", 1)[0] + " " + "9" * len(lines[0].split()[-1])
     with open(cache, "w") as f:

@@ -332,8 +332,8 @@ def test_long_tail_option_validated():
 
 
 def test_pivot_variant_option_validated():
-    # checked before any device call: FP32 mode accepts variants 0-2, split-BF16 mode 0-6, and -1
-    for precision, pv in (("mixed_fp32", 6), ("mixed_bf16x3", 7), ("mixed_bf16x3", -2)):
+    # checked before any device call: FP32 mode accepts variants 0-2, split-BF16 mode 0-7, and -1
+    for precision, pv in (("mixed_fp32", 6), ("mixed_bf16x3", 8), ("mixed_bf16x3", -2)):
         with pytest.raises(nd.NdrhoError) as e:
             nd.Context(0, precision=precision, pivot_variant=pv)
         assert e.value.name == "EINVAL" and "pivot_variant" in str(e.value)
