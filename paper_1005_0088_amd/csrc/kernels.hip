@@ -529,6 +529,134 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ p
   }
 }
 
+// The same FP64 contraction on eight waves of 32 x 16 per 64 x 64 tile: the
+// same LDS stages and the same products in the same order per accumulator
+// (so the results are those of k_zgemm bit for bit), but each wave holds a
+// third of the accumulators, so that four waves fit a SIMD (two workgroups
+// per compute unit) and hide one another's LDS and barrier waits.
+template <int FLAGS>
+__global__ __launch_bounds__(512, 4) void k_zgemm8(const GemmProb* __restrict__ probs,
+                                                   const TileRef* __restrict__ tiles, int64_t ntiles, int64_t npoles,
+                                                   const double2* __restrict__ A, int64_t sA,
+                                                   const double2* __restrict__ B, int64_t sB, const double2* C0,
+                                                   int64_t sC0, double2* C, int64_t sC,
+    const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
+  constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0;
+  constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
+  constexpr bool SYMA = (FLAGS & G_SYMA) != 0, A32 = (FLAGS & G_A32) != 0;
+  static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
+  static_assert(!A32, "the FP64 kernels read FP64 operands");
+  __shared__ double2 As[2][BK][BM + 1];
+  __shared__ double2 Bs[2][BK][BN + 1];
+
+  const int64_t total = ntiles * npoles;
+  const int64_t logical = xcd_remap(blockIdx.x, total);
+  const int64_t pole = logical / ntiles;
+  const TileRef tr = tiles[logical % ntiles];
+  const GemmProb pr = probs[tr.prob];
+  const double2* Ap = A + pole * sA + pr.a_off;
+  const double2* Bp = B + pole * sB + pr.b_off;
+  const int M = pr.m, N = pr.n, K = pr.k;
+  const int m0 = tr.tm * BM, n0 = tr.tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;   // wave piece: rows 32 wm.., columns 16 wn..
+
+  d4 p1[2], p2[2], p3[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    p1[i] = d4{0.0, 0.0, 0.0, 0.0};
+    p2[i] = d4{0.0, 0.0, 0.0, 0.0};
+    p3[i] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+
+  double2 ra0, ra1, rb0, rb1;
+  // element i (0, 1) of this thread's share of a 64 x 16 stage
+#define Z8_LDA(i, k0, dst)                                                             \
+  do {                                                                                 \
+    const int m_ = TA ? (tid >> 4) + 32 * (i) : (tid & 63);                           \
+    const int k_ = TA ? (tid & 15) : (tid >> 6) + 8 * (i);                            \
+    const int gm = m0 + m_, gk = (k0) + k_;                                            \
+    dst = (gm < M && gk < K) ? (TA ? Ap[gk + int64_t(gm) * pr.lda]                    \
+                                   : (SYMA && gm < gk) ? Ap[gk + int64_t(gm) * pr.lda]      \
+                                                       : Ap[gm + int64_t(gk) * pr.lda])     \
+                             : make_double2(0.0, 0.0);                                      \
+  } while (0)
+#define Z8_LDB(i, k0, dst)                                                             \
+  do {                                                                                 \
+    const int n_ = TB ? (tid & 63) : (tid >> 4) + 32 * (i);                           \
+    const int k_ = TB ? (tid >> 6) + 8 * (i) : (tid & 15);                            \
+    const int gn = n0 + n_, gk = (k0) + k_;                                            \
+    dst = (gn < N && gk < K) ? (TB ? Bp[gn + int64_t(gk) * pr.ldb] : Bp[gk + int64_t(gn) * pr.ldb]) : make_double2(0.0, 0.0); \
+  } while (0)
+#define Z8_STA(buf, i, v) As[buf][TA ? (tid & 15) : (tid >> 6) + 8 * (i)][TA ? (tid >> 4) + 32 * (i) : (tid & 63)] = (v)
+#define Z8_STB(buf, i, v) Bs[buf][TB ? (tid >> 6) + 8 * (i) : (tid & 15)][TB ? (tid & 63) : (tid >> 4) + 32 * (i)] = (v)
+#define Z8_LOAD(k0)          \
+  do {                       \
+    Z8_LDA(0, k0, ra0);      \
+    Z8_LDA(1, k0, ra1);      \
+    Z8_LDB(0, k0, rb0);      \
+    Z8_LDB(1, k0, rb1);      \
+  } while (0)
+#define Z8_STORE(buf)        \
+  do {                       \
+    Z8_STA(buf, 0, ra0);     \
+    Z8_STA(buf, 1, ra1);     \
+    Z8_STB(buf, 0, rb0);     \
+    Z8_STB(buf, 1, rb1);     \
+  } while (0)
+
+  const int nk = (K + BK - 1) / BK;
+  Z8_LOAD(0);
+  Z8_STORE(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) Z8_LOAD((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      double2 av[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = As[cur][kr][wm * 32 + i * 16 + (lane & 15)];
+      const double2 bv = Bs[cur][kr][wn * 16 + (lane & 15)];
+      double as[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) as[i] = av[i].x + av[i].y;
+      const double bs = bv.x + bv.y;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) p1[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv.x, av[i].x, p1[i], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) p2[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv.y, av[i].y, p2[i], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) p3[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(bs, as[i], p3[i], 0, 0, 0);
+    }
+    if (kt + 1 < nk) Z8_STORE(cur ^ 1);
+    __syncthreads();
+  }
+#undef Z8_LDA
+#undef Z8_LDB
+#undef Z8_STA
+#undef Z8_STB
+#undef Z8_LOAD
+#undef Z8_STORE
+
+  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
+  const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
+  const XMap xm = EXTC0 ? stage_ext_maps<512>(&As[0][0][0], BM, pr, xd, xk, xi, m0, n0) : XMap{nullptr, 0, 0, 0};
+  double2* Cp = C + pole * sC + pr.c_off;
+  double2 v[8];
+  int mm[8], nn[8];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      mm[4 * i + r] = m0 + wm * 32 + i * 16 + (lane & 15);
+      nn[4 * i + r] = n0 + wn * 16 + F64_DROW(r, lane);
+      v[4 * i + r] = make_double2(p1[i][r] - p2[i][r], p3[i][r] - p1[i][r] - p2[i][r]);
+    }
+  store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
+}
+
 // The same FP64 contraction for small problems: one wave per 32 x 32
 // output tile (four waves per workgroup, independent), operands read from
 // global memory straight into the MFMA operand registers: no LDS and no
@@ -1730,8 +1858,11 @@ static void gemm_inst(const DevOp& o, hipStream_t st) {
     hipLaunchKernelGGL(k_zgemm_w<F>, dim3(static_cast<unsigned>((total + 3) / 4)), dim3(256), 0, st, o.gemm,
                        o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
                        o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
-  else
+  else if constexpr ((F & G_EXTC0) != 0)  // the epilogue's extend-add spills on eight waves
     hipLaunchKernelGGL(k_zgemm<F>, dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
+                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
+  else
+    hipLaunchKernelGGL(k_zgemm8<F>, dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm, o.gemm_tiles,
                        o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
 }
 
