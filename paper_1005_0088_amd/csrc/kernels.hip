@@ -378,8 +378,10 @@ __global__ __launch_bounds__(THREADS) void k_smallinv(const InvDesc* __restrict_
 // Re = P1 - P2, Im = P3 - P1 - P2), issued so that consecutive MFMAs never
 // share an accumulator.  Transposes are plain transposes (the matrices are
 // complex symmetric, never Hermitian).  One 64x64 output tile per workgroup
-// of four waves (2 x 2 waves of 32 x 32), K staged through LDS in steps of 16
-// with double buffering.  The MFMA operands are swapped (B-tile as the A
+// of eight waves (2 x 4 waves of 32 x 16, a third of the accumulators per
+// wave, so that two workgroups per compute unit give four waves per SIMD and
+// hide one another's LDS and barrier waits), K staged through LDS in steps of
+// 16 with double buffering.  The MFMA operands are swapped (B-tile as the A
 // operand) so that each lane owns one row of C (the accumulator of the f64
 // 16x16x4 instruction holds D[4r + lane/16][lane%16] in register r), and a
 // wave's stores run down the columns of the column-major C.  With G_SYM only tiles
@@ -388,158 +390,11 @@ __global__ __launch_bounds__(THREADS) void k_smallinv(const InvDesc* __restrict_
 constexpr int BM = 64, BN = 64, BK = 16;
 
 template <int FLAGS>
-__global__ __launch_bounds__(256, 2) void k_zgemm(const GemmProb* __restrict__ probs,
+__global__ __launch_bounds__(512, 4) void k_zgemm(const GemmProb* __restrict__ probs,
                                                   const TileRef* __restrict__ tiles, int64_t ntiles, int64_t npoles,
                                                   const double2* __restrict__ A, int64_t sA,
                                                   const double2* __restrict__ B, int64_t sB, const double2* C0,
                                                   int64_t sC0, double2* C, int64_t sC,
-    const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
-  constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
-  constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
-  constexpr bool SYMA = (FLAGS & G_SYMA) != 0, A32 = (FLAGS & G_A32) != 0;
-  static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
-  static_assert(!A32, "the FP64 kernels read FP64 operands");
-  __shared__ double2 As[2][BK][BM + 1];
-  __shared__ double2 Bs[2][BK][BN + 1];
-
-  const int64_t total = ntiles * npoles;
-  const int64_t logical = xcd_remap(blockIdx.x, total);
-  const int64_t pole = logical / ntiles;
-  const TileRef tr = tiles[logical % ntiles];
-  const GemmProb pr = probs[tr.prob];
-  const double2* Ap = A + pole * sA + pr.a_off;
-  const double2* Bp = B + pole * sB + pr.b_off;
-  const int M = pr.m, N = pr.n, K = pr.k;
-  const int m0 = tr.tm * BM, n0 = tr.tn * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-
-  d4 p1[2][2], p2[2][2], p3[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      p1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      p2[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      p3[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-
-  double2 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-  // operand staging without local arrays (arrays captured by a lambda end up
-  // in scratch memory); element i of this thread's share of a 64x16 stage
-#define ZG_LDA(i, k0, dst)                                                             \
-  do {                                                                                 \
-    const int m_ = TA ? (tid >> 4) + 16 * (i) : (tid & 63);                           \
-    const int k_ = TA ? (tid & 15) : (tid >> 6) + 4 * (i);                            \
-    const int gm = m0 + m_, gk = (k0) + k_;                                            \
-    dst = (gm < M && gk < K) ? (TA ? Ap[gk + int64_t(gm) * pr.lda]                    \
-                                   : (SYMA && gm < gk) ? Ap[gk + int64_t(gm) * pr.lda]      \
-                                                       : Ap[gm + int64_t(gk) * pr.lda])     \
-                             : make_double2(0.0, 0.0);                                      \
-  } while (0)
-#define ZG_LDB(i, k0, dst)                                                             \
-  do {                                                                                 \
-    const int n_ = TB ? (tid & 63) : (tid >> 4) + 16 * (i);                           \
-    const int k_ = TB ? (tid >> 6) + 4 * (i) : (tid & 15);                            \
-    const int gn = n0 + n_, gk = (k0) + k_;                                            \
-    dst = (gn < N && gk < K) ? (TB ? Bp[gn + int64_t(gk) * pr.ldb] : Bp[gk + int64_t(gn) * pr.ldb]) : make_double2(0.0, 0.0); \
-  } while (0)
-#define ZG_STA(buf, i, v) As[buf][TA ? (tid & 15) : (tid >> 6) + 4 * (i)][TA ? (tid >> 4) + 16 * (i) : (tid & 63)] = (v)
-#define ZG_STB(buf, i, v) Bs[buf][TB ? (tid >> 6) + 4 * (i) : (tid & 15)][TB ? (tid & 63) : (tid >> 4) + 16 * (i)] = (v)
-#define ZG_LOAD(k0)          \
-  do {                       \
-    ZG_LDA(0, k0, ra0);      \
-    ZG_LDA(1, k0, ra1);      \
-    ZG_LDA(2, k0, ra2);      \
-    ZG_LDA(3, k0, ra3);      \
-    ZG_LDB(0, k0, rb0);      \
-    ZG_LDB(1, k0, rb1);      \
-    ZG_LDB(2, k0, rb2);      \
-    ZG_LDB(3, k0, rb3);      \
-  } while (0)
-#define ZG_STORE(buf, CV)                                                                            \
-  do {                                                                                               \
-    ZG_STA(buf, 0, CV(ra0));                                                                         \
-    ZG_STA(buf, 1, CV(ra1));                                                                         \
-    ZG_STA(buf, 2, CV(ra2));                                                                         \
-    ZG_STA(buf, 3, CV(ra3));                                                                         \
-    ZG_STB(buf, 0, CV(rb0));                                                                         \
-    ZG_STB(buf, 1, CV(rb1));                                                                         \
-    ZG_STB(buf, 2, CV(rb2));                                                                         \
-    ZG_STB(buf, 3, CV(rb3));                                                                         \
-  } while (0)
-#define ZG_ID(v) (v)
-
-  const int nk = (K + BK - 1) / BK;
-  ZG_LOAD(0);
-  ZG_STORE(0, ZG_ID);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) ZG_LOAD((kt + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      const int kr = kk * 4 + (lane >> 4);
-      double2 av[2], bv[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        av[i] = As[cur][kr][wm * 32 + i * 16 + (lane & 15)];
-        bv[i] = Bs[cur][kr][wn * 32 + i * 16 + (lane & 15)];
-      }
-      double as[2], bs[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        as[i] = av[i].x + av[i].y;
-        bs[i] = bv[i].x + bv[i].y;
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j].x, av[i].x, p1[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j].y, av[i].y, p2[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bs[j], as[i], p3[i][j], 0, 0, 0);
-    }
-    if (kt + 1 < nk) ZG_STORE(cur ^ 1, ZG_ID);
-    __syncthreads();
-  }
-
-  const double2* C0p = BETA ? C0 + pole * sC0 + pr.c0_off : EXTC0 ? C0 + pole * sC0 : nullptr;
-  const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
-  const XMap xm = EXTC0 ? stage_ext_maps<256>(&As[0][0][0], BM, pr, xd, xk, xi, m0, n0) : XMap{nullptr, 0, 0, 0};
-  double2* Cp = C + pole * sC + pr.c_off;
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    double2 v[8];
-    int mm[8], nn[8];
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        mm[4 * j + r] = m0 + wm * 32 + i * 16 + (lane & 15);
-        nn[4 * j + r] = n0 + wn * 32 + j * 16 + F64_DROW(r, lane);
-        v[4 * j + r] = make_double2(p1[i][j][r] - p2[i][j][r], p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
-      }
-    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
-  }
-}
-
-// The same FP64 contraction on eight waves of 32 x 16 per 64 x 64 tile: the
-// same LDS stages and the same products in the same order per accumulator
-// (so the results are those of k_zgemm bit for bit), but each wave holds a
-// third of the accumulators, so that four waves fit a SIMD (two workgroups
-// per compute unit) and hide one another's LDS and barrier waits.
-template <int FLAGS>
-__global__ __launch_bounds__(512, 4) void k_zgemm8(const GemmProb* __restrict__ probs,
-                                                   const TileRef* __restrict__ tiles, int64_t ntiles, int64_t npoles,
-                                                   const double2* __restrict__ A, int64_t sA,
-                                                   const double2* __restrict__ B, int64_t sB, const double2* C0,
-                                                   int64_t sC0, double2* C, int64_t sC,
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
   constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0;
   constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
@@ -644,17 +499,18 @@ __global__ __launch_bounds__(512, 4) void k_zgemm8(const GemmProb* __restrict__ 
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
   const XMap xm = EXTC0 ? stage_ext_maps<512>(&As[0][0][0], BM, pr, xd, xk, xi, m0, n0) : XMap{nullptr, 0, 0, 0};
   double2* Cp = C + pole * sC + pr.c_off;
-  double2 v[8];
-  int mm[8], nn[8];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i) {  // a chunk of four elements per 16-row block (eight spill with G_EXTC0)
+    double2 v[4];
+    int mm[4], nn[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      mm[4 * i + r] = m0 + wm * 32 + i * 16 + (lane & 15);
-      nn[4 * i + r] = n0 + wn * 16 + F64_DROW(r, lane);
-      v[4 * i + r] = make_double2(p1[i][r] - p2[i][r], p3[i][r] - p1[i][r] - p2[i][r]);
+      mm[r] = m0 + wm * 32 + i * 16 + (lane & 15);
+      nn[r] = n0 + wn * 16 + F64_DROW(r, lane);
+      v[r] = make_double2(p1[i][r] - p2[i][r], p3[i][r] - p1[i][r] - p2[i][r]);
     }
-  store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
+    store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
+  }
 }
 
 // The same FP64 contraction for small problems: one wave per 32 x 32
@@ -1559,9 +1415,10 @@ __global__ __launch_bounds__(1024) void k_cgemm_bf3w(const GemmProb* __restrict_
     cim[r] = 0.f;
   }
 
-  // staging position: each wave covers 16 rows x 4 pairs of k, so that its
-  // store of one plane (rows 12 banks apart) hits 64 distinct LDS banks
-  const int srow = 16 * (wave & 7) + (lane & 15), sk = 2 * ((lane >> 4) + 4 * (wave >> 3));
+  // staging position: each half-wave covers 8 consecutive rows x 4 pairs of
+  // k, so that its 4-byte stores of one plane (rows 12 banks apart) hit 32
+  // distinct banks (the store pass of 32 lanes over 32 banks)
+  const int srow = 16 * (wave & 7) + (lane & 7) + 8 * (lane >> 5), sk = 2 * (((lane >> 3) & 3) + 4 * (wave >> 3));
   const int arow = srow, ak = sk, brow = srow, bk = sk;
   double2 ra0[2], rb0[2], ra1[2], rb1[2];   // two stages in flight
   const __amdgpu_buffer_rsrc_t arsrc =
@@ -1661,12 +1518,12 @@ __global__ __launch_bounds__(1024) void k_cgemm_bf3w(const GemmProb* __restrict_
   const XMap xm = EXTC0 ? stage_ext_maps<1024>(lds, B3P_TM, pr, xd, xk, xi, m0, n0) : XMap{nullptr, 0, 0, 0};
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {  // chunks of eight registers
-    double2 v[8];
-    int mm[8], nn[8];
+  for (int h = 0; h < 4; ++h) {  // chunks of four registers (eight spill with G_EXTC0)
+    double2 v[4];
+    int mm[4], nn[4];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int r = 8 * h + t;
+    for (int t = 0; t < 4; ++t) {
+      const int r = 4 * h + t;
       mm[t] = m0 + wm * 32 + (lane & 31);
       nn[t] = n0 + wn * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
       v[t] = make_double2(static_cast<double>(cre[r]), static_cast<double>(cim[r]));
@@ -1858,11 +1715,8 @@ static void gemm_inst(const DevOp& o, hipStream_t st) {
     hipLaunchKernelGGL(k_zgemm_w<F>, dim3(static_cast<unsigned>((total + 3) / 4)), dim3(256), 0, st, o.gemm,
                        o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
                        o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
-  else if constexpr ((F & G_EXTC0) != 0)  // the epilogue's extend-add spills on eight waves
-    hipLaunchKernelGGL(k_zgemm<F>, dim3(static_cast<unsigned>(total)), dim3(256), 0, st, o.gemm, o.gemm_tiles,
-                       o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
   else
-    hipLaunchKernelGGL(k_zgemm8<F>, dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm, o.gemm_tiles,
+    hipLaunchKernelGGL(k_zgemm<F>, dim3(static_cast<unsigned>(total)), dim3(512), 0, st, o.gemm, o.gemm_tiles,
                        o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0, o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
 }
 
