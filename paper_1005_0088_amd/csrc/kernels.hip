@@ -25,12 +25,15 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// 1/p with scaling against overflow of |p|^2.
+// 1/p = conj(p) / |p|^2 with one division: p is first scaled exactly by the
+// power of two that brings its larger part into [0.5, 1), so that |p|^2
+// neither overflows nor underflows, and the result is scaled back.
 __device__ __forceinline__ double2 cinv(double2 p) {
-  const double s = fmax(fabs(p.x), fabs(p.y));
-  const double xr = p.x / s, xi = p.y / s;
-  const double d = (xr * xr + xi * xi) * s;
-  return make_double2(xr / d, -xi / d);
+  int e;
+  frexp(fmax(fabs(p.x), fabs(p.y)), &e);
+  const double xr = ldexp(p.x, -e), xi = ldexp(p.y, -e);
+  const double t = 1.0 / (xr * xr + xi * xi);
+  return make_double2(ldexp(xr * t, -e), ldexp(-xi * t, -e));
 }
 
 // Element i of a GEMM's A operand: FP64 complex, or FP32 complex widened
