@@ -91,7 +91,7 @@ typedef struct {
                            launch whose operands span 2^31 bytes or more runs variant 3 instead); 7 as 6
                            on sixteen waves of one 32x32 block each (same results bit for bit; the same
                            fallback).  FP32 mode accepts 0-2, split-BF16 mode 0-7 */
-  int32_t fp64_small_tiles; /* FP64 GEMM launches: -1 (default) one wave per 32x32 output tile where the
+  int32_t fp64_small_tiles; /* FP64 GEMM launches: -1 (default) 32x32 output tiles (two waves each) where the
                                launch's problems would fill less than half of the 64x64 tiles; 0 never;
                                1 always */
   int32_t split_streams; /* mixed mode, 0-4: 0 (default) runs every pass as one launch chain, captured in

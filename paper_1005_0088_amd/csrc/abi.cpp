@@ -506,7 +506,7 @@ struct ndrho_ctx {
           if ((var == V_BF3P_128 || var == V_BF3W_128) && !op.off32) var = V_BF3_128;  // 32-bit operand offsets only
           const bool split = nhi < nb && var != V_FP64;
           const int k64 = (op.flags & OP_PIVOT) ? NDRHO_K_GEMM_PIVOT : NDRHO_K_GEMM;
-          // FP64 launches of small problems: one wave per 32x32 tile
+          // FP64 launches of small problems: two waves per 32x32 tile, no LDS
           const bool small = opt.fp64_small_tiles < 0 ? op.small : opt.fp64_small_tiles != 0;
           auto fp64_launch = [&](DevOp x) {
             if (small) {

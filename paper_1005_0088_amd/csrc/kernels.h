@@ -19,7 +19,7 @@ struct DevOp {
   int gat_out32 = 0;     // GATHER: write the G_UU of the other poles as FP32
   bool fp32 = false;     // GEMM products on the FP32 matrix cores
   bool tile128 = false;  // FP32 GEMM on 128x128 tiles (else 64x64)
-  bool small = false;    // FP64 GEMM with one wave per 32x32 tile
+  bool small = false;    // FP64 GEMM with two waves per 32x32 tile, no LDS
   int bf3 = 0;           // split-BF16 products: 0 no; 1 128x128 tiles on 8 waves; 2 64x64 tiles on 4;
                          // 3 128x128 tiles, one split per element and stage; 4 128x128 tiles, K by
                          // 16 in double-buffered bf16 planes (needs Op::off32); 5 the same on sixteen

@@ -516,84 +516,85 @@ __global__ __launch_bounds__(512, 4) void k_zgemm(const GemmProb* __restrict__ p
   }
 }
 
-// The same FP64 contraction for small problems: one wave per 32 x 32
-// output tile (four waves per workgroup, independent), operands read from
-// global memory straight into the MFMA operand registers: no LDS and no
-// barriers, so a tile whose problem is much smaller than 64 x 64 costs
-// little.  K advances by 8 (two MFMA k-steps), all loads of a step issued
-// before its products; an element outside the problem is read from the
-// operand's first element and replaced by zero (no branches around loads).
+// The same FP64 contraction for small problems: two waves per 32 x 32
+// output tile, each a 32 x 16 half (two tiles per workgroup of four waves,
+// the waves independent), operands read from global memory straight into the
+// MFMA operand registers: no LDS and no barriers, so a tile whose problem is
+// much smaller than 64 x 64 costs little.  K advances by 8 (two MFMA
+// k-steps), all loads of a step issued before its products; an element
+// outside the problem is read from the operand's first element and replaced
+// by zero (no branches around loads).  A half holds a third of the
+// accumulators of a whole tile, so that four waves fit a SIMD and hide one
+// another's load latency; a half whose columns all lie beyond the problem
+// exits at once.
 template <int FLAGS>
-__global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__ probs,
+__global__ __launch_bounds__(256, 4) void k_zgemm_w(const GemmProb* __restrict__ probs,
                                                  const TileRef* __restrict__ tiles, int64_t ntiles, int64_t npoles,
                                                  const double2* __restrict__ A, int64_t sA,
                                                  const double2* __restrict__ B, int64_t sB, const double2* C0,
                                                  int64_t sC0, double2* C, int64_t sC,
     const ExtAddDesc* __restrict__ xe, const ExtAddChild* __restrict__ xk, const int32_t* __restrict__ xi) {
-  constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0, SYM = (FLAGS & G_SYM) != 0;
+  constexpr bool TA = (FLAGS & G_TA) != 0, TB = (FLAGS & G_TB) != 0;
   constexpr bool BETA = (FLAGS & G_BETA) != 0, EXTC0 = (FLAGS & G_EXTC0) != 0;
   constexpr bool SYMA = (FLAGS & G_SYMA) != 0, A32 = (FLAGS & G_A32) != 0;
   static_assert(!(SYMA && TA), "a lower-stored symmetric A is read untransposed");
   static_assert(!A32, "the FP64 kernels read FP64 operands");
   const int64_t total = ntiles * npoles;
-  const int64_t w = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  const int64_t wv = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  const int64_t w = wv >> 1;
   if (w >= total) return;  // the whole wave; nothing here synchronises waves
   const int lane = threadIdx.x & 63;
   const int64_t pole = w / ntiles;
   const TileRef tr = tiles[w % ntiles];
   const GemmProb pr = probs[tr.prob];
+  const int M = pr.m, N = pr.n, K = pr.k;
+  const int m0 = tr.tm * 32, n0 = tr.tn * 32 + 16 * static_cast<int>(wv & 1);
+  if (n0 >= N) return;  // the whole wave: no column of this half is in the problem
   const double2* Ap = A + pole * sA + pr.a_off;
   const double2* Bp = B + pole * sB + pr.b_off;
-  const int M = pr.m, N = pr.n, K = pr.k;
-  const int m0 = tr.tm * 32, n0 = tr.tn * 32;
   const int r = lane & 15, kq = lane >> 4;
 
-  d4 p1[2][2], p2[2][2], p3[2][2];
+  d4 p1[2], p2[2], p3[2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      p1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      p2[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      p3[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    }
+  for (int i = 0; i < 2; ++i) {
+    p1[i] = d4{0.0, 0.0, 0.0, 0.0};
+    p2[i] = d4{0.0, 0.0, 0.0, 0.0};
+    p3[i] = d4{0.0, 0.0, 0.0, 0.0};
+  }
   for (int k0 = 0; k0 < K; k0 += 8) {
-    double2 a[2][2], b[2][2];
-    bool oa[2][2], ob[2][2];
+    double2 a[2][2], b[2];
+    bool oa[2][2], ob[2];
 #pragma unroll
-    for (int st = 0; st < 2; ++st)
+    for (int st = 0; st < 2; ++st) {
+      const int gk = k0 + 4 * st + kq;
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const int gk = k0 + 4 * st + kq;
         const int gm = m0 + 16 * i + r;
         oa[st][i] = gm < M && gk < K;
         const int64_t ia = (TA || (SYMA && gm < gk)) ? gk + int64_t(gm) * pr.lda : gm + int64_t(gk) * pr.lda;
         a[st][i] = Ap[oa[st][i] ? ia : int64_t(0)];
-        const int gn = n0 + 16 * i + r;
-        ob[st][i] = gn < N && gk < K;
-        const int64_t ib = TB ? gn + int64_t(gk) * pr.ldb : gk + int64_t(gn) * pr.ldb;
-        b[st][i] = Bp[ob[st][i] ? ib : int64_t(0)];
       }
+      const int gn = n0 + r;
+      ob[st] = gn < N && gk < K;
+      const int64_t ib = TB ? gn + int64_t(gk) * pr.ldb : gk + int64_t(gn) * pr.ldb;
+      b[st] = Bp[ob[st] ? ib : int64_t(0)];
+    }
 #pragma unroll
     for (int st = 0; st < 2; ++st) {
-      double ar[2], ai[2], as[2], br[2], bi[2], bs[2];
+      double ar[2], ai[2], as[2];
+      const double br = ob[st] ? b[st].x : 0.0, bi = ob[st] ? b[st].y : 0.0, bs = br + bi;
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         ar[i] = oa[st][i] ? a[st][i].x : 0.0;
         ai[i] = oa[st][i] ? a[st][i].y : 0.0;
-        br[i] = ob[st][i] ? b[st][i].x : 0.0;
-        bi[i] = ob[st][i] ? b[st][i].y : 0.0;
         as[i] = ar[i] + ai[i];
-        bs[i] = br[i] + bi[i];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[j], ar[i], p1[i][j], 0, 0, 0);
-          p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bi[j], ai[i], p2[i][j], 0, 0, 0);
-          p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bs[j], as[i], p3[i][j], 0, 0, 0);
-        }
+      for (int i = 0; i < 2; ++i) {
+        p1[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(br, ar[i], p1[i], 0, 0, 0);
+        p2[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(bi, ai[i], p2[i], 0, 0, 0);
+        p3[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(bs, as[i], p3[i], 0, 0, 0);
+      }
     }
   }
 
@@ -603,16 +604,14 @@ __global__ __launch_bounds__(256, 2) void k_zgemm_w(const GemmProb* __restrict__
   double2* Cp = C + pole * sC + pr.c_off;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    double2 v[8];
-    int mm[8], nn[8];
+    double2 v[4];
+    int mm[4], nn[4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        mm[4 * j + q] = m0 + i * 16 + (lane & 15);
-        nn[4 * j + q] = n0 + j * 16 + F64_DROW(q, lane);
-        v[4 * j + q] = make_double2(p1[i][j][q] - p2[i][j][q], p3[i][j][q] - p1[i][j][q] - p2[i][j][q]);
-      }
+    for (int q = 0; q < 4; ++q) {
+      mm[q] = m0 + i * 16 + (lane & 15);
+      nn[q] = n0 + F64_DROW(q, lane);
+      v[q] = make_double2(p1[i][q] - p2[i][q], p3[i][q] - p1[i][q] - p2[i][q]);
+    }
     store_chunk<FLAGS>(v, mm, nn, pr, C0p, Cp, xd, xk, xi, xm);
   }
 }
@@ -1719,8 +1718,8 @@ hipError_t launch_smallinv(const DevOp& o, int* status, int spd_check, hipStream
 template <int F>
 static void gemm_inst(const DevOp& o, hipStream_t st) {
   const int64_t total = o.tile_count * o.npoles;
-  if (o.small)  // one wave per 32x32 tile, four per workgroup
-    hipLaunchKernelGGL(k_zgemm_w<F>, dim3(static_cast<unsigned>((total + 3) / 4)), dim3(256), 0, st, o.gemm,
+  if (o.small)  // two waves per 32x32 tile, two tiles per workgroup
+    hipLaunchKernelGGL(k_zgemm_w<F>, dim3(static_cast<unsigned>((2 * total + 3) / 4)), dim3(256), 0, st, o.gemm,
                        o.gemm_tiles, o.tile_count, static_cast<int64_t>(o.npoles), o.a, o.sa, o.b, o.sb, o.c0, o.sc0,
                        o.c, o.sc, o.ext, o.ext_child, o.ext_inv);
   else
