@@ -747,7 +747,9 @@ __global__ __launch_bounds__(64 * NWR * NWR, NWR == 2 ? 2 : 1) void k_cgemm32(co
   const ExtAddDesc xd = EXTC0 ? xe[pr.ext] : ExtAddDesc{};
   const XMap xm = EXTC0 ? stage_ext_maps<NT>(&As[0][0][0], TM, pr, xd, xk, xi, m0, n0) : XMap{nullptr, 0, 0, 0};
   double2* Cp = C + pole * sC + pr.c_off;
-  constexpr int CB = NWR == 2 ? 2 : 1;  // 16-column blocks per chunk (two spill within 128 registers)
+  // 16-column blocks per chunk: two hold too many registers within 128 (sixteen waves) or with the
+  // epilogue's extend-add
+  constexpr int CB = (NWR == 2 && !EXTC0) ? 2 : 1;
 #pragma unroll
   for (int i = 0; i < WT; ++i)
 #pragma unroll
