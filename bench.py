@@ -322,7 +322,7 @@ def main():
     ap.add_argument("--eig-iter", type=int, default=300, help="with --eigenstates: iteration limit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the whole hot path on a single MI355X "
+        print("bench.py measures one GPU only: the library runs the whole hot path on a single MI355X "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -50,7 +50,7 @@ enum {
   NDRHO_ESINGULAR = -4,   /* a zero, tiny or non-finite pivot in alpha S - H */
   NDRHO_EDEVICE = -5,     /* HIP runtime error, or no usable gfx950 device */
   NDRHO_ESTATE = -6,      /* call out of order (e.g. density_matrix before set_poles) */
-  NDRHO_EUNSUPPORTED = -7 /* option not supported by this build */
+  NDRHO_EUNSUPPORTED = -7 /* option not supported by the library */
 };
 
 /* Arithmetic of the front updates.  Storage, pivot-block inverses, the
